@@ -1,0 +1,226 @@
+"""Pins of the FP64 learned-field oracle (Sec. 4) against closed forms (no GPU).
+
+* trilinear lookup (Sec. 4.2, dense levels): reproduces affine feature fields
+  exactly, returns stored values at level vertices, weights sum to one, the
+  boundary u = 1 lands on the last vertex; gather and scatter are adjoint;
+* a hand-built network whose output has a closed form (asymmetric selections,
+  so a transposed weight, a wrong feature slot or a missing ReLU fails);
+* symmetry of the self field (Sec. 4.1) and the variable-swap identity of a
+  two-encoder field (Sec. 6.4);
+* the adjoint against central finite differences;
+* the first Adam step in closed form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import ndf_net as nn
+
+DIMS = (5, 4, 3)
+RES = [(2, 2, 2), (3, 3, 2), (4, 3, 3), (5, 4, 3)]
+
+
+def _layout(width=128, n_enc=1, dims=DIMS, res=RES):
+    return gen.NetLayout(dims[0], dims[1], dims[2], tuple(res), 8, width, n_enc)
+
+
+def _net(flat, width=128, n_enc=1, dims=DIMS, res=RES):
+    return nn.Net(flat, dims, res, 8, width, n_enc)
+
+
+def _cell_positions(R):
+    rx, ry, rz = R
+    c = np.arange(rx * ry * rz)
+    x, y, z = c % rx, (c // rx) % ry, c // (rx * ry)
+    return np.stack([x / (rx - 1), y / (ry - 1), z / (rz - 1)], axis=1)
+
+
+def test_layout_parse_matches_generator():
+    for n_enc in (1, 2):
+        L = _layout(n_enc=n_enc)
+        flat = gen.make_net_params(L)
+        net = _net(flat, n_enc=n_enc)
+        assert net.n_floats == L.n_floats
+        for name, shape in L.tensors():
+            if name.startswith("grid"):
+                e, l = map(int, name[4:].split("_"))
+                key = ("grid", e, l)
+            elif name[-2] == "_":
+                key = (name[:-2], int(name[-1]))
+            else:
+                key = name
+            np.testing.assert_array_equal(net[key], L.view(flat, name))
+
+
+def test_trilinear_affine_and_vertices():
+    rng = np.random.default_rng(0)
+    for R in RES + [(62, 88, 5)]:
+        u = rng.uniform(0, 1, (500, 3))
+        u[:5] = 1.0
+        u[5:10] = 0.0
+        idx, w = nn.trilinear(u, R)
+        assert np.allclose(w.sum(1), 1.0, atol=1e-15)
+        assert np.all(w >= 0)
+        pos = _cell_positions(R)
+        coef = rng.standard_normal(4)
+        vals = coef[0] + pos @ coef[1:]
+        interp = np.sum(w * vals[idx], axis=1)
+        assert np.max(np.abs(interp - (coef[0] + u @ coef[1:]))) < 1e-12
+        # at the level's own vertices the stored value comes back
+        idx, w = nn.trilinear(pos, R)
+        got = np.sum(w * vals[idx], axis=1)
+        assert np.max(np.abs(got - vals)) < 1e-12
+        # u = 1 on every axis is the last vertex with weight one
+        idx, w = nn.trilinear(np.ones((1, 3)), R)
+        assert idx[0, np.argmax(w[0])] == R[0] * R[1] * R[2] - 1 and w[0].max() == 1.0
+
+
+def test_gather_scatter_adjoint():
+    rng = np.random.default_rng(1)
+    L = _layout()
+    net = _net(gen.make_net_params(L, grid_scale=1.0))
+    u = rng.uniform(0, 1, (300, 3))
+    G = net.zeros_like()
+    for l in range(4):
+        G[("grid", 0, l)] = rng.standard_normal(G[("grid", 0, l)].shape)
+    y = rng.standard_normal((300, 32))
+    probe = _net(G.flat)
+    lhs = np.sum(nn.grid_encode(probe, 0, u) * y)
+    S = net.zeros_like()
+    nn.grid_scatter(net, 0, u, y, S)
+    rhs = sum(np.sum(G[("grid", 0, l)] * S[("grid", 0, l)]) for l in range(4))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def hand_built_params(dims=DIMS, res=RES, noise_seed=3):
+    """Parameters whose field is Phi(p1, p2) = Q(u1) Q(u2) + 1/8 with
+    Q(u) = u_x + 6 u_y + 4.5 (see test_hand_built_network_closed_form)."""
+    L = _layout(dims=dims, res=res)
+    flat = np.zeros(L.n_floats)
+    net = _net(flat, dims=dims, res=res)
+    rng = np.random.default_rng(noise_seed)
+    for l, R in enumerate(res):
+        g = net[("grid", 0, l)]
+        g[:] = rng.standard_normal(g.shape)          # unused slots hold noise
+        pos = _cell_positions(R)
+        if l == 0:
+            g[:, 2] = pos[:, 0] + 2.0                 # A(u) = u_x + 2
+        if l == 2:
+            g[:, 5] = 3.0 * pos[:, 1] + 1.0           # B(u) = 3 u_y + 1
+        if l == 3:
+            g[:, 0] = pos[:, 2]                       # C(u) = u_z
+    W1, b1 = net[("W1", 0)], net[("b1", 0)]
+    W1[3, 2] = 1.0                                    # a1[3] = A
+    W1[9, 21] = 2.0; b1[9] = 0.5                      # a1[9] = 2B + 1/2
+    W1[100, 24] = -1.0; b1[100] = -5.0                # a1[100] < 0, cut by ReLU
+    W2, b2 = net[("W2", 0)], net[("b2", 0)]
+    W2[7, 3] = 1.0; W2[7, 9] = 1.0                    # a2[7] = A + 2B + 1/2 = Q
+    W2[50, 100] = 3.0; b2[50] = 1.0                   # a2[50] = 1 only after ReLU
+    W3, b3 = net[("W3", 0)], net[("b3", 0)]
+    W3[11, 7] = 1.0                                   # lat[11] = Q
+    W3[12, 50] = 1.0; b3[12] = -3.0                   # lat[12] = -2
+    W4, b4 = net["W4"], net["b4"]
+    W4[20, 11] = 1.0; W4[20, 12] = 0.25               # a4[20] = Q1 Q2 + 1
+    W4[21, 12] = -1.0                                 # a4[21] = -4, cut by ReLU
+    W5, b5 = net["W5"], net["b5"]
+    W5[5, 20] = 2.0; W5[5, 21] = 7.0; b5[5] = 0.25    # a5[5] = 2 (Q1 Q2 + 1) + 1/4
+    net["w6"][5] = 0.5
+    net["b6"][0] = -1.0                               # y = Q1 Q2 + 1/8
+    return net.flat.astype(np.float32)
+
+
+def hand_built_value(v1, v2, dims=DIMS):
+    u1 = nn.vertex_positions(v1, dims)
+    u2 = nn.vertex_positions(v2, dims)
+    q1 = u1[:, 0] + 6 * u1[:, 1] + 4.5
+    q2 = u2[:, 0] + 6 * u2[:, 1] + 4.5
+    return q1 * q2 + 0.125
+
+
+def test_hand_built_network_closed_form():
+    flat = hand_built_params()
+    net = _net(flat)
+    V = DIMS[0] * DIMS[1] * DIMS[2]
+    v1, v2 = np.meshgrid(np.arange(V), np.arange(V))
+    v1, v2 = v1.ravel(), v2.ravel()
+    y, _ = nn.forward(net, v1, v2)
+    assert np.max(np.abs(y - hand_built_value(v1, v2))) < 1e-12
+
+
+def test_self_field_symmetric_exactly():
+    L = _layout()
+    net = _net(gen.make_net_params(L, grid_scale=0.5, bias_scale=0.1))
+    pairs = gen.random_pairs(60, 500, seed=4)
+    y12, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    y21, _ = nn.forward(net, pairs[:, 1], pairs[:, 0])
+    assert np.array_equal(y12, y21)
+
+
+def test_two_encoder_swap_identity():
+    # Phi_{nu mu}(p1, p2) = Phi_{mu nu}(p2, p1): swapping the encoders' parameters
+    # and the positions leaves the value unchanged
+    L = _layout(n_enc=2)
+    flat = gen.make_net_params(L, grid_scale=0.5, bias_scale=0.1)
+    net = _net(flat, n_enc=2)
+    sw = _net(flat, n_enc=2)
+    for key in list(net.slices):
+        if isinstance(key, tuple) and key[0] != "grid":
+            sw[(key[0], 1 - key[1])] = net[key]
+        elif isinstance(key, tuple):
+            sw[("grid", 1 - key[1], key[2])] = net[key]
+    pairs = gen.random_pairs(60, 300, seed=6)
+    y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    ys, _ = nn.forward(sw, pairs[:, 1], pairs[:, 0])
+    assert np.max(np.abs(y - ys)) < 1e-13
+    y_fwd, _ = nn.forward(net, pairs[:, 1], pairs[:, 0])
+    assert np.max(np.abs(y - y_fwd)) > 1e-6           # the field itself is not symmetric
+
+
+@pytest.mark.parametrize("n_enc", [1, 2])
+def test_adjoint_vs_finite_differences(n_enc):
+    width = 16
+    L = _layout(width=width, n_enc=n_enc)
+    flat = gen.make_net_params(L, seed=9, grid_scale=0.5, bias_scale=0.2).astype(np.float64)
+    net = _net(flat, width=width, n_enc=n_enc)
+    pairs = gen.random_pairs(60, 64, seed=8)
+    y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    t = y - 10.0                      # every residual positive: L = mean(y) + 10, smooth
+    loss, g, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    for key in net.slices:
+        o, shape = net.slices[key]
+        n = int(np.prod(shape))
+        d = np.zeros_like(flat)
+        d[o:o + n] = rng.standard_normal(n)
+        lp = nn.l1_loss(nn.forward(_net(flat + h * d, width=width, n_enc=n_enc),
+                                   pairs[:, 0], pairs[:, 1])[0], t)
+        lm = nn.l1_loss(nn.forward(_net(flat - h * d, width=width, n_enc=n_enc),
+                                   pairs[:, 0], pairs[:, 1])[0], t)
+        fd = (lp - lm) / (2 * h)
+        an = float(np.dot(g.flat, d))
+        assert abs(fd - an) <= 1e-6 * max(1e-3, abs(an)) + 1e-9, (key, fd, an)
+
+
+def test_l1_gradient_sign_convention():
+    L = _layout(width=16)
+    net = _net(gen.make_net_params(L, seed=3, grid_scale=0.5, bias_scale=0.2), width=16)
+    pairs = gen.random_pairs(60, 8, seed=1)
+    y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    _, g_lo, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], y - 1.0)
+    _, g_hi, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], y + 1.0)
+    np.testing.assert_allclose(g_lo.flat, -g_hi.flat, atol=1e-15)
+    assert g_lo["b6"][0] == pytest.approx(1.0)        # d mean(y - t) / d b6
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(1000)
+    g = rng.standard_normal(1000) * 10.0 ** rng.uniform(-9, 1, 1000)
+    lr = 3e-4
+    p1, m, v = nn.adam_update(p, g, np.zeros(1000), np.zeros(1000), 1, lr)
+    np.testing.assert_allclose(p1, p - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-14)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-14)
