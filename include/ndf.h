@@ -1,0 +1,200 @@
+/*
+ * ndf.h - C ABI of the MI355X (gfx950) hot path of neural dependence fields.
+ *
+ * Problem (Sec. 3): an ensemble of N members, each a scalar field per variable on
+ * an nx*ny*nz grid.  For a reference vertex p_ref the dependence field
+ * R(p_ref, .) holds, at every vertex p, a bivariate dependence measure between
+ * the local samples e(p_ref) and e(p) (the N member values at those vertices):
+ * Pearson's r (Sec. 3.1, Eq. 1) or mutual information by the nearest-neighbour
+ * estimator of Kraskov et al. (Sec. 3.2, Eq. 2).  The learned field (Sec. 4,
+ * Eq. 3) approximates R by a network Phi(p1, p2) that is trained on direct
+ * estimates and evaluated at every vertex (Sec. 5).
+ *
+ * Conventions for every call
+ *  - Pointers are DEVICE pointers unless marked [host].  The caller owns all
+ *    memory, including the workspace `ws`; the library allocates, frees and
+ *    synchronises nothing and keeps no pointer after a call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    only enqueue work on it; results are valid once the stream has reached
+ *    that point.
+ *  - Arguments are validated on the host before anything is enqueued: an
+ *    invalid call returns a negative NDF_E_* status and enqueues nothing.
+ *    NDF_E_HIP means a launch failed (hipGetLastError after the launch).
+ *  - Vertex index v = i + nx*(j + ny*k); V = nx*ny*nz.
+ *  - Calls that share a workspace must not overlap in time.
+ *
+ * Build: libndf.so (hipcc --offload-arch=gfx950).  No function needs a GPU to be
+ * looked up; every compute call needs one to run.
+ */
+#ifndef NDF_H
+#define NDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NDF_OK = 0,
+    NDF_E_ARG = -1,          /* null pointer, index or size out of range          */
+    NDF_E_WORKSPACE = -2,    /* ws NULL or ws_bytes below ndf_workspace_bytes()   */
+    NDF_E_HIP = -3,          /* a kernel launch failed                            */
+    NDF_E_UNSUPPORTED = -5   /* valid request outside what the kernels implement  */
+};
+
+enum {
+    NDF_PREC_FP32 = 0,       /* FP32 FMA stream (direct Pearson)                  */
+    NDF_PREC_SPLIT_BF16 = 1, /* hi+lo BF16 MFMA, FP32 accumulate (direct Pearson) */
+    NDF_PREC_BF16 = 2,       /* BF16 MFMA network, FP32 accumulate                */
+    NDF_PREC_FP8_E4M3 = 3    /* OCP E4M3 weights/activations, FP32 accumulate     */
+};
+
+enum {                       /* `op` of ndf_workspace_bytes                       */
+    NDF_OP_PEARSON_FIELD = 1,
+    NDF_OP_KSG_FIELD = 2,
+    NDF_OP_TRAIN = 3,
+    NDF_OP_INFER = 4,
+    NDF_OP_KSG_PAIRS = 5
+};
+
+enum {                       /* per-vertex flags written by ndf_prepare           */
+    NDF_FLAG_NONFINITE = 1,  /* a member value is NaN or infinite                 */
+    NDF_FLAG_CONSTANT = 2    /* all member values are equal (zero range)          */
+};
+
+/* The ensemble (Sec. 3: members E_i, variables nu, local samples e^nu(p)). */
+typedef struct ndf_ensemble {
+    int32_t n_members;       /* N, 2 <= N <= 4096 (KSG calls: N <= 2048)          */
+    int32_t nx, ny, nz;      /* grid; each >= 2                                   */
+    int32_t n_vars;          /* d >= 1                                            */
+    const float *x;          /* [n_vars][N][V] float32, member-major (input)      */
+    double *mean;            /* [n_vars][V] population mean      (ndf_prepare)    */
+    double *inv_std;         /* [n_vars][V] 1/population std, 0 where std == 0    */
+    int32_t *code;           /* [n_vars][V][N] KSG integer codes, vertex-major    */
+    int32_t *flags;          /* [n_vars][V] NDF_FLAG_* bits                       */
+} ndf_ensemble;
+
+/* The learned field (Sec. 4.1-4.2): per encoder a dense multi-resolution feature
+ * grid (n_levels levels of feats features, trilinear lookup) and an MLP
+ * L*F -> W -> W -> W (ReLU after the first two layers, linear latent); the two
+ * latents are multiplied element-wise and a decoder W -> W -> W -> 1 (ReLU,
+ * ReLU, linear) gives Phi.  n_enc = 1: one encoder and grid for both positions
+ * (self field, Phi symmetric); n_enc = 2: encoder 0 for p1, encoder 1 for p2.
+ * Grid vertex (i,j,k) is at u = (i/(nx-1), j/(ny-1), k/(nz-1)).  The kernels
+ * implement n_levels = 4, feats = 8, width = 128. */
+typedef struct ndf_net_config {
+    int32_t nx, ny, nz;      /* data grid whose vertices are evaluated            */
+    int32_t n_levels;        /* 4                                                 */
+    int32_t res[4][3];       /* level sizes (Rx, Ry, Rz), each >= 2               */
+    int32_t feats;           /* 8                                                 */
+    int32_t width;           /* 128                                               */
+    int32_t n_enc;           /* 1 or 2                                            */
+} ndf_net_config;
+
+/* Human-readable name of a status code (static storage). */
+const char *ndf_status_string(int status);
+
+/* Workspace bytes for `op`.  `ens` is used by the PEARSON/KSG ops, `net` by
+ * TRAIN/INFER; n = n_ref for the field ops, B (pairs per step) for TRAIN.
+ * `prec` as the call will use it.  Returns 0 for an invalid request. */
+size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_config *net,
+                           int64_t n, int32_t prec);
+
+/* Standardisation and KSG codes, one pass set per ensemble (Sec. 3.1 Eq. 1
+ * needs per-vertex means and variances; Sec. 3.2 the KSG neighbour search).
+ * Writes mean, inv_std (FP64, population moments), flags, and for every vertex
+ * v and member m the code rne((x - lo_v) * 2^23 / (hi_v - lo_v)) with lo/hi
+ * the column min/max, all in IEEE double (0 for a constant column). */
+int ndf_prepare(const ndf_ensemble *ens, void *stream);
+
+/* Direct Pearson field (Sec. 3.1, Eq. 1; Table 1 "Pearson"):
+ * out[r][v] = r(e^{var_ref}(ref_v[r]), e^{var_qry}(v)) for r < n_ref, v < V.
+ * ref_v [host] int64[n_ref].  prec NDF_PREC_FP32 streams the ensemble once per
+ * reference; NDF_PREC_SPLIT_BF16 runs all references as one MFMA contraction of
+ * standardised members (z = zhi + zlo, products hi*hi + hi*lo + lo*hi, FP32
+ * accumulate).  r = 0 where either vertex has zero variance.  Needs ndf_prepare. */
+int ndf_pearson_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
+                      const int64_t *ref_v, int32_t n_ref, float *out, int32_t prec,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Direct KSG mutual-information field in nats (Sec. 3.2, Eq. 2; estimator of
+ * [KSG04], first algorithm; Table 1 "MI"):  for the samples (x_m, y_m) =
+ * (code[ref][m], code[v][m]), eps_m = k-th smallest max-norm distance to the
+ * other samples, nx_m / ny_m = number of other samples strictly closer than
+ * eps_m in x / y, and
+ *   out[r][v] = psi(k) + psi(N) - (1/N) sum_m [psi(nx_m + 1) + psi(ny_m + 1)].
+ * Counts are exact integers; the sum is FP64.  0 where either vertex is
+ * constant.  counts (nullable) int32[n_ref][V][2][N] receives nx, ny in member
+ * order.  1 <= k <= 8, k < N.  Needs ndf_prepare. */
+int ndf_ksg_mi_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
+                     const int64_t *ref_v, int32_t n_ref, int32_t k, float *out,
+                     int32_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* Direct estimates for B vertex pairs (training targets of Eq. 3, Sec. 4.3):
+ * out[b] = r or MI between e^{var_a}(pairs[b][0]) and e^{var_b}(pairs[b][1]),
+ * with the definitions of ndf_pearson_field / ndf_ksg_mi_field.  pairs
+ * int64[B][2] (device).  KSG: counts (nullable) int32[B][2][N] in member order;
+ * ws of ndf_workspace_bytes(NDF_OP_KSG_PAIRS, ...) bytes. */
+int ndf_pearson_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
+                      const int64_t *pairs, int64_t B, float *out, void *stream);
+int ndf_ksg_mi_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
+                     const int64_t *pairs, int64_t B, int32_t k, float *out,
+                     int32_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the FP32 parameter vector (layout: for each encoder its grid levels
+ * float[Rx*Ry*Rz][feats], then W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3; then
+ * W4[W][W], b4, W5[W][W], b5, w6[W], b6[1]; every tensor starts at a multiple of
+ * 64 floats, gaps zero) and of the Adam state (m then v, same layout). */
+size_t ndf_net_param_bytes(const ndf_net_config *cfg);
+size_t ndf_net_optstate_bytes(const ndf_net_config *cfg);
+
+/* Seeded initialisation (He-uniform weights, zero biases, grid features
+ * U(-1e-4, 1e-4)) from a counter-based generator (SplitMix64 of seed and
+ * element index); also zeroes the Adam state when opt_state is non-NULL. */
+int ndf_net_init(const ndf_net_config *cfg, float *params, float *opt_state, uint64_t seed,
+                 void *stream);
+
+/* Mean L1 loss over B pairs (Eq. 3 with d = L1, Sec. 4.3) and its gradient with
+ * respect to every parameter (float[param_bytes/4], overwritten), by the
+ * library's forward and adjoint kernels (BF16 MFMA, FP32 accumulate, FP32
+ * atomic scatter into the grids).  pairs int64[B][2] (device), targets
+ * float[B]; loss_out float[1] (device). */
+int ndf_net_grad(const ndf_net_config *cfg, const float *params, const int64_t *pairs,
+                 const float *targets, int64_t B, float *grad_out, float *loss_out,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* One training step of Eq. 3 (Sec. 4.3): ndf_net_grad followed by Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; `step` counts from 1).
+ * opt_state holds m then v.  ws needs ndf_workspace_bytes(NDF_OP_TRAIN, .., B, ..)
+ * plus the parameter bytes rounded up to 256; the gradient is left there. */
+int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
+                   const int64_t *pairs, const float *targets, int64_t B, float lr,
+                   float *loss_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Inference parameters for `prec` (NDF_PREC_BF16 or NDF_PREC_FP8_E4M3) packed
+ * from the FP32 parameters: BF16 grids, weights in MFMA operand order, FP32
+ * biases; FP8 adds per-output-channel weight scales. */
+size_t ndf_net_qparam_bytes(const ndf_net_config *cfg, int32_t prec);
+int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t prec,
+                     void *qparams, void *stream);
+
+/* Learned dependence field (Sec. 5): out[r][v] = Phi(p_ref[r], p_v) at every grid
+ * vertex v, for ref_v [host] int64[n_ref].  The reference latent is computed
+ * once; every query is encoded, multiplied with it and decoded in one fused
+ * kernel (grid gather + MFMA MLP). */
+int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec,
+                    const int64_t *ref_v, int32_t n_ref, float *out, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Phi(p1, p2) for B vertex pairs (device int64[B][2]) from the FP32 parameters
+ * with the training forward kernels (BF16 MFMA, FP32 accumulate); y float[B]. */
+int ndf_net_forward(const ndf_net_config *cfg, const float *params, const int64_t *pairs,
+                    int64_t B, float *y, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDF_H */

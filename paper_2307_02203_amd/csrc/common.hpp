@@ -1,0 +1,54 @@
+// Shared device helpers of the gfx950 kernels: bf16/fp8 conversions, MFMA
+// operand types, wave reductions and launch bookkeeping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ndf.h"
+
+namespace ndf {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) int i32x4;
+
+constexpr int kWave = 64;
+
+// MFMA 32x32x16 (bf16 in, fp32 accumulate), one wave:
+//   A operand: lane l holds A[i = l%32][k = 8*(l/32) + e], e = 0..7
+//   B operand: lane l holds B[k = 8*(l/32) + e][j = l%32]
+//   D        : lane l, register r holds D[i = 8*(r/4) + 4*(l/32) + r%4][j = l%32]
+__device__ __forceinline__ f32x16 mfma32(const bf16x8 &a, const bf16x8 &b, const f32x16 &c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int d_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// Round-to-nearest-even float -> bf16 bits (finite inputs; NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf_bits2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ __bf16 f2bf(float f) { return __builtin_bit_cast(__bf16, f2bf_bits(f)); }
+__device__ __forceinline__ float bf2f(__bf16 b) { return bf_bits2f(__builtin_bit_cast(uint16_t, b)); }
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+inline int status_of_launch() { return hipGetLastError() == hipSuccess ? NDF_OK : NDF_E_HIP; }
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+}  // namespace ndf

@@ -1,0 +1,370 @@
+// Direct KSG mutual-information dependence (Sec. 3.2, Eq. 2; nearest-neighbour
+// estimator of Kraskov, Stoegbauer and Grassberger, their first algorithm).
+//
+// For one (reference a, query b) pair the N samples are (x_m, y_m) =
+// (code[a][m], code[b][m]), integer codes from ndf_prepare.  For every sample
+//   eps_m = k-th smallest max(|x_m - x_j|, |y_m - y_j|) over j != m,
+//   nx_m  = #{j != m : |x_m - x_j| < eps_m},  ny_m likewise in y,
+// and I = psi(k) + psi(N) - <psi(nx+1) + psi(ny+1)>, which with
+// psi(n) = H_{n-1} - gamma is H_{k-1} + H_{N-1} - <H_nx + H_ny>.
+//
+// GPU design (one 64-lane wave per pair, everything in LDS):
+//  * samples are ordered by x (ties broken by member index); a field shares one
+//    ordering of the reference column across all queries, so it is sorted once;
+//  * the k nearest neighbours of a sample are found by walking outwards in x
+//    order from its own position and stopping on each side once |dx| reaches the
+//    current k-th distance (no later sample can be closer under the max-norm);
+//  * the marginal counts are two binary searches each, over the sorted x codes
+//    and over the query's y codes sorted in LDS (bitonic sort);
+//  * all distances and counts are exact int32, so the counts equal a brute-force
+//    evaluation bit for bit; the harmonic sum is FP64.
+#include "common.hpp"
+
+namespace ndf {
+
+constexpr int kKsgMaxN = 4096;
+
+__device__ __forceinline__ int pow2_ceil(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+__device__ __forceinline__ int pow2_floor(int n) {
+    int p = 1;
+    while (p * 2 <= n) p <<= 1;
+    return p;
+}
+
+// Ascending bitonic sort of P (power of two) keys in LDS by one wave (64 lanes).
+template <typename T>
+__device__ void wave_bitonic_sort(T *a, int P) {
+    const int lane = threadIdx.x;
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < P / 2; t += 64) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                T u = a[i], w = a[j];
+                if ((u > w) == up) {
+                    a[i] = w;
+                    a[j] = u;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Number of entries < val among the first n of an ascending array.
+template <int STRIDE>
+__device__ __forceinline__ int count_less(const int *a, int n, int hp, int val) {
+    int pos = 0;
+    for (int s = hp; s > 0; s >>= 1)
+        if (pos + s <= n && a[(pos + s - 1) * STRIDE] < val) pos += s;
+    return pos;
+}
+
+// Neighbour search and counts for all samples of one pair.  xy[p] = (x, y) in
+// x order, ys = y codes ascending; returns this lane's FP64 sum of H_nx + H_ny.
+template <int K>
+__device__ double ksg_points(const int2 *xy, const int *ys, int N, const double *__restrict__ H,
+                             const uint16_t *perm, int32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x;
+    const int hp = pow2_floor(N);
+    double acc = 0.0;
+    for (int p = lane; p < N; p += 64) {
+        const int2 me = xy[p];
+        int best[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
+        int jl = p - 1, jr = p + 1;
+        bool al = jl >= 0, ar = jr < N;
+        while (al || ar) {
+            if (al) {
+                const int2 c = xy[jl];
+                const int dx = me.x - c.x;
+                if (dx >= best[K - 1]) {
+                    al = false;
+                } else {
+                    const int d = max(dx, abs(me.y - c.y));
+#pragma unroll
+                    for (int t = K - 1; t > 0; --t) best[t] = min(best[t], max(best[t - 1], d));
+                    best[0] = min(best[0], d);
+                    --jl;
+                    al = jl >= 0;
+                }
+            }
+            if (ar) {
+                const int2 c = xy[jr];
+                const int dx = c.x - me.x;
+                if (dx >= best[K - 1]) {
+                    ar = false;
+                } else {
+                    const int d = max(dx, abs(me.y - c.y));
+#pragma unroll
+                    for (int t = K - 1; t > 0; --t) best[t] = min(best[t], max(best[t - 1], d));
+                    best[0] = min(best[0], d);
+                    ++jr;
+                    ar = jr < N;
+                }
+            }
+        }
+        const int eps = best[K - 1];
+        int nx = 0, ny = 0;
+        if (eps > 0) {
+            // samples with value in (v - eps, v + eps), minus the sample itself
+            nx = count_less<2>(&xy[0].x, N, hp, me.x + eps) -
+                 count_less<2>(&xy[0].x, N, hp, me.x - eps + 1) - 1;
+            ny = count_less<1>(ys, N, hp, me.y + eps) - count_less<1>(ys, N, hp, me.y - eps + 1) -
+                 1;
+        }
+        acc += H[nx] + H[ny];
+        if (cnt) {
+            const int m = perm[p];
+            cnt[m] = nx;
+            cnt[N + m] = ny;
+        }
+    }
+    return acc;
+}
+
+// ----------------------------------------------------------- field mode ----
+// Prologue: for each reference, its codes in ascending (code, member) order and
+// the member permutation; plus the harmonic table H[0..N] (sequential FP64 sum).
+__global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
+                                    const int64_t *__restrict__ refs, int32_t *__restrict__ xs,
+                                    uint16_t *__restrict__ perm, double *__restrict__ H) {
+    extern __shared__ unsigned long long s_keys[];
+    const int r = blockIdx.x;
+    const int P = pow2_ceil(N);
+    const int32_t *c = code + refs[r] * N;
+    for (int m = threadIdx.x; m < P; m += 64)
+        s_keys[m] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
+    __syncthreads();
+    wave_bitonic_sort(s_keys, P);
+    for (int p = threadIdx.x; p < N; p += 64) {
+        xs[(int64_t)r * N + p] = (int32_t)(s_keys[p] >> 16);
+        perm[(int64_t)r * N + p] = (uint16_t)(s_keys[p] & 0xffff);
+    }
+    if (r == 0 && threadIdx.x == 0) {
+        double h = 0.0;
+        H[0] = 0.0;
+        for (int i = 1; i <= N; ++i) {
+            h += 1.0 / (double)i;
+            H[i] = h;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void ksg_field_kernel(
+    const int32_t *__restrict__ code_q, const int32_t *__restrict__ flags_r,
+    const int32_t *__restrict__ flags_q, int N, int64_t V, const int64_t *__restrict__ refs,
+    int n_ref, const int32_t *__restrict__ xs_all, const uint16_t *__restrict__ perm_all,
+    const double *__restrict__ H, float *__restrict__ out, int32_t *__restrict__ counts) {
+    extern __shared__ int4 s_raw[];
+    const int P = pow2_ceil(N);
+    int2 *xy = reinterpret_cast<int2 *>(s_raw);
+    int *ys = reinterpret_cast<int *>(xy + N);
+    uint16_t *perm = reinterpret_cast<uint16_t *>(ys + P);
+    const int lane = threadIdx.x;
+    const double base = H[K - 1] + H[N - 1];
+
+    for (int r = 0; r < n_ref; ++r) {
+        const int32_t fr = flags_r[refs[r]];
+        __syncthreads();
+        for (int p = lane; p < N; p += 64) {
+            xy[p].x = xs_all[(int64_t)r * N + p];
+            perm[p] = perm_all[(int64_t)r * N + p];
+        }
+        __syncthreads();
+        for (int64_t q = blockIdx.x; q < V; q += gridDim.x) {
+            const int32_t *cq = code_q + q * N;
+            const int32_t fq = flags_q[q];
+            int32_t *cnt = counts ? counts + ((int64_t)r * V + q) * 2 * N : nullptr;
+            if ((fr | fq) & (NDF_FLAG_CONSTANT | NDF_FLAG_NONFINITE)) {
+                if (lane == 0)
+                    out[(int64_t)r * V + q] = ((fr | fq) & NDF_FLAG_NONFINITE) ? __builtin_nanf("")
+                                                                                : 0.0f;
+                if (cnt)
+                    for (int i = lane; i < 2 * N; i += 64) cnt[i] = 0;
+                continue;
+            }
+            for (int p = lane; p < P; p += 64) {
+                if (p < N) {
+                    const int y = cq[perm[p]];
+                    xy[p].y = y;
+                    ys[p] = y;
+                } else {
+                    ys[p] = 0x7fffffff;
+                }
+            }
+            __syncthreads();
+            wave_bitonic_sort(ys, P);
+            const double acc = wave_sum_f64(ksg_points<K>(xy, ys, N, H, perm, cnt));
+            if (lane == 0) out[(int64_t)r * V + q] = (float)(base - acc / (double)N);
+            __syncthreads();
+        }
+    }
+}
+
+// ----------------------------------------------------------- pairs mode ----
+template <int K>
+__global__ __launch_bounds__(64) void ksg_pairs_kernel(
+    const int32_t *__restrict__ code_a, const int32_t *__restrict__ code_b,
+    const int32_t *__restrict__ flags_a, const int32_t *__restrict__ flags_b, int N, int64_t V,
+    const int64_t *__restrict__ pairs, int64_t B, const double *__restrict__ H,
+    float *__restrict__ out, int32_t *__restrict__ counts) {
+    extern __shared__ int4 s_raw[];
+    const int P = pow2_ceil(N);
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(s_raw);
+    int2 *xy = reinterpret_cast<int2 *>(keys + P);
+    int *ys = reinterpret_cast<int *>(xy + N);
+    uint16_t *perm = reinterpret_cast<uint16_t *>(ys + P);
+    const int lane = threadIdx.x;
+    const double base = H[K - 1] + H[N - 1];
+
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        const int64_t va = pairs[2 * b], vb = pairs[2 * b + 1];
+        int32_t *cnt = counts ? counts + b * 2 * N : nullptr;
+        if (va < 0 || va >= V || vb < 0 || vb >= V) {  // out-of-range pair: NaN, no reads
+            if (lane == 0) out[b] = __builtin_nanf("");
+            if (cnt)
+                for (int i = lane; i < 2 * N; i += 64) cnt[i] = -1;
+            continue;
+        }
+        const int32_t f = flags_a[va] | flags_b[vb];
+        if (f & (NDF_FLAG_CONSTANT | NDF_FLAG_NONFINITE)) {
+            if (lane == 0) out[b] = (f & NDF_FLAG_NONFINITE) ? __builtin_nanf("") : 0.0f;
+            if (cnt)
+                for (int i = lane; i < 2 * N; i += 64) cnt[i] = 0;
+            continue;
+        }
+        const int32_t *ca = code_a + va * N;
+        const int32_t *cb = code_b + vb * N;
+        for (int m = lane; m < P; m += 64) {
+            keys[m] = m < N ? (((unsigned long long)(uint32_t)ca[m]) << 16) | (unsigned)m : ~0ull;
+            ys[m] = m < N ? cb[m] : 0x7fffffff;
+        }
+        __syncthreads();
+        wave_bitonic_sort(keys, P);
+        wave_bitonic_sort(ys, P);
+        for (int p = lane; p < N; p += 64) {
+            const int m = (int)(keys[p] & 0xffff);
+            perm[p] = (uint16_t)m;
+            xy[p] = make_int2((int)(keys[p] >> 16), cb[m]);
+        }
+        __syncthreads();
+        const double acc = wave_sum_f64(ksg_points<K>(xy, ys, N, H, perm, cnt));
+        if (lane == 0) out[b] = (float)(base - acc / (double)N);
+        __syncthreads();
+    }
+}
+
+__global__ void harmonic_kernel(int N, double *H) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double h = 0.0;
+        H[0] = 0.0;
+        for (int i = 1; i <= N; ++i) {
+            h += 1.0 / (double)i;
+            H[i] = h;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers ----
+static int p2(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+size_t ksg_field_ws_bytes(int N, int n_ref) {
+    return align_up((size_t)(N + 1) * sizeof(double), 256) +
+           align_up((size_t)n_ref * sizeof(int64_t), 256) +
+           align_up((size_t)n_ref * N * sizeof(int32_t), 256) +
+           align_up((size_t)n_ref * N * sizeof(uint16_t), 256);
+}
+
+static int field_grid(int64_t V) {
+    // persistent workgroups: enough single-wave groups to fill 256 CUs several
+    // times over, never more than there are queries
+    int64_t g = 256 * 24;
+    return (int)(V < g ? V : g);
+}
+
+template <int K>
+static void launch_field_k(dim3 g, size_t lds, hipStream_t st, const int32_t *cq, const int32_t *fr,
+                           const int32_t *fq, int N, int64_t V, const int64_t *refs, int n_ref,
+                           const int32_t *xs, const uint16_t *perm, const double *H, float *out,
+                           int32_t *counts) {
+    hipLaunchKernelGGL(ksg_field_kernel<K>, g, dim3(64), lds, st, cq, fr, fq, N, V, refs, n_ref, xs,
+                       perm, H, out, counts);
+}
+
+int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int64_t *ref_v,
+                     int n_ref, int k, float *out, int32_t *counts, void *ws, hipStream_t st) {
+    const int N = e->n_members;
+    const int64_t V = (int64_t)e->nx * e->ny * e->nz;
+    char *w = (char *)ws;
+    double *H = (double *)w;
+    w += align_up((size_t)(N + 1) * sizeof(double), 256);
+    int64_t *refs = (int64_t *)w;
+    w += align_up((size_t)n_ref * sizeof(int64_t), 256);
+    int32_t *xs = (int32_t *)w;
+    w += align_up((size_t)n_ref * N * sizeof(int32_t), 256);
+    uint16_t *perm = (uint16_t *)w;
+    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return NDF_E_HIP;
+    const int P = p2(N);
+    const int32_t *cr = e->code + (int64_t)var_ref * V * N;
+    const int32_t *cq = e->code + (int64_t)var_qry * V * N;
+    hipLaunchKernelGGL(ksg_sort_ref_kernel, dim3(n_ref), dim3(64), (size_t)P * 8, st, cr, N, refs,
+                       xs, perm, H);
+    const size_t lds = (size_t)N * 8 + (size_t)P * 4 + (size_t)N * 2;
+    const dim3 g((unsigned)field_grid(V));
+    const int32_t *fr = e->flags + (int64_t)var_ref * V;
+    const int32_t *fq = e->flags + (int64_t)var_qry * V;
+    switch (k) {
+#define NDF_KSG_CASE(KK) \
+    case KK: launch_field_k<KK>(g, lds, st, cq, fr, fq, N, V, refs, n_ref, xs, perm, H, out, counts); break;
+        NDF_KSG_CASE(1) NDF_KSG_CASE(2) NDF_KSG_CASE(3) NDF_KSG_CASE(4)
+        NDF_KSG_CASE(5) NDF_KSG_CASE(6) NDF_KSG_CASE(7) NDF_KSG_CASE(8)
+#undef NDF_KSG_CASE
+        default: return NDF_E_UNSUPPORTED;
+    }
+    return status_of_launch();
+}
+
+size_t ksg_pairs_ws_bytes(int N) { return align_up((size_t)(N + 1) * sizeof(double), 256); }
+
+int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t *pairs, int64_t B,
+                     int k, float *out, int32_t *counts, double *H, hipStream_t st) {
+    const int N = e->n_members;
+    const int64_t V = (int64_t)e->nx * e->ny * e->nz;
+    const int P = p2(N);
+    hipLaunchKernelGGL(harmonic_kernel, dim3(1), dim3(64), 0, st, N, H);
+    const size_t lds = (size_t)P * 8 + (size_t)N * 8 + (size_t)P * 4 + (size_t)N * 2;
+    const int64_t gmax = 256 * 24;
+    const dim3 g((unsigned)(B < gmax ? B : gmax));
+    const int32_t *ca = e->code + (int64_t)var_a * V * N;
+    const int32_t *cb = e->code + (int64_t)var_b * V * N;
+    const int32_t *fa = e->flags + (int64_t)var_a * V;
+    const int32_t *fb = e->flags + (int64_t)var_b * V;
+    switch (k) {
+#define NDF_KSG_CASE(KK)                                                                       \
+    case KK:                                                                                   \
+        hipLaunchKernelGGL(ksg_pairs_kernel<KK>, g, dim3(64), lds, st, ca, cb, fa, fb, N, V, pairs, \
+                           B, H, out, counts);                                                    \
+        break;
+        NDF_KSG_CASE(1) NDF_KSG_CASE(2) NDF_KSG_CASE(3) NDF_KSG_CASE(4)
+        NDF_KSG_CASE(5) NDF_KSG_CASE(6) NDF_KSG_CASE(7) NDF_KSG_CASE(8)
+#undef NDF_KSG_CASE
+        default: return NDF_E_UNSUPPORTED;
+    }
+    return status_of_launch();
+}
+
+}  // namespace ndf

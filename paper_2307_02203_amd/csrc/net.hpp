@@ -1,0 +1,146 @@
+// Host-side description of the learned-field network (Sec. 4.1-4.2): config
+// checks, the FP32 parameter layout and the workspace plans of the network calls.
+#pragma once
+
+#include "common.hpp"
+
+namespace ndf {
+
+constexpr int kH = 128;      // hidden width
+constexpr int kF = 8;        // features per grid level
+constexpr int kL = 4;        // grid levels
+constexpr int kK0 = kL * kF; // encoder input width
+constexpr int64_t kAlign = 64;
+
+struct NetOffsets {
+    int64_t grid[2][kL];
+    int64_t W1[2], b1[2], W2[2], b2[2], W3[2], b3[2];
+    int64_t W4, b4, W5, b5, w6, b6;
+    int64_t cells[kL];
+    int64_t total;  // floats
+};
+
+inline int check_net_config(const ndf_net_config *c) {
+    if (!c) return NDF_E_ARG;
+    if (c->nx < 2 || c->ny < 2 || c->nz < 2) return NDF_E_ARG;
+    if (c->n_levels != kL || c->feats != kF || c->width != kH) return NDF_E_UNSUPPORTED;
+    if (c->n_enc != 1 && c->n_enc != 2) return NDF_E_ARG;
+    for (int l = 0; l < kL; ++l)
+        for (int a = 0; a < 3; ++a)
+            if (c->res[l][a] < 2 || c->res[l][a] > (1 << 16)) return NDF_E_ARG;
+    return NDF_OK;
+}
+
+inline NetOffsets net_offsets(const ndf_net_config *c) {
+    NetOffsets o{};
+    int64_t pos = 0;
+    auto take = [&](int64_t n) {
+        int64_t at = pos;
+        pos += (n + kAlign - 1) / kAlign * kAlign;
+        return at;
+    };
+    for (int l = 0; l < kL; ++l) o.cells[l] = (int64_t)c->res[l][0] * c->res[l][1] * c->res[l][2];
+    for (int e = 0; e < c->n_enc; ++e) {
+        for (int l = 0; l < kL; ++l) o.grid[e][l] = take(o.cells[l] * kF);
+        o.W1[e] = take(kH * kK0);
+        o.b1[e] = take(kH);
+        o.W2[e] = take(kH * kH);
+        o.b2[e] = take(kH);
+        o.W3[e] = take(kH * kH);
+        o.b3[e] = take(kH);
+    }
+    if (c->n_enc == 1) {
+        for (int l = 0; l < kL; ++l) o.grid[1][l] = o.grid[0][l];
+        o.W1[1] = o.W1[0]; o.b1[1] = o.b1[0];
+        o.W2[1] = o.W2[0]; o.b2[1] = o.b2[0];
+        o.W3[1] = o.W3[0]; o.b3[1] = o.b3[0];
+    }
+    o.W4 = take(kH * kH);
+    o.b4 = take(kH);
+    o.W5 = take(kH * kH);
+    o.b5 = take(kH);
+    o.w6 = take(kH);
+    o.b6 = take(1);
+    o.total = pos;
+    return o;
+}
+
+// Level geometry passed by value to kernels.
+struct GridGeom {
+    int nx, ny, nz;
+    int R[kL][3];
+};
+
+inline GridGeom grid_geom(const ndf_net_config *c) {
+    GridGeom g{};
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    for (int l = 0; l < kL; ++l)
+        for (int a = 0; a < 3; ++a) g.R[l][a] = c->res[l][a];
+    return g;
+}
+
+// Level sizes of level l (l may differ between lanes: selects instead of an
+// indexed load keep the geometry in scalar registers).
+__device__ __forceinline__ void level_dims(const GridGeom &g, int l, int R[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        R[a] = l == 0 ? g.R[0][a] : (l == 1 ? g.R[1][a] : (l == 2 ? g.R[2][a] : g.R[3][a]));
+}
+
+// Trilinear corners of grid vertex v on a level of sizes R: cell indices and
+// weights.  c = u (R - 1) with u = i / (n - 1), exact whenever c is an integer;
+// base = clamp(floor(c), 0, R - 2), f = c - base; corner (dx,dy,dz) = bit 0,1,2.
+__device__ __forceinline__ void corners_R(const GridGeom &g, const int R[3], int64_t v,
+                                          int64_t idx[8], float w[8]) {
+    const int64_t i = v % g.nx;
+    const int64_t j = (v / g.nx) % g.ny;
+    const int64_t k = v / ((int64_t)g.nx * g.ny);
+    const int64_t ii[3] = {i, j, k};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    int b[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float c = (float)((double)(ii[a] * (int64_t)(R[a] - 1)) / (double)(nn[a] - 1));
+        int bb = (int)floorf(c);
+        bb = bb < 0 ? 0 : (bb > R[a] - 2 ? R[a] - 2 : bb);
+        b[a] = bb;
+        f[a] = c - (float)bb;
+    }
+    const int64_t Rx = R[0], Ry = R[1];
+#pragma unroll
+    for (int cn = 0; cn < 8; ++cn) {
+        const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
+        idx[cn] = (b[0] + dx) + Rx * ((b[1] + dy) + Ry * (int64_t)(b[2] + dz));
+        w[cn] = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) * (dz ? f[2] : 1.f - f[2]);
+    }
+}
+
+__device__ __forceinline__ void corners(const GridGeom &g, int l, int64_t v, int64_t idx[8],
+                                        float w[8]) {
+    int R[3];
+    level_dims(g, l, R);
+    corners_R(g, R, v, idx, w);
+}
+
+size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B);
+size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec);
+size_t net_qparam_bytes(const ndf_net_config *c, int prec);
+
+int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t seed,
+                    hipStream_t st);
+int launch_net_grad(const ndf_net_config *c, const float *params, const int64_t *pairs,
+                    const float *targets, int64_t B, float *grad, float *loss, void *ws,
+                    hipStream_t st);
+int launch_net_forward(const ndf_net_config *c, const float *params, const int64_t *pairs,
+                       int64_t B, float *y, void *ws, hipStream_t st);
+int launch_adam(const ndf_net_config *c, float *params, float *opt, const float *grad,
+                int64_t step, float lr, hipStream_t st);
+int launch_net_quantize(const ndf_net_config *c, const float *params, int prec, void *q,
+                        hipStream_t st);
+int launch_infer_field(const ndf_net_config *c, const void *q, int prec, const int64_t *ref_v,
+                       int n_ref, float *out, void *ws, hipStream_t st);
+
+}  // namespace ndf

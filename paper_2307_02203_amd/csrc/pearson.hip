@@ -1,0 +1,274 @@
+// Direct Pearson dependence fields (Sec. 3.1, Eq. 1).
+//
+// With per-vertex population mean mu_v and 1/sigma_v from ndf_prepare,
+//   r(ref, v) = (1/N) sum_m z_ref[m] * (x[m][v] - mu_v) * inv_std_v,
+//   z_ref[m]  = (x[m][ref] - mu_ref) * inv_std_ref.
+// The ensemble is member-major, so a member row is a contiguous stream over
+// vertices and every kernel below reads it with coalesced row segments.
+//
+// * pearson_gemv_kernel: one reference, FP32 FMA, four vertices per thread
+//   (16-byte loads); bound by the 4 B/sample HBM stream.
+// * pearson_gemm_kernel: up to 64 references at once as a contraction over
+//   members on MFMA 32x32x16 bf16.  Standardised members are split into
+//   z = hi + lo (both bf16) in registers and the three products hi*hi, hi*lo,
+//   lo*hi are accumulated in FP32 (the lo*lo term is below 2^-16 relative).
+//   The reference operand is prepared once per call in MFMA operand order.
+// * pearson_pairs_kernel: one wave per vertex pair (training targets).
+#include "common.hpp"
+
+namespace ndf {
+
+// z_ref rows in FP32, zero-padded to kpad members: ws layout float[n_ref][kpad].
+__global__ void pearson_refcols_kernel(const float *__restrict__ x, const double *__restrict__ mean,
+                                       const double *__restrict__ inv_std, int N, int64_t V,
+                                       const int64_t *__restrict__ refs, int kpad,
+                                       float *__restrict__ zr) {
+    const int r = blockIdx.x;
+    const int64_t v = refs[r];
+    const double mu = mean[v], is = inv_std[v];
+    for (int m = threadIdx.x; m < kpad; m += blockDim.x) {
+        float z = 0.f;
+        if (m < N) z = (float)(((double)x[(int64_t)m * V + v] - mu) * is);
+        zr[(int64_t)r * kpad + m] = z;
+    }
+}
+
+// ---------------------------------------------------------------- GEMV ----
+template <bool VEC>
+__global__ __launch_bounds__(256) void pearson_gemv_kernel(
+    const float *__restrict__ x, const double *__restrict__ mean,
+    const double *__restrict__ inv_std, int N, int64_t V, const float *__restrict__ zr,
+    float *__restrict__ out) {
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (v >= V) return;
+    float mu[4], sc[4], acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const float invN = 1.0f / (float)N;
+    for (int e = 0; e < 4; ++e) {
+        const int64_t ve = v + e < V ? v + e : V - 1;
+        mu[e] = (float)mean[ve];
+        sc[e] = (float)(inv_std[ve] / (double)N);
+    }
+    (void)invN;
+    if (VEC) {
+        const f32x4 *xp = reinterpret_cast<const f32x4 *>(x + v);
+        const int64_t row = V / 4;
+#pragma unroll 8
+        for (int m = 0; m < N; ++m) {
+            const f32x4 a = __builtin_nontemporal_load(xp + (int64_t)m * row);
+            const float z = zr[m];
+            acc[0] = fmaf(z, a[0] - mu[0], acc[0]);
+            acc[1] = fmaf(z, a[1] - mu[1], acc[1]);
+            acc[2] = fmaf(z, a[2] - mu[2], acc[2]);
+            acc[3] = fmaf(z, a[3] - mu[3], acc[3]);
+        }
+    } else {
+        for (int m = 0; m < N; ++m) {
+            const float z = zr[m];
+            for (int e = 0; e < 4; ++e)
+                if (v + e < V) acc[e] = fmaf(z, x[(int64_t)m * V + v + e] - mu[e], acc[e]);
+        }
+    }
+    for (int e = 0; e < 4; ++e)
+        if (v + e < V) out[v + e] = acc[e] * sc[e];
+}
+
+// ---------------------------------------------------------------- GEMM ----
+// A operand (references) in MFMA order, ws layout:
+//   bf16 frag[ks][ib][part][lane][8], part 0 = hi, 1 = lo,
+//   lane l holds ref ib*32 + l%32, members ks*16 + 8*(l/32) + e.
+__global__ void pearson_afrag_kernel(const float *__restrict__ zr, int kpad, int n_ib,
+                                     int n_ref, uint16_t *__restrict__ frag) {
+    const int ks = blockIdx.x;
+    const int ib = blockIdx.y;
+    const int lane = threadIdx.x;  // 64
+    const int r = ib * 32 + (lane & 31);
+    for (int e = 0; e < 8; ++e) {
+        const int m = ks * 16 + 8 * (lane >> 5) + e;
+        const float z = (r < n_ref) ? zr[(int64_t)r * kpad + m] : 0.f;
+        const uint16_t hi = f2bf_bits(z);
+        const uint16_t lo = f2bf_bits(z - bf_bits2f(hi));
+        const int64_t base = (((int64_t)ks * n_ib + ib) * 2) * 64 * 8;
+        frag[base + lane * 8 + e] = hi;
+        frag[base + 64 * 8 + lane * 8 + e] = lo;
+    }
+}
+
+constexpr int kGemmJB = 4;  // 32-vertex blocks per wave -> 128 vertices per wave
+
+template <int NIB>
+__global__ __launch_bounds__(256) void pearson_gemm_kernel(
+    const float *__restrict__ x, const double *__restrict__ mean,
+    const double *__restrict__ inv_std, int N, int64_t V, const bf16x8 *__restrict__ afrag,
+    int n_ib_total, int n_ref, float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const int jl = lane & 31;
+    const int ib0 = blockIdx.y * NIB;  // first 32-ref block of this group
+    const int64_t vbase = ((int64_t)blockIdx.x * 4 + wave) * (32 * kGemmJB);
+
+    float mu[kGemmJB], is[kGemmJB];
+    int64_t vj[kGemmJB];
+    bool ok[kGemmJB];
+#pragma unroll
+    for (int jb = 0; jb < kGemmJB; ++jb) {
+        vj[jb] = vbase + jb * 32 + jl;
+        ok[jb] = vj[jb] < V;
+        const int64_t vv = ok[jb] ? vj[jb] : 0;
+        mu[jb] = (float)mean[vv];
+        is[jb] = (float)inv_std[vv];
+    }
+
+    f32x16 acc[NIB][kGemmJB];
+#pragma unroll
+    for (int i = 0; i < NIB; ++i)
+#pragma unroll
+        for (int jb = 0; jb < kGemmJB; ++jb)
+            for (int r = 0; r < 16; ++r) acc[i][jb][r] = 0.f;
+
+    const int ksteps = (N + 15) / 16;
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int mb = ks * 16 + 8 * h;
+        bf16x8 bhi[kGemmJB], blo[kGemmJB];
+#pragma unroll
+        for (int jb = 0; jb < kGemmJB; ++jb) {
+            float zv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = mb + e;
+                float a = 0.f;
+                if (ok[jb] && m < N) a = __builtin_nontemporal_load(x + (int64_t)m * V + vj[jb]);
+                zv[e] = (ok[jb] && m < N) ? (a - mu[jb]) * is[jb] : 0.f;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint16_t hb = f2bf_bits(zv[e]);
+                const uint16_t lb = f2bf_bits(zv[e] - bf_bits2f(hb));
+                bhi[jb][e] = __builtin_bit_cast(__bf16, hb);
+                blo[jb][e] = __builtin_bit_cast(__bf16, lb);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NIB; ++i) {
+            const int64_t fb = (((int64_t)ks * n_ib_total + ib0 + i) * 2) * 64;
+            const bf16x8 ahi = afrag[fb + lane];
+            const bf16x8 alo = afrag[fb + 64 + lane];
+#pragma unroll
+            for (int jb = 0; jb < kGemmJB; ++jb) {
+                acc[i][jb] = mfma32(ahi, bhi[jb], acc[i][jb]);
+                acc[i][jb] = mfma32(ahi, blo[jb], acc[i][jb]);
+                acc[i][jb] = mfma32(alo, bhi[jb], acc[i][jb]);
+            }
+        }
+    }
+    const float invN = 1.0f / (float)N;
+#pragma unroll
+    for (int i = 0; i < NIB; ++i)
+#pragma unroll
+        for (int jb = 0; jb < kGemmJB; ++jb) {
+            if (!ok[jb]) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ref = (ib0 + i) * 32 + d_row(r, lane);
+                if (ref < n_ref) out[(int64_t)ref * V + vj[jb]] = acc[i][jb][r] * invN;
+            }
+        }
+}
+
+// --------------------------------------------------------------- pairs ----
+__global__ __launch_bounds__(256) void pearson_pairs_kernel(
+    const float *__restrict__ xa, const float *__restrict__ xb, const double *__restrict__ mean_a,
+    const double *__restrict__ inv_a, const double *__restrict__ mean_b,
+    const double *__restrict__ inv_b, int N, int64_t V, const int64_t *__restrict__ pairs,
+    int64_t B, float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B) return;
+    const int64_t va = pairs[2 * b], vb = pairs[2 * b + 1];
+    if (va < 0 || va >= V || vb < 0 || vb >= V) {
+        if (lane == 0) out[b] = __builtin_nanf("");
+        return;
+    }
+    const float ma = (float)mean_a[va], mb = (float)mean_b[vb];
+    float acc = 0.f;
+    for (int m = lane; m < N; m += 64)
+        acc = fmaf(xa[(int64_t)m * V + va] - ma, xb[(int64_t)m * V + vb] - mb, acc);
+    double s = wave_sum_f64((double)acc);
+    if (lane == 0) out[b] = (float)(s * inv_a[va] * inv_b[vb] / (double)N);
+}
+
+// ------------------------------------------------------------ launchers ----
+size_t pearson_ws_bytes(int N, int n_ref, int prec) {
+    const int kpad = (int)align_up((size_t)N, 16);
+    size_t zr = align_up((size_t)n_ref * kpad * sizeof(float), 256);
+    size_t refs = align_up((size_t)n_ref * sizeof(int64_t), 256);
+    if (prec == NDF_PREC_SPLIT_BF16) {
+        const int n_ib = (int)ceil_div(n_ref, 64) * 2;
+        size_t frag = (size_t)(kpad / 16) * n_ib * 2 * 64 * 8 * sizeof(uint16_t);
+        return zr + refs + align_up(frag, 256);
+    }
+    return zr + refs;
+}
+
+int launch_pearson_field(const ndf_ensemble *e, int var_ref, int var_qry, const int64_t *ref_v,
+                         int n_ref, float *out, int prec, void *ws, hipStream_t st) {
+    const int N = e->n_members;
+    const int64_t V = (int64_t)e->nx * e->ny * e->nz;
+    const int kpad = (int)align_up((size_t)N, 16);
+    char *w = (char *)ws;
+    float *zr = (float *)w;
+    w += align_up((size_t)n_ref * kpad * sizeof(float), 256);
+    int64_t *refs = (int64_t *)w;
+    w += align_up((size_t)n_ref * sizeof(int64_t), 256);
+    hipError_t err = hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t),
+                                    hipMemcpyHostToDevice, st);
+    if (err != hipSuccess) return NDF_E_HIP;
+    const float *xr = e->x + (int64_t)var_ref * N * V;
+    const float *xq = e->x + (int64_t)var_qry * N * V;
+    hipLaunchKernelGGL(pearson_refcols_kernel, dim3(n_ref), dim3(256), 0, st, xr,
+                       e->mean + (int64_t)var_ref * V, e->inv_std + (int64_t)var_ref * V, N, V,
+                       refs, kpad, zr);
+    const double *mq = e->mean + (int64_t)var_qry * V;
+    const double *iq = e->inv_std + (int64_t)var_qry * V;
+    if (prec == NDF_PREC_FP32) {
+        const unsigned nb = (unsigned)ceil_div(ceil_div(V, 4), 256);
+        const bool vec = (V % 4) == 0;
+        for (int r = 0; r < n_ref; ++r) {
+            if (vec)
+                hipLaunchKernelGGL(pearson_gemv_kernel<true>, dim3(nb), dim3(256), 0, st, xq, mq,
+                                   iq, N, V, zr + (int64_t)r * kpad, out + (int64_t)r * V);
+            else
+                hipLaunchKernelGGL(pearson_gemv_kernel<false>, dim3(nb), dim3(256), 0, st, xq, mq,
+                                   iq, N, V, zr + (int64_t)r * kpad, out + (int64_t)r * V);
+        }
+        return status_of_launch();
+    }
+    // split-bf16 MFMA contraction, references in groups of 64 (or one 32-block)
+    const int n_ib = (int)ceil_div(n_ref, 64) * 2;
+    uint16_t *frag = (uint16_t *)w;
+    hipLaunchKernelGGL(pearson_afrag_kernel, dim3(kpad / 16, n_ib), dim3(64), 0, st, zr, kpad,
+                       n_ib, n_ref, frag);
+    const unsigned nbx = (unsigned)ceil_div(V, 4 * 32 * kGemmJB);
+    if (n_ref <= 32)
+        hipLaunchKernelGGL(pearson_gemm_kernel<1>, dim3(nbx, 1), dim3(256), 0, st, xq, mq, iq, N,
+                           V, (const bf16x8 *)frag, n_ib, n_ref, out);
+    else
+        hipLaunchKernelGGL(pearson_gemm_kernel<2>, dim3(nbx, (unsigned)ceil_div(n_ref, 64)),
+                           dim3(256), 0, st, xq, mq, iq, N, V, (const bf16x8 *)frag, n_ib, n_ref,
+                           out);
+    return status_of_launch();
+}
+
+int launch_pearson_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t *pairs,
+                         int64_t B, float *out, hipStream_t st) {
+    const int N = e->n_members;
+    const int64_t V = (int64_t)e->nx * e->ny * e->nz;
+    hipLaunchKernelGGL(pearson_pairs_kernel, dim3((unsigned)ceil_div(B, 4)), dim3(256), 0, st,
+                       e->x + (int64_t)var_a * N * V, e->x + (int64_t)var_b * N * V,
+                       e->mean + (int64_t)var_a * V, e->inv_std + (int64_t)var_a * V,
+                       e->mean + (int64_t)var_b * V, e->inv_std + (int64_t)var_b * V, N, V, pairs,
+                       B, out);
+    return status_of_launch();
+}
+
+}  // namespace ndf

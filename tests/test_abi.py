@@ -1,0 +1,122 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid arguments on the host before enqueuing
+anything (the pointers below are never dereferenced)."""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_2307_02203_amd import ndf
+
+ROOT = Path(__file__).resolve().parents[1]
+FAKE = 0x1000  # non-null, never dereferenced: every call below fails validation first
+
+
+def _declared():
+    txt = (ROOT / "include" / "ndf.h").read_text()
+    return sorted(set(re.findall(r"\b(ndf_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = ndf.lib()
+    declared = _declared()
+    assert len(declared) >= 16
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(ndf.EXPORTED) == declared
+
+
+def test_status_strings():
+    L = ndf.lib()
+    assert L.ndf_status_string(0) == b"ok"
+    assert b"workspace" in L.ndf_status_string(-2)
+
+
+def _ens(N=64, nx=16, ny=16, nz=8, n_vars=1, stats=True):
+    p = FAKE if stats else 0
+    return ndf.ndf_ensemble(N, nx, ny, nz, n_vars, FAKE, p, p, p, p)
+
+
+def test_prepare_rejects_bad_shapes():
+    L = ndf.lib()
+    for e in (_ens(N=1), _ens(nx=1), _ens(n_vars=0), _ens(stats=False), _ens(N=5000)):
+        assert L.ndf_prepare(ctypes.byref(e), None) == ndf.NDF_E_ARG
+    assert L.ndf_prepare(None, None) == ndf.NDF_E_ARG
+
+
+def test_field_calls_validate_before_launch():
+    L = ndf.lib()
+    e = _ens()
+    refs = np.array([1160], dtype=np.int64)
+    rp = refs.ctypes.data_as(ctypes.c_void_p)
+    bad = np.array([2048], dtype=np.int64)
+    bp = bad.ctypes.data_as(ctypes.c_void_p)
+    ws_need = L.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, ctypes.byref(e), None, 1, 0)
+    assert ws_need > 0
+    E = ctypes.byref(e)
+    # reference out of range, bad variable, missing output, small workspace, bad precision
+    assert L.ndf_pearson_field(E, 0, 0, bp, 1, FAKE, 0, FAKE, ws_need, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_field(E, 1, 0, rp, 1, FAKE, 0, FAKE, ws_need, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_field(E, 0, 0, rp, 1, None, 0, FAKE, ws_need, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_field(E, 0, 0, rp, 0, FAKE, 0, FAKE, ws_need, None) == ndf.NDF_E_ARG
+    assert (L.ndf_pearson_field(E, 0, 0, rp, 1, FAKE, 0, FAKE, ws_need - 1, None)
+            == ndf.NDF_E_WORKSPACE)
+    assert (L.ndf_pearson_field(E, 0, 0, rp, 1, FAKE, 0, None, ws_need, None)
+            == ndf.NDF_E_WORKSPACE)
+    assert L.ndf_pearson_field(E, 0, 0, rp, 1, FAKE, 7, FAKE, ws_need, None) == ndf.NDF_E_UNSUPPORTED
+    kws = L.ndf_workspace_bytes(ndf.NDF_OP_KSG_FIELD, E, None, 1, 0)
+    assert L.ndf_ksg_mi_field(E, 0, 0, rp, 1, 0, FAKE, None, FAKE, kws, None) == ndf.NDF_E_ARG
+    assert L.ndf_ksg_mi_field(E, 0, 0, rp, 1, 64, FAKE, None, FAKE, kws, None) == ndf.NDF_E_ARG
+    assert L.ndf_ksg_mi_field(E, 0, 0, rp, 1, 9, FAKE, None, FAKE, kws, None) == ndf.NDF_E_UNSUPPORTED
+    assert (L.ndf_ksg_mi_field(E, 0, 0, rp, 1, 4, FAKE, None, FAKE, kws - 8, None)
+            == ndf.NDF_E_WORKSPACE)
+    big = _ens(N=3000)
+    kb = L.ndf_workspace_bytes(ndf.NDF_OP_KSG_FIELD, ctypes.byref(big), None, 1, 0)
+    assert (L.ndf_ksg_mi_field(ctypes.byref(big), 0, 0, rp, 1, 4, FAKE, None, FAKE, kb, None)
+            == ndf.NDF_E_UNSUPPORTED)
+    pws = L.ndf_workspace_bytes(ndf.NDF_OP_KSG_PAIRS, E, None, 1, 0)
+    assert L.ndf_ksg_mi_pairs(E, 0, 0, FAKE, 0, 4, FAKE, None, FAKE, pws, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_pairs(E, 0, 0, None, 5, FAKE, None) == ndf.NDF_E_ARG
+
+
+def test_workspace_sizes_grow_with_references():
+    L = ndf.lib()
+    e = ctypes.byref(_ens(N=1000, nx=250, ny=352, nz=20))
+    a = L.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, e, None, 1, ndf.NDF_PREC_SPLIT_BF16)
+    b = L.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, e, None, 64, ndf.NDF_PREC_SPLIT_BF16)
+    assert 0 < a < b
+    assert L.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, e, None, 1, 9) == 0
+    assert L.ndf_workspace_bytes(99, e, None, 1, 0) == 0
+
+
+def test_net_config_validation_and_param_bytes():
+    import gen
+    L = ndf.lib()
+    lay = gen.NetLayout.for_grid(250, 352, 20)
+    cfg = ndf.net_config(250, 352, 20, lay.res)
+    assert ndf.ndf_net_param_bytes(cfg) == 4 * lay.n_floats
+    assert ndf.ndf_net_optstate_bytes(cfg) == 8 * lay.n_floats
+    lay2 = gen.NetLayout.for_grid(16, 16, 8, n_enc=2)
+    cfg2 = ndf.net_config(16, 16, 8, lay2.res, n_enc=2)
+    assert ndf.ndf_net_param_bytes(cfg2) == 4 * lay2.n_floats
+    bad = ndf.net_config(250, 352, 20, lay.res, width=64)
+    assert ndf.ndf_net_param_bytes(bad) == 0
+    assert L.ndf_net_init(ctypes.byref(bad), FAKE, None, 1, None) == ndf.NDF_E_UNSUPPORTED
+    bad3 = ndf.net_config(250, 352, 20, lay.res, n_enc=3)
+    assert L.ndf_net_init(ctypes.byref(bad3), FAKE, None, 1, None) == ndf.NDF_E_ARG
+    need = ndf.train_ws_bytes(cfg, 1024)
+    assert need > 0
+    C = ctypes.byref(cfg)
+    assert (L.ndf_net_grad(C, FAKE, FAKE, FAKE, 1024, FAKE, FAKE, FAKE, need - 1, None)
+            == ndf.NDF_E_WORKSPACE)
+    assert L.ndf_net_grad(C, FAKE, FAKE, FAKE, 0, FAKE, FAKE, FAKE, need, None) == ndf.NDF_E_ARG
+    assert (L.ndf_train_step(C, FAKE, FAKE, 0, FAKE, FAKE, 1024, ctypes.c_float(1e-3), FAKE, FAKE,
+                             need * 2, None) == ndf.NDF_E_ARG)
+    refs = np.array([1_760_000], dtype=np.int64)
+    assert (L.ndf_infer_field(C, FAKE, ndf.NDF_PREC_BF16, refs.ctypes.data_as(ctypes.c_void_p), 1,
+                              FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG)
+    assert (L.ndf_infer_field(C, FAKE, ndf.NDF_PREC_SPLIT_BF16,
+                              refs.ctypes.data_as(ctypes.c_void_p), 1, FAKE, FAKE, 1 << 30, None)
+            == ndf.NDF_E_UNSUPPORTED)

@@ -1,0 +1,256 @@
+"""GPU parity of the direct estimators against the FP64 oracle, through the C ABI.
+
+Tolerances: Pearson |dr| <= 1e-5 (FP32 stream and split-BF16 MFMA), KSG neighbour
+counts bit-exact and MI |dI| <= 1e-4 nats; codes bit-exact; moments to 1e-12.
+Sizes: the tiny ensemble (64 members, 2048 vertices) in full, a mid ensemble
+with ragged tails everywhere (200 members, 37x29x11 = 11803 vertices) in full,
+and the paper-shaped ensemble (1000 members, 1.76M vertices) on sampled vertices
+at the launch configuration the benchmark times.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+from oracle import direct
+from paper_2307_02203_amd import ndf
+
+pytestmark = pytest.mark.gpu
+
+PEARSON_TOL = 1e-5
+MI_TOL = 1e-4
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _ens(cfg, device="cuda"):
+    x = gen.make_ensemble(cfg, device=device)
+    e = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz)
+    ndf.ndf_prepare(e)
+    torch.cuda.synchronize()
+    return e
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return _ens(gen.CONFIGS["tiny"])
+
+
+@pytest.fixture(scope="module")
+def mid():
+    return _ens(gen.CONFIGS["mid"])
+
+
+def _cols(e, var, idx):
+    """Member-major host block x[var][:, idx] (float32) for the oracle."""
+    idx = torch.as_tensor(np.asarray(idx), dtype=torch.int64, device=e.device)
+    return e.x[var][:, idx].cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+def test_prepare_stats_and_codes(name, request):
+    e = request.getfixturevalue(name)
+    x = e.x[0].cpu().numpy()
+    mean = e.mean[0].cpu().numpy()
+    istd = e.inv_std[0].cpu().numpy()
+    code = e.code[0].cpu().numpy()
+    flags = e.flags[0].cpu().numpy()
+    V = e.n_vertices
+    assert np.all(flags == 0)
+    for v in range(V):
+        m, s = direct.moments(x[:, v])
+        assert abs(mean[v] - m) <= 1e-12 * max(1.0, abs(m))
+        assert abs(istd[v] * s - 1.0) <= 1e-12
+        c, flat = direct.ksg_codes(x[:, v])
+        assert not flat
+        assert np.array_equal(code[v], c), v
+
+
+def test_prepare_flags_constant_and_nonfinite():
+    cfg = gen.CONFIGS["tiny"]
+    x = gen.make_ensemble(cfg, device="cuda")
+    x[0, :, 7] = 2.5                     # constant column
+    x[0, 3, 9] = float("nan")            # non-finite sample
+    e = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz)
+    ndf.ndf_prepare(e)
+    f = e.flags[0].cpu().numpy()
+    assert f[7] == ndf.NDF_FLAG_CONSTANT and f[9] & ndf.NDF_FLAG_NONFINITE
+    assert np.sum(f != 0) == 2
+    assert e.inv_std[0, 7].item() == 0.0
+    assert torch.all(e.code[0, 7] == 0)
+    r = ndf.pearson_field(e, [1160])[0].cpu().numpy()
+    assert r[7] == 0.0
+    r7 = ndf.pearson_field(e, [7])[0].cpu().numpy()
+    assert np.all(np.delete(r7, 9) == 0.0)           # the NaN column stays NaN
+    assert math.isnan(r[9]) and math.isnan(r7[9])
+    mi = ndf.ksg_field(e, [1160])[0].cpu().numpy()
+    assert mi[7] == 0.0 and math.isnan(mi[9])
+
+
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+@pytest.mark.parametrize("prec", [ndf.NDF_PREC_FP32, ndf.NDF_PREC_SPLIT_BF16])
+def test_pearson_field_full(name, prec, request):
+    e = request.getfixturevalue(name)
+    cfg = gen.CONFIGS[name]
+    refs = [cfg.ref_v, 0, e.n_vertices - 1]
+    got = ndf.pearson_field(e, refs, prec=prec).cpu().numpy()
+    x = e.x[0].cpu().numpy()
+    for i, r in enumerate(refs):
+        want = direct.pearson_field(x[:, r], x)
+        err = np.max(np.abs(got[i] - want))
+        _log(f"pearson {name} prec={prec} ref={r} max|err|={err:.2e}")
+        assert err <= PEARSON_TOL
+    assert abs(got[0][cfg.ref_v] - 1.0) <= PEARSON_TOL
+
+
+@pytest.mark.parametrize("n_ref", [1, 5, 32, 33, 64, 70])
+def test_pearson_batch_split_bf16(mid, n_ref):
+    refs = gen.random_vertices(mid.n_vertices, n_ref, seed=40 + n_ref)
+    got = ndf.pearson_field(mid, refs, prec=ndf.NDF_PREC_SPLIT_BF16).cpu().numpy()
+    x = mid.x[0].cpu().numpy()
+    for i, r in enumerate(refs):
+        want = direct.pearson_field(x[:, r], x)
+        assert np.max(np.abs(got[i] - want)) <= PEARSON_TOL, (n_ref, i)
+
+
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+@pytest.mark.parametrize("k", [1, 3, 4, 8])
+def test_ksg_field_full_counts_exact(name, k, request):
+    e = request.getfixturevalue(name)
+    cfg = gen.CONFIGS[name]
+    ref = cfg.ref_v
+    mi, cnt = ndf.ksg_field(e, [ref], k=k, counts=True)
+    mi = mi[0].cpu().numpy()
+    cnt = cnt[0].cpu().numpy()
+    x = e.x[0].cpu().numpy()
+    want, wnx, wny = direct.ksg_field(x[:, ref], x, k, counts=True)
+    assert np.array_equal(cnt[:, 0, :], wnx)
+    assert np.array_equal(cnt[:, 1, :], wny)
+    err = np.max(np.abs(mi - want))
+    _log(f"ksg {name} k={k} max|dI|={err:.2e}")
+    assert err <= MI_TOL
+
+
+def test_ksg_pairs_match_oracle_and_field(mid):
+    cfg = gen.CONFIGS["mid"]
+    rng = np.random.default_rng(3)
+    pairs = np.stack([rng.integers(0, mid.n_vertices, 300),
+                      rng.integers(0, mid.n_vertices, 300)], axis=1)
+    pairs[:20, 0] = cfg.ref_v
+    mi, cnt = ndf.ksg_pairs(mid, pairs, k=4, counts=True)
+    mi = mi.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    x = mid.x[0].cpu().numpy()
+    for b, (a, q) in enumerate(pairs):
+        want, wnx, wny = direct.ksg_field(x[:, a], x[:, q:q + 1], 4, counts=True)
+        assert np.array_equal(cnt[b, 0], wnx[0]) and np.array_equal(cnt[b, 1], wny[0]), b
+        assert abs(mi[b] - want[0]) <= MI_TOL
+    # the same sample ordering and summation as the field kernel: bit-identical
+    field = ndf.ksg_field(mid, [cfg.ref_v], k=4)[0].cpu().numpy()
+    assert np.array_equal(mi[:20], field[pairs[:20, 1]])
+
+
+def test_pearson_pairs_match_oracle(mid):
+    rng = np.random.default_rng(4)
+    pairs = np.stack([rng.integers(0, mid.n_vertices, 500),
+                      rng.integers(0, mid.n_vertices, 500)], axis=1)
+    got = ndf.pearson_pairs(mid, pairs).cpu().numpy()
+    x = mid.x[0].cpu().numpy()
+    want = np.array([direct.pearson(x[:, a], x[:, b]) for a, b in pairs])
+    assert np.max(np.abs(got - want)) <= PEARSON_TOL
+
+
+def test_pairs_out_of_range_give_nan(mid):
+    pairs = np.array([[0, 1], [-1, 3], [5, mid.n_vertices]], dtype=np.int64)
+    r = ndf.pearson_pairs(mid, pairs).cpu().numpy()
+    mi = ndf.ksg_pairs(mid, pairs).cpu().numpy()
+    assert np.isfinite(r[0]) and np.isnan(r[1]) and np.isnan(r[2])
+    assert np.isfinite(mi[0]) and np.isnan(mi[1]) and np.isnan(mi[2])
+
+
+def test_ksg_field_is_deterministic(mid):
+    a = ndf.ksg_field(mid, [gen.CONFIGS["mid"].ref_v, 17], k=4)
+    b = ndf.ksg_field(mid, [gen.CONFIGS["mid"].ref_v, 17], k=4)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------ paper-shaped sizes --
+@pytest.fixture(scope="module")
+def paper():
+    cfg = gen.CONFIGS["paper"]
+    _log("generating paper-shaped ensemble (1000 x 1.76M)")
+    e = _ens(cfg)
+    return e
+
+
+def test_paper_pearson_and_ksg_sampled(paper):
+    cfg = gen.CONFIGS["paper"]
+    ref = cfg.ref_v
+    V = paper.n_vertices
+    sample = np.unique(np.concatenate([
+        gen.random_vertices(V, 400, seed=77), [0, 1, V - 1, V - 2, ref, ref + 1]]))
+    xr = _cols(paper, 0, [ref])[:, 0]
+    xs = _cols(paper, 0, sample)
+    # stats and codes at the sampled vertices
+    mean = paper.mean[0][torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    code = paper.code[0][torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    for i in range(len(sample)):
+        m, _ = direct.moments(xs[:, i])
+        assert abs(mean[i] - m) <= 1e-12 * max(1.0, abs(m))
+        c, _ = direct.ksg_codes(xs[:, i])
+        assert np.array_equal(code[i], c)
+    want_r = direct.pearson_field(xr, xs)
+    for prec in (ndf.NDF_PREC_FP32, ndf.NDF_PREC_SPLIT_BF16):
+        got = ndf.pearson_field(paper, [ref], prec=prec)[0]
+        g = got[torch.as_tensor(sample, device="cuda")].cpu().numpy()
+        err = np.max(np.abs(g - want_r))
+        _log(f"paper pearson prec={prec} sampled max|err|={err:.2e}")
+        assert err <= PEARSON_TOL
+        # properties at every vertex: finite, within [-1, 1] (+ rounding), 1 at ref
+        assert torch.isfinite(got).all()
+        assert got.abs().max().item() <= 1.0 + 1e-5
+        assert abs(got[ref].item() - 1.0) <= PEARSON_TOL
+    want_mi = direct.ksg_field(xr, xs, 4)
+    mi = ndf.ksg_field(paper, [ref], k=4)[0]
+    g = mi[torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    err = np.max(np.abs(g - want_mi))
+    _log(f"paper ksg sampled max|dI|={err:.2e}")
+    assert err <= MI_TOL
+    assert torch.isfinite(mi).all()
+    # the reference itself: y == x, so I = H_{N-1} - H_{k-1} when no codes tie
+    assert abs(mi[ref].item() - 5.651137527217) <= MI_TOL
+
+
+def test_paper_pearson_batch64_sampled(paper):
+    cfg = gen.CONFIGS["paper"]
+    V = paper.n_vertices
+    refs = np.concatenate([[cfg.ref_v], gen.random_vertices(V, 63, seed=2311)])
+    got = ndf.pearson_field(paper, refs, prec=ndf.NDF_PREC_SPLIT_BF16)
+    sample = gen.random_vertices(V, 200, seed=91)
+    xs = _cols(paper, 0, sample)
+    xr = _cols(paper, 0, refs)
+    g = got[:, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    for i in range(len(refs)):
+        want = direct.pearson_field(xr[:, i], xs)
+        assert np.max(np.abs(g[i] - want)) <= PEARSON_TOL, i
+    diag = got[torch.arange(64, device="cuda"), torch.as_tensor(refs, device="cuda")]
+    assert torch.all((diag - 1.0).abs() <= PEARSON_TOL)
+
+
+def test_paper_ksg_pairs_counts_exact(paper):
+    V = paper.n_vertices
+    pairs = gen.random_pairs(V, 64, seed=2312)
+    mi, cnt = ndf.ksg_pairs(paper, pairs, k=4, counts=True)
+    mi = mi.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    xa = _cols(paper, 0, pairs[:, 0])
+    xb = _cols(paper, 0, pairs[:, 1])
+    for b in range(len(pairs)):
+        want, wnx, wny = direct.ksg_field(xa[:, b], xb[:, b:b + 1], 4, counts=True)
+        assert np.array_equal(cnt[b, 0], wnx[0]) and np.array_equal(cnt[b, 1], wny[0])
+        assert abs(mi[b] - want[0]) <= MI_TOL
