@@ -26,15 +26,10 @@ __device__ __forceinline__ f32x16 mfma32(const bf16x8 &a, const bf16x8 &b, const
 
 __device__ __forceinline__ int d_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// Round-to-nearest-even float -> bf16 bits (finite inputs; NaN stays NaN).
-__device__ __forceinline__ uint16_t f2bf_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// float -> bf16, round to nearest even (one v_cvt_pk_bf16_f32 per pair on gfx950).
+__device__ __forceinline__ __bf16 f2bf(float f) { return static_cast<__bf16>(f); }
+__device__ __forceinline__ uint16_t f2bf_bits(float f) { return __builtin_bit_cast(uint16_t, f2bf(f)); }
 __device__ __forceinline__ float bf_bits2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ __bf16 f2bf(float f) { return __builtin_bit_cast(__bf16, f2bf_bits(f)); }
 __device__ __forceinline__ float bf2f(__bf16 b) { return bf_bits2f(__builtin_bit_cast(uint16_t, b)); }
 
 __device__ __forceinline__ double wave_sum_f64(double v) {

@@ -187,7 +187,12 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                                             const float *__restrict__ w6,
                                             const bf16x8 (&in)[8][2], bf16x8 (&out)[8][2],
                                             float (&part)[2], float *__restrict__ lat_out,
-                                            int64_t row0, const bool (&ok)[2], int lane) {
+                                            int64_t row0, const bool (&ok)[2], int lane, int h4) {
+    // per-lane row offset 4*(lane/32); rows of block ob are h4 + 32 ob + 8 (r/4) + r%4
+    const float *bias_h = bias + h4;
+    const float *ref_h = ref + h4;
+    const float *w6_h = w6 + h4;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         f32x16 acc0, acc1;
@@ -200,33 +205,46 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
             acc1 = mfma32(a, in[kb][1], acc1);
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = 32 * ob + d_row(r, lane);
-            const float bi = bias[i];
-            float v0 = acc0[r] + bi, v1 = acc1[r] + bi;
-            if (KIND == LAY_RELU || KIND == LAY_HEAD) {
-                v0 = v0 > 0.f ? v0 : 0.f;
-                v1 = v1 > 0.f ? v1 : 0.f;
-            }
-            if (KIND == LAY_LATENT || KIND == LAY_LATENT_OUT) {
-                v0 = bf2f(f2bf(v0));  // latent rounded to bf16
-                v1 = bf2f(f2bf(v1));
-            }
-            if (KIND == LAY_LATENT_OUT) {
-                if (ok[0]) lat_out[(row0 + (lane & 31)) * kH + i] = v0;
-                if (ok[1]) lat_out[(row0 + 32 + (lane & 31)) * kH + i] = v1;
-            } else if (KIND == LAY_HEAD) {
-                part[0] = fmaf(w6[i], v0, part[0]);
-                part[1] = fmaf(w6[i], v1, part[1]);
-            } else {
-                if (KIND == LAY_LATENT) {  // product with the reference latent: exact in FP32
-                    v0 *= ref[i];
-                    v1 *= ref[i];
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 t0, t1;  // built whole, so the previous contents of out[] die here
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = 8 * s + e;
+                const int i = 32 * ob + d_row(r, lane);
+                const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);  // i - h4, compile-time
+                const float bi = bias_h[ic];
+                float v0 = acc0[r] + bi, v1 = acc1[r] + bi;
+                if (KIND == LAY_RELU || KIND == LAY_HEAD) {
+                    v0 = v0 > 0.f ? v0 : 0.f;
+                    v1 = v1 > 0.f ? v1 : 0.f;
                 }
-                out[2 * ob + (r >> 3)][0][r & 7] = f2bf(v0);
-                out[2 * ob + (r >> 3)][1][r & 7] = f2bf(v1);
+                if (KIND == LAY_LATENT || KIND == LAY_LATENT_OUT) {
+                    v0 = bf2f(f2bf(v0));  // latent rounded to bf16
+                    v1 = bf2f(f2bf(v1));
+                }
+                if (KIND == LAY_LATENT_OUT) {
+                    if (ok[0]) lat_out[(row0 + (lane & 31)) * kH + i] = v0;
+                    if (ok[1]) lat_out[(row0 + 32 + (lane & 31)) * kH + i] = v1;
+                } else if (KIND == LAY_HEAD) {
+                    part[0] = fmaf(w6_h[ic], v0, part[0]);
+                    part[1] = fmaf(w6_h[ic], v1, part[1]);
+                } else {
+                    if (KIND == LAY_LATENT) {  // product with the reference latent: exact in FP32
+                        v0 *= ref_h[ic];
+                        v1 *= ref_h[ic];
+                    }
+                    t0[e] = f2bf(v0);
+                    t1[e] = f2bf(v1);
+                }
+            }
+            if (KIND == LAY_RELU || KIND == LAY_LATENT) {
+                out[2 * ob + s][0] = t0;
+                out[2 * ob + s][1] = t1;
             }
         }
+        // keep the scheduler from hoisting the next block's operand loads above
+        // this epilogue (that would hold ~128 extra registers)
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -262,6 +280,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
          tile += (int64_t)gridDim.x * kInferWaves) {
         const int64_t row0 = tile * 64;
+        // opaque per tile, so the per-lane LDS addresses derived from it are
+        // formed inside the loop (base + immediate) instead of hoisted and spilled
+        int h4 = 4 * h;
+        asm volatile("" : "+v"(h4));
         bool ok[2];
         int64_t vq[2];
 #pragma unroll
@@ -295,22 +317,25 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                         s[2 * p + 1] = fmaf(w[cn], __uint_as_float(u & 0xffff0000u), s[2 * p + 1]);
                     }
                 }
+                bf16x8 t;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) a[kb][q][e] = f2bf(s[e]);
+                for (int e = 0; e < 8; ++e) t[e] = f2bf(s[e]);
+                a[kb][q] = t;
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         float part[2] = {0.f, 0.f};
-        dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane);
-        dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane);
+        dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
+        dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
         if (MODE == 1) {
             dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, out, row0, ok,
-                                           lane);
+                                           lane, h4);
             continue;
         }
         dense_layer<8, LAY_LATENT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, nullptr, row0, ok,
-                                   lane);
-        dense_layer<8, LAY_RELU>(s_w[2], s_b[3], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane);
-        dense_layer<8, LAY_HEAD>(s_w[3], s_b[4], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane);
+                                   lane, h4);
+        dense_layer<8, LAY_RELU>(s_w[2], s_b[3], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
+        dense_layer<8, LAY_HEAD>(s_w[3], s_b[4], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;

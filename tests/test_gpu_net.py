@@ -1,0 +1,264 @@
+"""GPU parity of the learned field (Sec. 4-5) against the FP64 oracle, through the
+C ABI: initialisation, forward, adjoint (gradients), Adam, fused inference, and
+training convergence.
+
+BF16 MFMA with FP32 accumulate is compared with FP64: forward outputs within
+2e-2 of the output scale, gradients within 3e-2 relative L2 per tensor, the
+hand-built network within its bf16 input rounding; Adam exactly where the
+gradient sign is unambiguous.  Parameters and pairs come from the seeded
+generators; the oracle never sees a value produced by the GPU path.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+from oracle import direct
+from oracle import ndf_net as nn
+from paper_2307_02203_amd import ndf
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from test_oracle_net import hand_built_params, hand_built_value, DIMS as HB_DIMS, RES as HB_RES  # noqa: E402
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _setup(name, n_enc=1, seed=2320, grid_scale=0.5, bias_scale=0.1):
+    cfg = gen.CONFIGS[name]
+    lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, n_enc=n_enc)
+    flat = gen.make_net_params(lay, seed=seed, grid_scale=grid_scale, bias_scale=bias_scale)
+    c = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay.res, n_enc=n_enc)
+    P = torch.from_numpy(flat).cuda()
+    net = nn.Net(flat, (cfg.nx, cfg.ny, cfg.nz), lay.res, 8, 128, n_enc)
+    return cfg, lay, c, P, net
+
+
+def _check_bf16(got, want, what):
+    """BF16 operands (unit roundoff 2^-9) through six layers whose output is a
+    small difference of larger terms: relative L2 error <= 2e-2 and every
+    element within 0.1 of the output's RMS."""
+    got = np.asarray(got, dtype=np.float64)
+    rms = np.sqrt(np.mean(want ** 2))
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    mx = np.max(np.abs(got - want))
+    _log(f"{what}: rms={rms:.3g} relL2={rel:.2e} max|d|={mx:.3g}")
+    assert rel <= 2e-2 and mx <= 0.1 * rms
+
+
+def _forward_gpu(c, P, pairs):
+    pairs_t = torch.as_tensor(pairs, dtype=torch.int64, device="cuda").contiguous()
+    y = torch.empty(len(pairs), dtype=torch.float32, device="cuda")
+    ws = torch.empty(ndf.train_ws_bytes(c, len(pairs)), dtype=torch.uint8, device="cuda")
+    ndf.ndf_net_forward(c, P, pairs_t, y, ws)
+    return y.cpu().numpy().astype(np.float64)
+
+
+def _grad_gpu(c, P, pairs, targets):
+    B = len(pairs)
+    pairs_t = torch.as_tensor(pairs, dtype=torch.int64, device="cuda").contiguous()
+    t = torch.as_tensor(targets, dtype=torch.float32, device="cuda")
+    g = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    ws = torch.empty(ndf.train_ws_bytes(c, B), dtype=torch.uint8, device="cuda")
+    ndf.ndf_net_grad(c, P, pairs_t, t, g, loss, ws)
+    return g.cpu().numpy().astype(np.float64), loss.item()
+
+
+def _qparams(c, P, prec=ndf.NDF_PREC_BF16):
+    q = torch.empty(ndf.ndf_net_qparam_bytes(c, prec), dtype=torch.uint8, device="cuda")
+    ndf.ndf_net_quantize(c, P, prec, q)
+    return q
+
+
+def _infer_gpu(c, q, refs, V, prec=ndf.NDF_PREC_BF16):
+    out = torch.empty((len(refs), V), dtype=torch.float32, device="cuda")
+    ws = torch.empty(ndf.infer_ws_bytes(c, len(refs), prec), dtype=torch.uint8, device="cuda")
+    ndf.ndf_infer_field(c, q, prec, refs, out, ws)
+    return out
+
+
+def test_init_statistics():
+    cfg, lay, c, P, _ = _setup("tiny")
+    opt = torch.full((2 * P.numel(),), 7.0, device="cuda")
+    ndf.ndf_net_init(c, P, opt, 12345)
+    p = P.cpu().numpy()
+    assert torch.all(opt == 0)
+    for name, shape in lay.tensors():
+        v = lay.view(p, name)
+        if name.startswith("grid"):
+            assert np.all(np.abs(v) <= 1e-4) and v.std() > 4e-5
+        elif name[0] in "Ww":
+            a = math.sqrt(6.0 / shape[-1])
+            assert np.all(np.abs(v) <= a) and abs(v.std() - a / math.sqrt(3)) < 0.1 * a
+            assert abs(v.mean()) < 0.1 * a
+        else:
+            assert np.all(v == 0)
+    P2 = torch.empty_like(P)
+    ndf.ndf_net_init(c, P2, None, 12345)
+    assert torch.equal(P, P2)
+    ndf.ndf_net_init(c, P2, None, 54321)
+    assert not torch.equal(P, P2)
+
+
+def test_hand_built_network_closed_form():
+    dims, res = HB_DIMS, HB_RES
+    flat = hand_built_params()
+    c = ndf.net_config(dims[0], dims[1], dims[2], res)
+    P = torch.from_numpy(flat).cuda()
+    V = dims[0] * dims[1] * dims[2]
+    v1, v2 = np.meshgrid(np.arange(V), np.arange(V))
+    pairs = np.stack([v1.ravel(), v2.ravel()], axis=1)
+    want = hand_built_value(pairs[:, 0], pairs[:, 1], dims)
+    y = _forward_gpu(c, P, pairs)
+    # inputs are bf16 (8 bits): u_x + 2 in [2, 3] is rounded to 2^-7
+    assert np.max(np.abs(y - want) / np.abs(want)) < 2e-2
+    q = _qparams(c, P)
+    out = _infer_gpu(c, q, [0, 17, V - 1], V).cpu().numpy()
+    for i, r in enumerate([0, 17, V - 1]):
+        w = hand_built_value(np.full(V, r), np.arange(V), dims)
+        assert np.max(np.abs(out[i] - w) / np.abs(w)) < 2e-2
+
+
+@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 1), ("mid", 2)])
+def test_forward_parity(name, n_enc):
+    cfg, lay, c, P, net = _setup(name, n_enc)
+    pairs = gen.random_pairs(cfg.n_vertices, 3000, seed=11)
+    y = _forward_gpu(c, P, pairs)
+    want, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    _check_bf16(y, want, f"forward {name} n_enc={n_enc}")
+
+
+@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 2)])
+def test_gradient_parity(name, n_enc):
+    cfg, lay, c, P, net = _setup(name, n_enc, seed=2321)
+    pairs = gen.random_pairs(cfg.n_vertices, 2048, seed=12)
+    y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    signs = np.where(np.random.default_rng(5).random(len(pairs)) < 0.5, -1.0, 1.0)
+    t = y + signs          # residual signs fixed and far from the L1 kink
+    loss_o, g_o, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    g, loss = _grad_gpu(c, P, pairs, t.astype(np.float32))
+    assert abs(loss - loss_o) <= 1e-2 * loss_o
+    for name_t, _shape in lay.tensors():
+        a = lay.view(g, name_t)
+        b = lay.view(g_o.flat, name_t)
+        nb = np.linalg.norm(b)
+        if nb == 0:
+            assert np.all(a == 0), name_t
+            continue
+        rel = np.linalg.norm(a - b) / nb
+        _log(f"grad {name_t}: rel L2 {rel:.2e}")
+        assert rel <= 3e-2, name_t
+
+
+def test_train_step_adam_parity():
+    cfg, lay, c, P, net = _setup("tiny", 1, seed=2322)
+    B = 1024
+    pairs = gen.random_pairs(cfg.n_vertices, B, seed=13)
+    y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    t = (y + 1.0).astype(np.float32)
+    _, g_o, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    lr = 1e-3
+    p1, _, _ = nn.adam_update(net.flat, g_o.flat, np.zeros_like(net.flat),
+                              np.zeros_like(net.flat), 1, lr)
+    opt = torch.zeros(2 * P.numel(), device="cuda")
+    ws = torch.empty(ndf.train_ws_bytes(c, B) + P.numel() * 4 + 256, dtype=torch.uint8,
+                     device="cuda")
+    loss = torch.empty(1, device="cuda")
+    pairs_t = torch.as_tensor(pairs, device="cuda")
+    ndf.ndf_train_step(c, P, opt, 1, pairs_t, torch.as_tensor(t, device="cuda"), lr, loss, ws)
+    got = P.cpu().numpy().astype(np.float64)
+    gabs = np.abs(g_o.flat)
+    strong = gabs > 1e-2 * gabs.max()
+    assert strong.sum() > 1000
+    np.testing.assert_allclose(got[strong], p1[strong], rtol=0, atol=1e-6)
+    # parameters without gradient stay put (a few ReLU units that are dead in FP64
+    # but alive after bf16 rounding may move by lr)
+    untouched = gabs == 0
+    moved = got[untouched] != net.flat[untouched].astype(np.float32)
+    assert moved.mean() < 5e-3
+    # first moment m = 0.1 g, second v = 0.001 g^2 where the sign is unambiguous
+    m = opt[:P.numel()].cpu().numpy()
+    np.testing.assert_allclose(m[strong], 0.1 * g_o.flat[strong], rtol=5e-2, atol=0)
+
+
+@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 1), ("mid", 2)])
+def test_infer_field_parity(name, n_enc):
+    cfg, lay, c, P, net = _setup(name, n_enc, seed=2323)
+    V = cfg.n_vertices
+    refs = [cfg.ref_v, 0, V - 1]
+    q = _qparams(c, P)
+    out = _infer_gpu(c, q, refs, V).cpu().numpy()
+    for i, r in enumerate(refs):
+        want = nn.field(net, r)
+        _check_bf16(out[i], want, f"infer {name} n_enc={n_enc} ref={r}")
+
+
+def test_infer_self_field_symmetric_bitwise():
+    cfg, lay, c, P, net = _setup("mid", 1, seed=2324)
+    V = cfg.n_vertices
+    refs = gen.random_vertices(V, 24, seed=9)
+    q = _qparams(c, P)
+    out = _infer_gpu(c, q, refs, V).cpu().numpy()
+    for a in range(len(refs)):
+        for b in range(len(refs)):
+            assert out[a, refs[b]] == out[b, refs[a]]
+
+
+def test_infer_paper_size_sampled():
+    cfg, lay, c, P, net = _setup("paper", 1, seed=2325)
+    V = cfg.n_vertices
+    q = _qparams(c, P)
+    out = _infer_gpu(c, q, [cfg.ref_v], V)
+    assert torch.isfinite(out).all()
+    sample = np.unique(np.concatenate([gen.random_vertices(V, 3000, seed=31), [0, V - 1]]))
+    g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
+    _check_bf16(g, want, "infer paper")
+
+
+def test_training_learns_pearson_field():
+    """The learned field beats its initialisation and the best constant on
+    held-out pairs of the tiny ensemble (targets from the direct GPU estimator,
+    errors against the FP64 oracle)."""
+    cfg = gen.CONFIGS["tiny"]
+    x = gen.make_ensemble(cfg, device="cuda")
+    e = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz)
+    ndf.ndf_prepare(e)
+    lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz)
+    c = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay.res)
+    P = torch.empty(lay.n_floats, device="cuda")
+    opt = torch.empty(2 * lay.n_floats, device="cuda")
+    ndf.ndf_net_init(c, P, opt, 7)
+    B = 4096
+    ws = torch.empty(ndf.train_ws_bytes(c, B) + P.numel() * 4 + 256, dtype=torch.uint8,
+                     device="cuda")
+    loss = torch.empty(1, device="cuda")
+    held = gen.random_pairs(cfg.n_vertices, 4000, seed=2399)
+    xh = x[0].cpu().numpy()
+    truth = np.array([direct.pearson(xh[:, a], xh[:, b]) for a, b in held])
+
+    def mae():
+        return np.mean(np.abs(_forward_gpu(c, P, held) - truth))
+
+    mae0 = mae()
+    losses = []
+    for step in range(1, 401):
+        pairs = torch.as_tensor(gen.random_pairs(cfg.n_vertices, B, seed=2312 + step),
+                                device="cuda")
+        t = ndf.pearson_pairs(e, pairs)
+        ndf.ndf_train_step(c, P, opt, step, pairs, t, 3e-3, loss, ws)
+        if step % 50 == 0:
+            losses.append(loss.item())
+    mae1 = mae()
+    const = np.mean(np.abs(truth - np.median(truth)))
+    _log(f"training: losses {['%.4f' % l for l in losses]} MAE init {mae0:.4f} "
+         f"trained {mae1:.4f} best-constant {const:.4f}")
+    assert losses[-1] < 0.6 * losses[0]
+    assert mae1 < 0.5 * mae0 and mae1 < 0.6 * const
