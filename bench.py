@@ -50,7 +50,24 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--only", default=None,
+                    help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
+                         "targets, train_step, ndf_field) W+K times and exit")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
+
+
+def _copy_probe(a):
+    import torch
+    n = 1 << 28                      # 2^28 floats = 1 GiB
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(a.warmup + a.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "launches": a.warmup + a.steps}))
 
 
 def main():
@@ -59,6 +76,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU sharding is a design note only)"}))
         sys.exit(2)
+    if a.copy_probe:
+        _copy_probe(a)
+        return
     import torch
     import gen
     from paper_2307_02203_amd import ndf
@@ -108,9 +128,10 @@ def main():
                  for s in range(4)]
 
     # short training of the Pearson field so the timed inference runs a trained net
-    log(f"bench: training the learned field ({PREP_TRAIN_STEPS} steps of {B_PAIRS} pairs)")
+    n_train = 0 if a.only else PREP_TRAIN_STEPS
+    log(f"bench: training the learned field ({n_train} steps of {B_PAIRS} pairs)")
     t0 = time.time()
-    for s in range(1, PREP_TRAIN_STEPS + 1):
+    for s in range(1, n_train + 1):
         pr = torch.as_tensor(gen.random_pairs(V, B_PAIRS, seed=5000 + s), device=dev)
         ndf.ndf_pearson_pairs(ens, 0, 0, pr, t_pear)
         ndf.ndf_train_step(net, P, opt, s, pr, t_pear, LR, loss, ws_t)
@@ -118,33 +139,59 @@ def main():
     train_s = time.time() - t0
     final_loss = loss.item()
     ndf.ndf_net_quantize(net, P, ndf.NDF_PREC_BF16, qp)
-    step_no = [PREP_TRAIN_STEPS]
+    step_no = [n_train]
 
     stream = torch.cuda.current_stream()
     rows = ["prepare", "pearson_fp32", "pearson_b64", "ksg_field", "targets", "train_step",
             "ndf_field"]
 
-    def run_step(it, ev):
-        def mark(i):
-            ev[i].record(stream)
-        mark(0)
+    def row_prepare(it):
         ndf.ndf_prepare(ens)
-        mark(1)
+
+    def row_pearson_fp32(it):
         ndf.ndf_pearson_field(ens, 0, 0, [ref], out_p, ndf.NDF_PREC_FP32, ws_p)
-        mark(2)
+
+    def row_pearson_b64(it):
         ndf.ndf_pearson_field(ens, 0, 0, refs64, out_b, ndf.NDF_PREC_SPLIT_BF16, ws_b)
-        mark(3)
+
+    def row_ksg_field(it):
         ndf.ndf_ksg_mi_field(ens, 0, 0, [ref], K_NN, out_k, None, ws_k)
-        mark(4)
+
+    def row_targets(it):
         pr = pair_sets[it % 4]
         ndf.ndf_pearson_pairs(ens, 0, 0, pr, t_pear)
         ndf.ndf_ksg_mi_pairs(ens, 0, 0, pr, K_NN, t_ksg, None, ws_kp)
-        mark(5)
+
+    def row_train_step(it):
         step_no[0] += 1
-        ndf.ndf_train_step(net, P, opt, step_no[0], pr, t_pear, LR, loss, ws_t)
-        mark(6)
+        ndf.ndf_train_step(net, P, opt, step_no[0], pair_sets[it % 4], t_pear, LR, loss, ws_t)
+
+    def row_ndf_field(it):
         ndf.ndf_infer_field(net, qp, ndf.NDF_PREC_BF16, [ref], out_n, ws_i)
-        mark(7)
+
+    row_fn = {"prepare": row_prepare, "pearson_fp32": row_pearson_fp32,
+              "pearson_b64": row_pearson_b64, "ksg_field": row_ksg_field,
+              "targets": row_targets, "train_step": row_train_step, "ndf_field": row_ndf_field}
+
+    if a.only:
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ms = []
+        for it in range(a.warmup + a.steps):
+            ev0.record(stream)
+            row_fn[a.only](it)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            if it >= a.warmup:
+                ms.append(ev0.elapsed_time(ev1))
+        print(json.dumps({"row": a.only, "ms": ms, "median_ms": float(np.median(ms))}))
+        return
+
+    def run_step(it, ev):
+        for i, r in enumerate(rows):
+            ev[i].record(stream)
+            row_fn[r](it)
+        ev[len(rows)].record(stream)
 
     log(f"bench: {a.warmup} warmup + {a.steps} timed steps")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(8)]

@@ -90,32 +90,41 @@ __device__ __forceinline__ void level_dims(const GridGeom &g, int l, int R[3]) {
 }
 
 // Trilinear corners of grid vertex v on a level of sizes R: cell indices and
-// weights.  c = u (R - 1) with u = i / (n - 1), exact whenever c is an integer;
+// weights.  c = u (R - 1) with u = i / (n - 1), evaluated as one correctly
+// rounded division i (R - 1) / (n - 1) (exact whenever c is an integer);
 // base = clamp(floor(c), 0, R - 2), f = c - base; corner (dx,dy,dz) = bit 0,1,2.
-__device__ __forceinline__ void corners_R(const GridGeom &g, const int R[3], int64_t v,
-                                          int64_t idx[8], float w[8]) {
-    const int64_t i = v % g.nx;
-    const int64_t j = (v / g.nx) % g.ny;
-    const int64_t k = v / ((int64_t)g.nx * g.ny);
-    const int64_t ii[3] = {i, j, k};
+// Vertex and cell indices fit in 32 bits (V, cells < 2^31).
+__device__ __forceinline__ void corners_R32(const GridGeom &g, const int R[3], int64_t v64,
+                                            int idx[8], float w[8]) {
+    const uint32_t v = (uint32_t)v64;
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+    const uint32_t t = v / nx;
+    const uint32_t ii[3] = {v - t * nx, t % ny, t / ny};
     const int nn[3] = {g.nx, g.ny, g.nz};
     int b[3];
     float f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float c = (float)((double)(ii[a] * (int64_t)(R[a] - 1)) / (double)(nn[a] - 1));
+        const float c = (float)(ii[a] * (uint32_t)(R[a] - 1)) / (float)(nn[a] - 1);
         int bb = (int)floorf(c);
         bb = bb < 0 ? 0 : (bb > R[a] - 2 ? R[a] - 2 : bb);
         b[a] = bb;
         f[a] = c - (float)bb;
     }
-    const int64_t Rx = R[0], Ry = R[1];
 #pragma unroll
     for (int cn = 0; cn < 8; ++cn) {
         const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
-        idx[cn] = (b[0] + dx) + Rx * ((b[1] + dy) + Ry * (int64_t)(b[2] + dz));
+        idx[cn] = (b[0] + dx) + R[0] * ((b[1] + dy) + R[1] * (b[2] + dz));
         w[cn] = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) * (dz ? f[2] : 1.f - f[2]);
     }
+}
+
+__device__ __forceinline__ void corners_R(const GridGeom &g, const int R[3], int64_t v,
+                                          int64_t idx[8], float w[8]) {
+    int i32[8];
+    corners_R32(g, R, v, i32, w);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) idx[c] = i32[c];
 }
 
 __device__ __forceinline__ void corners(const GridGeom &g, int l, int64_t v, int64_t idx[8],

@@ -31,6 +31,9 @@ struct QLayout {
     int64_t w4, w5;
     int64_t b1[2], b2[2], b3[2];   // fp32 [128]
     int64_t b4, b5, w6, b6;        // fp32
+    // FP8 (OCP E4M3) copies of W2..W5 in 32x32x64 operand order + per-row scales
+    int64_t q2[2], q3[2], q4, q5;  // fp8 fragments, 16 KB each
+    int64_t s2[2], s3[2], s4, s5;  // fp32 [128] output-channel scales
     int64_t total;
 };
 
@@ -63,6 +66,19 @@ static QLayout qlayout(const ndf_net_config *c) {
     q.b5 = take(kH * 4);
     q.w6 = take(kH * 4);
     q.b6 = take(4);
+    for (int e = 0; e < c->n_enc; ++e) {
+        q.q2[e] = take(kH * kH);
+        q.q3[e] = take(kH * kH);
+        q.s2[e] = take(kH * 4);
+        q.s3[e] = take(kH * 4);
+    }
+    if (c->n_enc == 1) {
+        q.q2[1] = q.q2[0]; q.q3[1] = q.q3[0]; q.s2[1] = q.s2[0]; q.s3[1] = q.s3[0];
+    }
+    q.q4 = take(kH * kH);
+    q.q5 = take(kH * kH);
+    q.s4 = take(kH * 4);
+    q.s5 = take(kH * 4);
     q.total = pos;
     return q;
 }
@@ -105,6 +121,39 @@ __global__ void pack_frag_kernel(const float *__restrict__ W, int KIN, int permu
     }
 }
 
+// Per-output-row scale of W[128][128]: max_k |W[o][k]| / 448 (1 for an all-zero row).
+__global__ void row_scale_kernel(const float *__restrict__ W, float *__restrict__ sc) {
+    const int o = threadIdx.x;  // 128 threads
+    float m = 0.f;
+    for (int k = 0; k < kH; ++k) m = fmaxf(m, fabsf(W[o * kH + k]));
+    sc[o] = m > 0.f ? m / 448.f : 1.f;
+}
+
+// FP8 A fragments of W[128][128] for MFMA 32x32x64: fragment (ob, kb) lane l byte t
+// holds W[32 ob + l%32][f] / sc[row] with f the feature that the previous layer's
+// output layout puts at logical k = 64 kb + 32 (l/32) + t:
+//   f = 64 kb + 32 (t/16) + 8 ((t%16)/4) + 4 (l/32) + t%4.
+__global__ void pack_frag_fp8_kernel(const float *__restrict__ W, const float *__restrict__ sc,
+                                     uint32_t *__restrict__ frag) {
+    const int n = kH * kH / 4;  // dwords
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < n; d += gridDim.x * blockDim.x) {
+        const int lane = (d >> 3) & 63;
+        const int fi = d >> 9;  // ob*2 + kb
+        const int ob = fi >> 1, kb = fi & 1;
+        const int h = lane >> 5, row = 32 * ob + (lane & 31);
+        const float inv = 1.f / sc[row];
+        float v[4];
+        for (int b = 0; b < 4; ++b) {
+            const int t = 4 * (d & 7) + b;
+            const int f = 64 * kb + 32 * (t >> 4) + 8 * ((t & 15) >> 2) + 4 * h + (t & 3);
+            v[b] = W[row * kH + f] * inv;
+        }
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+        frag[d] = (uint32_t)w;
+    }
+}
+
 __global__ void copy_f32_kernel(const float *__restrict__ src, int n, float *__restrict__ dst) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -112,7 +161,7 @@ __global__ void copy_f32_kernel(const float *__restrict__ src, int n, float *__r
 
 int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void *qp,
                         hipStream_t st) {
-    if (prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
+    if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
     const NetOffsets o = net_offsets(c);
     const QLayout q = qlayout(c);
     char *Q = (char *)qp;
@@ -147,6 +196,18 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(128), 0, st, P + o.w6, kH,
                        (float *)(Q + q.w6));
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(1), 0, st, P + o.b6, 1, (float *)(Q + q.b6));
+    // FP8 copies of the 128x128 layers (both precisions share one packed blob)
+    auto fp8 = [&](const float *W, int64_t qoff, int64_t soff) {
+        hipLaunchKernelGGL(row_scale_kernel, dim3(1), dim3(kH), 0, st, W, (float *)(Q + soff));
+        hipLaunchKernelGGL(pack_frag_fp8_kernel, dim3(16), dim3(256), 0, st, W,
+                           (const float *)(Q + soff), (uint32_t *)(Q + qoff));
+    };
+    for (int e = 0; e < c->n_enc; ++e) {
+        fp8(P + o.W2[e], q.q2[e], q.s2[e]);
+        fp8(P + o.W3[e], q.q3[e], q.s3[e]);
+    }
+    fp8(P + o.W4, q.q4, q.s4);
+    fp8(P + o.W5, q.q5, q.s5);
     return status_of_launch();
 }
 
@@ -169,10 +230,7 @@ constexpr int kFragW = 4 * 8 * 64;
 // the training lookup.
 __device__ __forceinline__ void corners32(const GridGeom &g, const int R[3], int64_t v, int idx[8],
                                           float w[8]) {
-    int64_t i64[8];
-    corners_R(g, R, v, i64, w);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) idx[c] = (int)i64[c];
+    corners_R32(g, R, v, idx, w);
 }
 
 enum { LAY_RELU = 0, LAY_LATENT = 1, LAY_HEAD = 2, LAY_LATENT_OUT = 3 };
@@ -344,6 +402,265 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     }
 }
 
+
+// ------------------------------------------------------------ FP8 path ----
+// Layers 2..5 run as MFMA 32x32x64 on OCP E4M3 (MXFP8 style): weights carry a
+// per-output-row FP32 scale applied after the product; activations are split
+// per query into blocks of 32 features, each with its own power-of-two scale
+// (E8M0) that the scaled MFMA applies in hardware.  The first layer (32 inputs,
+// 6% of the work) stays BF16.  Block k = 64 kb + 32 h + t of a lane comes from
+// output blocks 2 kb (t < 16) and 2 kb + 1 (t >= 16) of the previous layer; the
+// packed weights absorb that order (see pack_frag_fp8_kernel).
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+
+__device__ __forceinline__ f32x16 mfma_fp8(const i32x8 &a, const i32x8 &b, int sb,
+                                           const f32x16 &c) {
+    // A unscaled (E8M0 127 = 2^0); B scaled by 2^(sb - 127)
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, sb);
+}
+
+// 32 values -> E4M3 with one power-of-two scale 2^e >= max|v| / 448.
+__device__ __forceinline__ void quant32(const float (&v)[32], i32x8 &out, int &sbyte) {
+    float m = 0.f;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) m = fmaxf(m, fabsf(v[t]));
+    // e = ceil(log2(m / 448)) from the float's fields, branch-free (m = 0 -> -126)
+    const uint32_t u = __float_as_uint(m * (1.0f / 448.0f));
+    const int ex = (int)((u >> 23) & 0xff);
+    int e = ex - 127 + ((u & 0x7fffff) != 0 ? 1 : 0);
+    e = ex == 0 ? -126 : e;
+    e = e < -126 ? -126 : (e > 126 ? 126 : e);
+    const float inv = __uint_as_float((uint32_t)(127 - e) << 23);  // 2^-e
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * d] * inv, v[4 * d + 1] * inv, 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * d + 2] * inv, v[4 * d + 3] * inv, w, true);
+        out[d] = w;
+    }
+    sbyte = e + 127;
+}
+
+struct InferArgs8 {
+    const uint16_t *grid[kL];
+    const bf16x8 *w1;
+    const i32x8 *q[4];    // W2..W5 fp8 fragments
+    const float *s[4];    // their row scales
+    const float *b[5];
+    const float *w6;
+    const float *b6;
+    GridGeom g;
+};
+
+constexpr int kFrag8 = 4 * 2 * 64;  // i32x8 per 128x128 fp8 layer
+
+template <int KIND, bool BF16IN>
+__device__ __forceinline__ void dense_layer_fp8(
+    const bf16x8 *__restrict__ w16, const i32x8 *__restrict__ w8, const float *__restrict__ sw,
+    const float *__restrict__ bias, const float *__restrict__ ref, const float *__restrict__ w6,
+    const bf16x8 (&in16)[2][2], const i32x8 (&in8)[2][2], const int (&sin)[2][2],
+    i32x8 (&out8)[2][2], int (&sout)[2][2], float (&part)[2], float *__restrict__ lat_out,
+    int64_t row0, const bool (&ok)[2], int lane, int h4) {
+    __builtin_amdgcn_sched_barrier(0);
+    const float *bias_h = bias + h4;
+    const float *ref_h = ref + h4;
+    const float *w6_h = w6 + h4;
+    const float *sw_h = sw + h4;
+    if (KIND == LAY_HEAD) {
+        // last layer: one output block and query block at a time, straight into
+        // the w6 dot product (keeps the register footprint of the head small)
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                f32x16 acc;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+                    acc = mfma_fp8(w8[(ob * 2 + kb) * 64 + lane], in8[kb][q], sin[kb][q], acc);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
+                    float x = fmaf(acc[r], sw_h[ic], bias_h[ic]);
+                    x = x > 0.f ? x : 0.f;
+                    part[q] = fmaf(w6_h[ic], x, part[q]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        return;
+    }
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+        f32x16 acc[2][2];
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[o][0][r] = acc[o][1][r] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                if (BF16IN) {
+                    const bf16x8 a = w16[((2 * op + o) * 2 + kb) * 64 + lane];
+                    acc[o][0] = mfma32(a, in16[kb][0], acc[o][0]);
+                    acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
+                } else {
+                    const i32x8 a = w8[((2 * op + o) * 2 + kb) * 64 + lane];
+                    acc[o][0] = mfma_fp8(a, in8[kb][0], sin[kb][0], acc[o][0]);
+                    acc[o][1] = mfma_fp8(a, in8[kb][1], sin[kb][1], acc[o][1]);
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            float v[32];
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int ob = 2 * op + o;
+                    const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
+                    float x = acc[o][q][r];
+                    if (!BF16IN) x *= sw_h[ic];
+                    x += bias_h[ic];
+                    if (KIND == LAY_RELU || KIND == LAY_HEAD) x = x > 0.f ? x : 0.f;
+                    if (KIND == LAY_LATENT || KIND == LAY_LATENT_OUT) x = bf2f(f2bf(x));
+                    if (KIND == LAY_LATENT_OUT) {
+                        if (ok[q]) lat_out[(row0 + 32 * q + (lane & 31)) * kH + ic + h4] = x;
+                    } else if (KIND == LAY_HEAD) {
+                        part[q] = fmaf(w6_h[ic], x, part[q]);
+                    } else if (KIND == LAY_LATENT) {
+                        x *= ref_h[ic];
+                    }
+                    v[16 * o + r] = x;
+                }
+            if (KIND == LAY_RELU || KIND == LAY_LATENT) quant32(v, out8[op][q], sout[op][q]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
+                                                                  const int64_t *__restrict__ qlist,
+                                                                  int64_t nq,
+                                                                  const float *__restrict__ ref_lat,
+                                                                  float *__restrict__ out) {
+    __shared__ bf16x8 s_w1[kFragW1];
+    __shared__ i32x8 s_q[4][kFrag8];
+    __shared__ float s_s[4][kH];
+    __shared__ float s_b[5][kH];
+    __shared__ float s_w6[kH];
+    __shared__ float s_ref[kH];
+
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w1[i];
+    const int nlay = MODE == 0 ? 4 : 2;
+    for (int L = 0; L < nlay; ++L)
+        for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L][i];
+    for (int i = tid; i < 4 * kH; i += kInferThreads) s_s[i / kH][i % kH] = A.s[i / kH][i % kH];
+    for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
+    for (int i = tid; i < kH; i += kInferThreads) {
+        s_w6[i] = A.w6[i];
+        s_ref[i] = MODE == 0 ? ref_lat[i] : 0.f;
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    const float b6 = A.b6[0];
+    const int64_t ntiles = ceil_div(nq, 64);
+    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
+         tile += (int64_t)gridDim.x * kInferWaves) {
+        const int64_t row0 = tile * 64;
+        int h4 = 4 * h;
+        asm volatile("" : "+v"(h4));
+        bool ok[2];
+        int64_t vq[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int64_t n = row0 + q * 32 + jl;
+            ok[q] = n < nq;
+            vq[q] = ok[q] ? (qlist ? qlist[n] : n) : 0;
+        }
+        bf16x8 g16[2][2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
+            int R[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                int idx[8];
+                float w[8];
+                corners32(A.g, R, vq[q], idx, w);
+                float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int cn = 0; cn < 8; ++cn) {
+                    const i32x4 raw = *reinterpret_cast<const i32x4 *>(grid + (int64_t)idx[cn] * kF);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const uint32_t u = (uint32_t)raw[p];
+                        s[2 * p] = fmaf(w[cn], __uint_as_float(u << 16), s[2 * p]);
+                        s[2 * p + 1] = fmaf(w[cn], __uint_as_float(u & 0xffff0000u), s[2 * p + 1]);
+                    }
+                }
+                bf16x8 t;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) t[e] = f2bf(s[e]);
+                g16[kb][q] = t;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        i32x8 a8[2][2], b8[2][2];
+        int sa[2][2], sb[2][2];
+        float part[2] = {0.f, 0.f};
+        dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8, sb,
+                                        a8, sa, part, nullptr, row0, ok, lane, h4);
+        dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_s[0], s_b[1], s_ref, s_w6, g16, a8,
+                                         sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+        if (MODE == 1) {
+            dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_s[1], s_b[2], s_ref, s_w6,
+                                                   g16, b8, sb, a8, sa, part, out, row0, ok, lane,
+                                                   h4);
+            continue;
+        }
+        dense_layer_fp8<LAY_LATENT, false>(nullptr, s_q[1], s_s[1], s_b[2], s_ref, s_w6, g16, b8,
+                                           sb, a8, sa, part, nullptr, row0, ok, lane, h4);
+        dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[2], s_s[2], s_b[3], s_ref, s_w6, g16, a8,
+                                         sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+        dense_layer_fp8<LAY_HEAD, false>(nullptr, s_q[3], s_s[3], s_b[4], s_ref, s_w6, g16, b8,
+                                         sb, a8, sa, part, nullptr, row0, ok, lane, h4);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
+            if (h == 0 && ok[q]) out[row0 + q * 32 + jl] = y;
+        }
+    }
+}
+
+static InferArgs8 make_args8(const ndf_net_config *c, const QLayout &q, const char *Q, int e) {
+    InferArgs8 a{};
+    for (int l = 0; l < kL; ++l) a.grid[l] = (const uint16_t *)(Q + q.grid[e][l]);
+    a.w1 = (const bf16x8 *)(Q + q.w1[e]);
+    a.q[0] = (const i32x8 *)(Q + q.q2[e]);
+    a.q[1] = (const i32x8 *)(Q + q.q3[e]);
+    a.q[2] = (const i32x8 *)(Q + q.q4);
+    a.q[3] = (const i32x8 *)(Q + q.q5);
+    a.s[0] = (const float *)(Q + q.s2[e]);
+    a.s[1] = (const float *)(Q + q.s3[e]);
+    a.s[2] = (const float *)(Q + q.s4);
+    a.s[3] = (const float *)(Q + q.s5);
+    a.b[0] = (const float *)(Q + q.b1[e]);
+    a.b[1] = (const float *)(Q + q.b2[e]);
+    a.b[2] = (const float *)(Q + q.b3[e]);
+    a.b[3] = (const float *)(Q + q.b4);
+    a.b[4] = (const float *)(Q + q.b5);
+    a.w6 = (const float *)(Q + q.w6);
+    a.b6 = (const float *)(Q + q.b6);
+    a.g = grid_geom(c);
+    return a;
+}
+
 static InferArgs make_args(const ndf_net_config *c, const QLayout &q, const char *Q, int e) {
     InferArgs a{};
     for (int l = 0; l < kL; ++l) a.grid[l] = (const uint16_t *)(Q + q.grid[e][l]);
@@ -372,7 +689,7 @@ static unsigned infer_blocks(int64_t nq) {
 
 int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const int64_t *ref_v,
                        int n_ref, float *out, void *ws, hipStream_t st) {
-    if (prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
+    if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
@@ -380,6 +697,17 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return NDF_E_HIP;
+    if (prec == NDF_PREC_FP8_E4M3) {
+        const InferArgs8 a0 = make_args8(c, q, Q, 0);
+        hipLaunchKernelGGL(infer_fp8_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                           st, a0, refs, (int64_t)n_ref, nullptr, lat);
+        const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
+        const int64_t V = (int64_t)c->nx * c->ny * c->nz;
+        for (int r = 0; r < n_ref; ++r)
+            hipLaunchKernelGGL(infer_fp8_kernel<0>, dim3(infer_blocks(V)), dim3(kInferThreads), 0,
+                               st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V);
+        return status_of_launch();
+    }
     // reference latents with encoder 0 (p1), queries with the last encoder (p2)
     const InferArgs a0 = make_args(c, q, Q, 0);
     hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,

@@ -254,3 +254,33 @@ def test_paper_ksg_pairs_counts_exact(paper):
         want, wnx, wny = direct.ksg_field(xa[:, b], xb[:, b:b + 1], 4, counts=True)
         assert np.array_equal(cnt[b, 0], wnx[0]) and np.array_equal(cnt[b, 1], wny[0])
         assert abs(mi[b] - want[0]) <= MI_TOL
+
+
+def test_cross_variable_fields():
+    """R_{mu nu}(p_ref, .) with mu != nu (Sec. 3): reference in variable 0, queries
+    in variable 1 of a two-variable ensemble, and the reverse."""
+    import dataclasses
+    cfg = dataclasses.replace(gen.CONFIGS["mid"], n_vars=2)
+    x = gen.make_ensemble(cfg, device="cuda")
+    e = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz)
+    ndf.ndf_prepare(e)
+    xh = x.cpu().numpy()
+    ref = cfg.ref_v
+    for vr, vq in ((0, 1), (1, 0)):
+        want = direct.pearson_field(xh[vr][:, ref], xh[vq])
+        for prec in (ndf.NDF_PREC_FP32, ndf.NDF_PREC_SPLIT_BF16):
+            got = ndf.pearson_field(e, [ref], prec=prec, var_ref=vr, var_qry=vq)[0].cpu().numpy()
+            assert np.max(np.abs(got - want)) <= PEARSON_TOL
+        mi, cnt = ndf.ksg_field(e, [ref], k=4, counts=True, var_ref=vr, var_qry=vq)
+        w, wnx, wny = direct.ksg_field(xh[vr][:, ref], xh[vq], 4, counts=True)
+        c = cnt[0].cpu().numpy()
+        assert np.array_equal(c[:, 0], wnx) and np.array_equal(c[:, 1], wny)
+        assert np.max(np.abs(mi[0].cpu().numpy() - w)) <= MI_TOL
+    # pairs across variables
+    pairs = gen.random_pairs(cfg.n_vertices, 200, seed=21)
+    r = ndf.pearson_pairs(e, pairs, var_a=0, var_b=1).cpu().numpy()
+    want = np.array([direct.pearson(xh[0][:, a], xh[1][:, b]) for a, b in pairs])
+    assert np.max(np.abs(r - want)) <= PEARSON_TOL
+    mi = ndf.ksg_pairs(e, pairs, k=4, var_a=1, var_b=0).cpu().numpy()
+    want = np.array([direct.ksg_field(xh[1][:, a], xh[0][:, b:b + 1], 4)[0] for a, b in pairs])
+    assert np.max(np.abs(mi - want)) <= MI_TOL

@@ -262,3 +262,37 @@ def test_training_learns_pearson_field():
          f"trained {mae1:.4f} best-constant {const:.4f}")
     assert losses[-1] < 0.6 * losses[0]
     assert mae1 < 0.5 * mae0 and mae1 < 0.6 * const
+
+
+@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 1), ("mid", 2)])
+def test_infer_field_fp8_parity(name, n_enc):
+    """MXFP8 layers 2..5 (E4M3, 3 mantissa bits: unit roundoff 2^-4): relative L2
+    error <= 8e-2 against the FP64 oracle; the BF16 field of the same packed
+    parameters is reported beside it."""
+    cfg, lay, c, P, net = _setup(name, n_enc, seed=2326)
+    V = cfg.n_vertices
+    refs = [cfg.ref_v, 0, V - 1]
+    q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
+    out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16).cpu().numpy()
+    for i, r in enumerate(refs):
+        want = nn.field(net, r)
+        rel8 = np.linalg.norm(out8[i] - want) / np.linalg.norm(want)
+        rel16 = np.linalg.norm(out16[i] - want) / np.linalg.norm(want)
+        _log(f"fp8 {name} n_enc={n_enc} ref={r}: relL2 fp8 {rel8:.3e} bf16 {rel16:.3e}")
+        assert rel8 <= 8e-2
+        assert rel16 <= 2e-2
+
+
+def test_infer_fp8_paper_size_sampled():
+    cfg, lay, c, P, net = _setup("paper", 1, seed=2327)
+    V = cfg.n_vertices
+    q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    out = _infer_gpu(c, q, [cfg.ref_v], V, ndf.NDF_PREC_FP8_E4M3)
+    assert torch.isfinite(out).all()
+    sample = gen.random_vertices(V, 3000, seed=32)
+    g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
+    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
+    _log(f"fp8 paper: relL2 {rel:.3e}")
+    assert rel <= 8e-2
