@@ -12,6 +12,7 @@ Workload: synthetic paper-shaped ensemble (1000 members on 250x352x20 =
   targets        direct Pearson and KSG-MI targets for 2^18 random vertex pairs
   train_step     one learned-field training step on 2^18 pairs (BF16 MFMA, Adam)
   ndf_field      learned field for 1 reference at all vertices (fused BF16 kernel)
+  ndf_field_fp8  the same field with MXFP8 (E4M3) layers 2..5
 
 `value` is the learned-field ms per field (the paper's headline quantity);
 `fields` gives every row.  All launches go on torch's current stream and are
@@ -40,6 +41,7 @@ PREP_TRAIN_STEPS = 300
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit VALU lane operations (non-packed)
 
 
@@ -50,6 +52,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=PREP_TRAIN_STEPS,
+                    help="learned-field training steps before timing")
     ap.add_argument("--only", default=None,
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
                          "targets, train_step, ndf_field) W+K times and exit")
@@ -106,6 +110,7 @@ def main():
     out_b = torch.empty((N_BATCH, V), device=dev)
     out_k = torch.empty((1, V), device=dev)
     out_n = torch.empty((1, V), device=dev)
+    out_n8 = torch.empty((1, V), device=dev)
     ws_p = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, ens, None, 1, 0),
                        dtype=torch.uint8, device=dev)
     ws_b = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, ens, None, N_BATCH,
@@ -128,7 +133,7 @@ def main():
                  for s in range(4)]
 
     # short training of the Pearson field so the timed inference runs a trained net
-    n_train = 0 if a.only else PREP_TRAIN_STEPS
+    n_train = 0 if a.only else a.train_steps
     log(f"bench: training the learned field ({n_train} steps of {B_PAIRS} pairs)")
     t0 = time.time()
     for s in range(1, n_train + 1):
@@ -143,7 +148,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     rows = ["prepare", "pearson_fp32", "pearson_b64", "ksg_field", "targets", "train_step",
-            "ndf_field"]
+            "ndf_field", "ndf_field_fp8"]
 
     def row_prepare(it):
         ndf.ndf_prepare(ens)
@@ -169,7 +174,11 @@ def main():
     def row_ndf_field(it):
         ndf.ndf_infer_field(net, qp, ndf.NDF_PREC_BF16, [ref], out_n, ws_i)
 
-    row_fn = {"prepare": row_prepare, "pearson_fp32": row_pearson_fp32,
+    def row_ndf_field_fp8(it):
+        ndf.ndf_infer_field(net, qp, ndf.NDF_PREC_FP8_E4M3, [ref], out_n8, ws_i)
+
+    row_fn = {"ndf_field_fp8": row_ndf_field_fp8, "prepare": row_prepare,
+              "pearson_fp32": row_pearson_fp32,
               "pearson_b64": row_pearson_b64, "ksg_field": row_ksg_field,
               "targets": row_targets, "train_step": row_train_step, "ndf_field": row_ndf_field}
 
@@ -194,7 +203,7 @@ def main():
         ev[len(rows)].record(stream)
 
     log(f"bench: {a.warmup} warmup + {a.steps} timed steps")
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(rows) + 1)]
            for _ in range(a.warmup + a.steps)]
     for it in range(a.warmup):
         run_step(it, evs[it])
@@ -210,11 +219,12 @@ def main():
         e = evs[it]
         for i, r in enumerate(rows):
             per_row[r].append(e[i].elapsed_time(e[i + 1]))
-        step_ms.append(e[0].elapsed_time(e[7]))
+        step_ms.append(e[0].elapsed_time(e[len(rows)]))
     med = {r: float(np.median(v)) for r, v in per_row.items()}
     ms_step = float(np.median(step_ms))
     fields = {
         "ndf_field_bf16": med["ndf_field"],
+        "ndf_field_fp8": med["ndf_field_fp8"],
         "pearson_field_fp32": med["pearson_fp32"],
         "pearson_batch64_split_bf16_per_field": med["pearson_b64"] / N_BATCH,
         "pearson_batch64_split_bf16_total": med["pearson_b64"],
@@ -232,11 +242,13 @@ def main():
                         / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"},
         "ndf_field": {"bound": "mfma", "achieved": 2.0 * 69760 * V / (med["ndf_field"] * 1e-3)
                       / 1e12, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s"},
+        "ndf_field_fp8": {"bound": "mfma", "achieved": 2.0 * 69760 * V
+                          / (med["ndf_field_fp8"] * 1e-3) / 1e12, "peak": PEAK_FP8_TFLOPS,
+                          "unit": "TFLOP/s"},
     }
     for r in roof.values():
         r["frac"] = r["achieved"] / r["peak"]
-    timed = {k: med[k] for k in ("pearson_fp32", "pearson_b64", "ksg_field", "ndf_field",
-                                 "train_step", "targets", "prepare")}
+    timed = {k: med[k] for k in rows}
     dominant = max(timed, key=timed.get)
 
     result = {
@@ -264,38 +276,48 @@ def main():
         "fields": fields,
         "speedup_ndf_vs_pearson_fp32": med["pearson_fp32"] / med["ndf_field"],
         "speedup_ndf_vs_ksg": med["ksg_field"] / med["ndf_field"],
+        "speedup_ndf_vs_pearson_batch64_per_field": med["pearson_b64"] / N_BATCH / med["ndf_field"],
         "dominant_kernel": dominant,
         "rooflines": roof,
-        "training": {"steps_before_timing": PREP_TRAIN_STEPS, "seconds": train_s,
+        "training": {"steps_before_timing": n_train, "seconds": train_s,
                      "final_l1_loss": final_loss, "lr": LR, "batch": B_PAIRS},
     }
     result["roofline"] = _roofline_of(dominant, roof, med, N, V)
 
     if not a.no_accuracy:
-        result["accuracy"] = _accuracy(ens, out_p, out_b, out_k, out_n, refs64, cfg)
+        result["accuracy"] = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(ens, cfg, lay, log)
     print(json.dumps(result))
 
 
+# Brute-force KSG needs, per ordered sample pair, |dx| and |dy| (one v_sad_u32
+# each), a max and a compare against the running k-th distance (4 lane ops) for
+# the neighbour pass, and two compares and two conditional adds for the marginal
+# counts: 8 32-bit VALU lane operations per pair.
+KSG_OPS_PER_PAIR = 8
+
+
 def _roofline_of(dominant, roof, med, N, V):
     if dominant in roof:
         r = dict(roof[dominant])
-    else:
-        # KSG-MI: integer VALU work; algorithmic unit = brute-force-equivalent pair
-        # evaluations N(N-1) per vertex, 4 lane ops each (two |d|, max, compare)
-        ops = 4.0 * N * (N - 1) * V
-        r = {"bound": "alu", "achieved": ops / (med[dominant] * 1e-3) / 1e12,
-             "peak": PEAK_ALU_TOPS, "unit": "Tops/s"}
+    elif dominant == "ksg_field":
+        # algorithmic unit: brute-force-equivalent pair evaluations V N (N - 1)
+        pairs = float(V) * N * (N - 1)
+        r = {"bound": "alu", "achieved": pairs / (med[dominant] * 1e-3) / 1e12,
+             "peak": PEAK_ALU_TOPS / KSG_OPS_PER_PAIR, "unit": "Tpair-evals/s"}
         r["frac"] = r["achieved"] / r["peak"]
-        r["note"] = ("brute-force-equivalent work; the kernel prunes the neighbour search "
-                     "in x order, so frac > 1 measures the pruning, not ALU utilisation")
+        r["note"] = ("peak = brute-force pair evaluations/s at the 32-bit VALU peak "
+                     f"({PEAK_ALU_TOPS:.1f} T lane-ops/s / {KSG_OPS_PER_PAIR} ops); the kernel "
+                     "prunes the search in reference order, so frac > 1 is the pruning gain")
+    else:
+        r = {"bound": "mixed", "achieved": None, "peak": None, "unit": None, "frac": None}
     r["kernel"] = dominant
     r["traffic"] = None
     return r
 
 
-def _accuracy(ens, out_p, out_b, out_k, out_n, refs64, cfg):
+def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg):
     """Errors of the timed outputs against the FP64 oracle on sampled vertices."""
     import torch
     import gen
@@ -311,6 +333,7 @@ def _accuracy(ens, out_p, out_b, out_k, out_n, refs64, cfg):
     b0 = out_b[0, idx].cpu().numpy()
     k = out_k[0, idx[:400]].cpu().numpy()
     n = out_n[0, idx].cpu().numpy()
+    n8 = out_n8[0, idx].cpu().numpy()
     return {
         "sample_vertices": int(len(sample)),
         "pearson_fp32_max_abs_err": float(np.max(np.abs(p - r_o))),
@@ -318,6 +341,8 @@ def _accuracy(ens, out_p, out_b, out_k, out_n, refs64, cfg):
         "ksg_mi_max_abs_err_400": float(np.max(np.abs(k - mi_o))),
         "ndf_vs_oracle_pearson_mae": float(np.mean(np.abs(n - r_o))),
         "ndf_vs_oracle_pearson_max_abs_err": float(np.max(np.abs(n - r_o))),
+        "ndf_fp8_vs_oracle_pearson_mae": float(np.mean(np.abs(n8 - r_o))),
+        "ndf_fp8_vs_ndf_bf16_max_abs_diff": float(np.max(np.abs(n8 - n))),
         "population_rho_mae_of_oracle": float(np.mean(np.abs(
             r_o - gen.population_rho(cfg, np.full(len(sample), cfg.ref_v), sample)))),
     }
@@ -332,7 +357,7 @@ def _cpu_baseline(ens, cfg, lay, log):
     V, N = cfg.n_vertices, cfg.n_members
     cores = len(os.sched_getaffinity(0))
     out = {}
-    sample = gen.random_vertices(V, 200_000, seed=99)
+    sample = gen.random_vertices(V, 400_000, seed=99)
     idx = torch.as_tensor(sample, device="cuda")
     xs = ens.x[0][:, idx].cpu().numpy()
     xr = ens.x[0][:, cfg.ref_v].cpu().numpy()
@@ -342,7 +367,7 @@ def _cpu_baseline(ens, cfg, lay, log):
     tp = time.time() - t0
     out["pearson_ms_per_field"] = tp * 1e3 * V / len(sample)
     log("cpu baseline: oracle KSG")
-    nk = 3000
+    nk = 60_000
     t0 = time.time()
     direct.ksg_field(xr, xs[:, :nk], K_NN)
     tk = time.time() - t0
@@ -350,7 +375,7 @@ def _cpu_baseline(ens, cfg, lay, log):
     log("cpu baseline: oracle learned field")
     flat = gen.make_net_params(lay)
     net = onn.Net(flat, (cfg.nx, cfg.ny, cfg.nz), lay.res, 8, 128, 1)
-    nn_s = 20_000
+    nn_s = 400_000
     q = gen.random_vertices(V, nn_s, seed=98)
     t0 = time.time()
     onn.forward(net, np.full(nn_s, cfg.ref_v), q)

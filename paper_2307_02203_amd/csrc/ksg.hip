@@ -9,13 +9,17 @@
 // psi(n) = H_{n-1} - gamma is H_{k-1} + H_{N-1} - <H_nx + H_ny>.
 //
 // GPU design (one 64-lane wave per pair, everything in LDS):
-//  * samples are ordered by x (ties broken by member index); a field shares one
-//    ordering of the reference column across all queries, so it is sorted once;
-//  * the k nearest neighbours of a sample are found by walking outwards in x
-//    order from its own position and stopping on each side once |dx| reaches the
-//    current k-th distance (no later sample can be closer under the max-norm);
+//  * the samples are kept in two orders, by x (ties by member index) and by y
+//    (ties by x position); a field shares the x order of the reference column
+//    across all queries, so it is sorted once;
+//  * the k nearest neighbours of a sample are found by walking outwards from its
+//    own position in one of the two orders, stopping on each side once the
+//    distance along that coordinate reaches the current k-th distance (under the
+//    max-norm no later sample can be closer).  Each sample walks the order in
+//    which its 2k nearest codes are spread widest, i.e. where the strip the walk
+//    must cover holds the fewest samples; any choice gives the same exact result;
 //  * the marginal counts are two binary searches each, over the sorted x codes
-//    and over the query's y codes sorted in LDS (bitonic sort);
+//    and over the sorted y codes;
 //  * all distances and counts are exact int32, so the counts equal a brute-force
 //    evaluation bit for bit; the harmonic sum is FP64.
 #include "common.hpp"
@@ -65,59 +69,77 @@ __device__ __forceinline__ int count_less(const int *a, int n, int hp, int val) 
     return pos;
 }
 
-// Neighbour search and counts for all samples of one pair.  xy[p] = (x, y) in
-// x order, ys = y codes ascending; returns this lane's FP64 sum of H_nx + H_ny.
+constexpr int kPad = 4;             // sentinel samples on each side of the x order
+constexpr int kFar = 1 << 28;       // sentinel x distance: beyond any code difference (< 2^24)
+
 template <int K>
-__device__ double ksg_points(const int2 *xy, const int *ys, int N, const double *__restrict__ H,
-                             const uint16_t *perm, int32_t *__restrict__ cnt) {
+__device__ __forceinline__ void insert_k(int (&best)[K], int d) {
+    // best ascending; keep the K smallest of best + {d} (ties kept with multiplicity)
+#pragma unroll
+    for (int t = K - 1; t > 0; --t) best[t] = min(best[t], max(best[t - 1], d));
+    best[0] = min(best[0], d);
+}
+
+// Neighbour search and counts for all samples of one pair.
+//   xo[p] = (x, y) in x order, yo[q] = (y, x) in y order, both with kPad
+//   sentinels on each side; yrank[p] = y-order position of x-order sample p;
+//   perm[p] = member of x-order sample p.  Returns this lane's FP64 sum of
+//   H_nx + H_ny.
+// A walk takes 4 samples per side per step; a side stops once the farthest of
+// its 4 is at least the current k-th distance away along the walked coordinate,
+// or is a sentinel.  Samples past that point never change the k smallest, so
+// the overscan is harmless, and a block starts at most 3 samples past the last
+// real one, so reads stay within the padding.
+template <int K>
+__device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yrank, int N,
+                             const double *__restrict__ H, const uint16_t *perm,
+                             int32_t *__restrict__ cnt) {
     const int lane = threadIdx.x;
     const int hp = pow2_floor(N);
     double acc = 0.0;
     for (int p = lane; p < N; p += 64) {
-        const int2 me = xy[p];
+        const int2 mxy = xo[p];
+        const int q = yrank[p];
+        // spread of the 2k nearest codes in each order
+        const int sx = xo[min(p + K, N - 1)].x - xo[max(p - K, 0)].x;
+        const int sy = yo[min(q + K, N - 1)].x - yo[max(q - K, 0)].x;
+        const bool walk_y = sy > sx;
+        const int2 *A = walk_y ? yo : xo;
+        const int pos = walk_y ? q : p;
+        const int2 me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
         int best[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
-        int jl = p - 1, jr = p + 1;
-        bool al = jl >= 0, ar = jr < N;
+        int jl = pos - 1, jr = pos + 1;
+        bool al = true, ar = true;
         while (al || ar) {
             if (al) {
-                const int2 c = xy[jl];
-                const int dx = me.x - c.x;
-                if (dx >= best[K - 1]) {
-                    al = false;
-                } else {
-                    const int d = max(dx, abs(me.y - c.y));
+                int2 c[4];
 #pragma unroll
-                    for (int t = K - 1; t > 0; --t) best[t] = min(best[t], max(best[t - 1], d));
-                    best[0] = min(best[0], d);
-                    --jl;
-                    al = jl >= 0;
-                }
+                for (int u = 0; u < 4; ++u) c[u] = A[jl - u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) insert_k<K>(best, max(me.x - c[u].x, abs(me.y - c[u].y)));
+                al = c[3].x != -kFar && (me.x - c[3].x) < best[K - 1];
+                jl -= 4;
             }
             if (ar) {
-                const int2 c = xy[jr];
-                const int dx = c.x - me.x;
-                if (dx >= best[K - 1]) {
-                    ar = false;
-                } else {
-                    const int d = max(dx, abs(me.y - c.y));
+                int2 c[4];
 #pragma unroll
-                    for (int t = K - 1; t > 0; --t) best[t] = min(best[t], max(best[t - 1], d));
-                    best[0] = min(best[0], d);
-                    ++jr;
-                    ar = jr < N;
-                }
+                for (int u = 0; u < 4; ++u) c[u] = A[jr + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) insert_k<K>(best, max(c[u].x - me.x, abs(me.y - c[u].y)));
+                ar = c[3].x != kFar && (c[3].x - me.x) < best[K - 1];
+                jr += 4;
             }
         }
         const int eps = best[K - 1];
         int nx = 0, ny = 0;
         if (eps > 0) {
             // samples with value in (v - eps, v + eps), minus the sample itself
-            nx = count_less<2>(&xy[0].x, N, hp, me.x + eps) -
-                 count_less<2>(&xy[0].x, N, hp, me.x - eps + 1) - 1;
-            ny = count_less<1>(ys, N, hp, me.y + eps) - count_less<1>(ys, N, hp, me.y - eps + 1) -
-                 1;
+            nx = count_less<2>(&xo[0].x, N, hp, mxy.x + eps) -
+                 count_less<2>(&xo[0].x, N, hp, mxy.x - eps + 1) - 1;
+            ny = count_less<2>(&yo[0].x, N, hp, mxy.y + eps) -
+                 count_less<2>(&yo[0].x, N, hp, mxy.y - eps + 1) - 1;
         }
         acc += H[nx] + H[ny];
         if (cnt) {
@@ -127,6 +149,38 @@ __device__ double ksg_points(const int2 *xy, const int *ys, int N, const double 
         }
     }
     return acc;
+}
+
+// The y order from a complete x order: sort (y, x position) keys in the yo
+// region, convert them in place to (y, x) and record each sample's y rank.
+__device__ __forceinline__ void build_y_order(int2 *xo, int2 *yo, uint16_t *yrank, int N, int P) {
+    const int lane = threadIdx.x;
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);
+    for (int p = lane; p < P; p += 64)
+        keys[p] = p < N ? (((unsigned long long)(uint32_t)xo[p].y) << 32) | (unsigned)p : ~0ull;
+    __syncthreads();
+    wave_bitonic_sort(keys, P);
+    for (int q = lane; q < N; q += 64) {
+        const unsigned long long key = keys[q];
+        const int p = (int)(key & 0xffffffffu);
+        yo[q] = make_int2((int)(key >> 32), xo[p].x);
+        yrank[p] = (uint16_t)q;
+    }
+    __syncthreads();
+    if (lane < kPad) {
+        yo[-1 - lane] = make_int2(-kFar, 0);
+        yo[N + lane] = make_int2(kFar, 0);
+    }
+    __syncthreads();
+}
+
+// Sentinels of the x order (written once per launch by each workgroup).
+__device__ __forceinline__ void ksg_sentinels(int2 *xy, int N) {
+    const int lane = threadIdx.x;
+    if (lane < kPad) {
+        xy[-1 - lane] = make_int2(-kFar, 0);
+        xy[N + lane] = make_int2(kFar, 0);
+    }
 }
 
 // ----------------------------------------------------------- field mode ----
@@ -157,6 +211,12 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
     }
 }
 
+// LDS plan of both kernels: xo (N + 2 kPad) int2 | yo (P + 2 kPad) int2, also the
+// sort keys | perm N uint16 | yrank N uint16.
+__host__ __device__ inline size_t ksg_lds_bytes(int N, int P) {
+    return (size_t)(N + 2 * kPad) * 8 + (size_t)(P + 2 * kPad) * 8 + (size_t)N * 4;
+}
+
 template <int K>
 __global__ __launch_bounds__(64) void ksg_field_kernel(
     const int32_t *__restrict__ code_q, const int32_t *__restrict__ flags_r,
@@ -165,17 +225,20 @@ __global__ __launch_bounds__(64) void ksg_field_kernel(
     const double *__restrict__ H, float *__restrict__ out, int32_t *__restrict__ counts) {
     extern __shared__ int4 s_raw[];
     const int P = pow2_ceil(N);
-    int2 *xy = reinterpret_cast<int2 *>(s_raw);
-    int *ys = reinterpret_cast<int *>(xy + N);
-    uint16_t *perm = reinterpret_cast<uint16_t *>(ys + P);
+    int2 *xo = reinterpret_cast<int2 *>(s_raw) + kPad;
+    int2 *yo = xo + N + 2 * kPad;
+    uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
+    uint16_t *yrank = perm + N;
+    int *tmp = reinterpret_cast<int *>(yo);  // the query row in member order
     const int lane = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
+    ksg_sentinels(xo, N);
 
     for (int r = 0; r < n_ref; ++r) {
         const int32_t fr = flags_r[refs[r]];
         __syncthreads();
         for (int p = lane; p < N; p += 64) {
-            xy[p].x = xs_all[(int64_t)r * N + p];
+            xo[p].x = xs_all[(int64_t)r * N + p];
             perm[p] = perm_all[(int64_t)r * N + p];
         }
         __syncthreads();
@@ -191,18 +254,13 @@ __global__ __launch_bounds__(64) void ksg_field_kernel(
                     for (int i = lane; i < 2 * N; i += 64) cnt[i] = 0;
                 continue;
             }
-            for (int p = lane; p < P; p += 64) {
-                if (p < N) {
-                    const int y = cq[perm[p]];
-                    xy[p].y = y;
-                    ys[p] = y;
-                } else {
-                    ys[p] = 0x7fffffff;
-                }
-            }
+            // the query's codes: one coalesced row read, permuted into x order in LDS
+            for (int m = lane; m < N; m += 64) tmp[m] = cq[m];
             __syncthreads();
-            wave_bitonic_sort(ys, P);
-            const double acc = wave_sum_f64(ksg_points<K>(xy, ys, N, H, perm, cnt));
+            for (int p = lane; p < N; p += 64) xo[p].y = tmp[perm[p]];
+            __syncthreads();
+            build_y_order(xo, yo, yrank, N, P);
+            const double acc = wave_sum_f64(ksg_points<K>(xo, yo, yrank, N, H, perm, cnt));
             if (lane == 0) out[(int64_t)r * V + q] = (float)(base - acc / (double)N);
             __syncthreads();
         }
@@ -218,12 +276,14 @@ __global__ __launch_bounds__(64) void ksg_pairs_kernel(
     float *__restrict__ out, int32_t *__restrict__ counts) {
     extern __shared__ int4 s_raw[];
     const int P = pow2_ceil(N);
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(s_raw);
-    int2 *xy = reinterpret_cast<int2 *>(keys + P);
-    int *ys = reinterpret_cast<int *>(xy + N);
-    uint16_t *perm = reinterpret_cast<uint16_t *>(ys + P);
+    int2 *xo = reinterpret_cast<int2 *>(s_raw) + kPad;
+    int2 *yo = xo + N + 2 * kPad;
+    uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
+    uint16_t *yrank = perm + N;
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);  // x-order sort
     const int lane = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
+    ksg_sentinels(xo, N);
 
     for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
         const int64_t va = pairs[2 * b], vb = pairs[2 * b + 1];
@@ -243,20 +303,18 @@ __global__ __launch_bounds__(64) void ksg_pairs_kernel(
         }
         const int32_t *ca = code_a + va * N;
         const int32_t *cb = code_b + vb * N;
-        for (int m = lane; m < P; m += 64) {
+        for (int m = lane; m < P; m += 64)
             keys[m] = m < N ? (((unsigned long long)(uint32_t)ca[m]) << 16) | (unsigned)m : ~0ull;
-            ys[m] = m < N ? cb[m] : 0x7fffffff;
-        }
         __syncthreads();
         wave_bitonic_sort(keys, P);
-        wave_bitonic_sort(ys, P);
         for (int p = lane; p < N; p += 64) {
             const int m = (int)(keys[p] & 0xffff);
             perm[p] = (uint16_t)m;
-            xy[p] = make_int2((int)(keys[p] >> 16), cb[m]);
+            xo[p] = make_int2((int)(keys[p] >> 16), cb[m]);
         }
         __syncthreads();
-        const double acc = wave_sum_f64(ksg_points<K>(xy, ys, N, H, perm, cnt));
+        build_y_order(xo, yo, yrank, N, P);
+        const double acc = wave_sum_f64(ksg_points<K>(xo, yo, yrank, N, H, perm, cnt));
         if (lane == 0) out[b] = (float)(base - acc / (double)N);
         __syncthreads();
     }
@@ -323,7 +381,7 @@ int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int6
     const int32_t *cq = e->code + (int64_t)var_qry * V * N;
     hipLaunchKernelGGL(ksg_sort_ref_kernel, dim3(n_ref), dim3(64), (size_t)P * 8, st, cr, N, refs,
                        xs, perm, H);
-    const size_t lds = (size_t)N * 8 + (size_t)P * 4 + (size_t)N * 2;
+    const size_t lds = ksg_lds_bytes(N, P);
     const dim3 g((unsigned)field_grid(V));
     const int32_t *fr = e->flags + (int64_t)var_ref * V;
     const int32_t *fq = e->flags + (int64_t)var_qry * V;
@@ -346,7 +404,7 @@ int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t 
     const int64_t V = (int64_t)e->nx * e->ny * e->nz;
     const int P = p2(N);
     hipLaunchKernelGGL(harmonic_kernel, dim3(1), dim3(64), 0, st, N, H);
-    const size_t lds = (size_t)P * 8 + (size_t)N * 8 + (size_t)P * 4 + (size_t)N * 2;
+    const size_t lds = ksg_lds_bytes(N, P);
     const int64_t gmax = 256 * 24;
     const dim3 g((unsigned)(B < gmax ? B : gmax));
     const int32_t *ca = e->code + (int64_t)var_a * V * N;

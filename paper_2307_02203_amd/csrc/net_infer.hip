@@ -419,11 +419,14 @@ __device__ __forceinline__ f32x16 mfma_fp8(const i32x8 &a, const i32x8 &b, int s
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, sb);
 }
 
-// 32 values -> E4M3 with one power-of-two scale 2^e >= max|v| / 448.
+// 32 values -> E4M3 with one power-of-two scale 2^e >= max|v| / 448.  The two
+// lanes that hold the two 32-blocks of one query's 64-feature k-block (l, l^32)
+// share the scale, so the scaled MFMA sees one scale per query and k-block.
 __device__ __forceinline__ void quant32(const float (&v)[32], i32x8 &out, int &sbyte) {
     float m = 0.f;
 #pragma unroll
     for (int t = 0; t < 32; ++t) m = fmaxf(m, fabsf(v[t]));
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
     // e = ceil(log2(m / 448)) from the float's fields, branch-free (m = 0 -> -126)
     const uint32_t u = __float_as_uint(m * (1.0f / 448.0f));
     const int ex = (int)((u >> 23) & 0xff);
