@@ -285,7 +285,10 @@ def main():
     result["roofline"] = _roofline_of(dominant, roof, med, N, V)
 
     if not a.no_accuracy:
-        result["accuracy"] = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg)
+        acc, sample, r_o = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg)
+        result["accuracy"] = acc
+        log("bench: gain of the trained field over the method without it")
+        result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, out_n, med, log)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(ens, cfg, lay, log)
     print(json.dumps(result))
@@ -345,7 +348,58 @@ def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg):
         "ndf_fp8_vs_ndf_bf16_max_abs_diff": float(np.max(np.abs(n8 - n))),
         "population_rho_mae_of_oracle": float(np.mean(np.abs(
             r_o - gen.population_rho(cfg, np.full(len(sample), cfg.ref_v), sample)))),
-    }
+    }, sample, r_o
+
+
+def _gain(ens, cfg, net, lay, sample, r_o, out_n, med, log):
+    """What the trained field gains over the method without it, on the sampled
+    vertices against the FP64 oracle: the untrained (initialised) field, the best
+    constant predictor, and the direct Pearson estimator with its members cut
+    until one field costs what the learned field costs (equal time)."""
+    import torch
+    from paper_2307_02203_amd import ndf
+    V, N = cfg.n_vertices, cfg.n_members
+    idx = torch.as_tensor(sample, device="cuda")
+    mae = lambda y: float(np.mean(np.abs(y - r_o)))  # noqa: E731
+    out = {"ndf_trained_mae": mae(out_n[0, idx].cpu().numpy()),
+           "best_constant_mae": mae(np.full_like(r_o, np.median(r_o)))}
+
+    P0 = torch.empty(lay.n_floats, device="cuda")
+    opt0 = torch.empty(2 * lay.n_floats, device="cuda")
+    ndf.ndf_net_init(net, P0, opt0, 2320)
+    qp0 = torch.empty(ndf.ndf_net_qparam_bytes(net, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                      device="cuda")
+    ndf.ndf_net_quantize(net, P0, ndf.NDF_PREC_BF16, qp0)
+    ws_i = torch.empty(ndf.infer_ws_bytes(net, 1, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                       device="cuda")
+    y0 = torch.empty((1, V), device="cuda")
+    ndf.ndf_infer_field(net, qp0, ndf.NDF_PREC_BF16, [cfg.ref_v], y0, ws_i)
+    out["ndf_untrained_mae"] = mae(y0[0, idx].cpu().numpy())
+    del P0, opt0, qp0, ws_i, y0
+
+    # members of the equal-time direct estimator: its cost is linear in N
+    m_eq = int(max(8, min(N, round(N * med["ndf_field"] / med["pearson_fp32"]))))
+    sub = ndf.Ensemble(ens.x[:, :m_eq], cfg.nx, cfg.ny, cfg.nz)
+    ndf.ndf_prepare(sub)
+    ws = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, sub, None, 1, 0),
+                     dtype=torch.uint8, device="cuda")
+    y = torch.empty((1, V), device="cuda")
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for it in range(7):
+        ev0.record(stream)
+        ndf.ndf_pearson_field(sub, 0, 0, [cfg.ref_v], y, ndf.NDF_PREC_FP32, ws)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        if it >= 2:
+            ms.append(ev0.elapsed_time(ev1))
+    out["equal_time_direct_pearson"] = {
+        "members": m_eq, "ms_per_field": float(np.median(ms)),
+        "mae": mae(y[0, idx].cpu().numpy())}
+    log(f"bench: gain {out}")
+    return out
 
 
 def _cpu_baseline(ens, cfg, lay, log):

@@ -8,7 +8,9 @@
 // and I = psi(k) + psi(N) - <psi(nx+1) + psi(ny+1)>, which with
 // psi(n) = H_{n-1} - gamma is H_{k-1} + H_{N-1} - <H_nx + H_ny>.
 //
-// GPU design (one 64-lane wave per pair, everything in LDS):
+// GPU design (one workgroup of four 64-lane waves per pair, everything in LDS;
+// four waves share one pair's LDS so that a CU keeps enough waves in flight to
+// hide LDS latency):
 //  * the samples are kept in two orders, by x (ties by member index) and by y
 //    (ties by x position); a field shares the x order of the reference column
 //    across all queries, so it is sorted once;
@@ -27,6 +29,8 @@
 namespace ndf {
 
 constexpr int kKsgMaxN = 4096;
+constexpr int kKsgWaves = 4;
+constexpr int kKsgThreads = 64 * kKsgWaves;
 
 __device__ __forceinline__ int pow2_ceil(int n) {
     int p = 1;
@@ -39,13 +43,13 @@ __device__ __forceinline__ int pow2_floor(int n) {
     return p;
 }
 
-// Ascending bitonic sort of P (power of two) keys in LDS by one wave (64 lanes).
+// Ascending bitonic sort of P (power of two) keys in LDS by the workgroup.
 template <typename T>
-__device__ void wave_bitonic_sort(T *a, int P) {
-    const int lane = threadIdx.x;
+__device__ void block_bitonic_sort(T *a, int P) {
+    const int tid = threadIdx.x;
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = lane; t < P / 2; t += 64) {
+            for (int t = tid; t < P / 2; t += kKsgThreads) {
                 const int i = 2 * t - (t & (stride - 1));
                 const int j = i + stride;
                 const bool up = (i & size) == 0;
@@ -83,36 +87,64 @@ __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
 // Neighbour search and counts for all samples of one pair.
 //   xo[p] = (x, y) in x order, yo[q] = (y, x) in y order, both with kPad
 //   sentinels on each side; yrank[p] = y-order position of x-order sample p;
-//   perm[p] = member of x-order sample p.  Returns this lane's FP64 sum of
-//   H_nx + H_ny.
+//   perm[p] = member of x-order sample p; epsL = N ints of LDS scratch.
+// Returns the FP64 sum of H_nx + H_ny over all samples.
+//
+// Walk phase: the x order is dealt to the waves in chunks of 64 samples, round
+// robin.  A lane walks one sample at a time and takes the wave's next unclaimed
+// sample as soon as its walk ends (claims are handed out in lane order from a
+// wave-uniform counter), so short and long walks do not wait for each other.
 // A walk takes 4 samples per side per step; a side stops once the farthest of
 // its 4 is at least the current k-th distance away along the walked coordinate,
 // or is a sentinel.  Samples past that point never change the k smallest, so
 // the overscan is harmless, and a block starts at most 3 samples past the last
 // real one, so reads stay within the padding.
+// Count phase: thread t takes samples t, t + 256, ... and counts the marginals
+// by binary search; the partial sums are combined in a fixed order, so the FP64
+// total is reproducible.  Returns the total in every thread.
 template <int K>
 __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yrank, int N,
                              const double *__restrict__ H, const uint16_t *perm,
-                             int32_t *__restrict__ cnt) {
-    const int lane = threadIdx.x;
-    const int hp = pow2_floor(N);
-    double acc = 0.0;
-    for (int p = lane; p < N; p += 64) {
-        const int2 mxy = xo[p];
-        const int q = yrank[p];
-        // spread of the 2k nearest codes in each order
-        const int sx = xo[min(p + K, N - 1)].x - xo[max(p - K, 0)].x;
+                             int32_t *__restrict__ cnt, int *epsL) {
+    __shared__ double s_part[kKsgWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    // i-th sample of this wave (increasing in i)
+    auto sample = [&](int i) { return ((i >> 6) * kKsgWaves + wave) * 64 + (i & 63); };
+    int p = sample(lane);
+    bool active = false;
+    const int2 *A = xo;
+    int2 me = make_int2(0, 0);
+    int jl = 0, jr = 0;
+    bool al = false, ar = false;
+    int best[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
+
+    auto start = [&](int pp) {
+        const int2 mxy = xo[pp];
+        const int q = yrank[pp];
+        // spread of the 2k nearest codes in each order: walk the sparser one
+        const int sx = xo[min(pp + K, N - 1)].x - xo[max(pp - K, 0)].x;
         const int sy = yo[min(q + K, N - 1)].x - yo[max(q - K, 0)].x;
         const bool walk_y = sy > sx;
-        const int2 *A = walk_y ? yo : xo;
-        const int pos = walk_y ? q : p;
-        const int2 me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
-        int best[K];
+        A = walk_y ? yo : xo;
+        const int pos = walk_y ? q : pp;
+        me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
+        jl = pos - 1;
+        jr = pos + 1;
+        al = ar = true;
 #pragma unroll
         for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
-        int jl = pos - 1, jr = pos + 1;
-        bool al = true, ar = true;
-        while (al || ar) {
+    };
+
+    if (p < N) {
+        start(p);
+        active = true;
+    }
+    int next = 64;  // first unclaimed sample (wave-uniform)
+    while (__any(active)) {
+        if (active) {
             if (al) {
                 int2 c[4];
 #pragma unroll
@@ -131,8 +163,31 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
                 ar = c[3].x != kFar && (c[3].x - me.x) < best[K - 1];
                 jr += 4;
             }
+            if (!al && !ar) {
+                epsL[p] = best[K - 1];
+                active = false;
+            }
         }
-        const int eps = best[K - 1];
+        const uint64_t idle = __ballot(!active);
+        if (sample(next) < N && idle) {
+            if (!active) {
+                const int np = sample(next + __popcll(idle & below));
+                if (np < N) {
+                    p = np;
+                    start(p);
+                    active = true;
+                }
+            }
+            next += __popcll(idle);
+        }
+    }
+    __syncthreads();
+
+    const int hp = pow2_floor(N);
+    double acc = 0.0;
+    for (int pp = tid; pp < N; pp += kKsgThreads) {
+        const int2 mxy = xo[pp];
+        const int eps = epsL[pp];
         int nx = 0, ny = 0;
         if (eps > 0) {
             // samples with value in (v - eps, v + eps), minus the sample itself
@@ -143,43 +198,49 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         }
         acc += H[nx] + H[ny];
         if (cnt) {
-            const int m = perm[p];
+            const int m = perm[pp];
             cnt[m] = nx;
             cnt[N + m] = ny;
         }
     }
-    return acc;
+    acc = wave_sum_f64(acc);
+    if (lane == 0) s_part[wave] = acc;
+    __syncthreads();
+    double total = 0.0;
+#pragma unroll
+    for (int w = 0; w < kKsgWaves; ++w) total += s_part[w];
+    return total;
 }
 
 // The y order from a complete x order: sort (y, x position) keys in the yo
 // region, convert them in place to (y, x) and record each sample's y rank.
 __device__ __forceinline__ void build_y_order(int2 *xo, int2 *yo, uint16_t *yrank, int N, int P) {
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);
-    for (int p = lane; p < P; p += 64)
+    for (int p = tid; p < P; p += kKsgThreads)
         keys[p] = p < N ? (((unsigned long long)(uint32_t)xo[p].y) << 32) | (unsigned)p : ~0ull;
     __syncthreads();
-    wave_bitonic_sort(keys, P);
-    for (int q = lane; q < N; q += 64) {
+    block_bitonic_sort(keys, P);
+    for (int q = tid; q < N; q += kKsgThreads) {
         const unsigned long long key = keys[q];
         const int p = (int)(key & 0xffffffffu);
         yo[q] = make_int2((int)(key >> 32), xo[p].x);
         yrank[p] = (uint16_t)q;
     }
     __syncthreads();
-    if (lane < kPad) {
-        yo[-1 - lane] = make_int2(-kFar, 0);
-        yo[N + lane] = make_int2(kFar, 0);
+    if (tid < kPad) {
+        yo[-1 - tid] = make_int2(-kFar, 0);
+        yo[N + tid] = make_int2(kFar, 0);
     }
     __syncthreads();
 }
 
 // Sentinels of the x order (written once per launch by each workgroup).
 __device__ __forceinline__ void ksg_sentinels(int2 *xy, int N) {
-    const int lane = threadIdx.x;
-    if (lane < kPad) {
-        xy[-1 - lane] = make_int2(-kFar, 0);
-        xy[N + lane] = make_int2(kFar, 0);
+    const int tid = threadIdx.x;
+    if (tid < kPad) {
+        xy[-1 - tid] = make_int2(-kFar, 0);
+        xy[N + tid] = make_int2(kFar, 0);
     }
 }
 
@@ -193,11 +254,11 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
     const int r = blockIdx.x;
     const int P = pow2_ceil(N);
     const int32_t *c = code + refs[r] * N;
-    for (int m = threadIdx.x; m < P; m += 64)
+    for (int m = threadIdx.x; m < P; m += kKsgThreads)
         s_keys[m] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
     __syncthreads();
-    wave_bitonic_sort(s_keys, P);
-    for (int p = threadIdx.x; p < N; p += 64) {
+    block_bitonic_sort(s_keys, P);
+    for (int p = threadIdx.x; p < N; p += kKsgThreads) {
         xs[(int64_t)r * N + p] = (int32_t)(s_keys[p] >> 16);
         perm[(int64_t)r * N + p] = (uint16_t)(s_keys[p] & 0xffff);
     }
@@ -212,13 +273,14 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
 }
 
 // LDS plan of both kernels: xo (N + 2 kPad) int2 | yo (P + 2 kPad) int2, also the
-// sort keys | perm N uint16 | yrank N uint16.
+// sort keys | perm N uint16 | yrank N uint16 | eps N int32.
 __host__ __device__ inline size_t ksg_lds_bytes(int N, int P) {
-    return (size_t)(N + 2 * kPad) * 8 + (size_t)(P + 2 * kPad) * 8 + (size_t)N * 4;
+    return (size_t)(N + 2 * kPad) * 8 + (size_t)(P + 2 * kPad) * 8 + (size_t)N * 4 +
+           (size_t)N * 4;
 }
 
 template <int K>
-__global__ __launch_bounds__(64) void ksg_field_kernel(
+__global__ __launch_bounds__(kKsgThreads) void ksg_field_kernel(
     const int32_t *__restrict__ code_q, const int32_t *__restrict__ flags_r,
     const int32_t *__restrict__ flags_q, int N, int64_t V, const int64_t *__restrict__ refs,
     int n_ref, const int32_t *__restrict__ xs_all, const uint16_t *__restrict__ perm_all,
@@ -229,15 +291,16 @@ __global__ __launch_bounds__(64) void ksg_field_kernel(
     int2 *yo = xo + N + 2 * kPad;
     uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
     uint16_t *yrank = perm + N;
+    int *epsL = reinterpret_cast<int *>(yrank + N);  // 4-byte aligned: N uint16 x 2
     int *tmp = reinterpret_cast<int *>(yo);  // the query row in member order
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
     ksg_sentinels(xo, N);
 
     for (int r = 0; r < n_ref; ++r) {
         const int32_t fr = flags_r[refs[r]];
         __syncthreads();
-        for (int p = lane; p < N; p += 64) {
+        for (int p = tid; p < N; p += kKsgThreads) {
             xo[p].x = xs_all[(int64_t)r * N + p];
             perm[p] = perm_all[(int64_t)r * N + p];
         }
@@ -247,21 +310,21 @@ __global__ __launch_bounds__(64) void ksg_field_kernel(
             const int32_t fq = flags_q[q];
             int32_t *cnt = counts ? counts + ((int64_t)r * V + q) * 2 * N : nullptr;
             if ((fr | fq) & (NDF_FLAG_CONSTANT | NDF_FLAG_NONFINITE)) {
-                if (lane == 0)
+                if (tid == 0)
                     out[(int64_t)r * V + q] = ((fr | fq) & NDF_FLAG_NONFINITE) ? __builtin_nanf("")
                                                                                 : 0.0f;
                 if (cnt)
-                    for (int i = lane; i < 2 * N; i += 64) cnt[i] = 0;
+                    for (int i = tid; i < 2 * N; i += kKsgThreads) cnt[i] = 0;
                 continue;
             }
             // the query's codes: one coalesced row read, permuted into x order in LDS
-            for (int m = lane; m < N; m += 64) tmp[m] = cq[m];
+            for (int m = tid; m < N; m += kKsgThreads) tmp[m] = cq[m];
             __syncthreads();
-            for (int p = lane; p < N; p += 64) xo[p].y = tmp[perm[p]];
+            for (int p = tid; p < N; p += kKsgThreads) xo[p].y = tmp[perm[p]];
             __syncthreads();
             build_y_order(xo, yo, yrank, N, P);
-            const double acc = wave_sum_f64(ksg_points<K>(xo, yo, yrank, N, H, perm, cnt));
-            if (lane == 0) out[(int64_t)r * V + q] = (float)(base - acc / (double)N);
+            const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
+            if (tid == 0) out[(int64_t)r * V + q] = (float)(base - acc / (double)N);
             __syncthreads();
         }
     }
@@ -269,7 +332,7 @@ __global__ __launch_bounds__(64) void ksg_field_kernel(
 
 // ----------------------------------------------------------- pairs mode ----
 template <int K>
-__global__ __launch_bounds__(64) void ksg_pairs_kernel(
+__global__ __launch_bounds__(kKsgThreads) void ksg_pairs_kernel(
     const int32_t *__restrict__ code_a, const int32_t *__restrict__ code_b,
     const int32_t *__restrict__ flags_a, const int32_t *__restrict__ flags_b, int N, int64_t V,
     const int64_t *__restrict__ pairs, int64_t B, const double *__restrict__ H,
@@ -280,8 +343,9 @@ __global__ __launch_bounds__(64) void ksg_pairs_kernel(
     int2 *yo = xo + N + 2 * kPad;
     uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
     uint16_t *yrank = perm + N;
+    int *epsL = reinterpret_cast<int *>(yrank + N);
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);  // x-order sort
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
     ksg_sentinels(xo, N);
 
@@ -289,33 +353,33 @@ __global__ __launch_bounds__(64) void ksg_pairs_kernel(
         const int64_t va = pairs[2 * b], vb = pairs[2 * b + 1];
         int32_t *cnt = counts ? counts + b * 2 * N : nullptr;
         if (va < 0 || va >= V || vb < 0 || vb >= V) {  // out-of-range pair: NaN, no reads
-            if (lane == 0) out[b] = __builtin_nanf("");
+            if (tid == 0) out[b] = __builtin_nanf("");
             if (cnt)
-                for (int i = lane; i < 2 * N; i += 64) cnt[i] = -1;
+                for (int i = tid; i < 2 * N; i += kKsgThreads) cnt[i] = -1;
             continue;
         }
         const int32_t f = flags_a[va] | flags_b[vb];
         if (f & (NDF_FLAG_CONSTANT | NDF_FLAG_NONFINITE)) {
-            if (lane == 0) out[b] = (f & NDF_FLAG_NONFINITE) ? __builtin_nanf("") : 0.0f;
+            if (tid == 0) out[b] = (f & NDF_FLAG_NONFINITE) ? __builtin_nanf("") : 0.0f;
             if (cnt)
-                for (int i = lane; i < 2 * N; i += 64) cnt[i] = 0;
+                for (int i = tid; i < 2 * N; i += kKsgThreads) cnt[i] = 0;
             continue;
         }
         const int32_t *ca = code_a + va * N;
         const int32_t *cb = code_b + vb * N;
-        for (int m = lane; m < P; m += 64)
+        for (int m = tid; m < P; m += kKsgThreads)
             keys[m] = m < N ? (((unsigned long long)(uint32_t)ca[m]) << 16) | (unsigned)m : ~0ull;
         __syncthreads();
-        wave_bitonic_sort(keys, P);
-        for (int p = lane; p < N; p += 64) {
+        block_bitonic_sort(keys, P);
+        for (int p = tid; p < N; p += kKsgThreads) {
             const int m = (int)(keys[p] & 0xffff);
             perm[p] = (uint16_t)m;
             xo[p] = make_int2((int)(keys[p] >> 16), cb[m]);
         }
         __syncthreads();
         build_y_order(xo, yo, yrank, N, P);
-        const double acc = wave_sum_f64(ksg_points<K>(xo, yo, yrank, N, H, perm, cnt));
-        if (lane == 0) out[b] = (float)(base - acc / (double)N);
+        const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
+        if (tid == 0) out[b] = (float)(base - acc / (double)N);
         __syncthreads();
     }
 }
@@ -345,11 +409,13 @@ size_t ksg_field_ws_bytes(int N, int n_ref) {
            align_up((size_t)n_ref * N * sizeof(uint16_t), 256);
 }
 
-static int field_grid(int64_t V) {
-    // persistent workgroups: enough single-wave groups to fill 256 CUs several
-    // times over, never more than there are queries
-    int64_t g = 256 * 24;
-    return (int)(V < g ? V : g);
+// Persistent workgroups: as many as the CUs hold at once given the LDS of one
+// pair (160 KB per CU), never more than there are items.
+static int resident_grid(int64_t items, size_t lds) {
+    int64_t per_cu = (int64_t)(163840 / (lds > 0 ? lds : 1));
+    per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    const int64_t g = 256 * per_cu;
+    return (int)(items < g ? items : g);
 }
 
 template <int K>
@@ -357,7 +423,7 @@ static void launch_field_k(dim3 g, size_t lds, hipStream_t st, const int32_t *cq
                            const int32_t *fq, int N, int64_t V, const int64_t *refs, int n_ref,
                            const int32_t *xs, const uint16_t *perm, const double *H, float *out,
                            int32_t *counts) {
-    hipLaunchKernelGGL(ksg_field_kernel<K>, g, dim3(64), lds, st, cq, fr, fq, N, V, refs, n_ref, xs,
+    hipLaunchKernelGGL(ksg_field_kernel<K>, g, dim3(kKsgThreads), lds, st, cq, fr, fq, N, V, refs, n_ref, xs,
                        perm, H, out, counts);
 }
 
@@ -379,10 +445,10 @@ int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int6
     const int P = p2(N);
     const int32_t *cr = e->code + (int64_t)var_ref * V * N;
     const int32_t *cq = e->code + (int64_t)var_qry * V * N;
-    hipLaunchKernelGGL(ksg_sort_ref_kernel, dim3(n_ref), dim3(64), (size_t)P * 8, st, cr, N, refs,
-                       xs, perm, H);
+    hipLaunchKernelGGL(ksg_sort_ref_kernel, dim3(n_ref), dim3(kKsgThreads), (size_t)P * 8, st, cr,
+                       N, refs, xs, perm, H);
     const size_t lds = ksg_lds_bytes(N, P);
-    const dim3 g((unsigned)field_grid(V));
+    const dim3 g((unsigned)resident_grid(V, lds));
     const int32_t *fr = e->flags + (int64_t)var_ref * V;
     const int32_t *fq = e->flags + (int64_t)var_qry * V;
     switch (k) {
@@ -405,8 +471,7 @@ int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t 
     const int P = p2(N);
     hipLaunchKernelGGL(harmonic_kernel, dim3(1), dim3(64), 0, st, N, H);
     const size_t lds = ksg_lds_bytes(N, P);
-    const int64_t gmax = 256 * 24;
-    const dim3 g((unsigned)(B < gmax ? B : gmax));
+    const dim3 g((unsigned)resident_grid(B, lds));
     const int32_t *ca = e->code + (int64_t)var_a * V * N;
     const int32_t *cb = e->code + (int64_t)var_b * V * N;
     const int32_t *fa = e->flags + (int64_t)var_a * V;
@@ -414,8 +479,8 @@ int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t 
     switch (k) {
 #define NDF_KSG_CASE(KK)                                                                       \
     case KK:                                                                                   \
-        hipLaunchKernelGGL(ksg_pairs_kernel<KK>, g, dim3(64), lds, st, ca, cb, fa, fb, N, V, pairs, \
-                           B, H, out, counts);                                                    \
+        hipLaunchKernelGGL(ksg_pairs_kernel<KK>, g, dim3(kKsgThreads), lds, st, ca, cb, fa, fb, N, V, \
+                           pairs, B, H, out, counts);                                             \
         break;
         NDF_KSG_CASE(1) NDF_KSG_CASE(2) NDF_KSG_CASE(3) NDF_KSG_CASE(4)
         NDF_KSG_CASE(5) NDF_KSG_CASE(6) NDF_KSG_CASE(7) NDF_KSG_CASE(8)

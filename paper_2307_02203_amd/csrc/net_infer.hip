@@ -235,9 +235,35 @@ __device__ __forceinline__ void corners32(const GridGeom &g, const int R[3], int
 
 enum { LAY_RELU = 0, LAY_LATENT = 1, LAY_HEAD = 2, LAY_LATENT_OUT = 3 };
 
+typedef __attribute__((ext_vector_type(2))) short s16x2;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+// Two floats -> packed bf16 pair, round to nearest even: the two-source form of
+// v_cvt_pk_bf16_f32 (the compiler otherwise converts each value on its own and
+// merges the halves with a v_perm).
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    uint32_t r;
+    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// ReLU of a packed bf16 pair: a bf16 is negative iff its sign bit is set, so a
+// signed 16-bit max with 0 (one v_pk_max_i16) clamps both halves.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+    const s16x2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), z));
+}
+// max(x, 0) as a signed integer max on the bit pattern: negative floats have
+// the sign bit set, so they compare below 0 and map to +0.  (fmaxf would first
+// quiet NaNs with an extra max per value.)
+__device__ __forceinline__ float relu_f32(float x) {
+    return __int_as_float(max(__float_as_int(x), 0));
+}
+__device__ __forceinline__ float bf_lo(uint32_t v) { return __uint_as_float(v << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
+
 // One 128-wide layer for the wave's 2 x 32 queries.  in: KB k-blocks of B
-// operands; per output block ob the two accumulators (one per query block) are
-// finished and turned into out[2 ob], out[2 ob + 1] (or the head / latent).
+// operands.  The accumulators start at the bias, so the epilogue is only the
+// bf16 packing (plus ReLU on the packed pairs, the latent product, or the head).
 template <int KB, int KIND>
 __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                                             const float *__restrict__ bias,
@@ -253,51 +279,68 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
+        // rows 8 g + 0..3 of block ob are contiguous: one 16-byte LDS read each
         f32x16 acc0, acc1;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+        for (int g = 0; g < 4; ++g) {
+            const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias_h + 32 * ob + 8 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc0[4 * g + i] = acc1[4 * g + i] = bv[i];
+        }
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const bf16x8 a = wf[(ob * KB + kb) * 64 + lane];
             acc0 = mfma32(a, in[kb][0], acc0);
             acc1 = mfma32(a, in[kb][1], acc1);
         }
+        if (KIND == LAY_HEAD) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            bf16x8 t0, t1;  // built whole, so the previous contents of out[] die here
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 wv = *reinterpret_cast<const f32x4 *>(w6_h + 32 * ob + 8 * g);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int r = 8 * s + e;
-                const int i = 32 * ob + d_row(r, lane);
-                const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);  // i - h4, compile-time
-                const float bi = bias_h[ic];
-                float v0 = acc0[r] + bi, v1 = acc1[r] + bi;
-                if (KIND == LAY_RELU || KIND == LAY_HEAD) {
-                    v0 = v0 > 0.f ? v0 : 0.f;
-                    v1 = v1 > 0.f ? v1 : 0.f;
-                }
-                if (KIND == LAY_LATENT || KIND == LAY_LATENT_OUT) {
-                    v0 = bf2f(f2bf(v0));  // latent rounded to bf16
-                    v1 = bf2f(f2bf(v1));
-                }
-                if (KIND == LAY_LATENT_OUT) {
-                    if (ok[0]) lat_out[(row0 + (lane & 31)) * kH + i] = v0;
-                    if (ok[1]) lat_out[(row0 + 32 + (lane & 31)) * kH + i] = v1;
-                } else if (KIND == LAY_HEAD) {
-                    part[0] = fmaf(w6_h[ic], v0, part[0]);
-                    part[1] = fmaf(w6_h[ic], v1, part[1]);
-                } else {
-                    if (KIND == LAY_LATENT) {  // product with the reference latent: exact in FP32
-                        v0 *= ref_h[ic];
-                        v1 *= ref_h[ic];
-                    }
-                    t0[e] = f2bf(v0);
-                    t1[e] = f2bf(v1);
+                for (int i = 0; i < 4; ++i) {
+                    part[0] = fmaf(wv[i], relu_f32(acc0[4 * g + i]), part[0]);
+                    part[1] = fmaf(wv[i], relu_f32(acc1[4 * g + i]), part[1]);
                 }
             }
-            if (KIND == LAY_RELU || KIND == LAY_LATENT) {
-                out[2 * ob + s][0] = t0;
-                out[2 * ob + s][1] = t1;
+        } else {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                u32x4 t0, t1;  // built whole, so the previous contents of out[] die here
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) {
+                    const int r = 8 * s + 2 * e2;  // rows r, r+1 (same 4-row group)
+                    uint32_t p0 = pack_bf16x2(acc0[r], acc0[r + 1]);
+                    uint32_t p1 = pack_bf16x2(acc1[r], acc1[r + 1]);
+                    if (KIND == LAY_RELU) {
+                        p0 = relu_bf16x2(p0);
+                        p1 = relu_bf16x2(p1);
+                    } else {  // latent: bf16 values (exact products with the bf16 reference)
+                        const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
+                        if (KIND == LAY_LATENT_OUT) {
+                            const int64_t n0 = row0 + (lane & 31), n1 = n0 + 32;
+                            if (ok[0]) {
+                                lat_out[n0 * kH + ic + h4] = bf_lo(p0);
+                                lat_out[n0 * kH + ic + h4 + 1] = bf_hi(p0);
+                            }
+                            if (ok[1]) {
+                                lat_out[n1 * kH + ic + h4] = bf_lo(p1);
+                                lat_out[n1 * kH + ic + h4 + 1] = bf_hi(p1);
+                            }
+                        } else {
+                            const f32x2 rv = *reinterpret_cast<const f32x2 *>(ref_h + ic);
+                            const float ra = rv[0], rb = rv[1];
+                            p0 = pack_bf16x2(bf_lo(p0) * ra, bf_hi(p0) * rb);
+                            p1 = pack_bf16x2(bf_lo(p1) * ra, bf_hi(p1) * rb);
+                        }
+                    }
+                    t0[e2] = p0;
+                    t1[e2] = p1;
+                }
+                if (KIND == LAY_RELU || KIND == LAY_LATENT) {
+                    out[2 * ob + s][0] = __builtin_bit_cast(bf16x8, t0);
+                    out[2 * ob + s][1] = __builtin_bit_cast(bf16x8, t1);
+                }
             }
         }
         // keep the scheduler from hoisting the next block's operand loads above
