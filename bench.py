@@ -54,6 +54,8 @@ def _parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--train-steps", type=int, default=PREP_TRAIN_STEPS,
                     help="learned-field training steps before timing")
+    ap.add_argument("--mi-train-steps", type=int, default=PREP_TRAIN_STEPS,
+                    help="training steps of the second learned field (KSG-MI targets)")
     ap.add_argument("--only", default=None,
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
                          "targets, train_step, ndf_field) W+K times and exit")
@@ -145,6 +147,29 @@ def main():
     final_loss = loss.item()
     ndf.ndf_net_quantize(net, P, ndf.NDF_PREC_BF16, qp)
     step_no = [n_train]
+
+    # one network per measure: a second field trained on KSG-MI targets (same
+    # architecture, so its inference cost is the timed ndf_field row)
+    n_mi = 0 if (a.only or a.no_accuracy) else a.mi_train_steps
+    out_mi = None
+    mi_train = None
+    if n_mi > 0:
+        log(f"bench: training the KSG-MI learned field ({n_mi} steps)")
+        P_mi = torch.empty(lay.n_floats, device=dev)
+        opt_mi = torch.empty(2 * lay.n_floats, device=dev)
+        ndf.ndf_net_init(net, P_mi, opt_mi, 2321)
+        t0 = time.time()
+        for s in range(1, n_mi + 1):
+            pr = torch.as_tensor(gen.random_pairs(V, B_PAIRS, seed=6000 + s), device=dev)
+            ndf.ndf_ksg_mi_pairs(ens, 0, 0, pr, K_NN, t_ksg, None, ws_kp)
+            ndf.ndf_train_step(net, P_mi, opt_mi, s, pr, t_ksg, LR, loss, ws_t)
+        torch.cuda.synchronize()
+        mi_train = {"steps": n_mi, "seconds": time.time() - t0, "final_l1_loss": loss.item()}
+        qp_mi = torch.empty_like(qp)
+        ndf.ndf_net_quantize(net, P_mi, ndf.NDF_PREC_BF16, qp_mi)
+        out_mi = torch.empty((1, V), device=dev)
+        ndf.ndf_infer_field(net, qp_mi, ndf.NDF_PREC_BF16, [ref], out_mi, ws_i)
+        del P_mi, opt_mi
 
     stream = torch.cuda.current_stream()
     rows = ["prepare", "pearson_fp32", "pearson_b64", "ksg_field", "targets", "train_step",
@@ -280,15 +305,17 @@ def main():
         "dominant_kernel": dominant,
         "rooflines": roof,
         "training": {"steps_before_timing": n_train, "seconds": train_s,
-                     "final_l1_loss": final_loss, "lr": LR, "batch": B_PAIRS},
+                     "final_l1_loss": final_loss, "lr": LR, "batch": B_PAIRS,
+                     "ksg_mi_field": mi_train},
     }
     result["roofline"] = _roofline_of(dominant, roof, med, N, V)
 
     if not a.no_accuracy:
-        acc, sample, r_o = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg)
+        acc, sample, r_o, mi_o = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi,
+                                           refs64, cfg)
         result["accuracy"] = acc
         log("bench: gain of the trained field over the method without it")
-        result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, out_n, med, log)
+        result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(ens, cfg, lay, log)
     print(json.dumps(result))
@@ -320,7 +347,10 @@ def _roofline_of(dominant, roof, med, N, V):
     return r
 
 
-def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg):
+N_MI_SAMPLE = 400   # vertices of the oracle KSG-MI comparison (brute force on the host)
+
+
+def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi, refs64, cfg):
     """Errors of the timed outputs against the FP64 oracle on sampled vertices."""
     import torch
     import gen
@@ -331,13 +361,19 @@ def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg):
     xs = ens.x[0][:, idx].cpu().numpy()
     xr = ens.x[0][:, cfg.ref_v].cpu().numpy()
     r_o = direct.pearson_field(xr, xs)
-    mi_o = direct.ksg_field(xr, xs[:, :400], K_NN)
+    mi_o = direct.ksg_field(xr, xs[:, :N_MI_SAMPLE], K_NN)
     p = out_p[0, idx].cpu().numpy()
     b0 = out_b[0, idx].cpu().numpy()
-    k = out_k[0, idx[:400]].cpu().numpy()
+    k = out_k[0, idx[:N_MI_SAMPLE]].cpu().numpy()
     n = out_n[0, idx].cpu().numpy()
     n8 = out_n8[0, idx].cpu().numpy()
+    extra = {}
+    if out_mi is not None:
+        m = out_mi[0, idx[:N_MI_SAMPLE]].cpu().numpy()
+        extra = {"ndf_mi_vs_oracle_mae_400": float(np.mean(np.abs(m - mi_o))),
+                 "ndf_mi_vs_oracle_max_abs_err_400": float(np.max(np.abs(m - mi_o)))}
     return {
+        **extra,
         "sample_vertices": int(len(sample)),
         "pearson_fp32_max_abs_err": float(np.max(np.abs(p - r_o))),
         "pearson_split_bf16_max_abs_err": float(np.max(np.abs(b0 - r_o))),
@@ -348,10 +384,10 @@ def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, refs64, cfg):
         "ndf_fp8_vs_ndf_bf16_max_abs_diff": float(np.max(np.abs(n8 - n))),
         "population_rho_mae_of_oracle": float(np.mean(np.abs(
             r_o - gen.population_rho(cfg, np.full(len(sample), cfg.ref_v), sample)))),
-    }, sample, r_o
+    }, sample, r_o, mi_o
 
 
-def _gain(ens, cfg, net, lay, sample, r_o, out_n, med, log):
+def _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log):
     """What the trained field gains over the method without it, on the sampled
     vertices against the FP64 oracle: the untrained (initialised) field, the best
     constant predictor, and the direct Pearson estimator with its members cut
@@ -375,6 +411,7 @@ def _gain(ens, cfg, net, lay, sample, r_o, out_n, med, log):
     y0 = torch.empty((1, V), device="cuda")
     ndf.ndf_infer_field(net, qp0, ndf.NDF_PREC_BF16, [cfg.ref_v], y0, ws_i)
     out["ndf_untrained_mae"] = mae(y0[0, idx].cpu().numpy())
+    y0_mi = y0[0, idx[:N_MI_SAMPLE]].cpu().numpy()
     del P0, opt0, qp0, ws_i, y0
 
     # members of the equal-time direct estimator: its cost is linear in N
@@ -398,6 +435,34 @@ def _gain(ens, cfg, net, lay, sample, r_o, out_n, med, log):
     out["equal_time_direct_pearson"] = {
         "members": m_eq, "ms_per_field": float(np.median(ms)),
         "mae": mae(y[0, idx].cpu().numpy())}
+    del sub, ws, y
+
+    if out_mi is not None:
+        # KSG-MI: its direct cost does not fall to the learned field's even at a
+        # handful of members; report the smallest sensible member count instead
+        mae_mi = lambda z: float(np.mean(np.abs(z - mi_o)))  # noqa: E731
+        m_few = 16
+        sub = ndf.Ensemble(ens.x[:, :m_few], cfg.nx, cfg.ny, cfg.nz)
+        ndf.ndf_prepare(sub)
+        ws = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_KSG_FIELD, sub, None, 1, 0),
+                         dtype=torch.uint8, device="cuda")
+        y = torch.empty((1, V), device="cuda")
+        ms = []
+        for it in range(4):
+            ev0.record(stream)
+            ndf.ndf_ksg_mi_field(sub, 0, 0, [cfg.ref_v], K_NN, y, None, ws)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            if it >= 1:
+                ms.append(ev0.elapsed_time(ev1))
+        out["ksg_mi"] = {
+            "ndf_trained_mae": mae_mi(out_mi[0, idx[:N_MI_SAMPLE]].cpu().numpy()),
+            "ndf_untrained_mae": mae_mi(y0_mi),
+            "best_constant_mae": mae_mi(np.full_like(mi_o, np.median(mi_o))),
+            "direct_few_members": {"members": m_few, "ms_per_field": float(np.median(ms)),
+                                   "mae": mae_mi(y[0, idx[:N_MI_SAMPLE]].cpu().numpy())},
+            "sample_vertices": N_MI_SAMPLE}
+        del sub, ws, y
     log(f"bench: gain {out}")
     return out
 

@@ -238,13 +238,16 @@ enum { LAY_RELU = 0, LAY_LATENT = 1, LAY_HEAD = 2, LAY_LATENT_OUT = 3 };
 typedef __attribute__((ext_vector_type(2))) short s16x2;
 typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 
-// Two floats -> packed bf16 pair, round to nearest even: the two-source form of
-// v_cvt_pk_bf16_f32 (the compiler otherwise converts each value on its own and
-// merges the halves with a v_perm).
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// Two floats -> packed bf16 pair (a in the low half), round to nearest even.  A
+// two-element vector conversion maps to the two-source v_cvt_pk_bf16_f32; the
+// scalar form would convert each value on its own and merge the halves.  (No
+// inline asm here: the compiler does not see an asm statement's reads of MFMA
+// results and would not insert the wait states they need.)
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-    uint32_t r;
-    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 // ReLU of a packed bf16 pair: a bf16 is negative iff its sign bit is set, so a
 // signed 16-bit max with 0 (one v_pk_max_i16) clamps both halves.

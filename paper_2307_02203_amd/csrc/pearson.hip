@@ -93,9 +93,15 @@ __global__ void pearson_afrag_kernel(const float *__restrict__ zr, int kpad, int
     }
 }
 
-constexpr int kGemmJB = 4;  // 32-vertex blocks per wave -> 128 vertices per wave
+// Each wave computes NIB 32-ref blocks x 64 vertices.  Lane l loads the vertex
+// pair 2 (l%32), 2 (l%32) + 1 of its member rows as one 8-byte access, so tile
+// t (0, 1) column j is vertex v0 + 2 j + t: a 256-byte contiguous segment per
+// member row and lane half.  The next k-step's loads are issued before the
+// current one's MFMAs (two k-steps in flight per wave), and the per-wave
+// register footprint is kept small enough for three waves per SIMD.
+constexpr int kGemmVerts = 64;
 
-template <int NIB>
+template <int NIB, bool VEC>
 __global__ __launch_bounds__(256) void pearson_gemm_kernel(
     const float *__restrict__ x, const double *__restrict__ mean,
     const double *__restrict__ inv_std, int N, int64_t V, const bf16x8 *__restrict__ afrag,
@@ -105,72 +111,95 @@ __global__ __launch_bounds__(256) void pearson_gemm_kernel(
     const int h = lane >> 5;
     const int jl = lane & 31;
     const int ib0 = blockIdx.y * NIB;  // first 32-ref block of this group
-    const int64_t vbase = ((int64_t)blockIdx.x * 4 + wave) * (32 * kGemmJB);
+    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * kGemmVerts + 2 * jl;  // tile t: v0 + t
 
-    float mu[kGemmJB], is[kGemmJB];
-    int64_t vj[kGemmJB];
-    bool ok[kGemmJB];
+    float mu[2], is[2];
+    bool ok[2];
 #pragma unroll
-    for (int jb = 0; jb < kGemmJB; ++jb) {
-        vj[jb] = vbase + jb * 32 + jl;
-        ok[jb] = vj[jb] < V;
-        const int64_t vv = ok[jb] ? vj[jb] : 0;
-        mu[jb] = (float)mean[vv];
-        is[jb] = (float)inv_std[vv];
+    for (int t = 0; t < 2; ++t) {
+        ok[t] = v0 + t < V;
+        const int64_t vv = ok[t] ? v0 + t : 0;
+        mu[t] = (float)mean[vv];
+        is[t] = (float)inv_std[vv];
     }
 
-    f32x16 acc[NIB][kGemmJB];
+    f32x16 acc[NIB][2];
 #pragma unroll
     for (int i = 0; i < NIB; ++i)
 #pragma unroll
-        for (int jb = 0; jb < kGemmJB; ++jb)
-            for (int r = 0; r < 16; ++r) acc[i][jb][r] = 0.f;
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][t][r] = 0.f;
 
-    const int ksteps = (N + 15) / 16;
-    for (int ks = 0; ks < ksteps; ++ks) {
-        const int mb = ks * 16 + 8 * h;
-        bf16x8 bhi[kGemmJB], blo[kGemmJB];
+    // raw member values of one k-step: xv[e][t] = x[m0 + e][v0 + t]
+    auto load = [&](int ks, float (&xv)[8][2]) {
+        const int m0 = ks * 16 + 8 * h;
 #pragma unroll
-        for (int jb = 0; jb < kGemmJB; ++jb) {
-            float zv[8];
+        for (int e = 0; e < 8; ++e) {
+            const int m = m0 + e;
+            const float *row = x + (int64_t)(m < N ? m : 0) * V;
+            if (VEC) {
+                f32x2 a = {0.f, 0.f};
+                if (m < N && ok[0]) a = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(row + v0));
+                xv[e][0] = a[0];
+                xv[e][1] = a[1];
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int m = mb + e;
-                float a = 0.f;
-                if (ok[jb] && m < N) a = __builtin_nontemporal_load(x + (int64_t)m * V + vj[jb]);
-                zv[e] = (ok[jb] && m < N) ? (a - mu[jb]) * is[jb] : 0.f;
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint16_t hb = f2bf_bits(zv[e]);
-                const uint16_t lb = f2bf_bits(zv[e] - bf_bits2f(hb));
-                bhi[jb][e] = __builtin_bit_cast(__bf16, hb);
-                blo[jb][e] = __builtin_bit_cast(__bf16, lb);
+                for (int t = 0; t < 2; ++t)
+                    xv[e][t] = (m < N && ok[t]) ? __builtin_nontemporal_load(row + v0 + t) : 0.f;
             }
         }
+    };
+
+    const int ksteps = (N + 15) / 16;
+    float cur[8][2], nxt[8][2];
+    load(0, cur);
+    for (int ks = 0; ks < ksteps; ++ks) {
+        if (ks + 1 < ksteps) load(ks + 1, nxt);
+        const int m0 = ks * 16 + 8 * h;
+        bf16x8 bhi[2], blo[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float z = (ok[t] && m0 + e < N) ? (cur[e][t] - mu[t]) * is[t] : 0.f;
+                const __bf16 hb = f2bf(z);
+                bhi[t][e] = hb;
+                blo[t][e] = f2bf(z - (float)hb);
+            }
 #pragma unroll
         for (int i = 0; i < NIB; ++i) {
             const int64_t fb = (((int64_t)ks * n_ib_total + ib0 + i) * 2) * 64;
             const bf16x8 ahi = afrag[fb + lane];
             const bf16x8 alo = afrag[fb + 64 + lane];
 #pragma unroll
-            for (int jb = 0; jb < kGemmJB; ++jb) {
-                acc[i][jb] = mfma32(ahi, bhi[jb], acc[i][jb]);
-                acc[i][jb] = mfma32(ahi, blo[jb], acc[i][jb]);
-                acc[i][jb] = mfma32(alo, bhi[jb], acc[i][jb]);
+            for (int t = 0; t < 2; ++t) {
+                acc[i][t] = mfma32(ahi, bhi[t], acc[i][t]);
+                acc[i][t] = mfma32(ahi, blo[t], acc[i][t]);
+                acc[i][t] = mfma32(alo, bhi[t], acc[i][t]);
             }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            cur[e][0] = nxt[e][0];
+            cur[e][1] = nxt[e][1];
         }
     }
     const float invN = 1.0f / (float)N;
 #pragma unroll
     for (int i = 0; i < NIB; ++i)
 #pragma unroll
-        for (int jb = 0; jb < kGemmJB; ++jb) {
-            if (!ok[jb]) continue;
+        for (int r = 0; r < 16; ++r) {
+            const int ref = (ib0 + i) * 32 + d_row(r, lane);
+            if (ref >= n_ref) continue;
+            float *o = out + (int64_t)ref * V + v0;
+            if (VEC && ok[0]) {
+                f32x2 y = {acc[i][0][r] * invN, acc[i][1][r] * invN};
+                *reinterpret_cast<f32x2 *>(o) = y;
+            } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int ref = (ib0 + i) * 32 + d_row(r, lane);
-                if (ref < n_ref) out[(int64_t)ref * V + vj[jb]] = acc[i][jb][r] * invN;
+                for (int t = 0; t < 2; ++t)
+                    if (ok[t]) o[t] = acc[i][t][r] * invN;
             }
         }
 }
@@ -248,14 +277,27 @@ int launch_pearson_field(const ndf_ensemble *e, int var_ref, int var_qry, const 
     uint16_t *frag = (uint16_t *)w;
     hipLaunchKernelGGL(pearson_afrag_kernel, dim3(kpad / 16, n_ib), dim3(64), 0, st, zr, kpad,
                        n_ib, n_ref, frag);
-    const unsigned nbx = (unsigned)ceil_div(V, 4 * 32 * kGemmJB);
-    if (n_ref <= 32)
-        hipLaunchKernelGGL(pearson_gemm_kernel<1>, dim3(nbx, 1), dim3(256), 0, st, xq, mq, iq, N,
-                           V, (const bf16x8 *)frag, n_ib, n_ref, out);
-    else
-        hipLaunchKernelGGL(pearson_gemm_kernel<2>, dim3(nbx, (unsigned)ceil_div(n_ref, 64)),
-                           dim3(256), 0, st, xq, mq, iq, N, V, (const bf16x8 *)frag, n_ib, n_ref,
-                           out);
+    const unsigned nbx = (unsigned)ceil_div(V, 4 * kGemmVerts);
+    // 8-byte accesses need every member row 8-byte aligned: V even
+    const bool vec = (V % 2) == 0;
+    const bf16x8 *af = (const bf16x8 *)frag;
+    if (n_ref <= 32) {
+        const dim3 g(nbx, 1);
+        if (vec)
+            hipLaunchKernelGGL((pearson_gemm_kernel<1, true>), g, dim3(256), 0, st, xq, mq, iq, N,
+                               V, af, n_ib, n_ref, out);
+        else
+            hipLaunchKernelGGL((pearson_gemm_kernel<1, false>), g, dim3(256), 0, st, xq, mq, iq, N,
+                               V, af, n_ib, n_ref, out);
+    } else {
+        const dim3 g(nbx, (unsigned)ceil_div(n_ref, 64));
+        if (vec)
+            hipLaunchKernelGGL((pearson_gemm_kernel<2, true>), g, dim3(256), 0, st, xq, mq, iq, N,
+                               V, af, n_ib, n_ref, out);
+        else
+            hipLaunchKernelGGL((pearson_gemm_kernel<2, false>), g, dim3(256), 0, st, xq, mq, iq, N,
+                               V, af, n_ib, n_ref, out);
+    }
     return status_of_launch();
 }
 
