@@ -339,12 +339,40 @@ def _roofline_of(dominant, roof, med, N, V):
         r["frac"] = r["achieved"] / r["peak"]
         r["note"] = ("peak = brute-force pair evaluations/s at the 32-bit VALU peak "
                      f"({PEAK_ALU_TOPS:.1f} T lane-ops/s / {KSG_OPS_PER_PAIR} ops); the kernel "
-                     "prunes the search in reference order, so frac > 1 is the pruning gain")
+                     "prunes the neighbour search, so frac > 1 is the pruning gain; its own "
+                     "VALU issue rate (rocprofv3 SQ_INSTS_VALU) is recorded in profiles/")
     else:
         r = {"bound": "mixed", "achieved": None, "peak": None, "unit": None, "frac": None}
     r["kernel"] = dominant
-    r["traffic"] = None
+    r["traffic"] = _measured_traffic(dominant)
     return r
+
+
+# HBM bytes per launch measured with rocprofv3 PMC counters (FETCH_SIZE, WRITE_SIZE,
+# scaled by a 1 GiB copy), recorded under profiles/ together with a hash of the
+# kernel source; reported only while the source still matches.
+_PMC_TRAFFIC = {
+    "ksg_field": ("profiles/pmc_ksg_field_paper_1760000v_1000m.txt",
+                  "paper_2307_02203_amd/csrc/ksg.hip"),
+}
+
+
+def _measured_traffic(row):
+    import hashlib
+    import re
+    if row not in _PMC_TRAFFIC:
+        return None
+    prof, src = (os.path.join(ROOT, f) for f in _PMC_TRAFFIC[row])
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"sha256 prefix at measurement: ([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    if not (m_sha and m_val) or not sha.startswith(m_sha.group(1)):
+        return None
+    return float(m_val.group(1))
 
 
 N_MI_SAMPLE = 400   # vertices of the oracle KSG-MI comparison (brute force on the host)

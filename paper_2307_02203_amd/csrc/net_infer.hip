@@ -33,7 +33,7 @@ struct QLayout {
     int64_t b4, b5, w6, b6;        // fp32
     // FP8 (OCP E4M3) copies of W2..W5 in 32x32x64 operand order + per-row scales
     int64_t q2[2], q3[2], q4, q5;  // fp8 fragments, 16 KB each
-    int64_t s2[2], s3[2], s4, s5;  // fp32 [128] output-channel scales
+    int64_t s2[2], s3[2], s4, s5;  // int32 [128] per-row E8M0 scale bytes
     int64_t total;
 };
 
@@ -96,6 +96,17 @@ size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec) {
 }
 
 // ----------------------------------------------------------- quantize ----
+// Exponent e of the E8M0 scale 2^e for a block whose largest magnitude is m >= 0:
+// the smallest e with m / 2^e <= 448 (the largest E4M3 value, 1.75 * 2^8),
+// read exactly from m's fields: with m = M * 2^E, M in [1, 2), e = E - 8 when
+// M <= 1.75, else E - 7.  Zero and subnormal m give the smallest scale.
+__device__ __forceinline__ int e4m3_block_exp(float m) {
+    const uint32_t b = __float_as_uint(m);
+    const int ex = (int)(b >> 23);
+    const int e = ex - 135 + ((b & 0x7fffffu) > 0x600000u ? 1 : 0);
+    return ex == 0 ? -126 : (e < -126 ? -126 : e);
+}
+
 __global__ void to_bf16_kernel(const float *__restrict__ src, int64_t n,
                                uint16_t *__restrict__ dst) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -121,19 +132,20 @@ __global__ void pack_frag_kernel(const float *__restrict__ W, int KIN, int permu
     }
 }
 
-// Per-output-row scale of W[128][128]: max_k |W[o][k]| / 448 (1 for an all-zero row).
-__global__ void row_scale_kernel(const float *__restrict__ W, float *__restrict__ sc) {
+// Per-output-row E8M0 scale byte of W[128][128]: 127 + e, 2^e the smallest power
+// of two with max_k |W[o][k]| / 2^e <= 448.
+__global__ void row_exp_kernel(const float *__restrict__ W, int *__restrict__ se) {
     const int o = threadIdx.x;  // 128 threads
     float m = 0.f;
     for (int k = 0; k < kH; ++k) m = fmaxf(m, fabsf(W[o * kH + k]));
-    sc[o] = m > 0.f ? m / 448.f : 1.f;
+    se[o] = 127 + e4m3_block_exp(m);
 }
 
 // FP8 A fragments of W[128][128] for MFMA 32x32x64: fragment (ob, kb) lane l byte t
-// holds W[32 ob + l%32][f] / sc[row] with f the feature that the previous layer's
-// output layout puts at logical k = 64 kb + 32 (l/32) + t:
+// holds W[32 ob + l%32][f] / 2^e[row] (exact: a power of two) with f the feature that
+// the previous layer's output layout puts at logical k = 64 kb + 32 (l/32) + t:
 //   f = 64 kb + 32 (t/16) + 8 ((t%16)/4) + 4 (l/32) + t%4.
-__global__ void pack_frag_fp8_kernel(const float *__restrict__ W, const float *__restrict__ sc,
+__global__ void pack_frag_fp8_kernel(const float *__restrict__ W, const int *__restrict__ se,
                                      uint32_t *__restrict__ frag) {
     const int n = kH * kH / 4;  // dwords
     for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < n; d += gridDim.x * blockDim.x) {
@@ -141,7 +153,7 @@ __global__ void pack_frag_fp8_kernel(const float *__restrict__ W, const float *_
         const int fi = d >> 9;  // ob*2 + kb
         const int ob = fi >> 1, kb = fi & 1;
         const int h = lane >> 5, row = 32 * ob + (lane & 31);
-        const float inv = 1.f / sc[row];
+        const float inv = __uint_as_float((uint32_t)(254 - se[row]) << 23);  // 2^-e
         float v[4];
         for (int b = 0; b < 4; ++b) {
             const int t = 4 * (d & 7) + b;
@@ -198,9 +210,9 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(1), 0, st, P + o.b6, 1, (float *)(Q + q.b6));
     // FP8 copies of the 128x128 layers (both precisions share one packed blob)
     auto fp8 = [&](const float *W, int64_t qoff, int64_t soff) {
-        hipLaunchKernelGGL(row_scale_kernel, dim3(1), dim3(kH), 0, st, W, (float *)(Q + soff));
+        hipLaunchKernelGGL(row_exp_kernel, dim3(1), dim3(kH), 0, st, W, (int *)(Q + soff));
         hipLaunchKernelGGL(pack_frag_fp8_kernel, dim3(16), dim3(256), 0, st, W,
-                           (const float *)(Q + soff), (uint32_t *)(Q + qoff));
+                           (const int *)(Q + soff), (uint32_t *)(Q + qoff));
     };
     for (int e = 0; e < c->n_enc; ++e) {
         fp8(P + o.W2[e], q.q2[e], q.s2[e]);
@@ -362,9 +374,9 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               float *__restrict__ out) {
     __shared__ bf16x8 s_w1[kFragW1];
     __shared__ bf16x8 s_w[4][kFragW];
-    __shared__ float s_b[5][kH];
-    __shared__ float s_w6[kH];
-    __shared__ float s_ref[kH];
+    __shared__ __attribute__((aligned(16))) float s_b[5][kH];
+    __shared__ __attribute__((aligned(16))) float s_w6[kH];
+    __shared__ __attribute__((aligned(16))) float s_ref[kH];
 
     const int tid = threadIdx.x;
     for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
@@ -450,41 +462,47 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
 
 
 // ------------------------------------------------------------ FP8 path ----
-// Layers 2..5 run as MFMA 32x32x64 on OCP E4M3 (MXFP8 style): weights carry a
-// per-output-row FP32 scale applied after the product; activations are split
-// per query into blocks of 32 features, each with its own power-of-two scale
-// (E8M0) that the scaled MFMA applies in hardware.  The first layer (32 inputs,
-// 6% of the work) stays BF16.  Block k = 64 kb + 32 h + t of a lane comes from
-// output blocks 2 kb (t < 16) and 2 kb + 1 (t >= 16) of the previous layer; the
-// packed weights absorb that order (see pack_frag_fp8_kernel).
+// Layers 2..5 run as MFMA 32x32x64 on OCP E4M3 with microscaling (MX): every
+// operand lane carries an E8M0 power-of-two scale for its 32 K-values, which
+// the scaled MFMA applies in hardware.
+//  * weights: per output row, 2^e with max|W_row| / 2^e <= 448 (the A operand
+//    lane of row i carries that row's scale), so accumulators come out in true
+//    units and start at the bias like the BF16 path;
+//  * activations: per query and 64-feature k-block, 2^e with max|a| / 2^e <=
+//    448 (the two lanes holding the block, l and l ^ 32, share it); the
+//    quantising conversion divides by the scale itself.
+// The first layer (32 inputs, 6% of the work) stays BF16.  Block k = 64 kb +
+// 32 h + t of a lane comes from output blocks 2 kb (t < 16) and 2 kb + 1
+// (t >= 16) of the previous layer; the packed weights absorb that order (see
+// pack_frag_fp8_kernel).
 typedef __attribute__((ext_vector_type(8))) int i32x8;
 
-__device__ __forceinline__ f32x16 mfma_fp8(const i32x8 &a, const i32x8 &b, int sb,
+__device__ __forceinline__ f32x16 mfma_fp8(const i32x8 &a, int sa, const i32x8 &b, int sb,
                                            const f32x16 &c) {
-    // A unscaled (E8M0 127 = 2^0); B scaled by 2^(sb - 127)
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, sb);
+    // A scaled by 2^(sa - 127), B by 2^(sb - 127)
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
 }
 
-// 32 values -> E4M3 with one power-of-two scale 2^e >= max|v| / 448.  The two
-// lanes that hold the two 32-blocks of one query's 64-feature k-block (l, l^32)
-// share the scale, so the scaled MFMA sees one scale per query and k-block.
-__device__ __forceinline__ void quant32(const float (&v)[32], i32x8 &out, int &sbyte) {
-    float m = 0.f;
-#pragma unroll
-    for (int t = 0; t < 32; ++t) m = fmaxf(m, fabsf(v[t]));
-    m = fmaxf(m, __shfl_xor(m, 32, 64));
-    // e = ceil(log2(m / 448)) from the float's fields, branch-free (m = 0 -> -126)
-    const uint32_t u = __float_as_uint(m * (1.0f / 448.0f));
-    const int ex = (int)((u >> 23) & 0xff);
-    int e = ex - 127 + ((u & 0x7fffff) != 0 ? 1 : 0);
-    e = ex == 0 ? -126 : e;
-    e = e < -126 ? -126 : (e > 126 ? 126 : e);
-    const float inv = __uint_as_float((uint32_t)(127 - e) << 23);  // 2^-e
+// Two floats divided by the power of two s -> E4M3 pair into half HI of w.
+template <bool HI>
+__device__ __forceinline__ int cvt_fp8x2(int w, float a, float b, float s) {
+    const s16x2 old = __builtin_bit_cast(s16x2, w);
+    return __builtin_bit_cast(int, __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(old, a, b, s, HI));
+}
+
+// The 32 values of one lane (acc[0][r], acc[1][r] of one query half, in that
+// order after the epilogue map f) -> E4M3 bytes t = 16 o + r, and the block's
+// E8M0 byte.  mbits: the lane's max |value| as float bits (non-negative).
+template <typename F>
+__device__ __forceinline__ void quant_block(F f, int mbits, i32x8 &out, int &sbyte) {
+    mbits = max(mbits, __shfl_xor(mbits, 32, 64));
+    const int e = e4m3_block_exp(__int_as_float(mbits));
+    const float s = __uint_as_float((uint32_t)(e + 127) << 23);
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * d] * inv, v[4 * d + 1] * inv, 0, false);
-        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * d + 2] * inv, v[4 * d + 3] * inv, w, true);
-        out[d] = w;
+        const int o = d >> 2, r = 4 * (d & 3);
+        const int w = cvt_fp8x2<false>(0, f(o, r), f(o, r + 1), s);
+        out[d] = cvt_fp8x2<true>(w, f(o, r + 2), f(o, r + 3), s);
     }
     sbyte = e + 127;
 }
@@ -493,7 +511,7 @@ struct InferArgs8 {
     const uint16_t *grid[kL];
     const bf16x8 *w1;
     const i32x8 *q[4];    // W2..W5 fp8 fragments
-    const float *s[4];    // their row scales
+    const int *se[4];     // their per-row E8M0 bytes
     const float *b[5];
     const float *w6;
     const float *b6;
@@ -504,7 +522,7 @@ constexpr int kFrag8 = 4 * 2 * 64;  // i32x8 per 128x128 fp8 layer
 
 template <int KIND, bool BF16IN>
 __device__ __forceinline__ void dense_layer_fp8(
-    const bf16x8 *__restrict__ w16, const i32x8 *__restrict__ w8, const float *__restrict__ sw,
+    const bf16x8 *__restrict__ w16, const i32x8 *__restrict__ w8, const int *__restrict__ se,
     const float *__restrict__ bias, const float *__restrict__ ref, const float *__restrict__ w6,
     const bf16x8 (&in16)[2][2], const i32x8 (&in8)[2][2], const int (&sin)[2][2],
     i32x8 (&out8)[2][2], int (&sout)[2][2], float (&part)[2], float *__restrict__ lat_out,
@@ -513,29 +531,35 @@ __device__ __forceinline__ void dense_layer_fp8(
     const float *bias_h = bias + h4;
     const float *ref_h = ref + h4;
     const float *w6_h = w6 + h4;
-    const float *sw_h = sw + h4;
+    const int il = lane & 31;
     if (KIND == LAY_HEAD) {
-        // last layer: one output block and query block at a time, straight into
+        // last layer: one output block and query half at a time, straight into
         // the w6 dot product (keeps the register footprint of the head small)
 #pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
+        for (int ob = 0; ob < 4; ++ob) {
+            const int sa = se[32 * ob + il];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 f32x16 acc;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias_h + 32 * ob + 8 * g);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[4 * g + i] = bv[i];
+                }
 #pragma unroll
                 for (int kb = 0; kb < 2; ++kb)
-                    acc = mfma_fp8(w8[(ob * 2 + kb) * 64 + lane], in8[kb][q], sin[kb][q], acc);
+                    acc = mfma_fp8(w8[(ob * 2 + kb) * 64 + lane], sa, in8[kb][q], sin[kb][q], acc);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
-                    float x = fmaf(acc[r], sw_h[ic], bias_h[ic]);
-                    x = x > 0.f ? x : 0.f;
-                    part[q] = fmaf(w6_h[ic], x, part[q]);
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 wv = *reinterpret_cast<const f32x4 *>(w6_h + 32 * ob + 8 * g);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        part[q] = fmaf(wv[i], relu_f32(acc[4 * g + i]), part[q]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+        }
         return;
     }
 #pragma unroll
@@ -544,50 +568,78 @@ __device__ __forceinline__ void dense_layer_fp8(
 #pragma unroll
         for (int o = 0; o < 2; ++o)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[o][0][r] = acc[o][1][r] = 0.f;
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 bv =
+                    *reinterpret_cast<const f32x4 *>(bias_h + 32 * (2 * op + o) + 8 * g);
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-            for (int o = 0; o < 2; ++o) {
-                if (BF16IN) {
-                    const bf16x8 a = w16[((2 * op + o) * 2 + kb) * 64 + lane];
-                    acc[o][0] = mfma32(a, in16[kb][0], acc[o][0]);
-                    acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
-                } else {
-                    const i32x8 a = w8[((2 * op + o) * 2 + kb) * 64 + lane];
-                    acc[o][0] = mfma_fp8(a, in8[kb][0], sin[kb][0], acc[o][0]);
-                    acc[o][1] = mfma_fp8(a, in8[kb][1], sin[kb][1], acc[o][1]);
-                }
+                for (int i = 0; i < 4; ++i) acc[o][0][4 * g + i] = acc[o][1][4 * g + i] = bv[i];
             }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            float v[32];
+        for (int o = 0; o < 2; ++o) {
+            const int ob = 2 * op + o;
+            if (BF16IN) {
 #pragma unroll
-            for (int o = 0; o < 2; ++o)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int ob = 2 * op + o;
-                    const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
-                    float x = acc[o][q][r];
-                    if (!BF16IN) x *= sw_h[ic];
-                    x += bias_h[ic];
-                    if (KIND == LAY_RELU || KIND == LAY_HEAD) x = x > 0.f ? x : 0.f;
-                    if (KIND == LAY_LATENT || KIND == LAY_LATENT_OUT) x = bf2f(f2bf(x));
-                    if (KIND == LAY_LATENT_OUT) {
-                        if (ok[q]) lat_out[(row0 + 32 * q + (lane & 31)) * kH + ic + h4] = x;
-                    } else if (KIND == LAY_HEAD) {
-                        part[q] = fmaf(w6_h[ic], x, part[q]);
-                    } else if (KIND == LAY_LATENT) {
-                        x *= ref_h[ic];
-                    }
-                    v[16 * o + r] = x;
+                for (int kb = 0; kb < 2; ++kb) {
+                    const bf16x8 a = w16[(ob * 2 + kb) * 64 + lane];
+                    acc[o][0] = mfma32(a, in16[kb][0], acc[o][0]);
+                    acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
                 }
-            if (KIND == LAY_RELU || KIND == LAY_LATENT) quant32(v, out8[op][q], sout[op][q]);
+            } else {
+                const int sa = se[32 * ob + il];
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    const i32x8 a = w8[(ob * 2 + kb) * 64 + lane];
+                    acc[o][0] = mfma_fp8(a, sa, in8[kb][0], sin[kb][0], acc[o][0]);
+                    acc[o][1] = mfma_fp8(a, sa, in8[kb][1], sin[kb][1], acc[o][1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (KIND == LAY_LATENT_OUT) {
+                if (ok[q]) {
+                    float *dst = lat_out + (row0 + 32 * q + il) * kH + h4;
+#pragma unroll
+                    for (int o = 0; o < 2; ++o)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            dst[32 * (2 * op + o) + 8 * (r >> 2) + (r & 3)] = acc[o][q][r];
+                }
+            } else if (KIND == LAY_RELU) {
+                int mb = 0;
+#pragma unroll
+                for (int o = 0; o < 2; ++o)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        acc[o][q][r] = relu_f32(acc[o][q][r]);
+                        mb = max(mb, __float_as_int(acc[o][q][r]));
+                    }
+                quant_block([&](int o, int r) { return acc[o][q][r]; }, mb, out8[op][q],
+                            sout[op][q]);
+            } else {  // LAY_LATENT: product with the reference latent
+                int mb = 0;
+#pragma unroll
+                for (int o = 0; o < 2; ++o)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const f32x4 rv = *reinterpret_cast<const f32x4 *>(
+                            ref_h + 32 * (2 * op + o) + 8 * g);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float y = acc[o][q][4 * g + i] * rv[i];
+                            acc[o][q][4 * g + i] = y;
+                            mb = max(mb, __float_as_int(y) & 0x7fffffff);
+                        }
+                    }
+                quant_block([&](int o, int r) { return acc[o][q][r]; }, mb, out8[op][q],
+                            sout[op][q]);
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
+// MODE 0: field; MODE 1: latents of the vertices in qlist (FP32).
 template <int MODE>
 __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   const int64_t *__restrict__ qlist,
@@ -596,17 +648,17 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   float *__restrict__ out) {
     __shared__ bf16x8 s_w1[kFragW1];
     __shared__ i32x8 s_q[4][kFrag8];
-    __shared__ float s_s[4][kH];
-    __shared__ float s_b[5][kH];
-    __shared__ float s_w6[kH];
-    __shared__ float s_ref[kH];
+    __shared__ int s_e[4][kH];
+    __shared__ __attribute__((aligned(16))) float s_b[5][kH];
+    __shared__ __attribute__((aligned(16))) float s_w6[kH];
+    __shared__ __attribute__((aligned(16))) float s_ref[kH];
 
     const int tid = threadIdx.x;
     for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w1[i];
     const int nlay = MODE == 0 ? 4 : 2;
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L][i];
-    for (int i = tid; i < 4 * kH; i += kInferThreads) s_s[i / kH][i % kH] = A.s[i / kH][i % kH];
+    for (int i = tid; i < 4 * kH; i += kInferThreads) s_e[i / kH][i % kH] = A.se[i / kH][i % kH];
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
@@ -665,19 +717,21 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         float part[2] = {0.f, 0.f};
         dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8, sb,
                                         a8, sa, part, nullptr, row0, ok, lane, h4);
-        dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_s[0], s_b[1], s_ref, s_w6, g16, a8,
-                                         sa, b8, sb, part, nullptr, row0, ok, lane, h4);
         if (MODE == 1) {
-            dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_s[1], s_b[2], s_ref, s_w6,
+            dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16,
+                                             a8, sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+            dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6,
                                                    g16, b8, sb, a8, sa, part, out, row0, ok, lane,
                                                    h4);
             continue;
         }
-        dense_layer_fp8<LAY_LATENT, false>(nullptr, s_q[1], s_s[1], s_b[2], s_ref, s_w6, g16, b8,
-                                           sb, a8, sa, part, nullptr, row0, ok, lane, h4);
-        dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[2], s_s[2], s_b[3], s_ref, s_w6, g16, a8,
+        dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16, a8,
                                          sa, b8, sb, part, nullptr, row0, ok, lane, h4);
-        dense_layer_fp8<LAY_HEAD, false>(nullptr, s_q[3], s_s[3], s_b[4], s_ref, s_w6, g16, b8,
+        dense_layer_fp8<LAY_LATENT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6, g16, b8,
+                                           sb, a8, sa, part, nullptr, row0, ok, lane, h4);
+        dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[2], s_e[2], s_b[3], s_ref, s_w6, g16, a8,
+                                         sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+        dense_layer_fp8<LAY_HEAD, false>(nullptr, s_q[3], s_e[3], s_b[4], s_ref, s_w6, g16, b8,
                                          sb, a8, sa, part, nullptr, row0, ok, lane, h4);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -695,10 +749,10 @@ static InferArgs8 make_args8(const ndf_net_config *c, const QLayout &q, const ch
     a.q[1] = (const i32x8 *)(Q + q.q3[e]);
     a.q[2] = (const i32x8 *)(Q + q.q4);
     a.q[3] = (const i32x8 *)(Q + q.q5);
-    a.s[0] = (const float *)(Q + q.s2[e]);
-    a.s[1] = (const float *)(Q + q.s3[e]);
-    a.s[2] = (const float *)(Q + q.s4);
-    a.s[3] = (const float *)(Q + q.s5);
+    a.se[0] = (const int *)(Q + q.s2[e]);
+    a.se[1] = (const int *)(Q + q.s3[e]);
+    a.se[2] = (const int *)(Q + q.s4);
+    a.se[3] = (const int *)(Q + q.s5);
     a.b[0] = (const float *)(Q + q.b1[e]);
     a.b[1] = (const float *)(Q + q.b2[e]);
     a.b[2] = (const float *)(Q + q.b3[e]);
