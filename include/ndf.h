@@ -135,8 +135,12 @@ int ndf_ksg_mi_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
 /* Direct estimates for B vertex pairs (training targets of Eq. 3, Sec. 4.3):
  * out[b] = r or MI between e^{var_a}(pairs[b][0]) and e^{var_b}(pairs[b][1]),
  * with the definitions of ndf_pearson_field / ndf_ksg_mi_field.  pairs
- * int64[B][2] (device).  KSG: counts (nullable) int32[B][2][N] in member order;
- * ws of ndf_workspace_bytes(NDF_OP_KSG_PAIRS, ...) bytes. */
+ * int64[B][2] (device); a pair with an index outside [0, V) gives NaN.  Both
+ * read the vertex-major codes of ndf_prepare (one contiguous row per vertex):
+ * Pearson's r is invariant to the per-vertex affine map that defines a code,
+ * and the rounding of the codes moves r by less than 1e-6.  KSG: counts
+ * (nullable) int32[B][2][N] in member order; ws of
+ * ndf_workspace_bytes(NDF_OP_KSG_PAIRS, ...) bytes. */
 int ndf_pearson_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
                       const int64_t *pairs, int64_t B, float *out, void *stream);
 int ndf_ksg_mi_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,

@@ -64,23 +64,54 @@ __device__ void block_bitonic_sort(T *a, int P) {
     }
 }
 
-// Number of entries < val among the first n of an ascending array.
-template <int STRIDE>
-__device__ __forceinline__ int count_less(const int *a, int n, int hp, int val) {
-    int pos = 0;
-    for (int s = hp; s > 0; s >>= 1)
-        if (pos + s <= n && a[(pos + s - 1) * STRIDE] < val) pos += s;
-    return pos;
+// Marginal counts of one sample with k-th distance eps > 0: entries of the sorted
+// x codes (xo[].x) and of the sorted y codes (yo[].x) strictly inside
+// (v - eps, v + eps), minus the sample itself.  The four lower-bound binary
+// searches advance in lockstep, so their LDS reads are in flight together; the
+// probe index is clamped into [0, N) and a probe past N never advances.
+__device__ __forceinline__ void marginal_counts(const int2 *xo, const int2 *yo, int N, int hp,
+                                                int2 mxy, int eps, int &nx, int &ny) {
+    const int val[4] = {mxy.x + eps, mxy.x - eps + 1, mxy.y + eps, mxy.y - eps + 1};
+    int pos[4] = {0, 0, 0, 0};
+    for (int st = hp; st > 0; st >>= 1) {
+        int c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = (i < 2 ? xo : yo)[min(pos[i] + st, N) - 1].x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (pos[i] + st <= N && c[i] < val[i]) pos[i] += st;
+    }
+    nx = pos[0] - pos[1] - 1;
+    ny = pos[2] - pos[3] - 1;
 }
 
 constexpr int kPad = 4;             // sentinel samples on each side of the x order
 constexpr int kFar = 1 << 28;       // sentinel x distance: beyond any code difference (< 2^24)
 
+// v_med3_i32: the middle of three signed integers.  With lo <= hi it is d
+// clamped to [lo, hi] in one instruction (the compiler forms it only for
+// constant bounds).  Operands are plain VALU results, so the asm needs no wait
+// states.
+__device__ __forceinline__ int med3_i32(int d, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(d), "v"(lo), "v"(hi));
+    return r;
+}
+
+// |a - b| of two codes (both in [0, 2^24)) in one v_sad_u32.
+__device__ __forceinline__ int absdiff_u32(int a, int b) {
+    int r;
+    asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 template <int K>
 __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
-    // best ascending; keep the K smallest of best + {d} (ties kept with multiplicity)
+    // best ascending; keep the K smallest of best + {d} (ties kept with
+    // multiplicity): best[t] = min(best[t], max(best[t - 1], d)) = d clamped
+    // to [best[t - 1], best[t]]
 #pragma unroll
-    for (int t = K - 1; t > 0; --t) best[t] = min(best[t], max(best[t - 1], d));
+    for (int t = K - 1; t > 0; --t) best[t] = med3_i32(d, best[t - 1], best[t]);
     best[0] = min(best[0], d);
 }
 
@@ -90,8 +121,9 @@ __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
 //   perm[p] = member of x-order sample p; epsL = N ints of LDS scratch.
 // Returns the FP64 sum of H_nx + H_ny over all samples.
 //
-// Walk phase: the x order is dealt to the waves in chunks of 64 samples, round
-// robin.  A lane walks one sample at a time and takes the wave's next unclaimed
+// Walk phase: first every sample's walk order and start position are computed
+// with all lanes busy.  Then the x order is dealt to the waves in chunks of 64
+// samples, round robin.  A lane walks one sample at a time and takes the wave's next unclaimed
 // sample as soon as its walk ends (claims are handed out in lane order from a
 // wave-uniform counter), so short and long walks do not wait for each other.
 // A walk takes 4 samples per side per step; a side stops once the farthest of
@@ -121,15 +153,23 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
 #pragma unroll
     for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
 
-    auto start = [&](int pp) {
-        const int2 mxy = xo[pp];
+    // Every sample's walk order and start position, with all lanes busy:
+    // epsL[p] = position | (walk in y order) << 16 until the walk of p ends.
+    for (int pp = tid; pp < N; pp += kKsgThreads) {
         const int q = yrank[pp];
         // spread of the 2k nearest codes in each order: walk the sparser one
         const int sx = xo[min(pp + K, N - 1)].x - xo[max(pp - K, 0)].x;
         const int sy = yo[min(q + K, N - 1)].x - yo[max(q - K, 0)].x;
-        const bool walk_y = sy > sx;
+        epsL[pp] = sy > sx ? (q | 0x10000) : pp;
+    }
+    __syncthreads();
+
+    auto start = [&](int pp) {
+        const int2 mxy = xo[pp];
+        const int info = epsL[pp];
+        const bool walk_y = info >= 0x10000;
         A = walk_y ? yo : xo;
-        const int pos = walk_y ? q : pp;
+        const int pos = info & 0xffff;
         me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
         jl = pos - 1;
         jr = pos + 1;
@@ -150,7 +190,8 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
 #pragma unroll
                 for (int u = 0; u < 4; ++u) c[u] = A[jl - u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) insert_k<K>(best, max(me.x - c[u].x, abs(me.y - c[u].y)));
+                for (int u = 0; u < 4; ++u)
+                    insert_k<K>(best, max(me.x - c[u].x, absdiff_u32(me.y, c[u].y)));
                 al = c[3].x != -kFar && (me.x - c[3].x) < best[K - 1];
                 jl -= 4;
             }
@@ -159,7 +200,8 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
 #pragma unroll
                 for (int u = 0; u < 4; ++u) c[u] = A[jr + u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) insert_k<K>(best, max(c[u].x - me.x, abs(me.y - c[u].y)));
+                for (int u = 0; u < 4; ++u)
+                    insert_k<K>(best, max(c[u].x - me.x, absdiff_u32(me.y, c[u].y)));
                 ar = c[3].x != kFar && (c[3].x - me.x) < best[K - 1];
                 jr += 4;
             }
@@ -189,13 +231,7 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         const int2 mxy = xo[pp];
         const int eps = epsL[pp];
         int nx = 0, ny = 0;
-        if (eps > 0) {
-            // samples with value in (v - eps, v + eps), minus the sample itself
-            nx = count_less<2>(&xo[0].x, N, hp, mxy.x + eps) -
-                 count_less<2>(&xo[0].x, N, hp, mxy.x - eps + 1) - 1;
-            ny = count_less<2>(&yo[0].x, N, hp, mxy.y + eps) -
-                 count_less<2>(&yo[0].x, N, hp, mxy.y - eps + 1) - 1;
-        }
+        if (eps > 0) marginal_counts(xo, yo, N, hp, mxy, eps, nx, ny);
         acc += H[nx] + H[ny];
         if (cnt) {
             const int m = perm[pp];
@@ -212,27 +248,163 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     return total;
 }
 
-// The y order from a complete x order: sort (y, x position) keys in the yo
-// region, convert them in place to (y, x) and record each sample's y rank.
-__device__ __forceinline__ void build_y_order(int2 *xo, int2 *yo, uint16_t *yrank, int N, int P) {
+// Ascending bitonic sort of 256 E keys held E per thread in registers (thread t
+// holds keys E t .. E t + E - 1).  Compare-exchange partners closer than E are in
+// the thread's own registers, partners up to 64 E apart are in the same wave
+// (lane shuffles), and only the strides of 64 E and more go through LDS (xchg,
+// 256 E keys), so a sort of 1024 keys takes 3 workgroup barriers instead of 55.
+template <int E>
+__device__ __forceinline__ void block_sort_regs(unsigned long long (&k)[E],
+                                                unsigned long long *xchg) {
     const int tid = threadIdx.x;
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);
-    for (int p = tid; p < P; p += kKsgThreads)
-        keys[p] = p < N ? (((unsigned long long)(uint32_t)xo[p].y) << 32) | (unsigned)p : ~0ull;
-    __syncthreads();
-    block_bitonic_sort(keys, P);
-    for (int q = tid; q < N; q += kKsgThreads) {
-        const unsigned long long key = keys[q];
-        const int p = (int)(key & 0xffffffffu);
-        yo[q] = make_int2((int)(key >> 32), xo[p].x);
-        yrank[p] = (uint16_t)q;
+    constexpr int PT = kKsgThreads * E;
+    for (int size = 2; size <= PT; size <<= 1) {
+        for (int stride = size >> 1; stride >= E; stride >>= 1) {
+            const bool cross = stride >= 64 * E;
+            if (cross) {
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < E; ++j) xchg[E * tid + j] = k[j];
+                __syncthreads();
+            }
+            // the lower index of a pair keeps the smaller key in an ascending
+            // block; stride >= E, so that is the same for all E keys of a thread
+            const bool keep_min = ((E * tid & stride) == 0) == ((E * tid & size) == 0);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int i = E * tid + j;
+                const unsigned long long o =
+                    cross ? xchg[i ^ stride] : __shfl_xor(k[j], stride / E, kWave);
+                // equal keys are interchangeable, so one comparison decides
+                k[j] = ((o < k[j]) == keep_min) ? o : k[j];
+            }
+        }
+#pragma unroll
+        for (int st = E / 2; st >= 1; st >>= 1) {
+            if (st >= size) continue;
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int jp = j ^ st;
+                if (jp < j) continue;
+                const bool up = ((E * tid + j) & size) == 0;
+                const unsigned long long a = k[j], b = k[jp];
+                const bool swap = (a > b) == up;
+                k[j] = swap ? b : a;
+                k[jp] = swap ? a : b;
+            }
+        }
     }
-    __syncthreads();
+    __syncthreads();  // xchg may be reused by the caller
+}
+
+// The y order from a complete x order: (y, x position) keys sorted in
+// registers, written out as yo[q] = (y, x) with each sample's y rank.  The
+// exchange buffer of the sort is the yo region itself.
+template <int E>
+__device__ __forceinline__ void build_y_order_e(int2 *xo, int2 *yo, uint16_t *yrank, int N) {
+    const int tid = threadIdx.x;
+    unsigned long long k[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int p = E * tid + j;
+        k[j] = p < N ? (((unsigned long long)(uint32_t)xo[p].y) << 32) | (unsigned)p : ~0ull;
+    }
+    block_sort_regs<E>(k, reinterpret_cast<unsigned long long *>(yo));
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int q = E * tid + j;
+        if (q < N) {
+            const int p = (int)(k[j] & 0xffffffffu);
+            yo[q] = make_int2((int)(k[j] >> 32), xo[p].x);
+            yrank[p] = (uint16_t)q;
+        }
+    }
     if (tid < kPad) {
         yo[-1 - tid] = make_int2(-kFar, 0);
         yo[N + tid] = make_int2(kFar, 0);
     }
     __syncthreads();
+}
+
+// The x order of a pair from its two code rows: (x code, member) keys sorted in
+// registers, written out as xo[p] = (x, y) and perm[p] = member (exchange buffer:
+// the yo region).
+template <int E>
+__device__ __forceinline__ void build_x_order_e(const int32_t *__restrict__ ca,
+                                                const int32_t *__restrict__ cb, int N, int2 *xo,
+                                                uint16_t *perm, int2 *yo) {
+    const int tid = threadIdx.x;
+    unsigned long long k[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int m = E * tid + j;
+        k[j] = m < N ? (((unsigned long long)(uint32_t)ca[m]) << 16) | (unsigned)m : ~0ull;
+    }
+    block_sort_regs<E>(k, reinterpret_cast<unsigned long long *>(yo));
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int p = E * tid + j;
+        if (p < N) {
+            const int m = (int)(k[j] & 0xffff);
+            perm[p] = (uint16_t)m;
+            xo[p] = make_int2((int)(k[j] >> 16), cb[m]);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void build_x_order(const int32_t *__restrict__ ca,
+                                              const int32_t *__restrict__ cb, int N, int P,
+                                              int2 *xo, uint16_t *perm, int2 *yo) {
+    if (P <= kKsgThreads)
+        build_x_order_e<1>(ca, cb, N, xo, perm, yo);
+    else if (P <= 2 * kKsgThreads)
+        build_x_order_e<2>(ca, cb, N, xo, perm, yo);
+    else if (P <= 4 * kKsgThreads)
+        build_x_order_e<4>(ca, cb, N, xo, perm, yo);
+    else {  // N > 1024: sort in LDS (8 keys per thread in registers would cost occupancy)
+        const int tid = threadIdx.x;
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);
+        for (int m = tid; m < P; m += kKsgThreads)
+            keys[m] = m < N ? (((unsigned long long)(uint32_t)ca[m]) << 16) | (unsigned)m : ~0ull;
+        __syncthreads();
+        block_bitonic_sort(keys, P);
+        for (int p = tid; p < N; p += kKsgThreads) {
+            const int m = (int)(keys[p] & 0xffff);
+            perm[p] = (uint16_t)m;
+            xo[p] = make_int2((int)(keys[p] >> 16), cb[m]);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void build_y_order(int2 *xo, int2 *yo, uint16_t *yrank, int N, int P) {
+    if (P <= kKsgThreads)
+        build_y_order_e<1>(xo, yo, yrank, N);
+    else if (P <= 2 * kKsgThreads)
+        build_y_order_e<2>(xo, yo, yrank, N);
+    else if (P <= 4 * kKsgThreads)
+        build_y_order_e<4>(xo, yo, yrank, N);
+    else {  // N > 1024: sort in LDS
+        const int tid = threadIdx.x;
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);
+        for (int p = tid; p < P; p += kKsgThreads)
+            keys[p] = p < N ? (((unsigned long long)(uint32_t)xo[p].y) << 32) | (unsigned)p : ~0ull;
+        __syncthreads();
+        block_bitonic_sort(keys, P);
+        for (int q = tid; q < N; q += kKsgThreads) {
+            const unsigned long long key = keys[q];
+            const int p = (int)(key & 0xffffffffu);
+            yo[q] = make_int2((int)(key >> 32), xo[p].x);
+            yrank[p] = (uint16_t)q;
+        }
+        __syncthreads();
+        if (tid < kPad) {
+            yo[-1 - tid] = make_int2(-kFar, 0);
+            yo[N + tid] = make_int2(kFar, 0);
+        }
+        __syncthreads();
+    }
 }
 
 // Sentinels of the x order (written once per launch by each workgroup).
@@ -273,7 +445,8 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
 }
 
 // LDS plan of both kernels: xo (N + 2 kPad) int2 | yo (P + 2 kPad) int2, also the
-// sort keys | perm N uint16 | yrank N uint16 | eps N int32.
+// sort keys and exchange buffer | perm N uint16 | yrank N uint16 | eps N int32,
+// with P = max(pow2_ceil(N), 256) (the register sort always moves 256 E keys).
 __host__ __device__ inline size_t ksg_lds_bytes(int N, int P) {
     return (size_t)(N + 2 * kPad) * 8 + (size_t)(P + 2 * kPad) * 8 + (size_t)N * 4 +
            (size_t)N * 4;
@@ -286,7 +459,7 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_field_kernel(
     int n_ref, const int32_t *__restrict__ xs_all, const uint16_t *__restrict__ perm_all,
     const double *__restrict__ H, float *__restrict__ out, int32_t *__restrict__ counts) {
     extern __shared__ int4 s_raw[];
-    const int P = pow2_ceil(N);
+    const int P = max(pow2_ceil(N), kKsgThreads);  // y-order region
     int2 *xo = reinterpret_cast<int2 *>(s_raw) + kPad;
     int2 *yo = xo + N + 2 * kPad;
     uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
@@ -338,13 +511,12 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_pairs_kernel(
     const int64_t *__restrict__ pairs, int64_t B, const double *__restrict__ H,
     float *__restrict__ out, int32_t *__restrict__ counts) {
     extern __shared__ int4 s_raw[];
-    const int P = pow2_ceil(N);
+    const int P = max(pow2_ceil(N), kKsgThreads);  // y-order region
     int2 *xo = reinterpret_cast<int2 *>(s_raw) + kPad;
     int2 *yo = xo + N + 2 * kPad;
     uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
     uint16_t *yrank = perm + N;
     int *epsL = reinterpret_cast<int *>(yrank + N);
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(yo);  // x-order sort
     const int tid = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
     ksg_sentinels(xo, N);
@@ -365,18 +537,7 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_pairs_kernel(
                 for (int i = tid; i < 2 * N; i += kKsgThreads) cnt[i] = 0;
             continue;
         }
-        const int32_t *ca = code_a + va * N;
-        const int32_t *cb = code_b + vb * N;
-        for (int m = tid; m < P; m += kKsgThreads)
-            keys[m] = m < N ? (((unsigned long long)(uint32_t)ca[m]) << 16) | (unsigned)m : ~0ull;
-        __syncthreads();
-        block_bitonic_sort(keys, P);
-        for (int p = tid; p < N; p += kKsgThreads) {
-            const int m = (int)(keys[p] & 0xffff);
-            perm[p] = (uint16_t)m;
-            xo[p] = make_int2((int)(keys[p] >> 16), cb[m]);
-        }
-        __syncthreads();
+        build_x_order(code_a + va * N, code_b + vb * N, N, P, xo, perm, yo);
         build_y_order(xo, yo, yrank, N, P);
         const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
         if (tid == 0) out[b] = (float)(base - acc / (double)N);
@@ -447,7 +608,7 @@ int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int6
     const int32_t *cq = e->code + (int64_t)var_qry * V * N;
     hipLaunchKernelGGL(ksg_sort_ref_kernel, dim3(n_ref), dim3(kKsgThreads), (size_t)P * 8, st, cr,
                        N, refs, xs, perm, H);
-    const size_t lds = ksg_lds_bytes(N, P);
+    const size_t lds = ksg_lds_bytes(N, P < kKsgThreads ? kKsgThreads : P);
     const dim3 g((unsigned)resident_grid(V, lds));
     const int32_t *fr = e->flags + (int64_t)var_ref * V;
     const int32_t *fq = e->flags + (int64_t)var_qry * V;
@@ -470,7 +631,7 @@ int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t 
     const int64_t V = (int64_t)e->nx * e->ny * e->nz;
     const int P = p2(N);
     hipLaunchKernelGGL(harmonic_kernel, dim3(1), dim3(64), 0, st, N, H);
-    const size_t lds = ksg_lds_bytes(N, P);
+    const size_t lds = ksg_lds_bytes(N, P < kKsgThreads ? kKsgThreads : P);
     const dim3 g((unsigned)resident_grid(B, lds));
     const int32_t *ca = e->code + (int64_t)var_a * V * N;
     const int32_t *cb = e->code + (int64_t)var_b * V * N;

@@ -13,7 +13,8 @@
 //   z = hi + lo (both bf16) in registers and the three products hi*hi, hi*lo,
 //   lo*hi are accumulated in FP32 (the lo*lo term is below 2^-16 relative).
 //   The reference operand is prepared once per call in MFMA operand order.
-// * pearson_pairs_kernel: one wave per vertex pair (training targets).
+// * pearson_pairs_kernel: one wave per vertex pair (training targets), from the
+//   vertex-major integer codes with exact int64 moment sums.
 #include "common.hpp"
 
 namespace ndf {
@@ -205,11 +206,23 @@ __global__ __launch_bounds__(256) void pearson_gemm_kernel(
 }
 
 // --------------------------------------------------------------- pairs ----
+// Training targets for random vertex pairs.  A pair's two member columns are
+// strided rows of the member-major ensemble (one 128-byte line per value), so
+// the pairs path reads the vertex-major integer codes instead: one contiguous
+// row of N codes per vertex.  Pearson's r is invariant to the per-vertex affine
+// map that defines the codes; their rounding to 2^-23 of the vertex range moves
+// r by well under 1e-6.  The five moment sums are exact in int64 (codes < 2^24,
+// N <= 4096), and r follows from them in FP64.
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void pearson_pairs_kernel(
-    const float *__restrict__ xa, const float *__restrict__ xb, const double *__restrict__ mean_a,
-    const double *__restrict__ inv_a, const double *__restrict__ mean_b,
-    const double *__restrict__ inv_b, int N, int64_t V, const int64_t *__restrict__ pairs,
-    int64_t B, float *__restrict__ out) {
+    const int32_t *__restrict__ code_a, const int32_t *__restrict__ code_b,
+    const int32_t *__restrict__ flags_a, const int32_t *__restrict__ flags_b, int N, int64_t V,
+    const int64_t *__restrict__ pairs, int64_t B, float *__restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= B) return;
@@ -218,12 +231,42 @@ __global__ __launch_bounds__(256) void pearson_pairs_kernel(
         if (lane == 0) out[b] = __builtin_nanf("");
         return;
     }
-    const float ma = (float)mean_a[va], mb = (float)mean_b[vb];
-    float acc = 0.f;
-    for (int m = lane; m < N; m += 64)
-        acc = fmaf(xa[(int64_t)m * V + va] - ma, xb[(int64_t)m * V + vb] - mb, acc);
-    double s = wave_sum_f64((double)acc);
-    if (lane == 0) out[b] = (float)(s * inv_a[va] * inv_b[vb] / (double)N);
+    const int32_t f = flags_a[va] | flags_b[vb];
+    if (f & (NDF_FLAG_NONFINITE | NDF_FLAG_CONSTANT)) {
+        if (lane == 0) out[b] = (f & NDF_FLAG_NONFINITE) ? __builtin_nanf("") : 0.0f;
+        return;
+    }
+    const int32_t *ra = code_a + va * N, *rb = code_b + vb * N;
+    long long sa = 0, sb = 0, saa = 0, sbb = 0, sab = 0;
+    auto add = [&](int x, int y) {
+        sa += x;
+        sb += y;
+        saa += (long long)x * x;
+        sbb += (long long)y * y;
+        sab += (long long)x * y;
+    };
+    if (VEC) {  // N % 4 == 0: 16-byte rows
+        for (int m = 4 * lane; m < N; m += 256) {
+            const i32x4 x = *reinterpret_cast<const i32x4 *>(ra + m);
+            const i32x4 y = *reinterpret_cast<const i32x4 *>(rb + m);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) add(x[e], y[e]);
+        }
+    } else {
+        for (int m = lane; m < N; m += 64) add(ra[m], rb[m]);
+    }
+    sa = wave_sum_i64(sa);
+    sb = wave_sum_i64(sb);
+    saa = wave_sum_i64(saa);
+    sbb = wave_sum_i64(sbb);
+    sab = wave_sum_i64(sab);
+    if (lane == 0) {
+        const double n = (double)N, da = (double)sa, db = (double)sb;
+        const double cov = (double)sab - da * db / n;
+        const double var_a = (double)saa - da * da / n;
+        const double var_b = (double)sbb - db * db / n;
+        out[b] = (float)(cov / sqrt(var_a * var_b));
+    }
 }
 
 // ------------------------------------------------------------ launchers ----
@@ -305,11 +348,17 @@ int launch_pearson_pairs(const ndf_ensemble *e, int var_a, int var_b, const int6
                          int64_t B, float *out, hipStream_t st) {
     const int N = e->n_members;
     const int64_t V = (int64_t)e->nx * e->ny * e->nz;
-    hipLaunchKernelGGL(pearson_pairs_kernel, dim3((unsigned)ceil_div(B, 4)), dim3(256), 0, st,
-                       e->x + (int64_t)var_a * N * V, e->x + (int64_t)var_b * N * V,
-                       e->mean + (int64_t)var_a * V, e->inv_std + (int64_t)var_a * V,
-                       e->mean + (int64_t)var_b * V, e->inv_std + (int64_t)var_b * V, N, V, pairs,
-                       B, out);
+    const int32_t *ca = e->code + (int64_t)var_a * V * N;
+    const int32_t *cb = e->code + (int64_t)var_b * V * N;
+    const int32_t *fa = e->flags + (int64_t)var_a * V;
+    const int32_t *fb = e->flags + (int64_t)var_b * V;
+    const dim3 g((unsigned)ceil_div(B, 4));
+    if (N % 4 == 0)
+        hipLaunchKernelGGL(pearson_pairs_kernel<true>, g, dim3(256), 0, st, ca, cb, fa, fb, N, V,
+                           pairs, B, out);
+    else
+        hipLaunchKernelGGL(pearson_pairs_kernel<false>, g, dim3(256), 0, st, ca, cb, fa, fb, N, V,
+                           pairs, B, out);
     return status_of_launch();
 }
 

@@ -165,6 +165,29 @@ def test_pearson_pairs_match_oracle(mid):
     assert np.max(np.abs(got - want)) <= PEARSON_TOL
 
 
+def test_odd_member_count_all_estimators():
+    """N = 75 (not a multiple of 4): the scalar row paths of the Pearson pairs and
+    the ragged last k-step of the split-BF16 contraction, with KSG counts exact."""
+    cfg = gen.CONFIGS["tiny"].with_members(75)
+    e = _ens(cfg)
+    x = e.x[0].cpu().numpy()
+    refs = [cfg.ref_v, 3]
+    for prec in (ndf.NDF_PREC_FP32, ndf.NDF_PREC_SPLIT_BF16):
+        got = ndf.pearson_field(e, refs, prec=prec).cpu().numpy()
+        for i, r in enumerate(refs):
+            assert np.max(np.abs(got[i] - direct.pearson_field(x[:, r], x))) <= PEARSON_TOL
+    pairs = gen.random_pairs(cfg.n_vertices, 300, seed=75)
+    r = ndf.pearson_pairs(e, pairs).cpu().numpy()
+    want = np.array([direct.pearson(x[:, a], x[:, b]) for a, b in pairs])
+    assert np.max(np.abs(r - want)) <= PEARSON_TOL
+    mi, cnt = ndf.ksg_pairs(e, pairs[:60], k=4, counts=True)
+    mi, cnt = mi.cpu().numpy(), cnt.cpu().numpy()
+    for b, (a, q) in enumerate(pairs[:60]):
+        w, wnx, wny = direct.ksg_field(x[:, a], x[:, q:q + 1], 4, counts=True)
+        assert np.array_equal(cnt[b, 0], wnx[0]) and np.array_equal(cnt[b, 1], wny[0]), b
+        assert abs(mi[b] - w[0]) <= MI_TOL
+
+
 def test_pairs_out_of_range_give_nan(mid):
     pairs = np.array([[0, 1], [-1, 3], [5, mid.n_vertices]], dtype=np.int64)
     r = ndf.pearson_pairs(mid, pairs).cpu().numpy()
