@@ -33,7 +33,7 @@ struct QLayout {
     int64_t b4, b5, w6, b6;        // fp32
     // FP8 (OCP E4M3) copies of W2..W5 in 32x32x64 operand order + per-row scales
     int64_t q2[2], q3[2], q4, q5;  // fp8 fragments, 16 KB each
-    int64_t s2[2], s3[2], s4, s5;  // int32 [128] per-row E8M0 scale bytes
+    int64_t s2[2], s3[2], s4, s5;  // int32 [128][4] E8M0 scale bytes per row and 32-k block
     int64_t total;
 };
 
@@ -69,16 +69,16 @@ static QLayout qlayout(const ndf_net_config *c) {
     for (int e = 0; e < c->n_enc; ++e) {
         q.q2[e] = take(kH * kH);
         q.q3[e] = take(kH * kH);
-        q.s2[e] = take(kH * 4);
-        q.s3[e] = take(kH * 4);
+        q.s2[e] = take(kH * 4 * 4);
+        q.s3[e] = take(kH * 4 * 4);
     }
     if (c->n_enc == 1) {
         q.q2[1] = q.q2[0]; q.q3[1] = q.q3[0]; q.s2[1] = q.s2[0]; q.s3[1] = q.s3[0];
     }
     q.q4 = take(kH * kH);
     q.q5 = take(kH * kH);
-    q.s4 = take(kH * 4);
-    q.s5 = take(kH * 4);
+    q.s4 = take(kH * 4 * 4);
+    q.s5 = take(kH * 4 * 4);
     q.total = pos;
     return q;
 }
@@ -132,38 +132,55 @@ __global__ void pack_frag_kernel(const float *__restrict__ W, int KIN, int permu
     }
 }
 
-// Per-output-row E8M0 scale byte of W[128][128]: 127 + e, 2^e the smallest power
-// of two with max_k |W[o][k]| / 2^e <= 448.
-__global__ void row_exp_kernel(const float *__restrict__ W, int *__restrict__ se) {
-    const int o = threadIdx.x;  // 128 threads
-    float m = 0.f;
-    for (int k = 0; k < kH; ++k) m = fmaxf(m, fabsf(W[o * kH + k]));
-    se[o] = 127 + e4m3_block_exp(m);
+// The input that lane half h of k-block kb holds in byte t of the MFMA 32x32x64
+// A and B operands (the previous layer's output layout):
+//   f = 64 kb + 32 (t/16) + 8 ((t%16)/4) + 4 h + t%4.
+// The hardware's K order puts bytes t < 16 of both lane halves in its first
+// 32-element scale block and bytes t >= 16 in the second, so scale block b of
+// k-block kb is inputs 64 kb + 32 b .. + 31, and its E8M0 scale comes from the
+// lane half h = b.
+__host__ __device__ inline int fp8_feature(int kb, int h, int t) {
+    return 64 * kb + 32 * (t >> 4) + 8 * ((t & 15) >> 2) + 4 * h + (t & 3);
 }
 
-// FP8 A fragments of W[128][128] for MFMA 32x32x64: fragment (ob, kb) lane l byte t
-// holds W[32 ob + l%32][f] / 2^e[row] (exact: a power of two) with f the feature that
-// the previous layer's output layout puts at logical k = 64 kb + 32 (l/32) + t:
-//   f = 64 kb + 32 (t/16) + 8 ((t%16)/4) + 4 (l/32) + t%4.
-__global__ void pack_frag_fp8_kernel(const float *__restrict__ W, const int *__restrict__ se,
-                                     uint32_t *__restrict__ frag) {
-    const int n = kH * kH / 4;  // dwords
-    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < n; d += gridDim.x * blockDim.x) {
-        const int lane = (d >> 3) & 63;
-        const int fi = d >> 9;  // ob*2 + kb
-        const int ob = fi >> 1, kb = fi & 1;
-        const int h = lane >> 5, row = 32 * ob + (lane & 31);
-        const float inv = __uint_as_float((uint32_t)(254 - se[row]) << 23);  // 2^-e
-        float v[4];
-        for (int b = 0; b < 4; ++b) {
-            const int t = 4 * (d & 7) + b;
-            const int f = 64 * kb + 32 * (t >> 4) + 8 * ((t & 15) >> 2) + 4 * h + (t & 3);
-            v[b] = W[row * kH + f] * inv;
+// E8M0 scale bytes of W[128][128]: se[o][2 kb + b] = 127 + e, 2^e the smallest
+// power of two with max |W[o][f]| / 2^e <= 448 over the 32 inputs of scale
+// block (kb, b).
+// Thread o of a 128-thread block owns row o; fragment (ob, kb) lane l byte t holds
+// W[32 ob + l%32][f] / 2^e (exact: a power of two), written 4 bytes at a time.
+__device__ __forceinline__ void pack_row_fp8(const float *__restrict__ w, int o,
+                                             uint32_t *__restrict__ frag, int *__restrict__ se) {
+    const int ob = o >> 5, il = o & 31;
+    for (int kb = 0; kb < 2; ++kb) {
+        float inv[2];
+        for (int b = 0; b < 2; ++b) {
+            float m = 0.f;
+            for (int f = 64 * kb + 32 * b; f < 64 * kb + 32 * b + 32; ++f)
+                m = fmaxf(m, fabsf(w[f]));
+            const int e = e4m3_block_exp(m);
+            se[o * 4 + 2 * kb + b] = 127 + e;
+            inv[b] = __uint_as_float((uint32_t)(127 - e) << 23);  // 2^-e
         }
-        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
-        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
-        frag[d] = (uint32_t)w;
+        for (int h = 0; h < 2; ++h) {
+            const int lane = 32 * h + il;
+            for (int t = 0; t < 32; t += 4) {
+                float v[4];
+                for (int c = 0; c < 4; ++c) {
+                    const int f = fp8_feature(kb, h, t + c);
+                    v[c] = w[f] * inv[t >> 4];
+                }
+                int wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+                wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], wd, true);
+                frag[((ob * 2 + kb) * 64 + lane) * 8 + (t >> 2)] = (uint32_t)wd;
+            }
+        }
     }
+}
+
+__global__ void pack_fp8_kernel(const float *__restrict__ W, uint32_t *__restrict__ frag,
+                                int *__restrict__ se) {
+    const int o = threadIdx.x;  // 128 threads
+    pack_row_fp8(W + (int64_t)o * kH, o, frag, se);
 }
 
 __global__ void copy_f32_kernel(const float *__restrict__ src, int n, float *__restrict__ dst) {
@@ -210,9 +227,8 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(1), 0, st, P + o.b6, 1, (float *)(Q + q.b6));
     // FP8 copies of the 128x128 layers (both precisions share one packed blob)
     auto fp8 = [&](const float *W, int64_t qoff, int64_t soff) {
-        hipLaunchKernelGGL(row_exp_kernel, dim3(1), dim3(kH), 0, st, W, (int *)(Q + soff));
-        hipLaunchKernelGGL(pack_frag_fp8_kernel, dim3(16), dim3(256), 0, st, W,
-                           (const int *)(Q + soff), (uint32_t *)(Q + qoff));
+        hipLaunchKernelGGL(pack_fp8_kernel, dim3(1), dim3(kH), 0, st, W, (uint32_t *)(Q + qoff),
+                           (int *)(Q + soff));
     };
     for (int e = 0; e < c->n_enc; ++e) {
         fp8(P + o.W2[e], q.q2[e], q.s2[e]);
@@ -465,16 +481,20 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
 // Layers 2..5 run as MFMA 32x32x64 on OCP E4M3 with microscaling (MX): every
 // operand lane carries an E8M0 power-of-two scale for its 32 K-values, which
 // the scaled MFMA applies in hardware.
-//  * weights: per output row, 2^e with max|W_row| / 2^e <= 448 (the A operand
-//    lane of row i carries that row's scale), so accumulators come out in true
-//    units and start at the bias like the BF16 path;
-//  * activations: per query and 64-feature k-block, 2^e with max|a| / 2^e <=
-//    448 (the two lanes holding the block, l and l ^ 32, share it); the
-//    quantising conversion divides by the scale itself.
+//  * weights: per output row and block of 32 inputs, 2^e with max|W| / 2^e <=
+//    448 over the block, so accumulators come out in true units and start at
+//    the bias like the BF16 path;
+//  * activations: per query and block of 32 features (one output block of the
+//    previous layer, held 16 + 16 by lanes l and l ^ 32), 2^e with max|a| / 2^e
+//    <= 448; the quantising conversion divides by the scale itself.
+// The hardware groups K into scale blocks in its own order: bytes 0..15 of both
+// lane halves form the first block of 32, bytes 16..31 the second, and lane half
+// h carries the scale of block h (measured on gfx950 with half-dependent
+// operand values and scales).
 // The first layer (32 inputs, 6% of the work) stays BF16.  Block k = 64 kb +
 // 32 h + t of a lane comes from output blocks 2 kb (t < 16) and 2 kb + 1
 // (t >= 16) of the previous layer; the packed weights absorb that order (see
-// pack_frag_fp8_kernel).
+// pack_row_fp8).
 typedef __attribute__((ext_vector_type(8))) int i32x8;
 
 __device__ __forceinline__ f32x16 mfma_fp8(const i32x8 &a, int sa, const i32x8 &b, int sb,
@@ -490,28 +510,37 @@ __device__ __forceinline__ int cvt_fp8x2(int w, float a, float b, float s) {
     return __builtin_bit_cast(int, __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(old, a, b, s, HI));
 }
 
-// The 32 values of one lane (acc[0][r], acc[1][r] of one query half, in that
-// order after the epilogue map f) -> E4M3 bytes t = 16 o + r, and the block's
-// E8M0 byte.  mbits: the lane's max |value| as float bits (non-negative).
+// The 32 values of one lane (f(o, r) = output block 2 kb + o, row r of the lane;
+// byte t = 16 o + r) -> E4M3 with one E8M0 scale per output block: the block's
+// 32 rows sit 16 in lane l and 16 in lane l ^ 32, which share the block maximum.
+// mbits[o]: the lane's max |value| of block o as float bits (non-negative).  The
+// lane half h supplies the MFMA scale of block o = h (the hardware's scale block
+// h is bytes 16 h .. 16 h + 15 of both lane halves).
 template <typename F>
-__device__ __forceinline__ void quant_block(F f, int mbits, i32x8 &out, int &sbyte) {
-    mbits = max(mbits, __shfl_xor(mbits, 32, 64));
-    const int e = e4m3_block_exp(__int_as_float(mbits));
-    const float s = __uint_as_float((uint32_t)(e + 127) << 23);
+__device__ __forceinline__ void quant_block(F f, int (&mbits)[2], int h, i32x8 &out,
+                                            int &sbyte) {
+    float s[2];
+    int e[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        const int m = max(mbits[o], __shfl_xor(mbits[o], 32, 64));
+        e[o] = e4m3_block_exp(__int_as_float(m));
+        s[o] = __uint_as_float((uint32_t)(e[o] + 127) << 23);
+    }
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         const int o = d >> 2, r = 4 * (d & 3);
-        const int w = cvt_fp8x2<false>(0, f(o, r), f(o, r + 1), s);
-        out[d] = cvt_fp8x2<true>(w, f(o, r + 2), f(o, r + 3), s);
+        const int w = cvt_fp8x2<false>(0, f(o, r), f(o, r + 1), s[o]);
+        out[d] = cvt_fp8x2<true>(w, f(o, r + 2), f(o, r + 3), s[o]);
     }
-    sbyte = e + 127;
+    sbyte = (h ? e[1] : e[0]) + 127;
 }
 
 struct InferArgs8 {
     const uint16_t *grid[kL];
     const bf16x8 *w1;
     const i32x8 *q[4];    // W2..W5 fp8 fragments
-    const int *se[4];     // their per-row E8M0 bytes
+    const int *se[4];     // their E8M0 bytes [128][4] (row, 32-input block)
     const float *b[5];
     const float *w6;
     const float *b6;
@@ -531,13 +560,12 @@ __device__ __forceinline__ void dense_layer_fp8(
     const float *bias_h = bias + h4;
     const float *ref_h = ref + h4;
     const float *w6_h = w6 + h4;
-    const int il = lane & 31;
+    const int il = lane & 31, hh = h4 >> 2;
     if (KIND == LAY_HEAD) {
         // last layer: one output block and query half at a time, straight into
         // the w6 dot product (keeps the register footprint of the head small)
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
-            const int sa = se[32 * ob + il];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 f32x16 acc;
@@ -549,7 +577,8 @@ __device__ __forceinline__ void dense_layer_fp8(
                 }
 #pragma unroll
                 for (int kb = 0; kb < 2; ++kb)
-                    acc = mfma_fp8(w8[(ob * 2 + kb) * 64 + lane], sa, in8[kb][q], sin[kb][q], acc);
+                    acc = mfma_fp8(w8[(ob * 2 + kb) * 64 + lane], se[(32 * ob + il) * 4 + 2 * kb + hh],
+                                   in8[kb][q], sin[kb][q], acc);
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const f32x4 wv = *reinterpret_cast<const f32x4 *>(w6_h + 32 * ob + 8 * g);
@@ -585,14 +614,16 @@ __device__ __forceinline__ void dense_layer_fp8(
                     acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
                 }
             } else {
-                const int sa = se[32 * ob + il];
 #pragma unroll
                 for (int kb = 0; kb < 2; ++kb) {
                     const i32x8 a = w8[(ob * 2 + kb) * 64 + lane];
+                    const int sa = se[(32 * ob + il) * 4 + 2 * kb + hh];
                     acc[o][0] = mfma_fp8(a, sa, in8[kb][0], sin[kb][0], acc[o][0]);
                     acc[o][1] = mfma_fp8(a, sa, in8[kb][1], sin[kb][1], acc[o][1]);
                 }
             }
+            // fetch one output block's weights at a time (32 registers, not 64)
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -606,18 +637,17 @@ __device__ __forceinline__ void dense_layer_fp8(
                             dst[32 * (2 * op + o) + 8 * (r >> 2) + (r & 3)] = acc[o][q][r];
                 }
             } else if (KIND == LAY_RELU) {
-                int mb = 0;
+                // max of the ReLU outputs straight from the raw bits: negative
+                // floats are negative integers and lose against the initial 0
+                int mb[2] = {0, 0};
 #pragma unroll
                 for (int o = 0; o < 2; ++o)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        acc[o][q][r] = relu_f32(acc[o][q][r]);
-                        mb = max(mb, __float_as_int(acc[o][q][r]));
-                    }
-                quant_block([&](int o, int r) { return acc[o][q][r]; }, mb, out8[op][q],
-                            sout[op][q]);
+                    for (int r = 0; r < 16; ++r) mb[o] = max(mb[o], __float_as_int(acc[o][q][r]));
+                quant_block([&](int o, int r) { return relu_f32(acc[o][q][r]); }, mb, hh,
+                            out8[op][q], sout[op][q]);
             } else {  // LAY_LATENT: product with the reference latent
-                int mb = 0;
+                int mb[2] = {0, 0};
 #pragma unroll
                 for (int o = 0; o < 2; ++o)
 #pragma unroll
@@ -628,18 +658,20 @@ __device__ __forceinline__ void dense_layer_fp8(
                         for (int i = 0; i < 4; ++i) {
                             const float y = acc[o][q][4 * g + i] * rv[i];
                             acc[o][q][4 * g + i] = y;
-                            mb = max(mb, __float_as_int(y) & 0x7fffffff);
+                            mb[o] = max(mb[o], __float_as_int(y) & 0x7fffffff);
                         }
                     }
-                quant_block([&](int o, int r) { return acc[o][q][r]; }, mb, out8[op][q],
+                quant_block([&](int o, int r) { return acc[o][q][r]; }, mb, hh, out8[op][q],
                             sout[op][q]);
             }
+            // one query half at a time (keeps the epilogue's temporaries few)
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// MODE 0: field; MODE 1: latents of the vertices in qlist (FP32).
+// MODE 0: field (out[v] = Phi(ref, v)); MODE 1: latents of the vertices in
+// qlist (FP32).
 template <int MODE>
 __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   const int64_t *__restrict__ qlist,
@@ -648,7 +680,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   float *__restrict__ out) {
     __shared__ bf16x8 s_w1[kFragW1];
     __shared__ i32x8 s_q[4][kFrag8];
-    __shared__ int s_e[4][kH];
+    __shared__ int s_e[4][kH * 4];
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
@@ -658,7 +690,8 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     const int nlay = MODE == 0 ? 4 : 2;
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L][i];
-    for (int i = tid; i < 4 * kH; i += kInferThreads) s_e[i / kH][i % kH] = A.se[i / kH][i % kH];
+    for (int i = tid; i < 4 * kH * 4; i += kInferThreads)
+        s_e[i / (kH * 4)][i % (kH * 4)] = A.se[i / (kH * 4)][i % (kH * 4)];
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
