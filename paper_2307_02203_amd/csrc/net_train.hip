@@ -98,33 +98,40 @@ __global__ __launch_bounds__(kThreads) void grid_fwd_kernel(const float *__restr
 }
 
 // ----------------------------------------------------------- grid bwd ----
+// Scatter-add of dL/dh0 into the grid gradient: one wave per (row, level) item,
+// lane = (corner c, feature f), so each atomic instruction of a wave updates the
+// eight features of eight corner cells (eight 32-byte runs) instead of 64 scattered
+// floats.  Every lane evaluates the trilinear lookup of the forward pass and keeps
+// its own corner, so the weights are the forward's bit for bit.
 __global__ __launch_bounds__(kThreads) void grid_bwd_kernel(float *__restrict__ grad, GridOffs go,
                                                             GridGeom g, int n_enc,
                                                             const int64_t *__restrict__ pairs,
                                                             int64_t B, int64_t row0, int64_t rows,
                                                             const float *__restrict__ dH0) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rows * kL) return;
-    const int64_t n = row0 + t / kL;
-    const int l = (int)(t % kL);
-    const int e = (n_enc == 2 && n >= B) ? 1 : 0;
-    int64_t v = row_vertex(pairs, B, n);
+    const int lane = threadIdx.x & 63, c = lane >> 3, f = lane & 7;
+    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
     const int64_t V = (int64_t)g.nx * g.ny * g.nz;
-    v = v < 0 ? 0 : (v >= V ? V - 1 : v);
-    int64_t idx[8];
-    float w[8];
-    corners(g, l, v, idx, w);
-    const f32x4 *d = reinterpret_cast<const f32x4 *>(dH0 + n * kK0 + l * kF);
-    const f32x4 d0 = d[0], d1 = d[1];
-    float *gg = grad + grid_off(go, e, l);
-    for (int cn = 0; cn < 8; ++cn) {
-        if (w[cn] == 0.f) continue;
-        float *c = gg + idx[cn] * kF;
+    for (int64_t it = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); it < rows * kL;
+         it += waves) {
+        const int64_t n = row0 + it / kL;
+        const int l = (int)(it % kL);
+        const int e = (n_enc == 2 && n >= B) ? 1 : 0;
+        int64_t v = row_vertex(pairs, B, n);
+        v = v < 0 ? 0 : (v >= V ? V - 1 : v);
+        int R[3];
+        level_dims(g, l, R);
+        int idx[8];
+        float w[8];
+        corners_R32(g, R, v, idx, w);
+        int ic = idx[0];
+        float wc = w[0];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            unsafeAtomicAdd(c + f, w[cn] * d0[f]);
-            unsafeAtomicAdd(c + 4 + f, w[cn] * d1[f]);
+        for (int k = 1; k < 8; ++k) {
+            ic = c == k ? idx[k] : ic;
+            wc = c == k ? w[k] : wc;
         }
+        const float d = dH0[n * kK0 + l * kF + f];
+        if (wc != 0.f) unsafeAtomicAdd(grad + grid_off(go, e, l) + (int64_t)ic * kF + f, wc * d);
     }
 }
 
@@ -592,7 +599,9 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
         hipLaunchKernelGGL((rows_mma_kernel<kH, kK0, EPI_PLAIN>), dim3(mma_blocks(rows)),
                            dim3(kThreads), 0, st, dP1, rows, P + o.W1[e], 1, kK0, nullptr, nullptr,
                            t.dH0 + r0 * kK0);
-        hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)ceil_div(rows * kL, kThreads)),
+        const int64_t items = rows * kL, per_block = kThreads / 64;
+        const int64_t gb = ceil_div(items, per_block);
+        hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)(gb < 16384 ? gb : 16384)),
                            dim3(kThreads), 0, st, G, go, g, n_enc, pairs, B, r0, rows, t.dH0);
     }
     return status_of_launch();
