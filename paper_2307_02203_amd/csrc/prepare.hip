@@ -7,19 +7,23 @@
 // multiply, divide) and round-half-even, so they are the same integers on any
 // conforming implementation; all later KSG distances are exact int32.
 //
-// One workgroup owns 64 consecutive vertices of one variable.  The ensemble is
-// member-major, so each member row contributes a 256-byte coalesced segment.
+// One workgroup owns 64 consecutive vertices of one variable and reads their
+// members twice (sum / min / max, then centred squares and codes).  The ensemble
+// is member-major, so each member row contributes a 256-byte coalesced segment.
 // Codes are written vertex-major through an LDS transpose (64 members x 64
-// vertices per tile).
+// vertices per tile).  (Two vertices per thread with 8-byte loads measured
+// slower: the larger tile cut the resident workgroups per CU from seven to three.)
 #include "common.hpp"
 
 #pragma clang fp contract(off)
 
 namespace ndf {
 
-constexpr int kPrepV = 64;          // vertices per workgroup
-constexpr int kPrepPh = 4;          // member phases per vertex
-constexpr int kPrepThreads = kPrepV * kPrepPh;
+constexpr int kPrepVW = 1;                    // consecutive vertices per thread (1 or 2)
+constexpr int kPrepG = 64;                    // vertex groups per workgroup
+constexpr int kPrepV = kPrepG * kPrepVW;      // vertices per workgroup
+constexpr int kPrepPh = 4;                    // member phases per vertex group
+constexpr int kPrepThreads = kPrepG * kPrepPh;
 
 __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
     const float *__restrict__ x, int N, int64_t V, double *__restrict__ mean,
@@ -27,11 +31,12 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
     const int var = blockIdx.y;
     const float *xv = x + (int64_t)var * N * V;
     const int t = threadIdx.x;
-    const int vl = t % kPrepV;
-    const int ph = t / kPrepV;
+    const int vg = t % kPrepG;
+    const int ph = t / kPrepG;
     const int64_t v0 = (int64_t)blockIdx.x * kPrepV;
-    const int64_t v = v0 + vl;
-    const bool live = v < V;
+    const int64_t vb = v0 + kPrepVW * vg;  // this thread's first vertex
+    // 8-byte loads need V even (every member row then starts 8-byte aligned)
+    const bool pairs = (V % 2) == 0;
 
     __shared__ double s_sum[kPrepPh][kPrepV];
     __shared__ float s_lo[kPrepPh][kPrepV];
@@ -39,74 +44,99 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
     __shared__ int s_bad[kPrepPh][kPrepV];
     __shared__ int32_t s_tile[64][kPrepV + 1];
 
+    auto load = [&](int m, float (&a)[kPrepVW]) {
+        const float *row = xv + (int64_t)m * V;
+        if (kPrepVW == 2 && pairs && vb + 1 < V) {
+            const f32x2 q = *reinterpret_cast<const f32x2 *>(row + vb);
+            a[0] = q[0];
+            a[1] = q[1];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPrepVW; ++j) a[j] = vb + j < V ? row[vb + j] : 0.f;
+        }
+    };
+
     // pass 1: sum, min, max, finiteness
-    double sum = 0.0;
-    float lo = INFINITY, hi = -INFINITY;
-    int bad = 0;
-    if (live) {
+    double sum[kPrepVW];
+    float lo[kPrepVW], hi[kPrepVW];
+    int bad[kPrepVW];
+#pragma unroll
+    for (int j = 0; j < kPrepVW; ++j) {
+        sum[j] = 0.0;
+        lo[j] = INFINITY;
+        hi[j] = -INFINITY;
+        bad[j] = 0;
+    }
+    if (vb < V) {
         for (int m = ph; m < N; m += kPrepPh) {
-            float a = xv[(int64_t)m * V + v];
-            sum += (double)a;
-            lo = fminf(lo, a);
-            hi = fmaxf(hi, a);
-            bad |= !isfinite(a);
+            float a[kPrepVW];
+            load(m, a);
+#pragma unroll
+            for (int j = 0; j < kPrepVW; ++j) {
+                sum[j] += (double)a[j];
+                lo[j] = fminf(lo[j], a[j]);
+                hi[j] = fmaxf(hi[j], a[j]);
+                bad[j] |= !isfinite(a[j]);
+            }
         }
     }
-    s_sum[ph][vl] = sum;
-    s_lo[ph][vl] = lo;
-    s_hi[ph][vl] = hi;
-    s_bad[ph][vl] = bad;
-    __syncthreads();
-    sum = 0.0;
-    lo = INFINITY;
-    hi = -INFINITY;
-    bad = 0;
-    for (int p = 0; p < kPrepPh; ++p) {
-        sum += s_sum[p][vl];
-        lo = fminf(lo, s_lo[p][vl]);
-        hi = fmaxf(hi, s_hi[p][vl]);
-        bad |= s_bad[p][vl];
+#pragma unroll
+    for (int j = 0; j < kPrepVW; ++j) {
+        const int vl = kPrepVW * vg + j;
+        s_sum[ph][vl] = sum[j];
+        s_lo[ph][vl] = lo[j];
+        s_hi[ph][vl] = hi[j];
+        s_bad[ph][vl] = bad[j];
     }
-    const double mu = sum / (double)N;
     __syncthreads();
-
-    // pass 2: centred sum of squares
-    double ss = 0.0;
-    if (live) {
-        for (int m = ph; m < N; m += kPrepPh) {
-            double d = (double)xv[(int64_t)m * V + v] - mu;
-            ss += d * d;
+    double mu[kPrepVW], dlo[kPrepVW], scale[kPrepVW];
+    bool flat[kPrepVW];
+#pragma unroll
+    for (int j = 0; j < kPrepVW; ++j) {
+        const int vl = kPrepVW * vg + j;
+        double sm = 0.0;
+        float l = INFINITY, h = -INFINITY;
+        int b = 0;
+        for (int p = 0; p < kPrepPh; ++p) {
+            sm += s_sum[p][vl];
+            l = fminf(l, s_lo[p][vl]);
+            h = fmaxf(h, s_hi[p][vl]);
+            b |= s_bad[p][vl];
         }
+        mu[j] = sm / (double)N;
+        flat[j] = !(h > l);
+        dlo[j] = (double)l;
+        scale[j] = flat[j] ? 0.0 : 8388608.0 / ((double)h - dlo[j]);
+        bad[j] = b;
     }
-    s_sum[ph][vl] = ss;
     __syncthreads();
-    ss = 0.0;
-    for (int p = 0; p < kPrepPh; ++p) ss += s_sum[p][vl];
-    const bool flat = !(hi > lo);
-    if (live && ph == 0) {
-        const double var_pop = ss / (double)N;
-        mean[(int64_t)var * V + v] = mu;
-        inv_std[(int64_t)var * V + v] = (var_pop > 0.0 && !flat) ? 1.0 / sqrt(var_pop) : 0.0;
-        flags[(int64_t)var * V + v] = (bad ? NDF_FLAG_NONFINITE : 0) | (flat ? NDF_FLAG_CONSTANT : 0);
-    }
 
-    // pass 3: codes, transposed through LDS into vertex-major rows
-    const double dlo = (double)lo;
-    const double scale = flat ? 0.0 : 8388608.0 / ((double)hi - dlo);
+    // pass 2: centred sum of squares and the codes, transposed through LDS into
+    // vertex-major rows.  A thread visits members ph, ph + 4, ... in increasing
+    // order, so its FP64 sum is the plain two-pass one.
     int32_t *cv = code + (int64_t)var * V * N;
+    double ss[kPrepVW];
+#pragma unroll
+    for (int j = 0; j < kPrepVW; ++j) ss[j] = 0.0;
     for (int m0 = 0; m0 < N; m0 += 64) {
         for (int mm = ph; mm < 64; mm += kPrepPh) {
             const int m = m0 + mm;
-            int32_t c = 0;
-            if (live && m < N && !flat) {
-                double tq = ((double)xv[(int64_t)m * V + v] - dlo) * scale;
-                c = (int32_t)__builtin_rint(tq);
+            float a[kPrepVW];
+            if (vb < V && m < N) load(m, a);
+#pragma unroll
+            for (int j = 0; j < kPrepVW; ++j) {
+                int32_t c = 0;
+                if (vb + j < V && m < N) {
+                    const double d = (double)a[j] - mu[j];
+                    ss[j] += d * d;
+                    if (!flat[j]) c = (int32_t)__builtin_rint(((double)a[j] - dlo[j]) * scale[j]);
+                }
+                s_tile[mm][kPrepVW * vg + j] = c;
             }
-            s_tile[mm][vl] = c;
         }
         __syncthreads();
-        // 64 rows (vertices) of up to 64 members; 16 threads per row, 4 members each
-        for (int pass = 0; pass < 4; ++pass) {
+        // kPrepV rows (vertices) of up to 64 members; 16 threads per row, 4 members each
+        for (int pass = 0; pass < kPrepV / 16; ++pass) {
             const int row = t / 16 + 16 * pass;
             const int c4 = t % 16;
             const int64_t vr = v0 + row;
@@ -127,6 +157,23 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
             }
         }
         __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kPrepVW; ++j) s_sum[ph][kPrepVW * vg + j] = ss[j];
+    __syncthreads();
+    if (ph == 0) {
+#pragma unroll
+        for (int j = 0; j < kPrepVW; ++j) {
+            const int64_t v = vb + j;
+            if (v >= V) continue;
+            double s2 = 0.0;
+            for (int p = 0; p < kPrepPh; ++p) s2 += s_sum[p][kPrepVW * vg + j];
+            const double var_pop = s2 / (double)N;
+            mean[(int64_t)var * V + v] = mu[j];
+            inv_std[(int64_t)var * V + v] = (var_pop > 0.0 && !flat[j]) ? 1.0 / sqrt(var_pop) : 0.0;
+            flags[(int64_t)var * V + v] =
+                (bad[j] ? NDF_FLAG_NONFINITE : 0) | (flat[j] ? NDF_FLAG_CONSTANT : 0);
+        }
     }
 }
 
