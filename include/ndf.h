@@ -74,6 +74,9 @@ typedef struct ndf_ensemble {
     double *inv_std;         /* [n_vars][V] 1/population std, 0 where std == 0    */
     int32_t *code;           /* [n_vars][V][N] KSG integer codes, vertex-major    */
     int32_t *flags;          /* [n_vars][V] NDF_FLAG_* bits                       */
+    uint16_t *order;         /* [n_vars][V][N] members in ascending (code, member)
+                                order per vertex (ndf_prepare), or NULL: the KSG
+                                calls then sort every column they use            */
 } ndf_ensemble;
 
 /* The learned field (Sec. 4.1-4.2): per encoder a dense multi-resolution feature
@@ -106,7 +109,10 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
  * needs per-vertex means and variances; Sec. 3.2 the KSG neighbour search).
  * Writes mean, inv_std (FP64, population moments), flags, and for every vertex
  * v and member m the code rne((x - lo_v) * 2^23 / (hi_v - lo_v)) with lo/hi
- * the column min/max, all in IEEE double (0 for a constant column). */
+ * the column min/max, all in IEEE double (0 for a constant column).  When
+ * ens->order is non-NULL it also writes each vertex's members sorted by code
+ * (ties by member index): the sorted orders the KSG neighbour search walks,
+ * built once per ensemble instead of once per (reference, query) pair. */
 int ndf_prepare(const ndf_ensemble *ens, void *stream);
 
 /* Direct Pearson field (Sec. 3.1, Eq. 1; Table 1 "Pearson"):

@@ -18,6 +18,7 @@ size_t ksg_field_ws_bytes(int N, int n_ref);
 int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int64_t *ref_v,
                      int n_ref, int k, float *out, int32_t *counts, void *ws, hipStream_t st);
 size_t ksg_pairs_ws_bytes(int N);
+int launch_ksg_orders(const ndf_ensemble *e, hipStream_t st);
 int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t *pairs, int64_t B,
                      int k, float *out, int32_t *counts, double *H, hipStream_t st);
 }  // namespace ndf
@@ -92,7 +93,9 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
 int ndf_prepare(const ndf_ensemble *ens, void *stream) {
     int s = check_ensemble(ens, true);
     if (s != NDF_OK) return s;
-    return launch_prepare(ens, S(stream));
+    s = launch_prepare(ens, S(stream));
+    if (s == NDF_OK && ens->order) s = launch_ksg_orders(ens, S(stream));
+    return s;
 }
 
 int ndf_pearson_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,

@@ -419,20 +419,34 @@ __device__ __forceinline__ void ksg_sentinels(int2 *xy, int N) {
 // ----------------------------------------------------------- field mode ----
 // Prologue: for each reference, its codes in ascending (code, member) order and
 // the member permutation; plus the harmonic table H[0..N] (sequential FP64 sum).
-__global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
+__global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code,
+                                    const uint16_t *__restrict__ order, int N,
                                     const int64_t *__restrict__ refs, int32_t *__restrict__ xs,
-                                    uint16_t *__restrict__ perm, double *__restrict__ H) {
+                                    uint16_t *__restrict__ perm, uint16_t *__restrict__ invp,
+                                    double *__restrict__ H) {
     extern __shared__ unsigned long long s_keys[];
     const int r = blockIdx.x;
     const int P = pow2_ceil(N);
     const int32_t *c = code + refs[r] * N;
-    for (int m = threadIdx.x; m < P; m += kKsgThreads)
-        s_keys[m] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
-    __syncthreads();
-    block_bitonic_sort(s_keys, P);
-    for (int p = threadIdx.x; p < N; p += kKsgThreads) {
-        xs[(int64_t)r * N + p] = (int32_t)(s_keys[p] >> 16);
-        perm[(int64_t)r * N + p] = (uint16_t)(s_keys[p] & 0xffff);
+    if (order) {  // the column's stored order
+        const uint16_t *o = order + refs[r] * N;
+        for (int p = threadIdx.x; p < N; p += kKsgThreads) {
+            const int m = o[p];
+            xs[(int64_t)r * N + p] = c[m];
+            perm[(int64_t)r * N + p] = (uint16_t)m;
+            invp[(int64_t)r * N + m] = (uint16_t)p;
+        }
+    } else {
+        for (int m = threadIdx.x; m < P; m += kKsgThreads)
+            s_keys[m] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
+        __syncthreads();
+        block_bitonic_sort(s_keys, P);
+        for (int p = threadIdx.x; p < N; p += kKsgThreads) {
+            const int m = (int)(s_keys[p] & 0xffff);
+            xs[(int64_t)r * N + p] = (int32_t)(s_keys[p] >> 16);
+            perm[(int64_t)r * N + p] = (uint16_t)m;
+            invp[(int64_t)r * N + m] = (uint16_t)p;
+        }
     }
     if (r == 0 && threadIdx.x == 0) {
         double h = 0.0;
@@ -440,6 +454,53 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code, int N,
         for (int i = 1; i <= N; ++i) {
             h += 1.0 / (double)i;
             H[i] = h;
+        }
+    }
+}
+
+// Every column's members in ascending (code, member) order: the sorted orders of
+// the neighbour search, built once per ensemble.  Persistent workgroups, one
+// column at a time.
+template <int E>
+__device__ __forceinline__ void sort_column_e(const int32_t *__restrict__ c, int N,
+                                              uint16_t *__restrict__ o,
+                                              unsigned long long *xchg) {
+    const int tid = threadIdx.x;
+    unsigned long long k[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int m = E * tid + j;
+        k[j] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
+    }
+    block_sort_regs<E>(k, xchg);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int p = E * tid + j;
+        if (p < N) o[p] = (uint16_t)(k[j] & 0xffff);
+    }
+}
+
+__global__ __launch_bounds__(kKsgThreads) void ksg_order_kernel(const int32_t *__restrict__ code,
+                                                                int N, int64_t ncol,
+                                                                uint16_t *__restrict__ order) {
+    extern __shared__ unsigned long long s_x[];
+    const int P = max(pow2_ceil(N), kKsgThreads);
+    for (int64_t v = blockIdx.x; v < ncol; v += gridDim.x) {
+        const int32_t *c = code + v * N;
+        uint16_t *o = order + v * N;
+        if (P <= kKsgThreads)
+            sort_column_e<1>(c, N, o, s_x);
+        else if (P <= 2 * kKsgThreads)
+            sort_column_e<2>(c, N, o, s_x);
+        else if (P <= 4 * kKsgThreads)
+            sort_column_e<4>(c, N, o, s_x);
+        else {
+            for (int m = threadIdx.x; m < P; m += kKsgThreads)
+                s_x[m] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
+            __syncthreads();
+            block_bitonic_sort(s_x, P);
+            for (int p = threadIdx.x; p < N; p += kKsgThreads) o[p] = (uint16_t)(s_x[p] & 0xffff);
+            __syncthreads();
         }
     }
 }
@@ -453,11 +514,13 @@ __host__ __device__ inline size_t ksg_lds_bytes(int N, int P) {
 }
 
 template <int K>
-__global__ __launch_bounds__(kKsgThreads) void ksg_field_kernel(
+__global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))) void ksg_field_kernel(
     const int32_t *__restrict__ code_q, const int32_t *__restrict__ flags_r,
     const int32_t *__restrict__ flags_q, int N, int64_t V, const int64_t *__restrict__ refs,
     int n_ref, const int32_t *__restrict__ xs_all, const uint16_t *__restrict__ perm_all,
-    const double *__restrict__ H, float *__restrict__ out, int32_t *__restrict__ counts) {
+    const double *__restrict__ H, float *__restrict__ out, int32_t *__restrict__ counts,
+    const int32_t *__restrict__ code_r, const uint16_t *__restrict__ order_q,
+    const uint16_t *__restrict__ invp_all) {
     extern __shared__ int4 s_raw[];
     const int P = max(pow2_ceil(N), kKsgThreads);  // y-order region
     int2 *xo = reinterpret_cast<int2 *>(s_raw) + kPad;
@@ -490,12 +553,31 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_field_kernel(
                     for (int i = tid; i < 2 * N; i += kKsgThreads) cnt[i] = 0;
                 continue;
             }
-            // the query's codes: one coalesced row read, permuted into x order in LDS
-            for (int m = tid; m < N; m += kKsgThreads) tmp[m] = cq[m];
-            __syncthreads();
-            for (int p = tid; p < N; p += kKsgThreads) xo[p].y = tmp[perm[p]];
-            __syncthreads();
-            build_y_order(xo, yo, yrank, N, P);
+            if (order_q) {
+                // both orders from stored ones: the query codes in x order, and the
+                // query's own sorted order for (y, x) and the y ranks
+                const uint16_t *oq = order_q + q * N;
+                const int32_t *cr = code_r + refs[r] * N;
+                const uint16_t *invp = invp_all + (int64_t)r * N;
+                for (int p = tid; p < N; p += kKsgThreads) xo[p].y = cq[perm[p]];
+                for (int j = tid; j < N; j += kKsgThreads) {
+                    const int m = oq[j];
+                    yo[j] = make_int2(cq[m], cr[m]);
+                    yrank[invp[m]] = (uint16_t)j;
+                }
+                if (tid < kPad) {
+                    yo[-1 - tid] = make_int2(-kFar, 0);
+                    yo[N + tid] = make_int2(kFar, 0);
+                }
+                __syncthreads();
+            } else {
+                // the query's codes: one coalesced row read, permuted into x order in LDS
+                for (int m = tid; m < N; m += kKsgThreads) tmp[m] = cq[m];
+                __syncthreads();
+                for (int p = tid; p < N; p += kKsgThreads) xo[p].y = tmp[perm[p]];
+                __syncthreads();
+                build_y_order(xo, yo, yrank, N, P);
+            }
             const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
             if (tid == 0) out[(int64_t)r * V + q] = (float)(base - acc / (double)N);
             __syncthreads();
@@ -505,11 +587,12 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_field_kernel(
 
 // ----------------------------------------------------------- pairs mode ----
 template <int K>
-__global__ __launch_bounds__(kKsgThreads) void ksg_pairs_kernel(
+__global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))) void ksg_pairs_kernel(
     const int32_t *__restrict__ code_a, const int32_t *__restrict__ code_b,
     const int32_t *__restrict__ flags_a, const int32_t *__restrict__ flags_b, int N, int64_t V,
     const int64_t *__restrict__ pairs, int64_t B, const double *__restrict__ H,
-    float *__restrict__ out, int32_t *__restrict__ counts) {
+    float *__restrict__ out, int32_t *__restrict__ counts, const uint16_t *__restrict__ order_a,
+    const uint16_t *__restrict__ order_b) {
     extern __shared__ int4 s_raw[];
     const int P = max(pow2_ceil(N), kKsgThreads);  // y-order region
     int2 *xo = reinterpret_cast<int2 *>(s_raw) + kPad;
@@ -537,8 +620,32 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_pairs_kernel(
                 for (int i = tid; i < 2 * N; i += kKsgThreads) cnt[i] = 0;
             continue;
         }
-        build_x_order(code_a + va * N, code_b + vb * N, N, P, xo, perm, yo);
-        build_y_order(xo, yo, yrank, N, P);
+        const int32_t *ca = code_a + va * N, *cb = code_b + vb * N;
+        if (order_a) {
+            // x order = a's stored order, y order = b's; epsL holds the inverse
+            // x permutation until the walk
+            const uint16_t *oa = order_a + va * N, *ob = order_b + vb * N;
+            for (int p = tid; p < N; p += kKsgThreads) {
+                const int m = oa[p];
+                perm[p] = (uint16_t)m;
+                xo[p] = make_int2(ca[m], cb[m]);
+                epsL[m] = p;
+            }
+            __syncthreads();
+            for (int j = tid; j < N; j += kKsgThreads) {
+                const int m = ob[j];
+                yo[j] = make_int2(cb[m], ca[m]);
+                yrank[epsL[m]] = (uint16_t)j;
+            }
+            if (tid < kPad) {
+                yo[-1 - tid] = make_int2(-kFar, 0);
+                yo[N + tid] = make_int2(kFar, 0);
+            }
+            __syncthreads();
+        } else {
+            build_x_order(ca, cb, N, P, xo, perm, yo);
+            build_y_order(xo, yo, yrank, N, P);
+        }
         const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
         if (tid == 0) out[b] = (float)(base - acc / (double)N);
         __syncthreads();
@@ -563,11 +670,13 @@ static int p2(int n) {
     return p;
 }
 
+// Workspace: H[0..N] | refs | x codes in x order [n_ref][N] | x-order members
+// [n_ref][N] | inverse x permutation [n_ref][N].
 size_t ksg_field_ws_bytes(int N, int n_ref) {
     return align_up((size_t)(N + 1) * sizeof(double), 256) +
            align_up((size_t)n_ref * sizeof(int64_t), 256) +
            align_up((size_t)n_ref * N * sizeof(int32_t), 256) +
-           align_up((size_t)n_ref * N * sizeof(uint16_t), 256);
+           2 * align_up((size_t)n_ref * N * sizeof(uint16_t), 256);
 }
 
 // Persistent workgroups: as many as the CUs hold at once given the LDS of one
@@ -579,13 +688,37 @@ static int resident_grid(int64_t items, size_t lds) {
     return (int)(items < g ? items : g);
 }
 
+struct FieldArgs {
+    const int32_t *cq, *fr, *fq;
+    int N;
+    int64_t V;
+    const int64_t *refs;
+    int n_ref;
+    const int32_t *xs;
+    const uint16_t *perm;
+    const double *H;
+    float *out;
+    int32_t *counts;
+    const int32_t *cr;
+    const uint16_t *order_q, *invp;
+};
+
 template <int K>
-static void launch_field_k(dim3 g, size_t lds, hipStream_t st, const int32_t *cq, const int32_t *fr,
-                           const int32_t *fq, int N, int64_t V, const int64_t *refs, int n_ref,
-                           const int32_t *xs, const uint16_t *perm, const double *H, float *out,
-                           int32_t *counts) {
-    hipLaunchKernelGGL(ksg_field_kernel<K>, g, dim3(kKsgThreads), lds, st, cq, fr, fq, N, V, refs, n_ref, xs,
-                       perm, H, out, counts);
+static void launch_field_k(dim3 g, size_t lds, hipStream_t st, const FieldArgs &a) {
+    hipLaunchKernelGGL(ksg_field_kernel<K>, g, dim3(kKsgThreads), lds, st, a.cq, a.fr, a.fq, a.N,
+                       a.V, a.refs, a.n_ref, a.xs, a.perm, a.H, a.out, a.counts, a.cr, a.order_q,
+                       a.invp);
+}
+
+// Sorted member orders of every column of every variable (ndf_prepare).
+int launch_ksg_orders(const ndf_ensemble *e, hipStream_t st) {
+    const int N = e->n_members;
+    const int64_t ncol = (int64_t)e->n_vars * e->nx * e->ny * e->nz;
+    const int P = p2(N) < kKsgThreads ? kKsgThreads : p2(N);
+    const size_t lds = (size_t)P * sizeof(unsigned long long);
+    hipLaunchKernelGGL(ksg_order_kernel, dim3((unsigned)resident_grid(ncol, lds)),
+                       dim3(kKsgThreads), lds, st, e->code, N, ncol, e->order);
+    return status_of_launch();
 }
 
 int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int64_t *ref_v,
@@ -600,21 +733,25 @@ int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int6
     int32_t *xs = (int32_t *)w;
     w += align_up((size_t)n_ref * N * sizeof(int32_t), 256);
     uint16_t *perm = (uint16_t *)w;
+    w += align_up((size_t)n_ref * N * sizeof(uint16_t), 256);
+    uint16_t *invp = (uint16_t *)w;
     if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return NDF_E_HIP;
     const int P = p2(N);
     const int32_t *cr = e->code + (int64_t)var_ref * V * N;
     const int32_t *cq = e->code + (int64_t)var_qry * V * N;
+    const uint16_t *ordr = e->order ? e->order + (int64_t)var_ref * V * N : nullptr;
+    const uint16_t *ordq = e->order ? e->order + (int64_t)var_qry * V * N : nullptr;
     hipLaunchKernelGGL(ksg_sort_ref_kernel, dim3(n_ref), dim3(kKsgThreads), (size_t)P * 8, st, cr,
-                       N, refs, xs, perm, H);
+                       ordr, N, refs, xs, perm, invp, H);
     const size_t lds = ksg_lds_bytes(N, P < kKsgThreads ? kKsgThreads : P);
     const dim3 g((unsigned)resident_grid(V, lds));
-    const int32_t *fr = e->flags + (int64_t)var_ref * V;
-    const int32_t *fq = e->flags + (int64_t)var_qry * V;
+    const FieldArgs a{cq, e->flags + (int64_t)var_ref * V, e->flags + (int64_t)var_qry * V,
+                      N, V, refs, n_ref, xs, perm, H, out, counts, cr, ordq, invp};
     switch (k) {
 #define NDF_KSG_CASE(KK) \
-    case KK: launch_field_k<KK>(g, lds, st, cq, fr, fq, N, V, refs, n_ref, xs, perm, H, out, counts); break;
+    case KK: launch_field_k<KK>(g, lds, st, a); break;
         NDF_KSG_CASE(1) NDF_KSG_CASE(2) NDF_KSG_CASE(3) NDF_KSG_CASE(4)
         NDF_KSG_CASE(5) NDF_KSG_CASE(6) NDF_KSG_CASE(7) NDF_KSG_CASE(8)
 #undef NDF_KSG_CASE
@@ -637,11 +774,13 @@ int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t 
     const int32_t *cb = e->code + (int64_t)var_b * V * N;
     const int32_t *fa = e->flags + (int64_t)var_a * V;
     const int32_t *fb = e->flags + (int64_t)var_b * V;
+    const uint16_t *oa = e->order ? e->order + (int64_t)var_a * V * N : nullptr;
+    const uint16_t *ob = e->order ? e->order + (int64_t)var_b * V * N : nullptr;
     switch (k) {
 #define NDF_KSG_CASE(KK)                                                                       \
     case KK:                                                                                   \
         hipLaunchKernelGGL(ksg_pairs_kernel<KK>, g, dim3(kKsgThreads), lds, st, ca, cb, fa, fb, N, V, \
-                           pairs, B, H, out, counts);                                             \
+                           pairs, B, H, out, counts, oa, ob);                                     \
         break;
         NDF_KSG_CASE(1) NDF_KSG_CASE(2) NDF_KSG_CASE(3) NDF_KSG_CASE(4)
         NDF_KSG_CASE(5) NDF_KSG_CASE(6) NDF_KSG_CASE(7) NDF_KSG_CASE(8)

@@ -37,7 +37,8 @@ class ndf_ensemble(ctypes.Structure):
     _fields_ = [("n_members", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("n_vars", ctypes.c_int32), ("x", ctypes.c_void_p),
                 ("mean", ctypes.c_void_p), ("inv_std", ctypes.c_void_p),
-                ("code", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+                ("code", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("order", ctypes.c_void_p)]
 
 
 class ndf_net_config(ctypes.Structure):
@@ -115,9 +116,10 @@ def _ws(nbytes, device):
 # ------------------------------------------------------------------ ensemble --
 class Ensemble:
     """Device ensemble x[n_vars][N][V] (float32, member-major) plus the per-vertex
-    statistics and KSG codes that ndf_prepare fills in."""
+    statistics, KSG codes and (with orders=True) per-vertex sorted member orders
+    that ndf_prepare fills in."""
 
-    def __init__(self, x: torch.Tensor, nx: int, ny: int, nz: int):
+    def __init__(self, x: torch.Tensor, nx: int, ny: int, nz: int, orders: bool = True):
         if x.dim() == 2:
             x = x.unsqueeze(0)
         assert x.dtype == torch.float32 and x.is_contiguous()
@@ -131,9 +133,13 @@ class Ensemble:
         self.inv_std = torch.empty((n_vars, V), dtype=torch.float64, device=dev)
         self.code = torch.empty((n_vars, V, N), dtype=torch.int32, device=dev)
         self.flags = torch.empty((n_vars, V), dtype=torch.int32, device=dev)
+        # uint16 member indices, held in an int16 tensor
+        self.order = (torch.empty((n_vars, V, N), dtype=torch.int16, device=dev)
+                      if orders else None)
         self.c = ndf_ensemble(N, nx, ny, nz, n_vars, x.data_ptr(), self.mean.data_ptr(),
                               self.inv_std.data_ptr(), self.code.data_ptr(),
-                              self.flags.data_ptr())
+                              self.flags.data_ptr(),
+                              self.order.data_ptr() if orders else None)
 
     @property
     def device(self):

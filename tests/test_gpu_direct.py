@@ -188,6 +188,26 @@ def test_odd_member_count_all_estimators():
         assert abs(mi[b] - w[0]) <= MI_TOL
 
 
+def test_ksg_without_stored_orders_matches(mid):
+    """An ensemble prepared without the per-vertex sorted orders (order = NULL):
+    the KSG kernels sort every column themselves and give bit-identical fields,
+    counts and pair estimates."""
+    cfg = gen.CONFIGS["mid"]
+    e = ndf.Ensemble(mid.x, cfg.nx, cfg.ny, cfg.nz, orders=False)
+    ndf.ndf_prepare(e)
+    refs = [cfg.ref_v, 7]
+    a, ca = ndf.ksg_field(mid, refs, k=4, counts=True)
+    b, cb = ndf.ksg_field(e, refs, k=4, counts=True)
+    assert torch.equal(a, b) and torch.equal(ca, cb)
+    pairs = gen.random_pairs(cfg.n_vertices, 200, seed=8)
+    assert torch.equal(ndf.ksg_pairs(mid, pairs), ndf.ksg_pairs(e, pairs))
+    # the stored orders themselves: ascending codes, ties by member index
+    codes = mid.code[0].cpu().numpy().astype(np.int64)
+    order = mid.order[0].cpu().numpy().astype(np.int64) & 0xFFFF
+    keys = codes * 65536 + np.arange(cfg.n_members)[None, :]
+    assert np.array_equal(np.take_along_axis(keys, order, axis=1), np.sort(keys, axis=1))
+
+
 def test_pairs_out_of_range_give_nan(mid):
     pairs = np.array([[0, 1], [-1, 3], [5, mid.n_vertices]], dtype=np.int64)
     r = ndf.pearson_pairs(mid, pairs).cpu().numpy()
