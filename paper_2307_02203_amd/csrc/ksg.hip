@@ -480,11 +480,82 @@ __device__ __forceinline__ void sort_column_e(const int32_t *__restrict__ c, int
     }
 }
 
+// One wave sorts 64 E keys held E per lane (lane l holds keys E l .. E l + E - 1):
+// partners closer than E are in the lane's registers, all others are lane
+// shuffles; no LDS and no barrier.
+template <int E>
+__device__ __forceinline__ void wave_sort_regs(unsigned long long (&k)[E]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int PT = 64 * E;
+    for (int size = 2; size <= PT; size <<= 1) {
+        for (int stride = size >> 1; stride >= E; stride >>= 1) {
+            const bool keep_min = ((E * lane & stride) == 0) == ((E * lane & size) == 0);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const unsigned long long o = __shfl_xor(k[j], stride / E, kWave);
+                k[j] = ((o < k[j]) == keep_min) ? o : k[j];
+            }
+        }
+#pragma unroll
+        for (int st = E / 2; st >= 1; st >>= 1) {
+            if (st >= size) continue;
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int jp = j ^ st;
+                if (jp < j) continue;
+                const bool up = ((E * lane + j) & size) == 0;
+                const unsigned long long a = k[j], b = k[jp];
+                const bool swap = (a > b) == up;
+                k[j] = swap ? b : a;
+                k[jp] = swap ? a : b;
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort_column(const int32_t *__restrict__ c, int N,
+                                                 uint16_t *__restrict__ o) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long k[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int m = E * lane + j;
+        k[j] = m < N ? (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m : ~0ull;
+    }
+    wave_sort_regs<E>(k);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int p = E * lane + j;
+        if (p < N) o[p] = (uint16_t)(k[j] & 0xffff);
+    }
+}
+
 __global__ __launch_bounds__(kKsgThreads) void ksg_order_kernel(const int32_t *__restrict__ code,
                                                                 int N, int64_t ncol,
                                                                 uint16_t *__restrict__ order) {
     extern __shared__ unsigned long long s_x[];
-    const int P = max(pow2_ceil(N), kKsgThreads);
+    const int P2 = pow2_ceil(N);
+    if (P2 <= 1024) {  // one column per wave
+        const int64_t waves = (int64_t)gridDim.x * kKsgWaves;
+        for (int64_t v = (int64_t)blockIdx.x * kKsgWaves + (threadIdx.x >> 6); v < ncol;
+             v += waves) {
+            const int32_t *c = code + v * N;
+            uint16_t *o = order + v * N;
+            if (P2 <= 64)
+                wave_sort_column<1>(c, N, o);
+            else if (P2 <= 128)
+                wave_sort_column<2>(c, N, o);
+            else if (P2 <= 256)
+                wave_sort_column<4>(c, N, o);
+            else if (P2 <= 512)
+                wave_sort_column<8>(c, N, o);
+            else
+                wave_sort_column<16>(c, N, o);
+        }
+        return;
+    }
+    const int P = max(P2, kKsgThreads);
     for (int64_t v = blockIdx.x; v < ncol; v += gridDim.x) {
         const int32_t *c = code + v * N;
         uint16_t *o = order + v * N;
