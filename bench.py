@@ -13,6 +13,8 @@ Workload: synthetic paper-shaped ensemble (1000 members on 250x352x20 =
   train_step     one learned-field training step on 2^18 pairs (BF16 MFMA, Adam)
   ndf_field      learned field for 1 reference at all vertices (fused BF16 kernel)
   ndf_field_fp8  the same field with MXFP8 (E4M3) layers 2..5
+  ndf_field_cached  the same field from cached query latents (merge + decoder
+                 only; the cache is built once per trained network, untimed)
 
 `value` is the learned-field ms per field (the paper's headline quantity);
 `fields` gives every row.  All launches go on torch's current stream and are
@@ -58,7 +60,8 @@ def _parse():
                     help="training steps of the second learned field (KSG-MI targets)")
     ap.add_argument("--only", default=None,
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
-                         "targets, train_step, ndf_field) W+K times and exit")
+                         "targets, train_step, ndf_field, ndf_field_fp8, ndf_field_cached) "
+                         "W+K times and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -147,6 +150,15 @@ def main():
     final_loss = loss.item()
     ndf.ndf_net_quantize(net, P, ndf.NDF_PREC_BF16, qp)
     step_no = [n_train]
+    # query-latent cache of the trained network (for the cached-field row)
+    cache = torch.empty(ndf.ndf_infer_latent_bytes(net), dtype=torch.uint8, device=dev)
+    ev_c0, ev_c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev_c0.record()
+    ndf.ndf_infer_latents(net, qp, cache)
+    ev_c1.record()
+    torch.cuda.synchronize()
+    cache_ms = ev_c0.elapsed_time(ev_c1)
+    out_nc = torch.empty((1, V), device=dev)
 
     # one network per measure: a second field trained on KSG-MI targets (same
     # architecture, so its inference cost is the timed ndf_field row)
@@ -173,7 +185,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     rows = ["prepare", "pearson_fp32", "pearson_b64", "ksg_field", "targets", "train_step",
-            "ndf_field", "ndf_field_fp8"]
+            "ndf_field", "ndf_field_fp8", "ndf_field_cached"]
 
     def row_prepare(it):
         ndf.ndf_prepare(ens)
@@ -202,7 +214,11 @@ def main():
     def row_ndf_field_fp8(it):
         ndf.ndf_infer_field(net, qp, ndf.NDF_PREC_FP8_E4M3, [ref], out_n8, ws_i)
 
-    row_fn = {"ndf_field_fp8": row_ndf_field_fp8, "prepare": row_prepare,
+    def row_ndf_field_cached(it):
+        ndf.ndf_infer_field_cached(net, qp, [ref], cache, out_nc, ws_i)
+
+    row_fn = {"ndf_field_fp8": row_ndf_field_fp8, "ndf_field_cached": row_ndf_field_cached,
+              "prepare": row_prepare,
               "pearson_fp32": row_pearson_fp32,
               "pearson_b64": row_pearson_b64, "ksg_field": row_ksg_field,
               "targets": row_targets, "train_step": row_train_step, "ndf_field": row_ndf_field}
@@ -250,6 +266,8 @@ def main():
     fields = {
         "ndf_field_bf16": med["ndf_field"],
         "ndf_field_fp8": med["ndf_field_fp8"],
+        "ndf_field_bf16_cached_query_latents": med["ndf_field_cached"],
+        "ndf_query_latent_cache_build_once": cache_ms,
         "pearson_field_fp32": med["pearson_fp32"],
         "pearson_batch64_split_bf16_per_field": med["pearson_b64"] / N_BATCH,
         "pearson_batch64_split_bf16_total": med["pearson_b64"],
@@ -270,6 +288,11 @@ def main():
         "ndf_field_fp8": {"bound": "mfma", "achieved": 2.0 * 69760 * V
                           / (med["ndf_field_fp8"] * 1e-3) / 1e12, "peak": PEAK_FP8_TFLOPS,
                           "unit": "TFLOP/s"},
+        # merge + decoder: 32,896 MAC per vertex, plus 256 B of cached latent read
+        "ndf_field_cached": {"bound": "mfma", "achieved": 2.0 * 32896 * V
+                             / (med["ndf_field_cached"] * 1e-3) / 1e12,
+                             "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                             "hbm_gbs": 256.0 * V / (med["ndf_field_cached"] * 1e-3) / 1e9},
     }
     for r in roof.values():
         r["frac"] = r["achieved"] / r["peak"]
@@ -312,7 +335,7 @@ def main():
 
     if not a.no_accuracy:
         acc, sample, r_o, mi_o = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi,
-                                           refs64, cfg)
+                                           refs64, cfg, out_nc)
         result["accuracy"] = acc
         log("bench: gain of the trained field over the method without it")
         result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log)
@@ -378,7 +401,7 @@ def _measured_traffic(row):
 N_MI_SAMPLE = 400   # vertices of the oracle KSG-MI comparison (brute force on the host)
 
 
-def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi, refs64, cfg):
+def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi, refs64, cfg, out_nc):
     """Errors of the timed outputs against the FP64 oracle on sampled vertices."""
     import torch
     import gen
@@ -410,6 +433,7 @@ def _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi, refs64, cfg):
         "ndf_vs_oracle_pearson_max_abs_err": float(np.max(np.abs(n - r_o))),
         "ndf_fp8_vs_oracle_pearson_mae": float(np.mean(np.abs(n8 - r_o))),
         "ndf_fp8_vs_ndf_bf16_max_abs_diff": float(np.max(np.abs(n8 - n))),
+        "ndf_cached_equals_fused_bitwise": bool(torch.equal(out_nc, out_n)),
         "population_rho_mae_of_oracle": float(np.mean(np.abs(
             r_o - gen.population_rho(cfg, np.full(len(sample), cfg.ref_v), sample)))),
     }, sample, r_o, mi_o

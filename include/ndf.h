@@ -185,7 +185,8 @@ int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, i
 
 /* Inference parameters for `prec` (NDF_PREC_BF16 or NDF_PREC_FP8_E4M3) packed
  * from the FP32 parameters: BF16 grids, weights in MFMA operand order, FP32
- * biases; FP8 adds per-output-channel weight scales. */
+ * biases; FP8 adds E8M0 scales per output row and block of 32 inputs.  One
+ * packed blob serves both precisions. */
 size_t ndf_net_qparam_bytes(const ndf_net_config *cfg, int32_t prec);
 int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t prec,
                      void *qparams, void *stream);
@@ -197,6 +198,20 @@ int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t pre
 int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec,
                     const int64_t *ref_v, int32_t n_ref, float *out, void *ws,
                     size_t ws_bytes, void *stream);
+
+/* Many fields of one trained network (interactive exploration of references,
+ * Sec. 5): the query latents e(p_v) do not depend on the reference, so they can
+ * be computed once.  ndf_infer_latents writes the BF16 latents of the query
+ * encoder for every grid vertex into `cache` (device, ndf_infer_latent_bytes
+ * bytes, caller-owned; the fused kernel's register order, 256 bytes per
+ * vertex); ndf_infer_field_cached then runs only the merge and the decoder per
+ * reference and gives the same values as ndf_infer_field with NDF_PREC_BF16,
+ * bit for bit.  ws as for ndf_infer_field (BF16). */
+size_t ndf_infer_latent_bytes(const ndf_net_config *cfg);
+int ndf_infer_latents(const ndf_net_config *cfg, const void *qparams, void *cache, void *stream);
+int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const int64_t *ref_v,
+                           int32_t n_ref, const void *cache, float *out, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /* Phi(p1, p2) for B vertex pairs (device int64[B][2]) from the FP32 parameters
  * with the training forward kernels (BF16 MFMA, FP32 accumulate); y float[B]. */

@@ -229,4 +229,28 @@ int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec
     return launch_infer_field(cfg, qparams, prec, ref_v, n_ref, out, ws, S(stream));
 }
 
+size_t ndf_infer_latent_bytes(const ndf_net_config *cfg) {
+    return check_net_config(cfg) == NDF_OK ? net_latent_cache_bytes(cfg) : 0;
+}
+
+int ndf_infer_latents(const ndf_net_config *cfg, const void *qparams, void *cache, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!qparams || !cache) return NDF_E_ARG;
+    return launch_infer_latents(cfg, qparams, cache, S(stream));
+}
+
+int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const int64_t *ref_v,
+                           int32_t n_ref, const void *cache, float *out, void *ws,
+                           size_t ws_bytes, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!qparams || !cache || !out || !ref_v || n_ref < 1) return NDF_E_ARG;
+    const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    for (int r = 0; r < n_ref; ++r)
+        if (ref_v[r] < 0 || ref_v[r] >= V) return NDF_E_ARG;
+    if (!ws || ws_bytes < net_infer_ws_bytes(cfg, n_ref, NDF_PREC_BF16)) return NDF_E_WORKSPACE;
+    return launch_infer_field_cached(cfg, qparams, ref_v, n_ref, cache, out, ws, S(stream));
+}
+
 }  // extern "C"

@@ -149,6 +149,10 @@ int launch_adam(const ndf_net_config *c, float *params, float *opt, const float 
                 int64_t step, float lr, hipStream_t st);
 int launch_net_quantize(const ndf_net_config *c, const float *params, int prec, void *q,
                         hipStream_t st);
+size_t net_latent_cache_bytes(const ndf_net_config *c);
+int launch_infer_latents(const ndf_net_config *c, const void *q, void *cache, hipStream_t st);
+int launch_infer_field_cached(const ndf_net_config *c, const void *q, const int64_t *ref_v,
+                              int n_ref, const void *cache, float *out, void *ws, hipStream_t st);
 int launch_infer_field(const ndf_net_config *c, const void *q, int prec, const int64_t *ref_v,
                        int n_ref, float *out, void *ws, hipStream_t st);
 

@@ -261,7 +261,14 @@ __device__ __forceinline__ void corners32(const GridGeom &g, const int R[3], int
     corners_R32(g, R, v, idx, w);
 }
 
-enum { LAY_RELU = 0, LAY_LATENT = 1, LAY_HEAD = 2, LAY_LATENT_OUT = 3 };
+enum { LAY_RELU = 0, LAY_LATENT = 1, LAY_HEAD = 2, LAY_LATENT_OUT = 3, LAY_LATENT_CACHE = 4 };
+
+// Query-latent cache: the bf16 latents of 64-vertex tiles in the B-operand
+// register order of the fused kernel, [tile][k-block 8][query half 2][lane 64]
+// 16-byte chunks (16 KB per tile), so a tile reloads with 16 coalesced loads.
+__device__ __forceinline__ int64_t cache_chunk(int64_t tile, int kb, int q, int lane) {
+    return ((tile * 8 + kb) * 2 + q) * 64 + lane;
+}
 
 typedef __attribute__((ext_vector_type(2))) short s16x2;
 typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
@@ -346,7 +353,8 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                     if (KIND == LAY_RELU) {
                         p0 = relu_bf16x2(p0);
                         p1 = relu_bf16x2(p1);
-                    } else {  // latent: bf16 values (exact products with the bf16 reference)
+                    } else if (KIND != LAY_LATENT_CACHE) {  // latent: bf16 values (exact
+                                                            // products with the bf16 reference)
                         const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
                         if (KIND == LAY_LATENT_OUT) {
                             const int64_t n0 = row0 + (lane & 31), n1 = n0 + 32;
@@ -371,6 +379,11 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                 if (KIND == LAY_RELU || KIND == LAY_LATENT) {
                     out[2 * ob + s][0] = __builtin_bit_cast(bf16x8, t0);
                     out[2 * ob + s][1] = __builtin_bit_cast(bf16x8, t1);
+                } else if (KIND == LAY_LATENT_CACHE) {
+                    u32x4 *cache = reinterpret_cast<u32x4 *>(lat_out);
+                    const int64_t tile = row0 / 64;
+                    cache[cache_chunk(tile, 2 * ob + s, 0, lane)] = t0;
+                    cache[cache_chunk(tile, 2 * ob + s, 1, lane)] = t1;
                 }
             }
         }
@@ -381,7 +394,8 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 }
 
 // MODE 0: field (out[v] = Phi(ref, v) for v < nq); MODE 1: latents of the
-// vertices in qlist (lat_out[n][128], bf16-rounded values stored as FP32).
+// vertices in qlist (lat_out[n][128], bf16-rounded values stored as FP32);
+// MODE 2: latents of vertices 0 .. nq-1 into the query-latent cache (out).
 template <int MODE>
 __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const int64_t *__restrict__ qlist,
@@ -396,7 +410,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
 
     const int tid = threadIdx.x;
     for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
-    const int nlay = MODE == 0 ? 4 : 2;  // latent mode needs W2, W3 only
+    const int nlay = MODE == 0 ? 4 : 2;  // latent modes need W2, W3 only
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
@@ -462,6 +476,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         if (MODE == 1) {
             dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, out, row0, ok,
                                            lane, h4);
+            continue;
+        }
+        if (MODE == 2) {
+            dense_layer<8, LAY_LATENT_CACHE>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, out, row0,
+                                             ok, lane, h4);
             continue;
         }
         dense_layer<8, LAY_LATENT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, nullptr, row0, ok,
@@ -774,6 +793,70 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     }
 }
 
+// The field from cached query latents: per 64-vertex tile, 16 loads of the bf16
+// latents, the product with the reference latent (the same packed arithmetic as
+// the uncached kernel, so both give the same bits), then layers 4, 5 and w6.
+// Only W4 and W5 (64 KB) live in LDS.
+__global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A,
+                                                                      const u32x4 *__restrict__ cache,
+                                                                      int64_t nq,
+                                                                      const float *__restrict__ ref_lat,
+                                                                      float *__restrict__ out) {
+    __shared__ bf16x8 s_w[2][kFragW];
+    __shared__ __attribute__((aligned(16))) float s_b[2][kH];
+    __shared__ __attribute__((aligned(16))) float s_w6[kH];
+    __shared__ __attribute__((aligned(16))) float s_ref[kH];
+    const int tid = threadIdx.x;
+    for (int L = 0; L < 2; ++L)
+        for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 3][i];
+    for (int i = tid; i < 2 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[3 + i / kH][i % kH];
+    for (int i = tid; i < kH; i += kInferThreads) {
+        s_w6[i] = A.w6[i];
+        s_ref[i] = ref_lat[i];
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    const float b6 = A.b6[0];
+    const int64_t ntiles = ceil_div(nq, 64);
+    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
+         tile += (int64_t)gridDim.x * kInferWaves) {
+        const int64_t row0 = tile * 64;
+        int h4 = 4 * h;
+        asm volatile("" : "+v"(h4));
+        bool ok[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) ok[q] = row0 + q * 32 + jl < nq;
+        const float *ref_h = s_ref + h4;
+        bf16x8 a[8][2], b[8][2];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const u32x4 lat = __builtin_nontemporal_load(cache + cache_chunk(tile, kb, q, lane));
+                // k-block kb = 2 ob + s holds rows r = 8 s + 2 e2, r + 1 of output block ob
+                const int ob = kb >> 1, sb = kb & 1;
+                u32x4 t;
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) {
+                    const int r = 8 * sb + 2 * e2;
+                    const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
+                    const f32x2 rv = *reinterpret_cast<const f32x2 *>(ref_h + ic);
+                    t[e2] = pack_bf16x2(bf_lo(lat[e2]) * rv[0], bf_hi(lat[e2]) * rv[1]);
+                }
+                b[kb][q] = __builtin_bit_cast(bf16x8, t);
+            }
+        float part[2] = {0.f, 0.f};
+        dense_layer<8, LAY_RELU>(s_w[0], s_b[0], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
+        dense_layer<8, LAY_HEAD>(s_w[1], s_b[1], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
+            if (h == 0 && ok[q]) out[row0 + q * 32 + jl] = y;
+        }
+    }
+}
+
 static InferArgs8 make_args8(const ndf_net_config *c, const QLayout &q, const char *Q, int e) {
     InferArgs8 a{};
     for (int l = 0; l < kL; ++l) a.grid[l] = (const uint16_t *)(Q + q.grid[e][l]);
@@ -821,6 +904,39 @@ static unsigned infer_blocks(int64_t nq) {
     const int64_t tiles = ceil_div(nq, 64);
     const int64_t b = ceil_div(tiles, kInferWaves);
     return (unsigned)(b < 256 ? (b > 0 ? b : 1) : 256);  // one resident workgroup per CU
+}
+
+size_t net_latent_cache_bytes(const ndf_net_config *c) {
+    const int64_t V = (int64_t)c->nx * c->ny * c->nz;
+    return (size_t)ceil_div(V, 64) * 8 * 2 * 64 * 16;
+}
+
+int launch_infer_latents(const ndf_net_config *c, const void *qp, void *cache, hipStream_t st) {
+    const QLayout q = qlayout(c);
+    const InferArgs a = make_args(c, q, (const char *)qp, c->n_enc - 1);
+    hipLaunchKernelGGL(infer_kernel<2>, dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
+                       nullptr, a.V, nullptr, (float *)cache);
+    return status_of_launch();
+}
+
+int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int64_t *ref_v,
+                              int n_ref, const void *cache, float *out, void *ws, hipStream_t st) {
+    const QLayout q = qlayout(c);
+    const char *Q = (const char *)qp;
+    float *lat = (float *)ws;
+    int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return NDF_E_HIP;
+    const InferArgs a0 = make_args(c, q, Q, 0);
+    hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                       refs, (int64_t)n_ref, nullptr, lat);
+    const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
+    for (int r = 0; r < n_ref; ++r)
+        hipLaunchKernelGGL(infer_cached_kernel, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
+                           st, a1, (const u32x4 *)cache, a1.V, lat + (int64_t)r * kH,
+                           out + (int64_t)r * a1.V);
+    return status_of_launch();
 }
 
 int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const int64_t *ref_v,

@@ -26,6 +26,7 @@ EXPORTED = [
     "ndf_ksg_mi_field", "ndf_pearson_pairs", "ndf_ksg_mi_pairs", "ndf_net_param_bytes",
     "ndf_net_optstate_bytes", "ndf_net_init", "ndf_net_grad", "ndf_net_forward",
     "ndf_train_step", "ndf_net_qparam_bytes", "ndf_net_quantize", "ndf_infer_field",
+    "ndf_infer_latent_bytes", "ndf_infer_latents", "ndf_infer_field_cached",
 ]
 
 
@@ -81,6 +82,10 @@ def lib():
             "ndf_net_qparam_bytes": (_SZ, [C, _I32]),
             "ndf_net_quantize": (ctypes.c_int, [C, _VP, _I32, _VP, _VP]),
             "ndf_infer_field": (ctypes.c_int, [C, _VP, _I32, _VP, _I32, _VP, _VP, _SZ, _VP]),
+            "ndf_infer_latent_bytes": (_SZ, [C]),
+            "ndf_infer_latents": (ctypes.c_int, [C, _VP, _VP, _VP]),
+            "ndf_infer_field_cached": (ctypes.c_int, [C, _VP, _VP, _I32, _VP, _VP, _VP, _SZ,
+                                                      _VP]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -280,6 +285,22 @@ def ndf_infer_field(cfg, qparams, prec, ref_v, out, ws, stream=None):
 
 def train_ws_bytes(cfg, B):
     return ndf_workspace_bytes(NDF_OP_TRAIN, None, cfg, B, 0)
+
+
+def ndf_infer_latent_bytes(cfg):
+    return int(lib().ndf_infer_latent_bytes(ctypes.byref(cfg)))
+
+
+def ndf_infer_latents(cfg, qparams, cache, stream=None):
+    _check(lib().ndf_infer_latents(ctypes.byref(cfg), _p(qparams), _p(cache), _stream(stream)),
+           "ndf_infer_latents")
+
+
+def ndf_infer_field_cached(cfg, qparams, ref_v, cache, out, ws, stream=None):
+    refs, rp = _host_i64(ref_v)
+    _check(lib().ndf_infer_field_cached(ctypes.byref(cfg), _p(qparams), rp, len(refs), _p(cache),
+                                        _p(out), _p(ws), ws.numel(), _stream(stream)),
+           "ndf_infer_field_cached")
 
 
 def infer_ws_bytes(cfg, n_ref, prec):

@@ -120,3 +120,12 @@ def test_net_config_validation_and_param_bytes():
     assert (L.ndf_infer_field(C, FAKE, ndf.NDF_PREC_SPLIT_BF16,
                               refs.ctypes.data_as(ctypes.c_void_p), 1, FAKE, FAKE, 1 << 30, None)
             == ndf.NDF_E_UNSUPPORTED)
+    # query-latent cache: 256 bytes per vertex, V rounded up to 64-vertex tiles
+    assert ndf.ndf_infer_latent_bytes(cfg) == -(-250 * 352 * 20 // 64) * 64 * 256
+    assert ndf.ndf_infer_latent_bytes(bad) == 0
+    assert L.ndf_infer_latents(C, FAKE, None, None) == ndf.NDF_E_ARG
+    assert (L.ndf_infer_field_cached(C, FAKE, refs.ctypes.data_as(ctypes.c_void_p), 1, FAKE,
+                                     FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG)
+    ok_ref = np.array([5], dtype=np.int64)
+    assert (L.ndf_infer_field_cached(C, FAKE, ok_ref.ctypes.data_as(ctypes.c_void_p), 1, FAKE,
+                                     FAKE, FAKE, 16, None) == ndf.NDF_E_WORKSPACE)

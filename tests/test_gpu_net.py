@@ -217,6 +217,24 @@ def test_infer_field_parity(name, n_enc):
         _check_bf16(out[i], want, f"infer {name} n_enc={n_enc} ref={r}")
 
 
+@pytest.mark.parametrize("name,n_enc", [("mid", 1), ("mid", 2)])
+def test_infer_field_cached_latents_bitwise(name, n_enc):
+    """Fields from the query-latent cache equal the fused field bit for bit."""
+    cfg, lay, c, P, net = _setup(name, n_enc, seed=2328)
+    V = cfg.n_vertices
+    refs = [cfg.ref_v, 0, V - 1]
+    q = _qparams(c, P, ndf.NDF_PREC_BF16)
+    want = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
+    cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
+    ndf.ndf_infer_latents(c, q, cache)
+    out = torch.empty((len(refs), V), device="cuda")
+    ws = torch.empty(ndf.infer_ws_bytes(c, len(refs), ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                     device="cuda")
+    ndf.ndf_infer_field_cached(c, q, refs, cache, out, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(out, want)
+
+
 def test_infer_self_field_symmetric_bitwise():
     cfg, lay, c, P, net = _setup("mid", 1, seed=2324)
     V = cfg.n_vertices
