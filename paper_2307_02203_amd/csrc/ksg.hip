@@ -156,7 +156,7 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     // Every sample's walk order and start position, with all lanes busy:
     // epsL[p] = position | (walk in y order) << 16 until the walk of p ends.
     for (int pp = tid; pp < N; pp += kKsgThreads) {
-        const int q = yrank[pp];
+        const int q = min((int)yrank[pp], N - 1);
         // spread of the 2k nearest codes in each order: walk the sparser one
         const int sx = xo[min(pp + K, N - 1)].x - xo[max(pp - K, 0)].x;
         const int sy = yo[min(q + K, N - 1)].x - yo[max(q - K, 0)].x;
@@ -169,7 +169,9 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         const int info = epsL[pp];
         const bool walk_y = info >= 0x10000;
         A = walk_y ? yo : xo;
-        const int pos = info & 0xffff;
+        // a walk starts inside the sentinel-padded order, so it ends at a
+        // sentinel at the latest, whatever the data
+        const int pos = min(info & 0xffff, N - 1);
         me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
         jl = pos - 1;
         jr = pos + 1;
@@ -431,7 +433,7 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code,
     if (order) {  // the column's stored order
         const uint16_t *o = order + refs[r] * N;
         for (int p = threadIdx.x; p < N; p += kKsgThreads) {
-            const int m = o[p];
+            const int m = min((int)o[p], N - 1);  // in bounds even if never prepared
             xs[(int64_t)r * N + p] = c[m];
             perm[(int64_t)r * N + p] = (uint16_t)m;
             invp[(int64_t)r * N + m] = (uint16_t)p;
@@ -632,9 +634,9 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
                 const uint16_t *invp = invp_all + (int64_t)r * N;
                 for (int p = tid; p < N; p += kKsgThreads) xo[p].y = cq[perm[p]];
                 for (int j = tid; j < N; j += kKsgThreads) {
-                    const int m = oq[j];
+                    const int m = min((int)oq[j], N - 1);  // in bounds even if never prepared
                     yo[j] = make_int2(cq[m], cr[m]);
-                    yrank[invp[m]] = (uint16_t)j;
+                    yrank[min((int)invp[m], N - 1)] = (uint16_t)j;
                 }
                 if (tid < kPad) {
                     yo[-1 - tid] = make_int2(-kFar, 0);
@@ -697,16 +699,16 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
             // x permutation until the walk
             const uint16_t *oa = order_a + va * N, *ob = order_b + vb * N;
             for (int p = tid; p < N; p += kKsgThreads) {
-                const int m = oa[p];
+                const int m = min((int)oa[p], N - 1);  // in bounds even if never prepared
                 perm[p] = (uint16_t)m;
                 xo[p] = make_int2(ca[m], cb[m]);
                 epsL[m] = p;
             }
             __syncthreads();
             for (int j = tid; j < N; j += kKsgThreads) {
-                const int m = ob[j];
+                const int m = min((int)ob[j], N - 1);
                 yo[j] = make_int2(cb[m], ca[m]);
-                yrank[epsL[m]] = (uint16_t)j;
+                yrank[min(epsL[m], N - 1)] = (uint16_t)j;
             }
             if (tid < kPad) {
                 yo[-1 - tid] = make_int2(-kFar, 0);
