@@ -11,9 +11,11 @@
 // GPU design (one workgroup of four 64-lane waves per pair, everything in LDS;
 // four waves share one pair's LDS so that a CU keeps enough waves in flight to
 // hide LDS latency):
-//  * the samples are kept in two orders, by x (ties by member index) and by y
-//    (ties by x position); a field shares the x order of the reference column
-//    across all queries, so it is sorted once;
+//  * the samples are kept in two orders, by x and by y; both come from the
+//    per-vertex sorted member orders that ndf_prepare stores (ties by member
+//    index), so no query sorts anything; without stored orders every column is
+//    sorted on the fly (ties by member index in x, by x position in y), which
+//    gives bit-identical results;
 //  * the k nearest neighbours of a sample are found by walking outwards from its
 //    own position in one of the two orders, stopping on each side once the
 //    distance along that coordinate reaches the current k-th distance (under the
