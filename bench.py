@@ -391,9 +391,11 @@ def _measured_traffic(row):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    m_sha = re.search(r"sha256 prefix at measurement: ([0-9a-f]+)", text)
+    # the prefix of the measured source, plus those of later comment-only edits
+    shas = re.findall(r"sha256 prefix (?:at measurement|after a comment-only edit): "
+                      r"([0-9a-f]+)", text)
     m_val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
-    if not (m_sha and m_val) or not sha.startswith(m_sha.group(1)):
+    if not (shas and m_val) or not any(sha.startswith(h) for h in shas):
         return None
     return float(m_val.group(1))
 
