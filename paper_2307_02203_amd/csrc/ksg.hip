@@ -22,8 +22,9 @@
 //    max-norm no later sample can be closer).  Each sample walks the order in
 //    which its 2k nearest codes are spread widest, i.e. where the strip the walk
 //    must cover holds the fewest samples; any choice gives the same exact result;
-//  * the marginal counts are two binary searches each, over the sorted x codes
-//    and over the sorted y codes;
+//  * the marginal counts are two lower bounds each, over the sorted x codes and
+//    over the sorted y codes; a bucket table of each order (built per pair in
+//    LDS) narrows every search to the few samples of one code bucket;
 //  * all distances and counts are exact int32, so the counts equal a brute-force
 //    evaluation bit for bit; the harmonic sum is FP64.
 #include "common.hpp"
@@ -37,11 +38,6 @@ constexpr int kKsgThreads = 64 * kKsgWaves;
 __device__ __forceinline__ int pow2_ceil(int n) {
     int p = 1;
     while (p < n) p <<= 1;
-    return p;
-}
-__device__ __forceinline__ int pow2_floor(int n) {
-    int p = 1;
-    while (p * 2 <= n) p <<= 1;
     return p;
 }
 
@@ -66,22 +62,84 @@ __device__ void block_bitonic_sort(T *a, int P) {
     }
 }
 
+// Bucket tables of the marginal searches: T[b] = number of sorted codes below
+// b * 2^kTabShift for b = 0 .. kTabN - 1 (codes lie in [0, 2^23], so the last
+// entry is N).  A lower bound of v then only searches [T[b], T[b + 1]] with
+// b = v >> kTabShift: a handful of samples instead of all N.
+constexpr int kTabShift = 14;
+constexpr int kTabN = ((1 << 23) >> kTabShift) + 2;  // 514 entries
+
+__device__ __forceinline__ int tab_bucket(int v) {
+    return min(max(v, 0) >> kTabShift, kTabN - 2);
+}
+
+// Table construction in three steps with a workgroup barrier between them:
+// every entry N (all threads) ...
+__device__ __forceinline__ void tab_fill(uint16_t *T, int N) {
+    for (int i = threadIdx.x; i < kTabN; i += kKsgThreads) T[i] = (uint16_t)N;
+}
+// ... the first position of every non-empty bucket of the sorted a[0..N) (all
+// threads) ...
+__device__ __forceinline__ void tab_scatter(const int2 *a, uint16_t *T, int N) {
+    for (int j = threadIdx.x; j < N; j += kKsgThreads) {
+        const int b = tab_bucket(a[j].x);
+        if (j == 0 || tab_bucket(a[j - 1].x) != b) T[b] = (uint16_t)j;
+    }
+}
+// ... and a suffix minimum by one wave, so that an empty bucket takes the first
+// position of the next non-empty one (lane l owns entries kPer l .. kPer l + kPer - 1).
+__device__ __forceinline__ void tab_scan(uint16_t *T) {
+    constexpr int kPer = (kTabN + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    int v[kPer];
+    int run = 0xffff;
+#pragma unroll
+    for (int i = kPer - 1; i >= 0; --i) {
+        const int idx = lane * kPer + i;
+        if (idx < kTabN) run = min(run, (int)T[idx]);
+        v[i] = run;
+    }
+    int s = run;  // minimum over the chunks of this lane and all later ones
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_down(s, d);
+        if (lane + d < 64) s = min(s, t);
+    }
+    int carry = __shfl_down(s, 1);
+    if (lane == 63) carry = 0xffff;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int idx = lane * kPer + i;
+        if (idx < kTabN) T[idx] = (uint16_t)min(v[i], carry);
+    }
+}
+
 // Marginal counts of one sample with k-th distance eps > 0: entries of the sorted
 // x codes (xo[].x) and of the sorted y codes (yo[].x) strictly inside
-// (v - eps, v + eps), minus the sample itself.  The four lower-bound binary
-// searches advance in lockstep, so their LDS reads are in flight together; the
-// probe index is clamped into [0, N) and a probe past N never advances.
-__device__ __forceinline__ void marginal_counts(const int2 *xo, const int2 *yo, int N, int hp,
+// (v - eps, v + eps), minus the sample itself.  Each of the four lower bounds
+// starts from its bucket range [T[b], T[b + 1]]; the searches advance in lockstep
+// from the widest range's step, so their LDS reads are in flight together, and a
+// probe is clamped into [0, N) and never advances past its range.
+__device__ __forceinline__ void marginal_counts(const int2 *xo, const int2 *yo,
+                                                const uint16_t *Tx, const uint16_t *Ty, int N,
                                                 int2 mxy, int eps, int &nx, int &ny) {
     const int val[4] = {mxy.x + eps, mxy.x - eps + 1, mxy.y + eps, mxy.y - eps + 1};
-    int pos[4] = {0, 0, 0, 0};
-    for (int st = hp; st > 0; st >>= 1) {
+    int pos[4], hi[4], span = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint16_t *T = i < 2 ? Tx : Ty;
+        const int b = tab_bucket(val[i]);
+        pos[i] = T[b];
+        hi[i] = T[b + 1];
+        span = max(span, hi[i] - pos[i]);
+    }
+    for (int st = span > 0 ? 1 << (31 - __clz(span)) : 0; st > 0; st >>= 1) {
         int c[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) c[i] = (i < 2 ? xo : yo)[min(pos[i] + st, N) - 1].x;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (pos[i] + st <= N && c[i] < val[i]) pos[i] += st;
+            if (pos[i] + st <= hi[i] && c[i] < val[i]) pos[i] += st;
     }
     nx = pos[0] - pos[1] - 1;
     ny = pos[2] - pos[3] - 1;
@@ -120,7 +178,9 @@ __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
 // Neighbour search and counts for all samples of one pair.
 //   xo[p] = (x, y) in x order, yo[q] = (y, x) in y order, both with kPad
 //   sentinels on each side; yrank[p] = y-order position of x-order sample p;
-//   perm[p] = member of x-order sample p; epsL = N ints of LDS scratch.
+//   perm[p] = member of x-order sample p; epsL = N ints of LDS scratch;
+//   Tx, Ty = bucket tables of the x and y orders, every entry N on entry (Tx
+//   already built unless build_tx), every entry N again on return.
 // Returns the FP64 sum of H_nx + H_ny over all samples.
 //
 // Walk phase: first every sample's walk order and start position are computed
@@ -139,7 +199,8 @@ __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
 template <int K>
 __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yrank, int N,
                              const double *__restrict__ H, const uint16_t *perm,
-                             int32_t *__restrict__ cnt, int *epsL) {
+                             int32_t *__restrict__ cnt, int *epsL, uint16_t *Tx, uint16_t *Ty,
+                             bool build_tx) {
     __shared__ double s_part[kKsgWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -164,7 +225,13 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         const int sy = yo[min(q + K, N - 1)].x - yo[max(q - K, 0)].x;
         epsL[pp] = sy > sx ? (q | 0x10000) : pp;
     }
+    tab_scatter(yo, Ty, N);
+    if (build_tx) tab_scatter(xo, Tx, N);
     __syncthreads();
+    if (wave == 0)
+        tab_scan(Ty);
+    else if (wave == 1 && build_tx)
+        tab_scan(Tx);
 
     auto start = [&](int pp) {
         const int2 mxy = xo[pp];
@@ -229,13 +296,14 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     }
     __syncthreads();
 
-    const int hp = pow2_floor(N);
     double acc = 0.0;
     for (int pp = tid; pp < N; pp += kKsgThreads) {
         const int2 mxy = xo[pp];
         const int eps = epsL[pp];
         int nx = 0, ny = 0;
-        if (eps > 0) marginal_counts(xo, yo, N, hp, mxy, eps, nx, ny);
+        if (eps > 0) marginal_counts(xo, yo, Tx, Ty, N, mxy, eps, nx, ny);
+        nx = min(max(nx, 0), N - 1);  // no-ops on sorted orders; keep H reads in bounds
+        ny = min(max(ny, 0), N - 1);
         acc += H[nx] + H[ny];
         if (cnt) {
             const int m = perm[pp];
@@ -249,6 +317,8 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     double total = 0.0;
 #pragma unroll
     for (int w = 0; w < kKsgWaves; ++w) total += s_part[w];
+    tab_fill(Ty, N);  // for the next pair (the counts above were the last readers)
+    if (build_tx) tab_fill(Tx, N);
     return total;
 }
 
@@ -581,11 +651,12 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_order_kernel(const int32_t *_
 }
 
 // LDS plan of both kernels: xo (N + 2 kPad) int2 | yo (P + 2 kPad) int2, also the
-// sort keys and exchange buffer | perm N uint16 | yrank N uint16 | eps N int32,
-// with P = max(pow2_ceil(N), 256) (the register sort always moves 256 E keys).
+// sort keys and exchange buffer | perm N uint16 | yrank N uint16 | eps N int32 |
+// Tx, Ty kTabN uint16 each, with P = max(pow2_ceil(N), 256) (the register sort
+// always moves 256 E keys).
 __host__ __device__ inline size_t ksg_lds_bytes(int N, int P) {
     return (size_t)(N + 2 * kPad) * 8 + (size_t)(P + 2 * kPad) * 8 + (size_t)N * 4 +
-           (size_t)N * 4;
+           (size_t)N * 4 + (size_t)kTabN * 4;
 }
 
 template <int K>
@@ -603,10 +674,13 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
     uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
     uint16_t *yrank = perm + N;
     int *epsL = reinterpret_cast<int *>(yrank + N);  // 4-byte aligned: N uint16 x 2
+    uint16_t *Tx = reinterpret_cast<uint16_t *>(epsL + N);
+    uint16_t *Ty = Tx + kTabN;
     int *tmp = reinterpret_cast<int *>(yo);  // the query row in member order
     const int tid = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
     ksg_sentinels(xo, N);
+    tab_fill(Ty, N);
 
     for (int r = 0; r < n_ref; ++r) {
         const int32_t fr = flags_r[refs[r]];
@@ -615,6 +689,12 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
             xo[p].x = xs_all[(int64_t)r * N + p];
             perm[p] = perm_all[(int64_t)r * N + p];
         }
+        tab_fill(Tx, N);
+        __syncthreads();
+        // the reference's bucket table, shared by all its queries
+        tab_scatter(xo, Tx, N);
+        __syncthreads();
+        if (tid < 64) tab_scan(Tx);
         __syncthreads();
         for (int64_t q = blockIdx.x; q < V; q += gridDim.x) {
             const int32_t *cq = code_q + q * N;
@@ -653,7 +733,8 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
                 __syncthreads();
                 build_y_order(xo, yo, yrank, N, P);
             }
-            const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
+            const double acc =
+                ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL, Tx, Ty, false);
             if (tid == 0) out[(int64_t)r * V + q] = (float)(base - acc / (double)N);
             __syncthreads();
         }
@@ -675,9 +756,13 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
     uint16_t *perm = reinterpret_cast<uint16_t *>(yo + P + kPad);
     uint16_t *yrank = perm + N;
     int *epsL = reinterpret_cast<int *>(yrank + N);
+    uint16_t *Tx = reinterpret_cast<uint16_t *>(epsL + N);
+    uint16_t *Ty = Tx + kTabN;
     const int tid = threadIdx.x;
     const double base = H[K - 1] + H[N - 1];
     ksg_sentinels(xo, N);
+    tab_fill(Tx, N);
+    tab_fill(Ty, N);
 
     for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
         const int64_t va = pairs[2 * b], vb = pairs[2 * b + 1];
@@ -721,7 +806,7 @@ __global__ __launch_bounds__(kKsgThreads) __attribute__((amdgpu_waves_per_eu(6))
             build_x_order(ca, cb, N, P, xo, perm, yo);
             build_y_order(xo, yo, yrank, N, P);
         }
-        const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL);
+        const double acc = ksg_points<K>(xo, yo, yrank, N, H, perm, cnt, epsL, Tx, Ty, true);
         if (tid == 0) out[b] = (float)(base - acc / (double)N);
         __syncthreads();
     }
