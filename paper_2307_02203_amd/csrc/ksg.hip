@@ -202,7 +202,8 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
                              int32_t *__restrict__ cnt, int *epsL, uint16_t *Tx, uint16_t *Ty,
                              bool build_tx) {
     __shared__ double s_part[kKsgWaves];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t below = (1ull << lane) - 1ull;
     // i-th sample of this wave (increasing in i)
     auto sample = [&](int i) { return ((i >> 6) * kKsgWaves + wave) * 64 + (i & 63); };
@@ -254,7 +255,8 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         active = true;
     }
     int next = 64;  // first unclaimed sample (wave-uniform)
-    while (__any(active)) {
+    bool more = sample(next) < N;
+    for (;;) {
         if (active) {
             if (al) {
                 int2 c[4];
@@ -282,17 +284,21 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
             }
         }
         const uint64_t idle = __ballot(!active);
-        if (sample(next) < N && idle) {
-            if (!active) {
-                const int np = sample(next + __popcll(idle & below));
-                if (np < N) {
-                    p = np;
-                    start(p);
-                    active = true;
-                }
-            }
-            next += __popcll(idle);
+        if (idle == 0) continue;
+        if (!more) {
+            if (idle == ~0ull) break;
+            continue;
         }
+        if (!active) {
+            const int np = sample(next + __popcll(idle & below));
+            if (np < N) {
+                p = np;
+                start(p);
+                active = true;
+            }
+        }
+        next = __builtin_amdgcn_readfirstlane(next + __popcll(idle));
+        more = sample(next) < N;
     }
     __syncthreads();
 
