@@ -146,7 +146,9 @@ __device__ __forceinline__ void marginal_counts(const int2 *xo, const int2 *yo,
 }
 
 constexpr int kPad = 4;             // sentinel samples on each side of the x order
-constexpr int kFar = 1 << 28;       // sentinel x distance: beyond any code difference (< 2^24)
+constexpr int kFar = 1 << 29;       // sentinel x: its distance to any sample exceeds kUnset
+constexpr int kUnset = 1 << 28;     // k-th distance before k samples are seen: above any
+                                    // code difference (< 2^24), below any sentinel distance
 
 // v_med3_i32: the middle of three signed integers.  With lo <= hi it is d
 // clamped to [lo, hi] in one instruction (the compiler forms it only for
@@ -189,13 +191,14 @@ __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
 // sample as soon as its walk ends (claims are handed out in lane order from a
 // wave-uniform counter), so short and long walks do not wait for each other.
 // A walk takes 4 samples per side per step; a side stops once the farthest of
-// its 4 is at least the current k-th distance away along the walked coordinate,
-// or is a sentinel.  Samples past that point never change the k smallest, so
-// the overscan is harmless, and a block starts at most 3 samples past the last
-// real one, so reads stay within the padding.
+// its 4 is at least the current k-th distance away along the walked coordinate
+// (always so for a sentinel, as the k-th distance starts at kUnset).  Samples
+// past that point never change the k smallest, so the overscan is harmless; a
+// block starts at most 3 samples past the last real one, and a stopped side
+// reads the 4 sentinels at its end, so reads stay within the padding.
 // Count phase: thread t takes samples t, t + 256, ... and counts the marginals
-// by binary search; the partial sums are combined in a fixed order, so the FP64
-// total is reproducible.  Returns the total in every thread.
+// by bucket table and binary search; the partial sums are combined in a fixed
+// order, so the FP64 total is reproducible.  Returns the total in every thread.
 template <int K>
 __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yrank, int N,
                              const double *__restrict__ H, const uint16_t *perm,
@@ -210,12 +213,11 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     int p = sample(lane);
     bool active = false;
     const int2 *A = xo;
+    const int2 *L = xo, *R = xo;  // next blocks: L[0..3] left (farthest first), R[0..3] right
     int2 me = make_int2(0, 0);
-    int jl = 0, jr = 0;
-    bool al = false, ar = false;
     int best[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
+    for (int t = 0; t < K; ++t) best[t] = kUnset;
 
     // Every sample's walk order and start position, with all lanes busy:
     // epsL[p] = position | (walk in y order) << 16 until the walk of p ends.
@@ -243,11 +245,10 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         // sentinel at the latest, whatever the data
         const int pos = min(info & 0xffff, N - 1);
         me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
-        jl = pos - 1;
-        jr = pos + 1;
-        al = ar = true;
+        L = A + pos - 4;
+        R = A + pos + 1;
 #pragma unroll
-        for (int t = 0; t < K; ++t) best[t] = 0x7fffffff;
+        for (int t = 0; t < K; ++t) best[t] = kUnset;
     };
 
     if (p < N) {
@@ -258,26 +259,27 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     bool more = sample(next) < N;
     for (;;) {
         if (active) {
-            if (al) {
-                int2 c[4];
+            // Both sides every step, no branches: a finished side reads the
+            // sentinel block at its end of the order, whose distances exceed
+            // every k-th distance, so it changes nothing.
+            int2 c[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) c[u] = A[jl - u];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    insert_k<K>(best, max(me.x - c[u].x, absdiff_u32(me.y, c[u].y)));
-                al = c[3].x != -kFar && (me.x - c[3].x) < best[K - 1];
-                jl -= 4;
+            for (int u = 0; u < 4; ++u) {
+                c[u] = L[u];
+                c[4 + u] = R[u];
             }
-            if (ar) {
-                int2 c[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) c[u] = A[jr + u];
+            for (int u = 3; u >= 0; --u)
+                insert_k<K>(best, max(me.x - c[u].x, absdiff_u32(me.y, c[u].y)));
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    insert_k<K>(best, max(c[u].x - me.x, absdiff_u32(me.y, c[u].y)));
-                ar = c[3].x != kFar && (c[3].x - me.x) < best[K - 1];
-                jr += 4;
-            }
+            for (int u = 0; u < 4; ++u)
+                insert_k<K>(best, max(c[4 + u].x - me.x, absdiff_u32(me.y, c[4 + u].y)));
+            // a side goes on while its farthest sample is nearer than the k-th
+            // distance (never for a sentinel, never past the padding)
+            const bool al = (me.x - c[0].x) < best[K - 1];
+            const bool ar = (c[7].x - me.x) < best[K - 1];
+            L = al ? L - 4 : A - kPad;
+            R = ar ? R + 4 : A + N;
             if (!al && !ar) {
                 epsL[p] = best[K - 1];
                 active = false;
