@@ -314,7 +314,6 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
     const float *bias_h = bias + h4;
     const float *ref_h = ref + h4;
     const float *w6_h = w6 + h4;
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         // rows 8 g + 0..3 of block ob are contiguous: one 16-byte LDS read each
@@ -387,9 +386,6 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                 }
             }
         }
-        // keep the scheduler from hoisting the next block's operand loads above
-        // this epilogue (that would hold ~128 extra registers)
-        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -467,7 +463,6 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
 #pragma unroll
                 for (int e = 0; e < 8; ++e) t[e] = f2bf(s[e]);
                 a[kb][q] = t;
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
         float part[2] = {0.f, 0.f};
