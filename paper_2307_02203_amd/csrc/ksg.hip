@@ -207,7 +207,6 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     __shared__ double s_part[kKsgWaves];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint64_t below = (1ull << lane) - 1ull;
     // i-th sample of this wave (increasing in i)
     auto sample = [&](int i) { return ((i >> 6) * kKsgWaves + wave) * 64 + (i & 63); };
     int p = sample(lane);
@@ -237,14 +236,12 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
         tab_scan(Tx);
 
     auto start = [&](int pp) {
-        const int2 mxy = xo[pp];
         const int info = epsL[pp];
-        const bool walk_y = info >= 0x10000;
-        A = walk_y ? yo : xo;
+        A = info >= 0x10000 ? yo : xo;
         // a walk starts inside the sentinel-padded order, so it ends at a
         // sentinel at the latest, whatever the data
         const int pos = min(info & 0xffff, N - 1);
-        me = walk_y ? make_int2(mxy.y, mxy.x) : mxy;  // (walked, other)
+        me = A[pos];  // the sample itself in its walk order: (walked, other)
         L = A + pos - 4;
         R = A + pos + 1;
 #pragma unroll
@@ -292,7 +289,10 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
             continue;
         }
         if (!active) {
-            const int np = sample(next + __popcll(idle & below));
+            // rank of this lane among the idle ones
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0));
+            const int np = sample(next + rank);
             if (np < N) {
                 p = np;
                 start(p);
