@@ -86,7 +86,10 @@ typedef struct ndf_ensemble {
  * ReLU, linear) gives Phi.  n_enc = 1: one encoder and grid for both positions
  * (self field, Phi symmetric); n_enc = 2: encoder 0 for p1, encoder 1 for p2.
  * Grid vertex (i,j,k) is at u = (i/(nx-1), j/(ny-1), k/(nz-1)).  The kernels
- * implement n_levels = 4, feats = 8, width = 128. */
+ * implement n_levels = 4, feats = 8, width = 128.  Limits (NDF_E_UNSUPPORTED
+ * beyond them): nx*ny*nz < 2^24, each of nx, ny, nz <= 65535, and
+ * (n-1)*(R-1) < 2^24 for every axis and level (the lookup's exact integer
+ * arithmetic). */
 typedef struct ndf_net_config {
     int32_t nx, ny, nz;      /* data grid whose vertices are evaluated            */
     int32_t n_levels;        /* 4                                                 */

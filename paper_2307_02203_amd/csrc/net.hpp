@@ -23,11 +23,19 @@ struct NetOffsets {
 inline int check_net_config(const ndf_net_config *c) {
     if (!c) return NDF_E_ARG;
     if (c->nx < 2 || c->ny < 2 || c->nz < 2) return NDF_E_ARG;
+    // the trilinear lookup divides exactly by multiply-high: numerators below
+    // 2^24 (vertex indices, i (R - 1)), divisors below 2^16
+    if (c->nx > 65535 || c->ny > 65535 || c->nz > 65535) return NDF_E_UNSUPPORTED;
+    if ((int64_t)c->nx * c->ny * c->nz >= (1 << 24)) return NDF_E_UNSUPPORTED;
     if (c->n_levels != kL || c->feats != kF || c->width != kH) return NDF_E_UNSUPPORTED;
     if (c->n_enc != 1 && c->n_enc != 2) return NDF_E_ARG;
     for (int l = 0; l < kL; ++l)
         for (int a = 0; a < 3; ++a)
             if (c->res[l][a] < 2 || c->res[l][a] > (1 << 16)) return NDF_E_ARG;
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int l = 0; l < kL; ++l)
+        for (int a = 0; a < 3; ++a)
+            if ((int64_t)(n[a] - 1) * (c->res[l][a] - 1) >= (1 << 24)) return NDF_E_UNSUPPORTED;
     return NDF_OK;
 }
 
@@ -69,6 +77,9 @@ inline NetOffsets net_offsets(const ndf_net_config *c) {
 struct GridGeom {
     int nx, ny, nz;
     int R[kL][3];
+    float inv[3];        // 1 / (n - 1) per axis
+    uint64_t md[3];      // ceil(2^40 / (n - 1)) per axis
+    uint64_t mx, my;     // ceil(2^40 / nx), ceil(2^40 / ny)
 };
 
 inline GridGeom grid_geom(const ndf_net_config *c) {
@@ -78,6 +89,13 @@ inline GridGeom grid_geom(const ndf_net_config *c) {
     g.nz = c->nz;
     for (int l = 0; l < kL; ++l)
         for (int a = 0; a < 3; ++a) g.R[l][a] = c->res[l][a];
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+        g.inv[a] = 1.0f / (float)(n[a] - 1);
+        g.md[a] = ((1ull << 40) + (uint64_t)(n[a] - 2)) / (uint64_t)(n[a] - 1);
+    }
+    g.mx = ((1ull << 40) + (uint64_t)c->nx - 1) / (uint64_t)c->nx;
+    g.my = ((1ull << 40) + (uint64_t)c->ny - 1) / (uint64_t)c->ny;
     return g;
 }
 
@@ -98,18 +116,23 @@ __device__ __forceinline__ void corners_R32(const GridGeom &g, const int R[3], i
                                             int idx[8], float w[8]) {
     const uint32_t v = (uint32_t)v64;
     const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
-    const uint32_t t = v / nx;
-    const uint32_t ii[3] = {v - t * nx, t % ny, t / ny};
+    // exact divisions by multiply-high: numerators < 2^24, divisors < 2^16
+    const uint32_t t = (uint32_t)(((uint64_t)v * g.mx) >> 40);  // v / nx
+    const uint32_t k = (uint32_t)(((uint64_t)t * g.my) >> 40);  // t / ny
+    const uint32_t ii[3] = {v - t * nx, t - k * ny, k};
     const int nn[3] = {g.nx, g.ny, g.nz};
     int b[3];
     float f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float c = (float)(ii[a] * (uint32_t)(R[a] - 1)) / (float)(nn[a] - 1);
-        int bb = (int)floorf(c);
-        bb = bb < 0 ? 0 : (bb > R[a] - 2 ? R[a] - 2 : bb);
+        // c = i (R - 1) / (n - 1) = q + rem / (n - 1): cell q (at most R - 2), so a
+        // vertex on a level vertex gets weight exactly 1 and its neighbour 0
+        const uint32_t p = ii[a] * (uint32_t)(R[a] - 1);
+        const uint32_t q = (uint32_t)(((uint64_t)p * g.md[a]) >> 40);
+        const uint32_t rem = p - q * (uint32_t)(nn[a] - 1);
+        const int bb = min((int)q, R[a] - 2);
         b[a] = bb;
-        f[a] = c - (float)bb;
+        f[a] = (float)((int)q - bb) + (float)rem * g.inv[a];
     }
 #pragma unroll
     for (int cn = 0; cn < 8; ++cn) {

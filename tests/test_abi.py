@@ -106,6 +106,18 @@ def test_net_config_validation_and_param_bytes():
     assert L.ndf_net_init(ctypes.byref(bad), FAKE, None, 1, None) == ndf.NDF_E_UNSUPPORTED
     bad3 = ndf.net_config(250, 352, 20, lay.res, n_enc=3)
     assert L.ndf_net_init(ctypes.byref(bad3), FAKE, None, 1, None) == ndf.NDF_E_ARG
+    # limits of the lookup's exact integer arithmetic: V < 2^24, n <= 65535,
+    # (n - 1)(R - 1) < 2^24
+    big = ndf.net_config(512, 512, 64, lay.res)              # V = 2^24
+    assert L.ndf_net_init(ctypes.byref(big), FAKE, None, 1, None) == ndf.NDF_E_UNSUPPORTED
+    assert ndf.ndf_net_param_bytes(big) == 0
+    wide = ndf.net_config(70000, 2, 2, lay.res)
+    assert L.ndf_net_init(ctypes.byref(wide), FAKE, None, 1, None) == ndf.NDF_E_UNSUPPORTED
+    res_fine = [[4097, 8, 2], [4097, 8, 2], [4097, 8, 2], [4097, 8, 2]]
+    fine = ndf.net_config(4097, 4, 2, res_fine)             # (n - 1)(R - 1) = 2^24
+    assert L.ndf_net_init(ctypes.byref(fine), FAKE, None, 1, None) == ndf.NDF_E_UNSUPPORTED
+    ok_cfg = ndf.net_config(4096, 4, 2, [[4096, 4, 2]] * 4)  # (n - 1)(R - 1) < 2^24
+    assert ndf.ndf_net_param_bytes(ok_cfg) > 0
     need = ndf.train_ws_bytes(cfg, 1024)
     assert need > 0
     C = ctypes.byref(cfg)
