@@ -595,6 +595,139 @@ __device__ __forceinline__ void wave_sort_regs(unsigned long long (&k)[E]) {
     }
 }
 
+// Ascending bitonic sort of 64 E 32-bit keys held E per lane, in the form whose
+// merge of two sorted halves starts by comparing element i with its mirror
+// i ^ (size - 1): every comparator then puts the minimum at the lower index, so a
+// pair in one lane is one v_min and one v_max, and a pair across lanes one lane
+// shuffle plus a min or max.
+template <int E>
+__device__ __forceinline__ void wave_sort_regs32(uint32_t (&k)[E]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int LE = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : E == 8 ? 3 : 4;
+    constexpr int LPT = 6 + LE;  // log2 of the key count
+#pragma unroll
+    for (int ls = 1; ls <= LPT; ++ls) {
+        const int size = 1 << ls;
+        if (size <= E) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int jp = j ^ (size - 1);
+                if (jp > j) {
+                    const uint32_t a = k[j], b = k[jp];
+                    k[j] = min(a, b);
+                    k[jp] = max(a, b);
+                }
+            }
+        } else {
+            // partner of (lane, j) is (lane ^ (size / E - 1), E - 1 - j)
+            const bool lower = ((E * lane) & (size >> 1)) == 0;
+            uint32_t t[E];
+#pragma unroll
+            for (int j = 0; j < E; ++j) t[j] = __shfl_xor(k[E - 1 - j], size / E - 1, kWave);
+#pragma unroll
+            for (int j = 0; j < E; ++j) k[j] = lower ? min(k[j], t[j]) : max(k[j], t[j]);
+        }
+#pragma unroll
+        for (int ls2 = ls - 2; ls2 >= 0; --ls2) {
+            const int stride = 1 << ls2;
+            if (stride >= E) {
+                const bool lower = ((E * lane) & stride) == 0;
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const uint32_t o = __shfl_xor(k[j], stride / E, kWave);
+                    k[j] = lower ? min(k[j], o) : max(k[j], o);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int jp = j ^ stride;
+                    if (jp > j) {
+                        const uint32_t a = k[j], b = k[jp];
+                        k[j] = min(a, b);
+                        k[jp] = max(a, b);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Sorted member order of one column with 64 < N <= 1024 (E >= 2 per lane).  The
+// sort runs on 32-bit keys (code >> 2, member): codes lie in [0, 2^23], so
+// code >> 2 takes 22 bits and the member 10.  Samples whose codes agree above
+// the two lowest bits then sit in member order; where such neighbours exist,
+// odd-even transposition passes on the full (code, member) keys finish the
+// order, and a column that is still unsorted after four rounds (many near-equal
+// codes) is sorted again on full 64-bit keys.
+template <int E>
+__device__ __forceinline__ void wave_sort_column32(const int32_t *__restrict__ c, int N,
+                                                   uint16_t *__restrict__ o) {
+    static_assert(E >= 2, "pairs of one lane");
+    const int lane = threadIdx.x & 63;
+    uint32_t k[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int m = E * lane + j;
+        k[j] = m < N ? (((uint32_t)c[m] >> 2) << 10) | (uint32_t)m : 0xffffffffu;
+    }
+    wave_sort_regs32<E>(k);
+    // neighbours with equal code >> 2 (padding keys never tie with a sample)
+    bool tie = false;
+#pragma unroll
+    for (int j = 0; j + 1 < E; ++j) tie |= (k[j] >> 10) == (k[j + 1] >> 10) && k[j + 1] != 0xffffffffu;
+    const uint32_t nk = __shfl_down(k[0], 1, kWave);
+    if (lane < 63) tie |= (k[E - 1] >> 10) == (nk >> 10) && nk != 0xffffffffu;
+    if (!__any(tie)) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int p = E * lane + j;
+            if (p < N) o[p] = (uint16_t)(k[j] & 0x3ff);
+        }
+        return;
+    }
+    unsigned long long f[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int m = (int)(k[j] & 0x3ff);
+        f[j] = k[j] == 0xffffffffu ? ~0ull
+                                   : (((unsigned long long)(uint32_t)c[m]) << 16) | (unsigned)m;
+    }
+    auto in_order = [&]() {
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j + 1 < E; ++j) bad |= f[j] > f[j + 1];
+        const unsigned long long nf = __shfl_down(f[0], 1, kWave);
+        if (lane < 63) bad |= f[E - 1] > nf;
+        return !__any(bad);
+    };
+    bool done = false;
+    for (int round = 0; round < 4 && !(done = in_order()); ++round) {
+#pragma unroll
+        for (int j = 0; j + 1 < E; j += 2) {  // pairs (2i, 2i + 1)
+            const unsigned long long a = f[j], b = f[j + 1];
+            f[j] = a < b ? a : b;
+            f[j + 1] = a < b ? b : a;
+        }
+        const unsigned long long nf = __shfl_down(f[0], 1, kWave);
+        const unsigned long long pf = __shfl_up(f[E - 1], 1, kWave);
+#pragma unroll
+        for (int j = 1; j + 1 < E; j += 2) {  // pairs (2i + 1, 2i + 2) inside a lane
+            const unsigned long long a = f[j], b = f[j + 1];
+            f[j] = a < b ? a : b;
+            f[j + 1] = a < b ? b : a;
+        }
+        // the pair across a lane boundary: the lower position keeps the minimum
+        if (lane < 63) f[E - 1] = f[E - 1] < nf ? f[E - 1] : nf;
+        if (lane > 0) f[0] = f[0] > pf ? f[0] : pf;
+    }
+    if (!done && !in_order()) wave_sort_regs<E>(f);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int p = E * lane + j;
+        if (p < N) o[p] = (uint16_t)(f[j] & 0xffff);
+    }
+}
+
 template <int E>
 __device__ __forceinline__ void wave_sort_column(const int32_t *__restrict__ c, int N,
                                                  uint16_t *__restrict__ o) {
@@ -627,13 +760,13 @@ __global__ __launch_bounds__(kKsgThreads) void ksg_order_kernel(const int32_t *_
             if (P2 <= 64)
                 wave_sort_column<1>(c, N, o);
             else if (P2 <= 128)
-                wave_sort_column<2>(c, N, o);
+                wave_sort_column32<2>(c, N, o);
             else if (P2 <= 256)
-                wave_sort_column<4>(c, N, o);
+                wave_sort_column32<4>(c, N, o);
             else if (P2 <= 512)
-                wave_sort_column<8>(c, N, o);
+                wave_sort_column32<8>(c, N, o);
             else
-                wave_sort_column<16>(c, N, o);
+                wave_sort_column32<16>(c, N, o);
         }
         return;
     }
