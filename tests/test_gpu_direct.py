@@ -208,6 +208,45 @@ def test_ksg_without_stored_orders_matches(mid):
     assert np.array_equal(np.take_along_axis(keys, order, axis=1), np.sort(keys, axis=1))
 
 
+@pytest.mark.parametrize("n_members", [1000, 200, 100])
+def test_stored_orders_with_near_ties(n_members):
+    """Sorted member orders on columns built to defeat the 32-bit sort keys: codes
+    that agree above their two lowest bits (few distinct values, many repeats) and
+    columns of many near-equal codes next to well-spread ones.  The stored order
+    must be ascending (code, member) exactly, and the KSG counts of such pairs must
+    equal the oracle's."""
+    rng = np.random.default_rng(31)
+    V = 96
+    x = rng.standard_normal((1, n_members, V)).astype(np.float32)
+    lo, hi = -1.0, 1.0
+    step = (hi - lo) / 2.0 ** 23
+    for v in range(0, V, 3):
+        # codes 0..7 (two groups of four sharing code >> 2), plus the two range ends
+        x[0, :, v] = lo + step * rng.integers(0, 8, n_members)
+        x[0, 0, v], x[0, 1, v] = lo, hi
+    for v in range(1, V, 3):
+        # a dense cluster of codes 0..40 among spread values
+        x[0, : n_members // 2, v] = lo + step * rng.integers(0, 41, n_members // 2)
+        x[0, n_members // 2:, v] = rng.uniform(lo, hi, n_members - n_members // 2)
+        x[0, 0, v], x[0, 1, v] = lo, hi
+    xt = torch.from_numpy(x).cuda()
+    e = ndf.Ensemble(xt, 6, 4, 4)
+    ndf.ndf_prepare(e)
+    torch.cuda.synchronize()
+    codes = e.code[0].cpu().numpy().astype(np.int64)
+    want_codes = np.stack([direct.ksg_codes(x[0][:, v])[0] for v in range(V)])
+    assert np.array_equal(codes, want_codes)
+    order = e.order[0].cpu().numpy().astype(np.int64) & 0xFFFF
+    keys = codes * 65536 + np.arange(n_members)[None, :]
+    assert np.array_equal(np.take_along_axis(keys, order, axis=1), np.sort(keys, axis=1))
+    pairs = np.array([[0, 1], [3, 4], [1, 2], [6, 7], [9, 10]], dtype=np.int64)
+    mi, cnt = ndf.ksg_pairs(e, pairs, k=4, counts=True)
+    cnt = cnt.cpu().numpy()
+    for b, (a, q) in enumerate(pairs):
+        w, wnx, wny = direct.ksg_field(x[0][:, a], x[0][:, q:q + 1], 4, counts=True)
+        assert np.array_equal(cnt[b, 0], wnx[0]) and np.array_equal(cnt[b, 1], wny[0]), b
+
+
 def test_pairs_out_of_range_give_nan(mid):
     pairs = np.array([[0, 1], [-1, 3], [5, mid.n_vertices]], dtype=np.int64)
     r = ndf.pearson_pairs(mid, pairs).cpu().numpy()
