@@ -11,8 +11,10 @@
 // members twice (sum / min / max, then centred squares and codes).  The ensemble
 // is member-major, so each member row contributes a 256-byte coalesced segment.
 // Codes are written vertex-major through an LDS transpose (64 members x 64
-// vertices per tile).  (Two vertices per thread with 8-byte loads measured
-// slower: the larger tile cut the resident workgroups per CU from seven to three.)
+// vertices per tile).  Each thread keeps 8 (first pass) or 16 (second pass) of
+// its member loads in flight; one load at a time left the kernel latency-bound at
+// 3.3 TB/s.  (Two vertices per thread with 8-byte loads measured slower: the
+// larger tile cut the resident workgroups per CU.)
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -67,17 +69,30 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
         hi[j] = -INFINITY;
         bad[j] = 0;
     }
+    auto accumulate = [&](const float (&a)[kPrepVW]) {
+#pragma unroll
+        for (int j = 0; j < kPrepVW; ++j) {
+            sum[j] += (double)a[j];
+            lo[j] = fminf(lo[j], a[j]);
+            hi[j] = fmaxf(hi[j], a[j]);
+            bad[j] |= !isfinite(a[j]);
+        }
+    };
     if (vb < V) {
-        for (int m = ph; m < N; m += kPrepPh) {
+        // eight members' loads in flight at a time; the sums keep member order
+        constexpr int U = 8;
+        int m = ph;
+        for (; m + kPrepPh * (U - 1) < N; m += kPrepPh * U) {
+            float a[U][kPrepVW];
+#pragma unroll
+            for (int u = 0; u < U; ++u) load(m + kPrepPh * u, a[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) accumulate(a[u]);
+        }
+        for (; m < N; m += kPrepPh) {
             float a[kPrepVW];
             load(m, a);
-#pragma unroll
-            for (int j = 0; j < kPrepVW; ++j) {
-                sum[j] += (double)a[j];
-                lo[j] = fminf(lo[j], a[j]);
-                hi[j] = fmaxf(hi[j], a[j]);
-                bad[j] |= !isfinite(a[j]);
-            }
+            accumulate(a);
         }
     }
 #pragma unroll
@@ -119,10 +134,18 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
 #pragma unroll
     for (int j = 0; j < kPrepVW; ++j) ss[j] = 0.0;
     for (int m0 = 0; m0 < N; m0 += 64) {
-        for (int mm = ph; mm < 64; mm += kPrepPh) {
+        // the tile's 16 loads of this thread in flight together
+        float at[64 / kPrepPh][kPrepVW];
+#pragma unroll
+        for (int i = 0; i < 64 / kPrepPh; ++i) {
+            const int m = m0 + ph + kPrepPh * i;
+            if (vb < V && m < N) load(m, at[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 64 / kPrepPh; ++i) {
+            const int mm = ph + kPrepPh * i;
             const int m = m0 + mm;
-            float a[kPrepVW];
-            if (vb < V && m < N) load(m, a);
+            const float (&a)[kPrepVW] = at[i];
 #pragma unroll
             for (int j = 0; j < kPrepVW; ++j) {
                 int32_t c = 0;
