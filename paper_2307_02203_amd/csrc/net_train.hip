@@ -250,29 +250,46 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const float *__restrict
     float bsum[4] = {0.f, 0.f, 0.f, 0.f};
     const int c4 = tid & 31;
     const int64_t ntiles = ceil_div(rows, 64);
+    // the next tile's rows are loaded into registers while the current one's
+    // MFMAs run
+    constexpr int XQ = 64 * KIN / 4;             // float4 per X tile
+    constexpr int XPT = XQ / kThreads;           // per thread
+    f32x4 gv[8], xv[XPT];
+    auto fetch = [&](int64_t tile) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int64_t gr = tile * 64 + s * 8 + (tid >> 5);
+            gv[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (gr < rows) gv[s] = *reinterpret_cast<const f32x4 *>(G + gr * kH + 4 * c4);
+        }
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int q = tid + i * kThreads;
+            const int64_t gr = tile * 64 + q / (KIN / 4);
+            xv[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (gr < rows) xv[i] = *reinterpret_cast<const f32x4 *>(X + gr * KIN + 4 * (q % (KIN / 4)));
+        }
+    };
+    if ((int64_t)blockIdx.x < ntiles) fetch(blockIdx.x);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const int row = s * 8 + (tid >> 5);
-            const int64_t gr = tile * 64 + row;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f};
-            if (gr < rows) v = *reinterpret_cast<const f32x4 *>(G + gr * kH + 4 * c4);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                bsum[e] += v[e];
-                s_g[(4 * c4 + e) * kLD + row] = f2bf(v[e]);
+                bsum[e] += gv[s][e];
+                s_g[(4 * c4 + e) * kLD + row] = f2bf(gv[s][e]);
             }
         }
-        constexpr int XQ = 64 * KIN / 4;  // float4 per X tile
-        for (int q = tid; q < XQ; q += kThreads) {
-            const int row = q / (KIN / 4), cc = q % (KIN / 4);
-            const int64_t gr = tile * 64 + row;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f};
-            if (gr < rows) v = *reinterpret_cast<const f32x4 *>(X + gr * KIN + 4 * cc);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s_x[(4 * cc + e) * kLD + row] = f2bf(v[e]);
+        for (int i = 0; i < XPT; ++i) {
+            const int q = tid + i * kThreads;
+            const int row = q / (KIN / 4), cc = q % (KIN / 4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s_x[(4 * cc + e) * kLD + row] = f2bf(xv[i][e]);
         }
         __syncthreads();
+        if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&s_g[(ob * 32 + jl) * kLD + kb * 16 + 8 * h]);
