@@ -283,11 +283,15 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
             }
         }
         const uint64_t idle = __ballot(!active);
-        if (idle == 0) continue;
         if (!more) {
             if (idle == ~0ull) break;
             continue;
         }
+        // refill once a quarter of the lanes is idle: the claim code runs with
+        // only the idle lanes on, so batching claims costs fewer issue slots than
+        // the short idle wait (measured: 51.3 ms refilling at every step, 50.5 ms
+        // at 16 idle lanes, 52.2 ms at 32)
+        if (__popcll(idle) < 16) continue;
         if (!active) {
             // rank of this lane among the idle ones
             const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
