@@ -187,9 +187,10 @@ __device__ __forceinline__ void insert_k(int (&best)[K], int d) {
 //
 // Walk phase: first every sample's walk order and start position are computed
 // with all lanes busy.  Then the x order is dealt to the waves in chunks of 64
-// samples, round robin.  A lane walks one sample at a time and takes the wave's next unclaimed
-// sample as soon as its walk ends (claims are handed out in lane order from a
-// wave-uniform counter), so short and long walks do not wait for each other.
+// samples, round robin.  A lane walks one sample at a time; once 16 lanes of the
+// wave have finished, they take the wave's next unclaimed samples (handed out in
+// lane order from a wave-uniform counter), so short and long walks do not wait
+// for each other.
 // A walk takes 4 samples per side per step; a side stops once the farthest of
 // its 4 is at least the current k-th distance away along the walked coordinate
 // (always so for a sentinel, as the k-th distance starts at kUnset).  Samples
