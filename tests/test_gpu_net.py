@@ -246,6 +246,34 @@ def test_infer_self_field_symmetric_bitwise():
             assert out[a, refs[b]] == out[b, refs[a]]
 
 
+def test_infer_two_encoder_swap_bitwise():
+    """Cross-variable field (two encoders, Sec. 6.4): Phi_{nu mu}(p1, p2) =
+    Phi_{mu nu}(p2, p1).  With the encoders' parameters swapped, the fused kernels
+    give the same bits at swapped positions."""
+    cfg, lay, c, P, net = _setup("mid", 2, seed=2326)
+    V = cfg.n_vertices
+    flat = P.cpu().numpy()
+    sw = flat.copy()
+    off, _ = lay.offsets()
+    for e in (0, 1):
+        for l in range(lay.n_levels):
+            (o0, sh), (o1, _) = off[f"grid{e}_{l}"], off[f"grid{1 - e}_{l}"]
+            n = int(np.prod(sh))
+            sw[o1:o1 + n] = flat[o0:o0 + n]
+        for t in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            (o0, sh), (o1, _) = off[f"{t}_{e}"], off[f"{t}_{1 - e}"]
+            n = int(np.prod(sh))
+            sw[o1:o1 + n] = flat[o0:o0 + n]
+    refs = gen.random_vertices(V, 24, seed=12)
+    out = _infer_gpu(c, _qparams(c, P), refs, V).cpu().numpy()
+    out_sw = _infer_gpu(c, _qparams(c, torch.from_numpy(sw).cuda()), refs, V).cpu().numpy()
+    for a in range(len(refs)):
+        for b in range(len(refs)):
+            assert out[a, refs[b]] == out_sw[b, refs[a]]
+    # the cross field itself is not symmetric
+    assert np.max(np.abs(out[:, refs] - out[:, refs].T)) > 1e-4
+
+
 def test_infer_paper_size_sampled():
     cfg, lay, c, P, net = _setup("paper", 1, seed=2325)
     V = cfg.n_vertices
