@@ -549,8 +549,8 @@ __global__ void ksg_sort_ref_kernel(const int32_t *__restrict__ code,
 }
 
 // Every column's members in ascending (code, member) order: the sorted orders of
-// the neighbour search, built once per ensemble.  Persistent workgroups, one
-// column at a time.
+// the neighbour search, built once per ensemble.  Workgroups stride over the
+// columns (one per wave for N <= 1024, else one per workgroup).
 template <int E>
 __device__ __forceinline__ void sort_column_e(const int32_t *__restrict__ c, int N,
                                               uint16_t *__restrict__ o,
