@@ -186,6 +186,16 @@ int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, i
                    const int64_t *pairs, const float *targets, int64_t B, float lr,
                    float *loss_out, void *ws, size_t ws_bytes, void *stream);
 
+/* Multi-variable fields (Sec. 6.4): the network of the variable pair (nu, mu)
+ * from that of (mu, nu), Phi_{nu mu}(p1, p2) = Phi_{mu nu}(p2, p1), by exchanging
+ * the two encoders (grids and encoder layers); the decoder is shared.  With it,
+ * d (d + 1) / 2 trained networks give all d^2 fields of a correlation volume
+ * matrix.  cfg->n_enc must be 2.  params and params_out are FP32 parameter
+ * blobs (ndf_net_param_bytes) in device memory that must not overlap.  Enqueues
+ * one copy kernel.  Returns NDF_E_ARG for n_enc != 2, null or equal pointers. */
+int ndf_net_swap_encoders(const ndf_net_config *cfg, const float *params, float *params_out,
+                          void *stream);
+
 /* Inference parameters for `prec` (NDF_PREC_BF16 or NDF_PREC_FP8_E4M3) packed
  * from the FP32 parameters: BF16 grids, weights in MFMA operand order, FP32
  * biases; FP8 adds E8M0 scales per output row and block of 32 inputs.  One

@@ -206,6 +206,14 @@ size_t ndf_net_qparam_bytes(const ndf_net_config *cfg, int32_t prec) {
     return net_qparam_bytes(cfg, prec);
 }
 
+int ndf_net_swap_encoders(const ndf_net_config *cfg, const float *params, float *params_out,
+                          void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (cfg->n_enc != 2 || !params || !params_out || params == params_out) return NDF_E_ARG;
+    return launch_net_swap_encoders(cfg, params, params_out, S(stream));
+}
+
 int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t prec, void *qparams,
                      void *stream) {
     int s = check_net_config(cfg);

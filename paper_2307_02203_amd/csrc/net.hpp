@@ -172,6 +172,8 @@ int launch_adam(const ndf_net_config *c, float *params, float *opt, const float 
                 int64_t step, float lr, hipStream_t st);
 int launch_net_quantize(const ndf_net_config *c, const float *params, int prec, void *q,
                         hipStream_t st);
+int launch_net_swap_encoders(const ndf_net_config *c, const float *in, float *out,
+                             hipStream_t st);
 size_t net_latent_cache_bytes(const ndf_net_config *c);
 int launch_infer_latents(const ndf_net_config *c, const void *q, void *cache, hipStream_t st);
 int launch_infer_field_cached(const ndf_net_config *c, const void *q, const int64_t *ref_v,

@@ -634,4 +634,31 @@ int launch_adam(const ndf_net_config *c, float *params, float *opt, const float 
     return status_of_launch();
 }
 
+// Phi_{nu mu} from Phi_{mu nu} (Sec. 6.4): the two encoder blocks [grid0..b3_0]
+// and [grid1..b3_1] have the same layout and length, so out is in with the two
+// ranges exchanged and the decoder copied.
+__global__ void swap_encoders_kernel(const float *__restrict__ in, float *__restrict__ out,
+                                     int64_t e0, int64_t e1, int64_t total) {
+    const int64_t len = e1 - e0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kThreads) {
+        int64_t src = i;
+        if (i >= e0 && i < e1)
+            src = i + len;
+        else if (i >= e1 && i < e1 + len)
+            src = i - len;
+        out[i] = in[src];
+    }
+}
+
+int launch_net_swap_encoders(const ndf_net_config *c, const float *in, float *out,
+                             hipStream_t st) {
+    const NetOffsets o = net_offsets(c);
+    // encoder 1 starts where encoder 0 ends; both end before W4
+    const int64_t e0 = o.grid[0][0], e1 = o.grid[1][0];
+    hipLaunchKernelGGL(swap_encoders_kernel, dim3(gs_blocks(o.total)), dim3(kThreads), 0, st, in,
+                       out, e0, e1, o.total);
+    return status_of_launch();
+}
+
 }  // namespace ndf

@@ -27,6 +27,7 @@ EXPORTED = [
     "ndf_net_optstate_bytes", "ndf_net_init", "ndf_net_grad", "ndf_net_forward",
     "ndf_train_step", "ndf_net_qparam_bytes", "ndf_net_quantize", "ndf_infer_field",
     "ndf_infer_latent_bytes", "ndf_infer_latents", "ndf_infer_field_cached",
+    "ndf_net_swap_encoders",
 ]
 
 
@@ -86,6 +87,7 @@ def lib():
             "ndf_infer_latents": (ctypes.c_int, [C, _VP, _VP, _VP]),
             "ndf_infer_field_cached": (ctypes.c_int, [C, _VP, _VP, _I32, _VP, _VP, _VP, _SZ,
                                                       _VP]),
+            "ndf_net_swap_encoders": (ctypes.c_int, [C, _VP, _VP, _VP]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -270,6 +272,11 @@ def ndf_train_step(cfg, params, opt_state, step, pairs, targets, lr, loss_out, w
     _check(lib().ndf_train_step(ctypes.byref(cfg), _p(params), _p(opt_state), int(step),
                                 _p(pairs), _p(targets), pairs.shape[0], float(lr), _p(loss_out),
                                 _p(ws), ws.numel(), _stream(stream)), "ndf_train_step")
+
+
+def ndf_net_swap_encoders(cfg, params, params_out, stream=None):
+    _check(lib().ndf_net_swap_encoders(ctypes.byref(cfg), _p(params), _p(params_out),
+                                       _stream(stream)), "ndf_net_swap_encoders")
 
 
 def ndf_net_quantize(cfg, params, prec, qparams, stream=None):

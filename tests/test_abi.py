@@ -132,6 +132,12 @@ def test_net_config_validation_and_param_bytes():
     assert (L.ndf_infer_field(C, FAKE, ndf.NDF_PREC_SPLIT_BF16,
                               refs.ctypes.data_as(ctypes.c_void_p), 1, FAKE, FAKE, 1 << 30, None)
             == ndf.NDF_E_UNSUPPORTED)
+    # encoder swap (Sec. 6.4): two encoders only, distinct buffers
+    cfg2e = ndf.net_config(250, 352, 20, lay.res, n_enc=2)
+    FAKE2 = ctypes.c_void_p(0x2000)
+    assert L.ndf_net_swap_encoders(C, FAKE, FAKE2, None) == ndf.NDF_E_ARG
+    assert L.ndf_net_swap_encoders(ctypes.byref(cfg2e), FAKE, FAKE, None) == ndf.NDF_E_ARG
+    assert L.ndf_net_swap_encoders(ctypes.byref(cfg2e), None, FAKE2, None) == ndf.NDF_E_ARG
     # query-latent cache: 256 bytes per vertex, V rounded up to 64-vertex tiles
     assert ndf.ndf_infer_latent_bytes(cfg) == -(-250 * 352 * 20 // 64) * 64 * 256
     assert ndf.ndf_infer_latent_bytes(bad) == 0
