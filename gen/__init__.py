@@ -8,10 +8,11 @@ measures or the network arithmetic lives here.
 from .ensemble import (CONFIGS, EnsembleConfig, blob_geometry, amplitudes,
                        make_ensemble, vertex_index, vertex_coords,
                        population_cov, population_rho)
-from .draws import random_pairs, random_vertices
+from .draws import random_pairs, random_vertices, random_positions, ray_positions
 from .netparams import NetLayout, make_net_params
 
 __all__ = ["CONFIGS", "EnsembleConfig", "blob_geometry", "amplitudes",
            "make_ensemble", "vertex_index", "vertex_coords", "population_cov",
-           "population_rho", "random_pairs", "random_vertices", "NetLayout",
+           "population_rho", "random_pairs", "random_vertices", "random_positions",
+           "ray_positions", "NetLayout",
            "make_net_params"]

@@ -226,6 +226,32 @@ int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const
                            int32_t n_ref, const void *cache, float *out, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Difference of two learned fields (multi-point analysis, Sec. 6.4):
+ * out[v] = Phi(p_a, p_v) - Phi(p_b, p_v) at every grid vertex v, for reference
+ * vertices ref_a, ref_b in [0, V).  cache holds the query latents written by
+ * ndf_infer_latents for the same qparams; ws needs
+ * ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, 2, NDF_PREC_BF16) bytes.  One
+ * pass over the cache decodes both fields per
+ * tile; the result equals the FP32 difference of the two ndf_infer_field_cached
+ * fields bit for bit.  NDF_E_ARG for a null pointer or a vertex out of range. */
+int ndf_infer_field_difference(const ndf_net_config *cfg, const void *qparams, int64_t ref_a,
+                               int64_t ref_b, const void *cache, float *out, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/* The learned field at arbitrary sample positions instead of grid vertices (the
+ * positions a ray marcher visits, Sec. 5; the network's input domain of
+ * Sec. 4.3): out[r][i] = Phi(p_ref[r], pos[i]) for ref_v [host] int64[n_ref]
+ * vertices and pos float[n][3] (device, x y z per position) in the domain
+ * [-1, 1]^3, where -1 and +1 are the first and last grid vertex of an axis
+ * (vertex (i, j, k) sits at 2 i/(nx - 1) - 1, ...).  Each grid level is
+ * interpolated trilinearly at the position; coordinates outside the domain are
+ * clamped to its boundary, NaN coordinates to -1.  out float[n_ref][n] (device).
+ * prec, qparams and ws as for ndf_infer_field.  n = 0 enqueues nothing.
+ * NDF_E_ARG for null pointers, n < 0, n_ref < 1 or a reference out of range. */
+int ndf_infer_points(const ndf_net_config *cfg, const void *qparams, int32_t prec,
+                     const int64_t *ref_v, int32_t n_ref, const float *pos, int64_t n, float *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
 /* Phi(p1, p2) for B vertex pairs (device int64[B][2]) from the FP32 parameters
  * with the training forward kernels (BF16 MFMA, FP32 accumulate); y float[B]. */
 int ndf_net_forward(const ndf_net_config *cfg, const float *params, const int64_t *pairs,

@@ -144,11 +144,24 @@ def _enc_index(net, side):
     return 0 if net.n_enc == 1 else side
 
 
+def domain_to_unit(p):
+    """u in [0,1]^3 of positions p (n,3) in the network's domain [-1,1]^3
+    (Sec. 4.3): u = (p + 1)/2, coordinates outside the domain clamped to its
+    boundary and NaN coordinates mapped to -1 (a reading: the paper only samples
+    inside the domain)."""
+    p = np.asarray(p, dtype=np.float64)
+    u = np.clip((p + 1.0) / 2.0, 0.0, 1.0)
+    return np.where(np.isnan(p), 0.0, u)
+
+
 def forward(net, v1, v2):
     """Phi(p1, p2) for vertex pairs; returns (y, cache)."""
     dims = (net.nx, net.ny, net.nz)
-    u1 = vertex_positions(v1, dims)
-    u2 = vertex_positions(v2, dims)
+    return forward_unit(net, vertex_positions(v1, dims), vertex_positions(v2, dims))
+
+
+def forward_unit(net, u1, u2):
+    """Phi(p1, p2) for positions given as u in [0,1]^3 (n,3); returns (y, cache)."""
     ea, eb = _enc_index(net, 0), _enc_index(net, 1)
     A = encoder(net, ea, grid_encode(net, ea, u1))
     B = encoder(net, eb, grid_encode(net, eb, u2))
@@ -167,6 +180,15 @@ def field(net, ref_v, dims_v=None):
     V = net.nx * net.ny * net.nz
     v = np.arange(V, dtype=np.int64) if dims_v is None else np.asarray(dims_v)
     y, _ = forward(net, np.full(v.shape, ref_v, dtype=np.int64), v)
+    return y
+
+
+def field_points(net, ref_v, pos):
+    """Phi(p_ref, p) at continuous positions pos (n,3) in [-1,1]^3, the positions a
+    ray marcher samples (Sec. 5)."""
+    u2 = domain_to_unit(pos)
+    u1 = vertex_positions(np.full(u2.shape[0], ref_v, dtype=np.int64), (net.nx, net.ny, net.nz))
+    y, _ = forward_unit(net, u1, u2)
     return y
 
 

@@ -261,4 +261,31 @@ int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const
     return launch_infer_field_cached(cfg, qparams, ref_v, n_ref, cache, out, ws, S(stream));
 }
 
+int ndf_infer_points(const ndf_net_config *cfg, const void *qparams, int32_t prec,
+                     const int64_t *ref_v, int32_t n_ref, const float *pos, int64_t n, float *out,
+                     void *ws, size_t ws_bytes, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!qparams || !ref_v || n_ref < 1 || n < 0 || (n > 0 && (!pos || !out))) return NDF_E_ARG;
+    if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
+    const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    for (int r = 0; r < n_ref; ++r)
+        if (ref_v[r] < 0 || ref_v[r] >= V) return NDF_E_ARG;
+    if (!ws || ws_bytes < net_infer_ws_bytes(cfg, n_ref, prec)) return NDF_E_WORKSPACE;
+    if (n == 0) return NDF_OK;
+    return launch_infer_points(cfg, qparams, prec, ref_v, n_ref, pos, n, out, ws, S(stream));
+}
+
+int ndf_infer_field_difference(const ndf_net_config *cfg, const void *qparams, int64_t ref_a,
+                               int64_t ref_b, const void *cache, float *out, void *ws,
+                               size_t ws_bytes, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!qparams || !cache || !out) return NDF_E_ARG;
+    const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    if (ref_a < 0 || ref_a >= V || ref_b < 0 || ref_b >= V) return NDF_E_ARG;
+    if (!ws || ws_bytes < net_infer_ws_bytes(cfg, 2, NDF_PREC_BF16)) return NDF_E_WORKSPACE;
+    return launch_infer_difference(cfg, qparams, ref_a, ref_b, cache, out, ws, S(stream));
+}
+
 }  // extern "C"

@@ -142,6 +142,32 @@ __device__ __forceinline__ void corners_R32(const GridGeom &g, const int R[3], i
     }
 }
 
+// Trilinear corners of a continuous position p in the network's input domain
+// [-1, 1]^3 (Sec. 4.3) on a level of sizes R: c = (p + 1)/2 (R - 1) per axis as one
+// FP32 fma, clamped to [0, R - 1], so positions outside the domain (and NaN, which
+// the max turns into 0) take the boundary's value; base = min(floor(c), R - 2),
+// f = c - base.  The position 2 i/(n - 1) - 1 of vertex i gives the vertex lookup's
+// cell, with weights equal up to the rounding of c.
+__device__ __forceinline__ void corners_pos32(const int R[3], const float p[3], int idx[8],
+                                              float w[8]) {
+    int b[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float hr = 0.5f * (float)(R[a] - 1);
+        const float c = fminf(fmaxf(fmaf(p[a], hr, hr), 0.f), (float)(R[a] - 1));
+        const int bb = min(max((int)c, 0), R[a] - 2);
+        b[a] = bb;
+        f[a] = c - (float)bb;
+    }
+#pragma unroll
+    for (int cn = 0; cn < 8; ++cn) {
+        const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
+        idx[cn] = (b[0] + dx) + R[0] * ((b[1] + dy) + R[1] * (b[2] + dz));
+        w[cn] = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) * (dz ? f[2] : 1.f - f[2]);
+    }
+}
+
 __device__ __forceinline__ void corners_R(const GridGeom &g, const int R[3], int64_t v,
                                           int64_t idx[8], float w[8]) {
     int i32[8];
@@ -180,5 +206,10 @@ int launch_infer_field_cached(const ndf_net_config *c, const void *q, const int6
                               int n_ref, const void *cache, float *out, void *ws, hipStream_t st);
 int launch_infer_field(const ndf_net_config *c, const void *q, int prec, const int64_t *ref_v,
                        int n_ref, float *out, void *ws, hipStream_t st);
+int launch_infer_points(const ndf_net_config *c, const void *q, int prec, const int64_t *ref_v,
+                        int n_ref, const float *pos, int64_t n, float *out, void *ws,
+                        hipStream_t st);
+int launch_infer_difference(const ndf_net_config *c, const void *q, int64_t ref_a, int64_t ref_b,
+                            const void *cache, float *out, void *ws, hipStream_t st);
 
 }  // namespace ndf

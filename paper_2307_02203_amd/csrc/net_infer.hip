@@ -391,13 +391,16 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 
 // MODE 0: field (out[v] = Phi(ref, v) for v < nq); MODE 1: latents of the
 // vertices in qlist (lat_out[n][128], bf16-rounded values stored as FP32);
-// MODE 2: latents of vertices 0 .. nq-1 into the query-latent cache (out).
+// MODE 2: latents of vertices 0 .. nq-1 into the query-latent cache (out);
+// MODE 3: field at the continuous positions qpos[n][3] in [-1, 1]^3.
 template <int MODE>
 __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const int64_t *__restrict__ qlist,
                                                               int64_t nq,
                                                               const float *__restrict__ ref_lat,
-                                                              float *__restrict__ out) {
+                                                              float *__restrict__ out,
+                                                              const float *__restrict__ qpos) {
+    constexpr bool kField = MODE == 0 || MODE == 3;
     __shared__ bf16x8 s_w1[kFragW1];
     __shared__ bf16x8 s_w[4][kFragW];
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
@@ -406,13 +409,13 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
 
     const int tid = threadIdx.x;
     for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
-    const int nlay = MODE == 0 ? 4 : 2;  // latent modes need W2, W3 only
+    const int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
-        s_ref[i] = MODE == 0 ? ref_lat[i] : 0.f;
+        s_ref[i] = kField ? ref_lat[i] : 0.f;
     }
     __syncthreads();
 
@@ -428,11 +431,14 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         asm volatile("" : "+v"(h4));
         bool ok[2];
         int64_t vq[2];
+        float pq[2][3];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int64_t n = row0 + q * 32 + jl;
             ok[q] = n < nq;
-            vq[q] = ok[q] ? (qlist ? qlist[n] : n) : 0;
+            vq[q] = ok[q] && MODE != 3 ? (qlist ? qlist[n] : n) : 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pq[q][a] = MODE == 3 && ok[q] ? qpos[3 * n + a] : 0.f;
         }
         // grid gather: k-block kb, half h -> level 2 kb + h (its 8 features)
         bf16x8 a[8][2], b[8][2];
@@ -447,7 +453,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             for (int q = 0; q < 2; ++q) {
                 int idx[8];
                 float w[8];
-                corners32(A.g, R, vq[q], idx, w);
+                if (MODE == 3)
+                    corners_pos32(R, pq[q], idx, w);
+                else
+                    corners32(A.g, R, vq[q], idx, w);
                 float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int cn = 0; cn < 8; ++cn) {
@@ -685,13 +694,15 @@ __device__ __forceinline__ void dense_layer_fp8(
 }
 
 // MODE 0: field (out[v] = Phi(ref, v)); MODE 1: latents of the vertices in
-// qlist (FP32).
+// qlist (FP32); MODE 3: field at the continuous positions qpos[n][3].
 template <int MODE>
 __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   const int64_t *__restrict__ qlist,
                                                                   int64_t nq,
                                                                   const float *__restrict__ ref_lat,
-                                                                  float *__restrict__ out) {
+                                                                  float *__restrict__ out,
+                                                                  const float *__restrict__ qpos) {
+    constexpr bool kField = MODE == 0 || MODE == 3;
     __shared__ bf16x8 s_w1[kFragW1];
     __shared__ i32x8 s_q[4][kFrag8];
     __shared__ int s_e[4][kH * 4];
@@ -701,7 +712,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
 
     const int tid = threadIdx.x;
     for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w1[i];
-    const int nlay = MODE == 0 ? 4 : 2;
+    const int nlay = kField ? 4 : 2;
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L][i];
     for (int i = tid; i < 4 * kH * 4; i += kInferThreads)
@@ -709,7 +720,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
-        s_ref[i] = MODE == 0 ? ref_lat[i] : 0.f;
+        s_ref[i] = kField ? ref_lat[i] : 0.f;
     }
     __syncthreads();
 
@@ -723,11 +734,14 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         asm volatile("" : "+v"(h4));
         bool ok[2];
         int64_t vq[2];
+        float pq[2][3];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int64_t n = row0 + q * 32 + jl;
             ok[q] = n < nq;
-            vq[q] = ok[q] ? (qlist ? qlist[n] : n) : 0;
+            vq[q] = ok[q] && MODE != 3 ? (qlist ? qlist[n] : n) : 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pq[q][a] = MODE == 3 && ok[q] ? qpos[3 * n + a] : 0.f;
         }
         bf16x8 g16[2][2];
 #pragma unroll
@@ -740,7 +754,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
             for (int q = 0; q < 2; ++q) {
                 int idx[8];
                 float w[8];
-                corners32(A.g, R, vq[q], idx, w);
+                if (MODE == 3)
+                    corners_pos32(R, pq[q], idx, w);
+                else
+                    corners32(A.g, R, vq[q], idx, w);
                 float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int cn = 0; cn < 8; ++cn) {
@@ -791,7 +808,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
 // The field from cached query latents: per 64-vertex tile, 16 loads of the bf16
 // latents, the product with the reference latent (the same packed arithmetic as
 // the uncached kernel, so both give the same bits), then layers 4, 5 and w6.
-// Only W4 and W5 (64 KB) live in LDS.
+// Only W4 and W5 (64 KB) live in LDS.  SUB: subtract the field from out instead
+// of storing it (the difference of two fields, Sec. 6.4, in two launches; each
+// lane reads back only what it stored itself).
+template <bool SUB>
 __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A,
                                                                       const u32x4 *__restrict__ cache,
                                                                       int64_t nq,
@@ -847,7 +867,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
-            if (h == 0 && ok[q]) out[row0 + q * 32 + jl] = y;
+            if (h == 0 && ok[q]) {
+                float *o = out + row0 + q * 32 + jl;
+                *o = SUB ? *o - y : y;
+            }
         }
     }
 }
@@ -910,7 +933,7 @@ int launch_infer_latents(const ndf_net_config *c, const void *qp, void *cache, h
     const QLayout q = qlayout(c);
     const InferArgs a = make_args(c, q, (const char *)qp, c->n_enc - 1);
     hipLaunchKernelGGL(infer_kernel<2>, dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
-                       nullptr, a.V, nullptr, (float *)cache);
+                       nullptr, a.V, nullptr, (float *)cache, nullptr);
     return status_of_launch();
 }
 
@@ -925,10 +948,10 @@ int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int
         return NDF_E_HIP;
     const InferArgs a0 = make_args(c, q, Q, 0);
     hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                       refs, (int64_t)n_ref, nullptr, lat);
+                       refs, (int64_t)n_ref, nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     for (int r = 0; r < n_ref; ++r)
-        hipLaunchKernelGGL(infer_cached_kernel, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
+        hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
                            st, a1, (const u32x4 *)cache, a1.V, lat + (int64_t)r * kH,
                            out + (int64_t)r * a1.V);
     return status_of_launch();
@@ -947,23 +970,76 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
         hipLaunchKernelGGL(infer_fp8_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                           st, a0, refs, (int64_t)n_ref, nullptr, lat);
+                           st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
         const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
         const int64_t V = (int64_t)c->nx * c->ny * c->nz;
         for (int r = 0; r < n_ref; ++r)
             hipLaunchKernelGGL(infer_fp8_kernel<0>, dim3(infer_blocks(V)), dim3(kInferThreads), 0,
-                               st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V);
+                               st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V,
+                               nullptr);
         return status_of_launch();
     }
     // reference latents with encoder 0 (p1), queries with the last encoder (p2)
     const InferArgs a0 = make_args(c, q, Q, 0);
     hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                       refs, (int64_t)n_ref, nullptr, lat);
+                       refs, (int64_t)n_ref, nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     const int64_t V = a1.V;
     for (int r = 0; r < n_ref; ++r)
         hipLaunchKernelGGL(infer_kernel<0>, dim3(infer_blocks(V)), dim3(kInferThreads), 0, st, a1,
-                           nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V);
+                           nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V, nullptr);
+    return status_of_launch();
+}
+
+int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const int64_t *ref_v,
+                        int n_ref, const float *pos, int64_t n, float *out, void *ws,
+                        hipStream_t st) {
+    if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
+    const QLayout q = qlayout(c);
+    const char *Q = (const char *)qp;
+    float *lat = (float *)ws;
+    int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return NDF_E_HIP;
+    if (prec == NDF_PREC_FP8_E4M3) {
+        const InferArgs8 a0 = make_args8(c, q, Q, 0);
+        hipLaunchKernelGGL(infer_fp8_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                           st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
+        for (int r = 0; r < n_ref; ++r)
+            hipLaunchKernelGGL(infer_fp8_kernel<3>, dim3(infer_blocks(n)), dim3(kInferThreads), 0,
+                               st, a1, nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n,
+                               pos);
+        return status_of_launch();
+    }
+    const InferArgs a0 = make_args(c, q, Q, 0);
+    hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                       refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
+    for (int r = 0; r < n_ref; ++r)
+        hipLaunchKernelGGL(infer_kernel<3>, dim3(infer_blocks(n)), dim3(kInferThreads), 0, st, a1,
+                           nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n, pos);
+    return status_of_launch();
+}
+
+int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref_a, int64_t ref_b,
+                            const void *cache, float *out, void *ws, hipStream_t st) {
+    const QLayout q = qlayout(c);
+    const char *Q = (const char *)qp;
+    float *lat = (float *)ws;
+    int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)2 * kH * sizeof(float), 256));
+    const int64_t both[2] = {ref_a, ref_b};
+    if (hipMemcpyAsync(refs, both, sizeof(both), hipMemcpyHostToDevice, st) != hipSuccess)
+        return NDF_E_HIP;
+    const InferArgs a0 = make_args(c, q, Q, 0);
+    hipLaunchKernelGGL(infer_kernel<1>, dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
+                       nullptr, lat, nullptr);
+    const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
+    hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
+                       st, a1, (const u32x4 *)cache, a1.V, lat, out);
+    hipLaunchKernelGGL(infer_cached_kernel<true>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
+                       st, a1, (const u32x4 *)cache, a1.V, lat + kH, out);
     return status_of_launch();
 }
 

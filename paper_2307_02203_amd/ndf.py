@@ -27,7 +27,7 @@ EXPORTED = [
     "ndf_net_optstate_bytes", "ndf_net_init", "ndf_net_grad", "ndf_net_forward",
     "ndf_train_step", "ndf_net_qparam_bytes", "ndf_net_quantize", "ndf_infer_field",
     "ndf_infer_latent_bytes", "ndf_infer_latents", "ndf_infer_field_cached",
-    "ndf_net_swap_encoders",
+    "ndf_net_swap_encoders", "ndf_infer_points", "ndf_infer_field_difference",
 ]
 
 
@@ -88,6 +88,10 @@ def lib():
             "ndf_infer_field_cached": (ctypes.c_int, [C, _VP, _VP, _I32, _VP, _VP, _VP, _SZ,
                                                       _VP]),
             "ndf_net_swap_encoders": (ctypes.c_int, [C, _VP, _VP, _VP]),
+            "ndf_infer_points": (ctypes.c_int, [C, _VP, _I32, _VP, _I32, _VP, _I64, _VP, _VP,
+                                                _SZ, _VP]),
+            "ndf_infer_field_difference": (ctypes.c_int, [C, _VP, _I64, _I64, _VP, _VP, _VP,
+                                                          _SZ, _VP]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -308,6 +312,26 @@ def ndf_infer_field_cached(cfg, qparams, ref_v, cache, out, ws, stream=None):
     _check(lib().ndf_infer_field_cached(ctypes.byref(cfg), _p(qparams), rp, len(refs), _p(cache),
                                         _p(out), _p(ws), ws.numel(), _stream(stream)),
            "ndf_infer_field_cached")
+
+
+def ndf_infer_points(cfg, qparams, prec, ref_v, pos, out, ws, stream=None):
+    """out[r][i] = Phi(p_ref[r], pos[i]) for pos float32 [n][3] in [-1, 1]^3."""
+    refs, rp = _host_i64(ref_v)
+    if pos.dim() != 2 or pos.shape[1] != 3 or pos.dtype != torch.float32 \
+            or not pos.is_contiguous():
+        raise NdfError("ndf_infer_points: pos must be a contiguous float32 [n][3] tensor")
+    if out.dtype != torch.float32 or not out.is_contiguous() \
+            or out.numel() < len(refs) * pos.shape[0]:
+        raise NdfError("ndf_infer_points: out must be a contiguous float32 [n_ref][n] tensor")
+    _check(lib().ndf_infer_points(ctypes.byref(cfg), _p(qparams), prec, rp, len(refs), _p(pos),
+                                  pos.shape[0], _p(out), _p(ws), ws.numel(), _stream(stream)),
+           "ndf_infer_points")
+
+
+def ndf_infer_field_difference(cfg, qparams, ref_a, ref_b, cache, out, ws, stream=None):
+    _check(lib().ndf_infer_field_difference(ctypes.byref(cfg), _p(qparams), int(ref_a),
+                                            int(ref_b), _p(cache), _p(out), _p(ws), ws.numel(),
+                                            _stream(stream)), "ndf_infer_field_difference")
 
 
 def infer_ws_bytes(cfg, n_ref, prec):

@@ -147,3 +147,24 @@ def test_net_config_validation_and_param_bytes():
     ok_ref = np.array([5], dtype=np.int64)
     assert (L.ndf_infer_field_cached(C, FAKE, ok_ref.ctypes.data_as(ctypes.c_void_p), 1, FAKE,
                                      FAKE, FAKE, 16, None) == ndf.NDF_E_WORKSPACE)
+    # learned field at continuous positions (ray-march sampling) and field differences
+    okp = ok_ref.ctypes.data_as(ctypes.c_void_p)
+    badp = refs.ctypes.data_as(ctypes.c_void_p)
+    BF = ndf.NDF_PREC_BF16
+    assert L.ndf_infer_points(C, FAKE, BF, okp, 1, None, 10, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert L.ndf_infer_points(C, FAKE, BF, okp, 1, FAKE, 10, None, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert L.ndf_infer_points(C, FAKE, BF, okp, 1, FAKE, -1, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert L.ndf_infer_points(C, FAKE, BF, okp, 0, FAKE, 10, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert L.ndf_infer_points(C, FAKE, BF, badp, 1, FAKE, 10, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert (L.ndf_infer_points(C, FAKE, ndf.NDF_PREC_FP32, okp, 1, FAKE, 10, FAKE, FAKE, 1 << 30,
+                               None) == ndf.NDF_E_UNSUPPORTED)
+    assert L.ndf_infer_points(C, FAKE, BF, okp, 1, FAKE, 10, FAKE, FAKE, 16, None) == ndf.NDF_E_WORKSPACE
+    # n = 0 is valid and enqueues nothing (no device needed)
+    assert L.ndf_infer_points(C, FAKE, BF, okp, 1, None, 0, None, FAKE, 1 << 30, None) == ndf.NDF_OK
+    V = 250 * 352 * 20
+    assert L.ndf_infer_field_difference(C, FAKE, 0, V, FAKE, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert L.ndf_infer_field_difference(C, FAKE, -1, 0, FAKE, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    assert L.ndf_infer_field_difference(C, FAKE, 0, 1, None, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
+    need2 = ndf.infer_ws_bytes(cfg, 2, BF)
+    assert (L.ndf_infer_field_difference(C, FAKE, 0, 1, FAKE, FAKE, FAKE, need2 - 1, None)
+            == ndf.NDF_E_WORKSPACE)

@@ -429,3 +429,76 @@ def test_correlation_volume_matrix_two_variables():
         const = np.mean(np.abs(want - np.median(want)))
         _log(f"correlation volume ({mu},{nu}): MAE {mae:.4f} best constant {const:.4f}")
         assert mae < 0.3 * const, (mu, nu)
+
+
+def _points_gpu(c, q, refs, pos, prec):
+    pos_t = torch.as_tensor(pos, dtype=torch.float32, device="cuda").contiguous()
+    out = torch.empty((len(refs), len(pos)), dtype=torch.float32, device="cuda")
+    ws = torch.empty(ndf.infer_ws_bytes(c, len(refs), prec), dtype=torch.uint8, device="cuda")
+    ndf.ndf_infer_points(c, q, prec, refs, pos_t, out, ws)
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 1), ("mid", 2)])
+def test_infer_points_parity(name, n_enc):
+    """The learned field at continuous positions, as a ray marcher samples it
+    (Sec. 5): uniform positions in the domain, positions outside it (clamped),
+    equally spaced samples along rays and the positions of grid vertices, 4517 in
+    all (a ragged last tile).  BF16 against the FP64 oracle to the BF16 bar, FP8
+    to relative L2 0.2; at vertex positions the BF16 values equal the vertex
+    field up to the FP32 rounding of the position (within 2% of the field RMS)."""
+    cfg, lay, c, P, net = _setup(name, n_enc, seed=2330)
+    V = cfg.n_vertices
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    vs = gen.random_vertices(V, 37, seed=44)
+    vpos = (2.0 * nn.vertex_positions(vs, dims) - 1.0).astype(np.float32)
+    pos = np.concatenate([gen.random_positions(3000, seed=41),
+                          gen.random_positions(200, seed=42, spread=1.5),
+                          gen.ray_positions(20, 64, seed=43), vpos]).astype(np.float32)
+    refs = [cfg.ref_v, 0]
+    q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    out16 = _points_gpu(c, q, refs, pos, ndf.NDF_PREC_BF16)
+    out8 = _points_gpu(c, q, refs, pos, ndf.NDF_PREC_FP8_E4M3)
+    for i, r in enumerate(refs):
+        want = nn.field_points(net, r, pos.astype(np.float64))
+        _check_bf16(out16[i], want, f"points {name} n_enc={n_enc} ref={r}")
+        rel8 = np.linalg.norm(out8[i] - want) / np.linalg.norm(want)
+        _log(f"points fp8 {name} n_enc={n_enc} ref={r}: relL2 {rel8:.3e}")
+        assert rel8 <= 0.2
+    field = _infer_gpu(c, q, refs, V).cpu().numpy()[:, vs]
+    for i in range(len(refs)):
+        rms = np.sqrt(np.mean(field[i] ** 2))
+        d = np.max(np.abs(out16[i, -len(vs):] - field[i]))
+        _log(f"points at vertices vs vertex field: max|d| {d:.3g} (rms {rms:.3g})")
+        assert d <= 0.02 * rms
+
+
+def test_infer_field_difference():
+    """Difference of two learned fields (Sec. 6.4) from the query-latent cache:
+    bit for bit the FP32 difference of the two cached fields, zero for equal
+    references, and within the BF16 bar of the FP64 difference."""
+    cfg, lay, c, P, net = _setup("mid", 2, seed=2331)
+    V = cfg.n_vertices
+    q = _qparams(c, P)
+    cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
+    ndf.ndf_infer_latents(c, q, cache)
+    a, b = cfg.ref_v, 5
+    fields = torch.empty((2, V), device="cuda")
+    ws = torch.empty(ndf.infer_ws_bytes(c, 2, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                     device="cuda")
+    ndf.ndf_infer_field_cached(c, q, [a, b], cache, fields, ws)
+    out = torch.full((V,), float("nan"), device="cuda")
+    ndf.ndf_infer_field_difference(c, q, a, b, cache, out, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(out, fields[0] - fields[1])
+    same = torch.full((V,), float("nan"), device="cuda")
+    ndf.ndf_infer_field_difference(c, q, a, a, cache, same, ws)
+    assert torch.equal(same, torch.zeros_like(same))
+    fa, fb = nn.field(net, a), nn.field(net, b)
+    want = fa - fb
+    got = out.cpu().numpy().astype(np.float64)
+    scale = max(np.sqrt(np.mean(fa ** 2)), np.sqrt(np.mean(fb ** 2)))
+    err = np.max(np.abs(got - want))
+    _log(f"difference field: max|d| {err:.3g} field rms {scale:.3g}")
+    assert err <= 0.2 * scale
+    assert np.linalg.norm(got - want) <= 2e-2 * (np.linalg.norm(fa) + np.linalg.norm(fb))

@@ -77,6 +77,55 @@ def test_trilinear_affine_and_vertices():
         assert idx[0, np.argmax(w[0])] == R[0] * R[1] * R[2] - 1 and w[0].max() == 1.0
 
 
+def test_domain_positions_map_to_grid():
+    """Continuous positions in the domain [-1,1]^3 (Sec. 4.3): -1 and +1 are the
+    first and last vertex of an axis, so the trilinear features of an affine
+    level field at p equal the affine function of u = (p + 1)/2 exactly, a vertex's
+    position gives the vertex lookup's features, and positions outside the
+    domain take the boundary's value."""
+    rng = np.random.default_rng(4)
+    np.testing.assert_array_equal(nn.domain_to_unit(np.array([[-1.0, 0.0, 1.0]])),
+                                  [[0.0, 0.5, 1.0]])
+    np.testing.assert_array_equal(nn.domain_to_unit(np.array([[-3.0, 2.5, np.nan]])),
+                                  [[0.0, 1.0, 0.0]])
+    L = _layout()
+    net = _net(gen.make_net_params(L, grid_scale=1.0))
+    coef = rng.standard_normal((4, 8))
+    for l, R in enumerate(RES):
+        pos = _cell_positions(R)
+        net[("grid", 0, l)] = coef[0] + pos @ coef[1:]
+    p = rng.uniform(-1, 1, (400, 3))
+    h0 = nn.grid_encode(net, 0, nn.domain_to_unit(p))
+    want = coef[0] + ((p + 1) / 2) @ coef[1:]
+    for l in range(len(RES)):
+        assert np.max(np.abs(h0[:, 8 * l:8 * l + 8] - want)) < 1e-12
+    # vertex positions 2 i/(n - 1) - 1 reproduce the vertex lookup
+    v = np.arange(DIMS[0] * DIMS[1] * DIMS[2])
+    u_v = nn.vertex_positions(v, DIMS)
+    p_v = 2.0 * u_v - 1.0
+    np.testing.assert_allclose(nn.grid_encode(net, 0, nn.domain_to_unit(p_v)),
+                               nn.grid_encode(net, 0, u_v), rtol=0, atol=1e-12)
+    # outside the domain: the clamped boundary point
+    q = rng.uniform(-1, 1, (50, 3))
+    out = q.copy()
+    out[:, 0] = rng.uniform(1.0, 3.0, 50)
+    inside = q.copy()
+    inside[:, 0] = 1.0
+    np.testing.assert_array_equal(nn.grid_encode(net, 0, nn.domain_to_unit(out)),
+                                  nn.grid_encode(net, 0, nn.domain_to_unit(inside)))
+
+
+def test_field_points_at_vertices_is_the_field():
+    """Phi(p_ref, p) at the positions of grid vertices equals the vertex field."""
+    L = _layout(n_enc=2)
+    net = _net(gen.make_net_params(L, seed=9, grid_scale=1.0, bias_scale=0.2), n_enc=2)
+    V = DIMS[0] * DIMS[1] * DIMS[2]
+    p_v = 2.0 * nn.vertex_positions(np.arange(V), DIMS) - 1.0
+    for ref in (0, 17, V - 1):
+        np.testing.assert_allclose(nn.field_points(net, ref, p_v), nn.field(net, ref),
+                                   rtol=1e-12, atol=1e-12)
+
+
 def test_gather_scatter_adjoint():
     rng = np.random.default_rng(1)
     L = _layout()
