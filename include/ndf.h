@@ -77,6 +77,9 @@ typedef struct ndf_ensemble {
     uint16_t *order;         /* [n_vars][V][N] members in ascending (code, member)
                                 order per vertex (ndf_prepare), or NULL: the KSG
                                 calls then sort every column they use            */
+    float *xt;               /* [n_vars][V][N] vertex-major copy of x written by
+                                ndf_prepare, or NULL; needed only by the calls at
+                                continuous positions (ndf_pearson_points)         */
 } ndf_ensemble;
 
 /* The learned field (Sec. 4.1-4.2): per encoder a dense multi-resolution feature
@@ -156,6 +159,21 @@ int ndf_ksg_mi_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
                      const int64_t *pairs, int64_t B, int32_t k, float *out,
                      int32_t *counts, void *ws, size_t ws_bytes, void *stream);
 
+/* Training targets at continuous positions (Sec. 4.3: pairs of positions drawn
+ * from the domain, the ensemble sampled there by trilinear interpolation):
+ * out[b] = r(e^{var_a}(p1), e^{var_b}(p2)) for pos float[B][2][3] (device;
+ * p1 = pos[b][0], p2 = pos[b][1], x y z in [-1, 1]^3 with -1 and +1 the first
+ * and last vertex of an axis, clamped to the domain).  The local sample at p is
+ * e(p)_m = sum_c w_c x_m(v_c) over the eight vertices of the grid cell holding
+ * p (data-grid coordinate c = (p + 1)/2 (n - 1), base = min(floor(c), n - 2),
+ * trilinear weights), computed as sum_c w_c (x_m(v_c) - mean(v_c)) in FP64 so
+ * the interpolated column is centred exactly; r from FP64 sums.  r = 0 where an
+ * interpolated column has zero variance, NaN where a corner with nonzero weight
+ * holds a non-finite value.  Reads ens->xt (NDF_E_ARG when NULL) and the means
+ * of ndf_prepare.  B = 0 enqueues nothing. */
+int ndf_pearson_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, const float *pos,
+                       int64_t B, float *out, void *stream);
+
 /* Bytes of the FP32 parameter vector (layout: for each encoder its grid levels
  * float[Rx*Ry*Rz][feats], then W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3; then
  * W4[W][W], b4, W5[W][W], b5, w6[W], b6[1]; every tensor starts at a multiple of
@@ -185,6 +203,22 @@ int ndf_net_grad(const ndf_net_config *cfg, const float *params, const int64_t *
 int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
                    const int64_t *pairs, const float *targets, int64_t B, float lr,
                    float *loss_out, void *ws, size_t ws_bytes, void *stream);
+
+/* The same three calls for pairs of continuous positions (Sec. 4.3 trains on
+ * positions drawn from the domain, not only on grid vertices): pos float[B][2][3]
+ * (device; pos[b][0] = p1, pos[b][1] = p2, x y z in [-1, 1]^3 with -1 and +1 the
+ * first and last vertex of an axis; each grid level is interpolated trilinearly
+ * at the position, coordinates outside the domain clamped, NaN to -1).  Targets
+ * at such positions come from ndf_pearson_points.  Arguments and workspace
+ * otherwise as for ndf_net_forward, ndf_net_grad and ndf_train_step. */
+int ndf_net_forward_at(const ndf_net_config *cfg, const float *params, const float *pos,
+                       int64_t B, float *y, void *ws, size_t ws_bytes, void *stream);
+int ndf_net_grad_at(const ndf_net_config *cfg, const float *params, const float *pos,
+                    const float *targets, int64_t B, float *grad_out, float *loss_out,
+                    void *ws, size_t ws_bytes, void *stream);
+int ndf_train_step_at(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
+                      const float *pos, const float *targets, int64_t B, float lr,
+                      float *loss_out, void *ws, size_t ws_bytes, void *stream);
 
 /* Multi-variable fields (Sec. 6.4): the network of the variable pair (nu, mu)
  * from that of (mu, nu), Phi_{nu mu}(p1, p2) = Phi_{mu nu}(p2, p1), by exchanging

@@ -9,4 +9,6 @@ the GPU library (``paper_2307_02203_amd``) and does not import it.
                        (Sec. 3.2, Eq. 2, estimator of [KSG04]) via plain C (ndf_oracle.c)
 * ``oracle.ndf_net`` : the learned field (Sec. 4, Eq. 3; Sec. 4.1-4.3) forward,
                        adjoint and Adam in float64 numpy
+* ``oracle.points``  : training targets at continuous positions (Sec. 4.3):
+                       trilinear interpolation of the ensemble, Pearson in float64
 """

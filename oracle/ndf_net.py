@@ -212,8 +212,28 @@ def _encoder_backward(net, e, c, dlat, grads):
 
 def loss_and_grad(net, v1, v2, t):
     """Mean L1 loss (Eq. 3 with d = L1) and its gradient w.r.t. every parameter."""
+    dims = (net.nx, net.ny, net.nz)
+    return loss_and_grad_unit(net, vertex_positions(v1, dims), vertex_positions(v2, dims), t)
+
+
+def loss_and_grad_points(net, pos, t):
+    """loss_and_grad for pairs of continuous positions pos (B,2,3) in [-1,1]^3
+    (the training pairs of Sec. 4.3)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    return loss_and_grad_unit(net, domain_to_unit(pos[:, 0]), domain_to_unit(pos[:, 1]), t)
+
+
+def forward_points(net, pos):
+    """Phi(p1, p2) for pairs of continuous positions pos (B,2,3)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    y, _ = forward_unit(net, domain_to_unit(pos[:, 0]), domain_to_unit(pos[:, 1]))
+    return y
+
+
+def loss_and_grad_unit(net, u1, u2, t):
+    """loss_and_grad for positions given as u in [0,1]^3."""
     t = np.asarray(t, dtype=np.float64)
-    y, c = forward(net, v1, v2)
+    y, c = forward_unit(net, u1, u2)
     n = y.shape[0]
     gy = np.sign(y - t) / n
     g = net.zeros_like()

@@ -14,6 +14,8 @@ int launch_pearson_field(const ndf_ensemble *e, int var_ref, int var_qry, const 
                          int n_ref, float *out, int prec, void *ws, hipStream_t st);
 int launch_pearson_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t *pairs,
                          int64_t B, float *out, hipStream_t st);
+int launch_pearson_points(const ndf_ensemble *e, int var_a, int var_b, const float *pos,
+                          int64_t B, float *out, hipStream_t st);
 size_t ksg_field_ws_bytes(int N, int n_ref);
 int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int64_t *ref_v,
                      int n_ref, int k, float *out, int32_t *counts, void *ws, hipStream_t st);
@@ -136,6 +138,17 @@ int ndf_pearson_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
     return launch_pearson_pairs(ens, var_a, var_b, pairs, B, out, S(stream));
 }
 
+int ndf_pearson_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, const float *pos,
+                       int64_t B, float *out, void *stream) {
+    int s = check_ensemble(ens, true);
+    if (s == NDF_OK) s = check_var(ens, var_a);
+    if (s == NDF_OK) s = check_var(ens, var_b);
+    if (s != NDF_OK) return s;
+    if (!ens->xt || B < 0 || (B > 0 && (!pos || !out))) return NDF_E_ARG;
+    if (B == 0) return NDF_OK;
+    return launch_pearson_points(ens, var_a, var_b, pos, B, out, S(stream));
+}
+
 int ndf_ksg_mi_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
                      const int64_t *pairs, int64_t B, int32_t k, float *out, int32_t *counts,
                      void *ws, size_t ws_bytes, void *stream) {
@@ -171,7 +184,19 @@ int ndf_net_grad(const ndf_net_config *cfg, const float *params, const int64_t *
     if (s != NDF_OK) return s;
     if (!params || !pairs || !targets || !grad_out || !loss_out || B < 1) return NDF_E_ARG;
     if (!ws || ws_bytes < net_train_ws_bytes(cfg, B)) return NDF_E_WORKSPACE;
-    return launch_net_grad(cfg, params, pairs, targets, B, grad_out, loss_out, ws, S(stream));
+    return launch_net_grad(cfg, params, pairs, nullptr, targets, B, grad_out, loss_out, ws,
+                           S(stream));
+}
+
+int ndf_net_grad_at(const ndf_net_config *cfg, const float *params, const float *pos,
+                    const float *targets, int64_t B, float *grad_out, float *loss_out, void *ws,
+                    size_t ws_bytes, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!params || !pos || !targets || !grad_out || !loss_out || B < 1) return NDF_E_ARG;
+    if (!ws || ws_bytes < net_train_ws_bytes(cfg, B)) return NDF_E_WORKSPACE;
+    return launch_net_grad(cfg, params, nullptr, pos, targets, B, grad_out, loss_out, ws,
+                           S(stream));
 }
 
 int ndf_net_forward(const ndf_net_config *cfg, const float *params, const int64_t *pairs,
@@ -180,7 +205,16 @@ int ndf_net_forward(const ndf_net_config *cfg, const float *params, const int64_
     if (s != NDF_OK) return s;
     if (!params || !pairs || !y || B < 1) return NDF_E_ARG;
     if (!ws || ws_bytes < net_train_ws_bytes(cfg, B)) return NDF_E_WORKSPACE;
-    return launch_net_forward(cfg, params, pairs, B, y, ws, S(stream));
+    return launch_net_forward(cfg, params, pairs, nullptr, B, y, ws, S(stream));
+}
+
+int ndf_net_forward_at(const ndf_net_config *cfg, const float *params, const float *pos,
+                       int64_t B, float *y, void *ws, size_t ws_bytes, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!params || !pos || !y || B < 1) return NDF_E_ARG;
+    if (!ws || ws_bytes < net_train_ws_bytes(cfg, B)) return NDF_E_WORKSPACE;
+    return launch_net_forward(cfg, params, nullptr, pos, B, y, ws, S(stream));
 }
 
 int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
@@ -195,7 +229,24 @@ int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, i
     if (!ws || ws_bytes < net_train_ws_bytes(cfg, B) + align_up(pbytes, 256))
         return NDF_E_WORKSPACE;
     float *grad = (float *)((char *)ws + net_train_ws_bytes(cfg, B));
-    s = launch_net_grad(cfg, params, pairs, targets, B, grad, loss_out, ws, S(stream));
+    s = launch_net_grad(cfg, params, pairs, nullptr, targets, B, grad, loss_out, ws, S(stream));
+    if (s != NDF_OK) return s;
+    return launch_adam(cfg, params, opt_state, grad, step, lr, S(stream));
+}
+
+int ndf_train_step_at(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
+                      const float *pos, const float *targets, int64_t B, float lr,
+                      float *loss_out, void *ws, size_t ws_bytes, void *stream) {
+    int s = check_net_config(cfg);
+    if (s != NDF_OK) return s;
+    if (!params || !opt_state || !pos || !targets || !loss_out || B < 1 || step < 1 ||
+        !(lr >= 0.f) || !isfinite(lr))
+        return NDF_E_ARG;
+    const size_t pbytes = (size_t)net_offsets(cfg).total * sizeof(float);
+    if (!ws || ws_bytes < net_train_ws_bytes(cfg, B) + align_up(pbytes, 256))
+        return NDF_E_WORKSPACE;
+    float *grad = (float *)((char *)ws + net_train_ws_bytes(cfg, B));
+    s = launch_net_grad(cfg, params, nullptr, pos, targets, B, grad, loss_out, ws, S(stream));
     if (s != NDF_OK) return s;
     return launch_adam(cfg, params, opt_state, grad, step, lr, S(stream));
 }

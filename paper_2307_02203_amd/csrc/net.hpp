@@ -189,11 +189,13 @@ size_t net_qparam_bytes(const ndf_net_config *c, int prec);
 
 int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t seed,
                     hipStream_t st);
+// Rows come from vertex pairs int64[B][2] (pos null) or from continuous
+// position pairs float[B][2][3] in [-1, 1]^3 (pairs null).
 int launch_net_grad(const ndf_net_config *c, const float *params, const int64_t *pairs,
-                    const float *targets, int64_t B, float *grad, float *loss, void *ws,
-                    hipStream_t st);
+                    const float *pos, const float *targets, int64_t B, float *grad, float *loss,
+                    void *ws, hipStream_t st);
 int launch_net_forward(const ndf_net_config *c, const float *params, const int64_t *pairs,
-                       int64_t B, float *y, void *ws, hipStream_t st);
+                       const float *pos, int64_t B, float *y, void *ws, hipStream_t st);
 int launch_adam(const ndf_net_config *c, float *params, float *opt, const float *grad,
                 int64_t step, float lr, hipStream_t st);
 int launch_net_quantize(const ndf_net_config *c, const float *params, int prec, void *q,

@@ -67,23 +67,46 @@ __device__ __forceinline__ int64_t row_vertex(const int64_t *pairs, int64_t B, i
     return n < B ? pairs[2 * n] : pairs[2 * (n - B) + 1];
 }
 
+// Row n's position as continuous coordinates in [-1, 1]^3 when the pairs are
+// given as positions pos[B][2][3] (the training pairs of Sec. 4.3).
+__device__ __forceinline__ const float *row_pos(const float *pos, int64_t B, int64_t n) {
+    return pos + 3 * (n < B ? 2 * n : 2 * (n - B) + 1);
+}
+
+// Trilinear corners of row n on a level of sizes R: from its vertex index
+// (pairs) or its continuous position (pos, when non-null).
+__device__ __forceinline__ void row_corners(const GridGeom &g, const int R[3],
+                                            const int64_t *pairs, const float *pos, int64_t B,
+                                            int64_t n, int idx[8], float w[8]) {
+    if (pos) {
+        const float *p = row_pos(pos, B, n);
+        const float pp[3] = {p[0], p[1], p[2]};
+        corners_pos32(R, pp, idx, w);
+    } else {
+        int64_t v = row_vertex(pairs, B, n);
+        const int64_t V = (int64_t)g.nx * g.ny * g.nz;
+        v = v < 0 ? 0 : (v >= V ? V - 1 : v);  // out-of-range pairs are clamped
+        corners_R32(g, R, v, idx, w);
+    }
+}
+
 // ----------------------------------------------------------- grid fwd ----
 // H0[n][l*8 + f] for rows n < 2B (first endpoints, then second endpoints).
 __global__ __launch_bounds__(kThreads) void grid_fwd_kernel(const float *__restrict__ params,
                                                             GridOffs go, GridGeom g, int n_enc,
                                                             const int64_t *__restrict__ pairs,
+                                                            const float *__restrict__ pos,
                                                             int64_t B, float *__restrict__ H0) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * B * kL) return;
     const int64_t n = t / kL;
     const int l = (int)(t % kL);
     const int e = (n_enc == 2 && n >= B) ? 1 : 0;
-    int64_t v = row_vertex(pairs, B, n);
-    const int64_t V = (int64_t)g.nx * g.ny * g.nz;
-    v = v < 0 ? 0 : (v >= V ? V - 1 : v);  // out-of-range pairs are clamped
-    int64_t idx[8];
+    int R[3];
+    level_dims(g, l, R);
+    int idx[8];
     float w[8];
-    corners(g, l, v, idx, w);
+    row_corners(g, R, pairs, pos, B, n, idx, w);
     const f32x4 *grid = reinterpret_cast<const f32x4 *>(params + grid_off(go, e, l));
     f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
 #pragma unroll
@@ -106,23 +129,21 @@ __global__ __launch_bounds__(kThreads) void grid_fwd_kernel(const float *__restr
 __global__ __launch_bounds__(kThreads) void grid_bwd_kernel(float *__restrict__ grad, GridOffs go,
                                                             GridGeom g, int n_enc,
                                                             const int64_t *__restrict__ pairs,
+                                                            const float *__restrict__ pos,
                                                             int64_t B, int64_t row0, int64_t rows,
                                                             const float *__restrict__ dH0) {
     const int lane = threadIdx.x & 63, c = lane >> 3, f = lane & 7;
     const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    const int64_t V = (int64_t)g.nx * g.ny * g.nz;
     for (int64_t it = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); it < rows * kL;
          it += waves) {
         const int64_t n = row0 + it / kL;
         const int l = (int)(it % kL);
         const int e = (n_enc == 2 && n >= B) ? 1 : 0;
-        int64_t v = row_vertex(pairs, B, n);
-        v = v < 0 ? 0 : (v >= V ? V - 1 : v);
         int R[3];
         level_dims(g, l, R);
         int idx[8];
         float w[8];
-        corners_R32(g, R, v, idx, w);
+        row_corners(g, R, pairs, pos, B, n, idx, w);
         int ic = idx[0];
         float wc = w[0];
 #pragma unroll
@@ -497,12 +518,13 @@ GridOffs grid_offs(const NetOffsets &o) {
 
 // Forward pass into the workspace; with targets also the loss and gy.
 void forward(const ndf_net_config *c, const NetOffsets &o, const float *P, const int64_t *pairs,
-             const float *targets, int64_t B, const TrainWS &t, hipStream_t st) {
+             const float *pos, const float *targets, int64_t B, const TrainWS &t,
+             hipStream_t st) {
     const int64_t R = 2 * B;
     const GridGeom g = grid_geom(c);
     const GridOffs go = grid_offs(o);
     hipLaunchKernelGGL(grid_fwd_kernel, dim3((unsigned)ceil_div(R * kL, kThreads)), dim3(kThreads),
-                       0, st, P, go, g, c->n_enc, pairs, B, t.H0);
+                       0, st, P, go, g, c->n_enc, pairs, pos, B, t.H0);
     const int n_enc = c->n_enc;
     for (int e = 0; e < n_enc; ++e) {
         const int64_t r0 = n_enc == 1 ? 0 : e * B, rows = n_enc == 1 ? R : B;
@@ -558,23 +580,23 @@ int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t
 }
 
 int launch_net_forward(const ndf_net_config *c, const float *params, const int64_t *pairs,
-                       int64_t B, float *y, void *ws, hipStream_t st) {
+                       const float *pos, int64_t B, float *y, void *ws, hipStream_t st) {
     const NetOffsets o = net_offsets(c);
     TrainWS t = carve(ws, B);
     t.y = y;
-    forward(c, o, params, pairs, nullptr, B, t, st);
+    forward(c, o, params, pairs, pos, nullptr, B, t, st);
     return status_of_launch();
 }
 
 int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pairs,
-                    const float *targets, int64_t B, float *G, float *loss, void *ws,
-                    hipStream_t st) {
+                    const float *pos, const float *targets, int64_t B, float *G, float *loss,
+                    void *ws, hipStream_t st) {
     const NetOffsets o = net_offsets(c);
     const TrainWS t = carve(ws, B);
     const int64_t R = 2 * B;
     hipLaunchKernelGGL(fill_kernel, dim3(gs_blocks(o.total)), dim3(kThreads), 0, st, G, o.total,
                        0.f);
-    forward(c, o, P, pairs, targets, B, t, st);
+    forward(c, o, P, pairs, pos, targets, B, t, st);
     const int nparts = (int)ceil_div(B, kThreads);
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, st, t.partial, nparts, B, loss);
     // decoder adjoint
@@ -619,7 +641,8 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
         const int64_t items = rows * kL, per_block = kThreads / 64;
         const int64_t gb = ceil_div(items, per_block);
         hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)(gb < 16384 ? gb : 16384)),
-                           dim3(kThreads), 0, st, G, go, g, n_enc, pairs, B, r0, rows, t.dH0);
+                           dim3(kThreads), 0, st, G, go, g, n_enc, pairs, pos, B, r0, rows,
+                           t.dH0);
     }
     return status_of_launch();
 }

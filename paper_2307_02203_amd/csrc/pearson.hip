@@ -269,6 +269,103 @@ __global__ __launch_bounds__(256) void pearson_pairs_kernel(
     }
 }
 
+// --------------------------------------------------- continuous positions ----
+// Corner vertices and trilinear weights (FP64) of the data-grid cell holding the
+// position p in [-1, 1]^3: c = (p + 1)/2 (n - 1) per axis, clamped to [0, n - 1]
+// (NaN to 0), base = min(floor(c), n - 2), f = c - base.
+__device__ __forceinline__ void data_cell(const float *p, int nx, int ny, int nz, int64_t v[8],
+                                          double w[8]) {
+    const int n[3] = {nx, ny, nz};
+    int64_t b[3];
+    double f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double c = ((double)p[a] + 1.0) * 0.5 * (double)(n[a] - 1);
+        c = c == c ? fmin(fmax(c, 0.0), (double)(n[a] - 1)) : 0.0;
+        const int bb = min((int)c, n[a] - 2);
+        b[a] = bb;
+        f[a] = c - (double)bb;
+    }
+#pragma unroll
+    for (int cn = 0; cn < 8; ++cn) {
+        const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
+        v[cn] = (b[0] + dx) + (int64_t)nx * ((b[1] + dy) + (int64_t)ny * (b[2] + dz));
+        w[cn] = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+    }
+}
+
+// Pearson's r between the interpolated local samples at two positions (targets
+// at continuous positions): one wave per pair; the sixteen corner columns are
+// rows of the vertex-major copy xt (coalesced).  Member m's centred sample is
+// sum_c w_c (x_m(v_c) - mean(v_c)) in FP64; corners of weight 0 are skipped (a
+// non-finite value there does not reach the result).
+template <bool VEC>
+__global__ __launch_bounds__(256) void pearson_points_kernel(
+    const float *__restrict__ xt_a, const float *__restrict__ xt_b,
+    const double *__restrict__ mean_a, const double *__restrict__ mean_b,
+    const int32_t *__restrict__ flags_a, const int32_t *__restrict__ flags_b, int N, int nx,
+    int ny, int nz, const float *__restrict__ pos, int64_t B, float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B) return;
+    int64_t va[8], vb[8];
+    double wa[8], wb[8];
+    data_cell(pos + 6 * b, nx, ny, nz, va, wa);
+    data_cell(pos + 6 * b + 3, nx, ny, nz, vb, wb);
+    bool bad = false;
+    double mua[8], mub[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        bad |= wa[c] != 0.0 && (flags_a[va[c]] & NDF_FLAG_NONFINITE);
+        bad |= wb[c] != 0.0 && (flags_b[vb[c]] & NDF_FLAG_NONFINITE);
+        mua[c] = mean_a[va[c]];
+        mub[c] = mean_b[vb[c]];
+    }
+    if (bad) {
+        if (lane == 0) out[b] = __builtin_nanf("");
+        return;
+    }
+    double sab = 0.0, saa = 0.0, sbb = 0.0;
+    if (VEC) {  // N % 4 == 0: 16-byte loads of every corner row
+        for (int m = 4 * lane; m < N; m += 256) {
+            f32x4 xa[8], xb[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                xa[c] = *reinterpret_cast<const f32x4 *>(xt_a + va[c] * N + m);
+                xb[c] = *reinterpret_cast<const f32x4 *>(xt_b + vb[c] * N + m);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double da = 0.0, db = 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (wa[c] != 0.0) da += wa[c] * ((double)xa[c][e] - mua[c]);
+                    if (wb[c] != 0.0) db += wb[c] * ((double)xb[c][e] - mub[c]);
+                }
+                sab += da * db;
+                saa += da * da;
+                sbb += db * db;
+            }
+        }
+    } else {
+        for (int m = lane; m < N; m += 64) {
+            double da = 0.0, db = 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if (wa[c] != 0.0) da += wa[c] * ((double)xt_a[va[c] * N + m] - mua[c]);
+                if (wb[c] != 0.0) db += wb[c] * ((double)xt_b[vb[c] * N + m] - mub[c]);
+            }
+            sab += da * db;
+            saa += da * da;
+            sbb += db * db;
+        }
+    }
+    sab = wave_sum_f64(sab);
+    saa = wave_sum_f64(saa);
+    sbb = wave_sum_f64(sbb);
+    if (lane == 0) out[b] = (saa > 0.0 && sbb > 0.0) ? (float)(sab / sqrt(saa * sbb)) : 0.0f;
+}
+
 // ------------------------------------------------------------ launchers ----
 size_t pearson_ws_bytes(int N, int n_ref, int prec) {
     const int kpad = (int)align_up((size_t)N, 16);
@@ -359,6 +456,24 @@ int launch_pearson_pairs(const ndf_ensemble *e, int var_a, int var_b, const int6
     else
         hipLaunchKernelGGL(pearson_pairs_kernel<false>, g, dim3(256), 0, st, ca, cb, fa, fb, N, V,
                            pairs, B, out);
+    return status_of_launch();
+}
+
+int launch_pearson_points(const ndf_ensemble *e, int var_a, int var_b, const float *pos,
+                          int64_t B, float *out, hipStream_t st) {
+    const int N = e->n_members;
+    const int64_t V = (int64_t)e->nx * e->ny * e->nz;
+    const float *xa = e->xt + (int64_t)var_a * V * N;
+    const float *xb = e->xt + (int64_t)var_b * V * N;
+    const double *ma = e->mean + (int64_t)var_a * V, *mb = e->mean + (int64_t)var_b * V;
+    const int32_t *fa = e->flags + (int64_t)var_a * V, *fb = e->flags + (int64_t)var_b * V;
+    const dim3 g((unsigned)ceil_div(B, 4));
+    if (N % 4 == 0)
+        hipLaunchKernelGGL(pearson_points_kernel<true>, g, dim3(256), 0, st, xa, xb, ma, mb, fa, fb,
+                           N, e->nx, e->ny, e->nz, pos, B, out);
+    else
+        hipLaunchKernelGGL(pearson_points_kernel<false>, g, dim3(256), 0, st, xa, xb, ma, mb, fa,
+                           fb, N, e->nx, e->ny, e->nz, pos, B, out);
     return status_of_launch();
 }
 

@@ -200,11 +200,42 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
     }
 }
 
+// Vertex-major copy xt[v][m] of the member-major ensemble x[m][v] (for the
+// reads of a few scattered vertices' full columns, as interpolation at
+// continuous positions does): 64 x 64 tiles through LDS, 256-byte coalesced
+// reads and writes.
+__global__ __launch_bounds__(256) void transpose_kernel(const float *__restrict__ x, int N,
+                                                        int64_t V, float *__restrict__ xt) {
+    __shared__ float tile[64][65];
+    const int var = blockIdx.z;
+    const float *xv = x + (int64_t)var * N * V;
+    float *tv = xt + (int64_t)var * V * N;
+    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int m0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int m = m0 + i;
+        const int64_t v = v0 + tx;
+        tile[i][tx] = (m < N && v < V) ? __builtin_nontemporal_load(xv + (int64_t)m * V + v) : 0.f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t v = v0 + i;
+        const int m = m0 + tx;
+        if (v < V && m < N) tv[v * N + m] = tile[tx][i];
+    }
+}
+
 int launch_prepare(const ndf_ensemble *e, hipStream_t st) {
     const int64_t V = (int64_t)e->nx * e->ny * e->nz;
     dim3 grid((unsigned)ceil_div(V, kPrepV), (unsigned)e->n_vars);
     hipLaunchKernelGGL(prepare_kernel, grid, dim3(kPrepThreads), 0, st, e->x, e->n_members, V,
                        e->mean, e->inv_std, e->code, e->flags);
+    if (e->xt) {
+        dim3 tg((unsigned)ceil_div(V, 64), (unsigned)ceil_div(e->n_members, 64),
+                (unsigned)e->n_vars);
+        hipLaunchKernelGGL(transpose_kernel, tg, dim3(256), 0, st, e->x, e->n_members, V, e->xt);
+    }
     return status_of_launch();
 }
 

@@ -28,6 +28,7 @@ EXPORTED = [
     "ndf_train_step", "ndf_net_qparam_bytes", "ndf_net_quantize", "ndf_infer_field",
     "ndf_infer_latent_bytes", "ndf_infer_latents", "ndf_infer_field_cached",
     "ndf_net_swap_encoders", "ndf_infer_points", "ndf_infer_field_difference",
+    "ndf_pearson_points", "ndf_net_forward_at", "ndf_net_grad_at", "ndf_train_step_at",
 ]
 
 
@@ -40,7 +41,7 @@ class ndf_ensemble(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("n_vars", ctypes.c_int32), ("x", ctypes.c_void_p),
                 ("mean", ctypes.c_void_p), ("inv_std", ctypes.c_void_p),
                 ("code", ctypes.c_void_p), ("flags", ctypes.c_void_p),
-                ("order", ctypes.c_void_p)]
+                ("order", ctypes.c_void_p), ("xt", ctypes.c_void_p)]
 
 
 class ndf_net_config(ctypes.Structure):
@@ -71,6 +72,7 @@ def lib():
             "ndf_ksg_mi_field": (ctypes.c_int, [E, _I32, _I32, _VP, _I32, _I32, _VP, _VP, _VP,
                                                 _SZ, _VP]),
             "ndf_pearson_pairs": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _VP, _VP]),
+            "ndf_pearson_points": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _VP, _VP]),
             "ndf_ksg_mi_pairs": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _I32, _VP, _VP, _VP,
                                                 _SZ, _VP]),
             "ndf_net_param_bytes": (_SZ, [C]),
@@ -78,6 +80,10 @@ def lib():
             "ndf_net_init": (ctypes.c_int, [C, _VP, _VP, ctypes.c_uint64, _VP]),
             "ndf_net_grad": (ctypes.c_int, [C, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _SZ, _VP]),
             "ndf_net_forward": (ctypes.c_int, [C, _VP, _VP, _I64, _VP, _VP, _SZ, _VP]),
+            "ndf_net_grad_at": (ctypes.c_int, [C, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _SZ, _VP]),
+            "ndf_net_forward_at": (ctypes.c_int, [C, _VP, _VP, _I64, _VP, _VP, _SZ, _VP]),
+            "ndf_train_step_at": (ctypes.c_int, [C, _VP, _VP, _I64, _VP, _VP, _I64,
+                                                 ctypes.c_float, _VP, _VP, _SZ, _VP]),
             "ndf_train_step": (ctypes.c_int, [C, _VP, _VP, _I64, _VP, _VP, _I64, ctypes.c_float,
                                               _VP, _VP, _SZ, _VP]),
             "ndf_net_qparam_bytes": (_SZ, [C, _I32]),
@@ -127,10 +133,11 @@ def _ws(nbytes, device):
 # ------------------------------------------------------------------ ensemble --
 class Ensemble:
     """Device ensemble x[n_vars][N][V] (float32, member-major) plus the per-vertex
-    statistics, KSG codes and (with orders=True) per-vertex sorted member orders
-    that ndf_prepare fills in."""
+    statistics, KSG codes, (with orders=True) per-vertex sorted member orders and
+    (with transposed=True) the vertex-major copy of x that ndf_prepare fills in."""
 
-    def __init__(self, x: torch.Tensor, nx: int, ny: int, nz: int, orders: bool = True):
+    def __init__(self, x: torch.Tensor, nx: int, ny: int, nz: int, orders: bool = True,
+                 transposed: bool = False):
         if x.dim() == 2:
             x = x.unsqueeze(0)
         assert x.dtype == torch.float32 and x.is_contiguous()
@@ -147,10 +154,13 @@ class Ensemble:
         # uint16 member indices, held in an int16 tensor
         self.order = (torch.empty((n_vars, V, N), dtype=torch.int16, device=dev)
                       if orders else None)
+        self.xt = (torch.empty((n_vars, V, N), dtype=torch.float32, device=dev)
+                   if transposed else None)
         self.c = ndf_ensemble(N, nx, ny, nz, n_vars, x.data_ptr(), self.mean.data_ptr(),
                               self.inv_std.data_ptr(), self.code.data_ptr(),
                               self.flags.data_ptr(),
-                              self.order.data_ptr() if orders else None)
+                              self.order.data_ptr() if orders else None,
+                              self.xt.data_ptr() if transposed else None)
 
     @property
     def device(self):
@@ -220,6 +230,22 @@ def pearson_pairs(ens, pairs, var_a=0, var_b=0, stream=None):
     return out
 
 
+def ndf_pearson_points(ens, var_a, var_b, pos, out, stream=None):
+    _check_pos_pairs(pos, "ndf_pearson_points")
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < pos.shape[0]:
+        raise NdfError("ndf_pearson_points: out must be a contiguous float32 [B] tensor")
+    _check(lib().ndf_pearson_points(ctypes.byref(ens.c), var_a, var_b, _p(pos), pos.shape[0],
+                                    _p(out), _stream(stream)), "ndf_pearson_points")
+
+
+def pearson_points(ens, pos, var_a=0, var_b=0, stream=None):
+    """r between the interpolated samples at pos[b][0] and pos[b][1] ([-1, 1]^3)."""
+    pos = torch.as_tensor(pos, dtype=torch.float32, device=ens.device).contiguous()
+    out = torch.empty(pos.shape[0], dtype=torch.float32, device=ens.device)
+    ndf_pearson_points(ens, var_a, var_b, pos, out, stream)
+    return out
+
+
 def ksg_pairs(ens, pairs, k=4, counts=False, var_a=0, var_b=0, stream=None):
     pairs = torch.as_tensor(pairs, dtype=torch.int64, device=ens.device).contiguous()
     out = torch.empty(pairs.shape[0], dtype=torch.float32, device=ens.device)
@@ -276,6 +302,33 @@ def ndf_train_step(cfg, params, opt_state, step, pairs, targets, lr, loss_out, w
     _check(lib().ndf_train_step(ctypes.byref(cfg), _p(params), _p(opt_state), int(step),
                                 _p(pairs), _p(targets), pairs.shape[0], float(lr), _p(loss_out),
                                 _p(ws), ws.numel(), _stream(stream)), "ndf_train_step")
+
+
+def _check_pos_pairs(pos, name):
+    if pos.dim() != 3 or tuple(pos.shape[1:]) != (2, 3) or pos.dtype != torch.float32 \
+            or not pos.is_contiguous():
+        raise NdfError(f"{name}: pos must be a contiguous float32 [B][2][3] tensor")
+
+
+def ndf_net_grad_at(cfg, params, pos, targets, grad_out, loss_out, ws, stream=None):
+    _check_pos_pairs(pos, "ndf_net_grad_at")
+    _check(lib().ndf_net_grad_at(ctypes.byref(cfg), _p(params), _p(pos), _p(targets),
+                                 pos.shape[0], _p(grad_out), _p(loss_out), _p(ws), ws.numel(),
+                                 _stream(stream)), "ndf_net_grad_at")
+
+
+def ndf_net_forward_at(cfg, params, pos, y, ws, stream=None):
+    _check_pos_pairs(pos, "ndf_net_forward_at")
+    _check(lib().ndf_net_forward_at(ctypes.byref(cfg), _p(params), _p(pos), pos.shape[0],
+                                    _p(y), _p(ws), ws.numel(), _stream(stream)),
+           "ndf_net_forward_at")
+
+
+def ndf_train_step_at(cfg, params, opt_state, step, pos, targets, lr, loss_out, ws, stream=None):
+    _check_pos_pairs(pos, "ndf_train_step_at")
+    _check(lib().ndf_train_step_at(ctypes.byref(cfg), _p(params), _p(opt_state), int(step),
+                                   _p(pos), _p(targets), pos.shape[0], float(lr), _p(loss_out),
+                                   _p(ws), ws.numel(), _stream(stream)), "ndf_train_step_at")
 
 
 def ndf_net_swap_encoders(cfg, params, params_out, stream=None):

@@ -168,3 +168,35 @@ def test_net_config_validation_and_param_bytes():
     need2 = ndf.infer_ws_bytes(cfg, 2, BF)
     assert (L.ndf_infer_field_difference(C, FAKE, 0, 1, FAKE, FAKE, FAKE, need2 - 1, None)
             == ndf.NDF_E_WORKSPACE)
+
+
+def test_positions_entry_points_reject_bad_arguments():
+    """The calls at continuous positions validate on the host (no device needed)."""
+    import gen
+    L = ndf.lib()
+    lay = gen.NetLayout.for_grid(250, 352, 20)
+    cfg = ndf.net_config(250, 352, 20, lay.res)
+    C = ctypes.byref(cfg)
+    FAKE = ctypes.c_void_p(0x1000)
+    need = ndf.train_ws_bytes(cfg, 64)
+    assert L.ndf_net_forward_at(C, FAKE, None, 64, FAKE, FAKE, need, None) == ndf.NDF_E_ARG
+    assert L.ndf_net_forward_at(C, FAKE, FAKE, 0, FAKE, FAKE, need, None) == ndf.NDF_E_ARG
+    assert (L.ndf_net_forward_at(C, FAKE, FAKE, 64, FAKE, FAKE, need - 1, None)
+            == ndf.NDF_E_WORKSPACE)
+    assert (L.ndf_net_grad_at(C, FAKE, None, FAKE, 64, FAKE, FAKE, FAKE, need, None)
+            == ndf.NDF_E_ARG)
+    assert (L.ndf_net_grad_at(C, FAKE, FAKE, FAKE, 64, FAKE, FAKE, FAKE, need - 1, None)
+            == ndf.NDF_E_WORKSPACE)
+    assert (L.ndf_train_step_at(C, FAKE, FAKE, 0, FAKE, FAKE, 64, ctypes.c_float(1e-3), FAKE,
+                                FAKE, need * 2, None) == ndf.NDF_E_ARG)
+    assert (L.ndf_train_step_at(C, FAKE, FAKE, 1, FAKE, FAKE, 64, ctypes.c_float(1e-3), FAKE,
+                                FAKE, need, None) == ndf.NDF_E_WORKSPACE)
+    # Pearson at positions needs the vertex-major copy
+    e = ndf.ndf_ensemble(16, 8, 8, 4, 1, 0x1000, 0x2000, 0x3000, 0x4000, 0x5000, None, None)
+    E = ctypes.byref(e)
+    assert L.ndf_pearson_points(E, 0, 0, FAKE, 10, FAKE, None) == ndf.NDF_E_ARG
+    e.xt = 0x6000
+    assert L.ndf_pearson_points(E, 0, 1, FAKE, 10, FAKE, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_points(E, 0, 0, None, 10, FAKE, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_points(E, 0, 0, FAKE, -1, FAKE, None) == ndf.NDF_E_ARG
+    assert L.ndf_pearson_points(E, 0, 0, None, 0, None, None) == ndf.NDF_OK
