@@ -16,6 +16,12 @@ Workload: synthetic paper-shaped ensemble (1000 members on 250x352x20 =
   ndf_field_cached  the same field from cached query latents (merge + decoder
                  only; the cache is built once per trained network, untimed)
 
+After the timed steps the calls beyond that path are timed on their own
+(`next_rows`, not part of a step): the same field at 1.76M sample positions along
+rays, the difference of two fields from the latent cache, Pearson targets for
+2^18 pairs of continuous positions (trilinear interpolation of the ensemble) and
+a training step on them.
+
 `value` is the learned-field ms per field (the paper's headline quantity);
 `fields` gives every row.  All launches go on torch's current stream and are
 timed with HIP events on it.  Inputs are resident in HBM before timing starts.
@@ -60,8 +66,11 @@ def _parse():
                     help="training steps of the second learned field (KSG-MI targets)")
     ap.add_argument("--only", default=None,
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
-                         "targets, train_step, ndf_field, ndf_field_fp8, ndf_field_cached) "
-                         "W+K times and exit")
+                         "targets, train_step, ndf_field, ndf_field_fp8, ndf_field_cached, "
+                         "or one of the next rows: ndf_points_rays, ndf_field_difference, "
+                         "pearson_points, train_step_at) W+K times and exit")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip timing the calls beyond the hot path")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -223,6 +232,63 @@ def main():
               "pearson_b64": row_pearson_b64, "ksg_field": row_ksg_field,
               "targets": row_targets, "train_step": row_train_step, "ndf_field": row_ndf_field}
 
+    def next_rows():
+        """The calls beyond the hot path, with their own buffers."""
+        ens_t = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz, orders=False, transposed=True)
+        ndf.ndf_prepare(ens_t)
+        n_rays, n_steps = V // 256, 256
+        ray_pos = torch.as_tensor(gen.ray_positions(n_rays, n_steps, seed=2350), device=dev)
+        out_rp = torch.empty((1, ray_pos.shape[0]), device=dev)
+        out_d = torch.empty(V, device=dev)
+        ws_i2 = torch.empty(ndf.infer_ws_bytes(net, 2, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                            device=dev)
+        ref2 = int(gen.random_vertices(V, 1, seed=2351)[0])
+        pos_sets = [torch.as_tensor(gen.random_positions(2 * B_PAIRS, seed=2360 + s)
+                                    .reshape(B_PAIRS, 2, 3), device=dev) for s in range(4)]
+        t_pp = torch.empty(B_PAIRS, device=dev)
+        P_at, opt_at = P.clone(), opt.clone()
+        step_at = [step_no[0]]
+
+        def rays(it):
+            ndf.ndf_infer_points(net, qp, ndf.NDF_PREC_BF16, [ref], ray_pos, out_rp, ws_i)
+
+        def diff(it):
+            ndf.ndf_infer_field_difference(net, qp, ref, ref2, cache, out_d, ws_i2)
+
+        def ppoints(it):
+            ndf.ndf_pearson_points(ens_t, 0, 0, pos_sets[it % 4], t_pp)
+
+        def train_at(it):
+            step_at[0] += 1
+            ndf.ndf_train_step_at(net, P_at, opt_at, step_at[0], pos_sets[it % 4], t_pp, LR,
+                                  loss, ws_t)
+
+        ppoints(0)
+        return {"ndf_points_rays": rays, "ndf_field_difference": diff,
+                "pearson_points": ppoints, "train_step_at": train_at}, ray_pos.shape[0]
+
+    def time_rows(fns, warmup, steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        out = {}
+        for name, fn in fns.items():
+            ms = []
+            for it in range(warmup + steps):
+                ev0.record(stream)
+                fn(it)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                if it >= warmup:
+                    ms.append(ev0.elapsed_time(ev1))
+            out[name] = ms
+        return out
+
+    if a.only and a.only not in row_fn:
+        fns, _ = next_rows()
+        ms = time_rows({a.only: fns[a.only]}, a.warmup, a.steps)[a.only]
+        print(json.dumps({"row": a.only, "ms": ms, "median_ms": float(np.median(ms))}))
+        return
+
     if a.only:
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -332,6 +398,34 @@ def main():
                      "ksg_mi_field": mi_train},
     }
     result["roofline"] = _roofline_of(dominant, roof, med, N, V)
+
+    if not a.no_next_rows:
+        log("bench: next rows (continuous positions, difference fields)")
+        fns, n_ray = next_rows()
+        nm = {k: float(np.median(v)) for k, v in time_rows(fns, 1, a.steps).items()}
+        nroof = {
+            "ndf_points_rays": {"bound": "mfma", "achieved": 2.0 * 69760 * n_ray
+                                / (nm["ndf_points_rays"] * 1e-3) / 1e12,
+                                "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s"},
+            "ndf_field_difference": {"bound": "mfma", "achieved": 2.0 * 2 * 32896 * V
+                                     / (nm["ndf_field_difference"] * 1e-3) / 1e12,
+                                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s"},
+            # 2 x 8 corner rows of N FP32 members per pair
+            "pearson_points": {"bound": "hbm", "achieved": 16.0 * 4 * N * B_PAIRS
+                               / (nm["pearson_points"] * 1e-3) / 1e9,
+                               "peak": PEAK_HBM_GBS, "unit": "GB/s"},
+        }
+        for r in nroof.values():
+            r["frac"] = r["achieved"] / r["peak"]
+        result["next_rows"] = {
+            "ms": {"ndf_points_rays_1.76M_samples": nm["ndf_points_rays"],
+                   "ndf_field_difference_from_cache": nm["ndf_field_difference"],
+                   "pearson_points_targets_2^18_pairs": nm["pearson_points"],
+                   "train_step_at_positions_2^18_pairs": nm["train_step_at"]},
+            "rooflines": nroof,
+            "workload": f"{n_ray} samples on {n_ray // 256} rays x 256 steps; two references "
+                        "for the difference; 2^18 uniform position pairs in [-1,1]^3",
+        }
 
     if not a.no_accuracy:
         acc, sample, r_o, mi_o = _accuracy(ens, out_p, out_b, out_k, out_n, out_n8, out_mi,
