@@ -18,9 +18,9 @@ Workload: synthetic paper-shaped ensemble (1000 members on 250x352x20 =
 
 After the timed steps the calls beyond that path are timed on their own
 (`next_rows`, not part of a step): the same field at 1.76M sample positions along
-rays, the difference of two fields from the latent cache, Pearson targets for
-2^18 pairs of continuous positions (trilinear interpolation of the ensemble) and
-a training step on them.
+rays, the difference of two fields from the latent cache, Pearson and KSG-MI
+targets for 2^18 pairs of continuous positions (trilinear interpolation of the
+ensemble) and a training step on them.
 
 `value` is the learned-field ms per field (the paper's headline quantity);
 `fields` gives every row.  All launches go on torch's current stream and are
@@ -68,7 +68,7 @@ def _parse():
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
                          "targets, train_step, ndf_field, ndf_field_fp8, ndf_field_cached, "
                          "or one of the next rows: ndf_points_rays, ndf_field_difference, "
-                         "pearson_points, train_step_at) W+K times and exit")
+                         "pearson_points, ksg_points, train_step_at) W+K times and exit")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip timing the calls beyond the hot path")
     ap.add_argument("--copy-probe", action="store_true",
@@ -246,6 +246,9 @@ def main():
         pos_sets = [torch.as_tensor(gen.random_positions(2 * B_PAIRS, seed=2360 + s)
                                     .reshape(B_PAIRS, 2, 3), device=dev) for s in range(4)]
         t_pp = torch.empty(B_PAIRS, device=dev)
+        t_kp = torch.empty(B_PAIRS, device=dev)
+        ws_kq = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_KSG_POINTS, ens_t, None, B_PAIRS,
+                                                    0), dtype=torch.uint8, device=dev)
         P_at, opt_at = P.clone(), opt.clone()
         step_at = [step_no[0]]
 
@@ -258,6 +261,9 @@ def main():
         def ppoints(it):
             ndf.ndf_pearson_points(ens_t, 0, 0, pos_sets[it % 4], t_pp)
 
+        def kpoints(it):
+            ndf.ndf_ksg_mi_points(ens_t, 0, 0, pos_sets[it % 4], K_NN, t_kp, None, ws_kq)
+
         def train_at(it):
             step_at[0] += 1
             ndf.ndf_train_step_at(net, P_at, opt_at, step_at[0], pos_sets[it % 4], t_pp, LR,
@@ -265,7 +271,8 @@ def main():
 
         ppoints(0)
         return {"ndf_points_rays": rays, "ndf_field_difference": diff,
-                "pearson_points": ppoints, "train_step_at": train_at}, ray_pos.shape[0]
+                "pearson_points": ppoints, "ksg_points": kpoints,
+                "train_step_at": train_at}, ray_pos.shape[0]
 
     def time_rows(fns, warmup, steps):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -421,6 +428,7 @@ def main():
             "ms": {"ndf_points_rays_1.76M_samples": nm["ndf_points_rays"],
                    "ndf_field_difference_from_cache": nm["ndf_field_difference"],
                    "pearson_points_targets_2^18_pairs": nm["pearson_points"],
+                   "ksg_points_targets_2^18_pairs": nm["ksg_points"],
                    "train_step_at_positions_2^18_pairs": nm["train_step_at"]},
             "rooflines": nroof,
             "workload": f"{n_ray} samples on {n_ray // 256} rays x 256 steps; two references "

@@ -56,7 +56,8 @@ enum {                       /* `op` of ndf_workspace_bytes                     
     NDF_OP_KSG_FIELD = 2,
     NDF_OP_TRAIN = 3,
     NDF_OP_INFER = 4,
-    NDF_OP_KSG_PAIRS = 5
+    NDF_OP_KSG_PAIRS = 5,
+    NDF_OP_KSG_POINTS = 6
 };
 
 enum {                       /* per-vertex flags written by ndf_prepare           */
@@ -106,7 +107,8 @@ typedef struct ndf_net_config {
 const char *ndf_status_string(int status);
 
 /* Workspace bytes for `op`.  `ens` is used by the PEARSON/KSG ops, `net` by
- * TRAIN/INFER; n = n_ref for the field ops, B (pairs per step) for TRAIN.
+ * TRAIN/INFER; n = n_ref for the field ops, B (pairs per step) for TRAIN and
+ * KSG_POINTS.
  * `prec` as the call will use it.  Returns 0 for an invalid request. */
 size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_config *net,
                            int64_t n, int32_t prec);
@@ -173,6 +175,21 @@ int ndf_ksg_mi_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
  * of ndf_prepare.  B = 0 enqueues nothing. */
 int ndf_pearson_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, const float *pos,
                        int64_t B, float *out, void *stream);
+
+/* KSG mutual information (nats) between the interpolated samples at position
+ * pairs (Sec. 4.3 with the estimator of ndf_ksg_mi_field): each interpolated
+ * column (the samples of ndf_pearson_points, summed over the corners of nonzero
+ * weight in corner order in FP64, no contraction) is mapped to integer codes
+ * exactly as ndf_prepare maps a vertex (min-max onto [0, 2^23], round-half-even),
+ * so at a vertex's own position the codes, counts and estimate are that
+ * vertex's.  out float[B]; counts (nullable) int32[B][2][N] in member order; 0
+ * for a constant interpolated column, NaN for a non-finite one.  1 <= k <= 8,
+ * k < N <= 2048, B <= 2^29.  ws: ndf_workspace_bytes(NDF_OP_KSG_POINTS, ens,
+ * NULL, B, 0) bytes (the 2B code columns, 8 B x N per pair, plus small
+ * tables).  Reads ens->xt (NDF_E_ARG when NULL).  B = 0 enqueues nothing. */
+int ndf_ksg_mi_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, const float *pos,
+                      int64_t B, int32_t k, float *out, int32_t *counts, void *ws,
+                      size_t ws_bytes, void *stream);
 
 /* Bytes of the FP32 parameter vector (layout: for each encoder its grid levels
  * float[Rx*Ry*Rz][feats], then W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3; then

@@ -23,6 +23,9 @@ size_t ksg_pairs_ws_bytes(int N);
 int launch_ksg_orders(const ndf_ensemble *e, hipStream_t st);
 int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t *pairs, int64_t B,
                      int k, float *out, int32_t *counts, double *H, hipStream_t st);
+size_t ksg_points_ws_bytes(int N, int64_t B);
+int launch_ksg_points(const ndf_ensemble *e, int var_a, int var_b, const float *pos, int64_t B,
+                      int k, float *out, int32_t *counts, void *ws, hipStream_t st);
 }  // namespace ndf
 
 using namespace ndf;
@@ -82,6 +85,9 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
         case NDF_OP_KSG_PAIRS:
             if (check_ensemble(ens, false) != NDF_OK) return 0;
             return ksg_pairs_ws_bytes(ens->n_members);
+        case NDF_OP_KSG_POINTS:
+            if (check_ensemble(ens, false) != NDF_OK || n < 1 || n > (1ll << 29)) return 0;
+            return ksg_points_ws_bytes(ens->n_members, n);
         case NDF_OP_TRAIN:
             if (check_net_config(net) != NDF_OK || n < 1) return 0;
             return net_train_ws_bytes(net, n);
@@ -160,6 +166,22 @@ int ndf_ksg_mi_pairs(const ndf_ensemble *ens, int32_t var_a, int32_t var_b,
     if (k > 8 || ens->n_members > kMaxMembersKsg) return NDF_E_UNSUPPORTED;
     if (!ws || ws_bytes < ksg_pairs_ws_bytes(ens->n_members)) return NDF_E_WORKSPACE;
     return launch_ksg_pairs(ens, var_a, var_b, pairs, B, k, out, counts, (double *)ws, S(stream));
+}
+
+int ndf_ksg_mi_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, const float *pos,
+                      int64_t B, int32_t k, float *out, int32_t *counts, void *ws,
+                      size_t ws_bytes, void *stream) {
+    int s = check_ensemble(ens, true);
+    if (s == NDF_OK) s = check_var(ens, var_a);
+    if (s == NDF_OK) s = check_var(ens, var_b);
+    if (s != NDF_OK) return s;
+    if (!ens->xt || B < 0 || B > (1ll << 29) || (B > 0 && (!pos || !out)) || k < 1 ||
+        k >= ens->n_members)
+        return NDF_E_ARG;
+    if (k > 8 || ens->n_members > kMaxMembersKsg) return NDF_E_UNSUPPORTED;
+    if (B == 0) return NDF_OK;
+    if (!ws || ws_bytes < ksg_points_ws_bytes(ens->n_members, B)) return NDF_E_WORKSPACE;
+    return launch_ksg_points(ens, var_a, var_b, pos, B, k, out, counts, ws, S(stream));
 }
 
 size_t ndf_net_param_bytes(const ndf_net_config *cfg) {

@@ -42,6 +42,33 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
     return v;
 }
 
+// Corner vertices and trilinear weights (FP64) of the data-grid cell holding the
+// position p in [-1, 1]^3: c = (p + 1)/2 (n - 1) per axis, clamped to [0, n - 1]
+// (NaN to 0), base = min(floor(c), n - 2), f = c - base.
+// Every operation is a correctly rounded IEEE double operation in a fixed order
+// (no contraction), so the weights are reproducible bit for bit.
+__device__ __forceinline__ void data_cell(const float *p, int nx, int ny, int nz, int64_t v[8],
+                                          double w[8]) {
+#pragma clang fp contract(off)
+    const int n[3] = {nx, ny, nz};
+    int64_t b[3];
+    double f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double c = ((double)p[a] + 1.0) * 0.5 * (double)(n[a] - 1);
+        c = c == c ? fmin(fmax(c, 0.0), (double)(n[a] - 1)) : 0.0;
+        const int bb = min((int)c, n[a] - 2);
+        b[a] = bb;
+        f[a] = c - (double)bb;
+    }
+#pragma unroll
+    for (int cn = 0; cn < 8; ++cn) {
+        const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
+        v[cn] = (b[0] + dx) + (int64_t)nx * ((b[1] + dy) + (int64_t)ny * (b[2] + dz));
+        w[cn] = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+    }
+}
+
 inline int status_of_launch() { return hipGetLastError() == hipSuccess ? NDF_OK : NDF_E_HIP; }
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -19,6 +19,7 @@ _LIB_PATH = Path(__file__).resolve().parent / "libndf.so"
 NDF_OK, NDF_E_ARG, NDF_E_WORKSPACE, NDF_E_HIP, NDF_E_UNSUPPORTED = 0, -1, -2, -3, -5
 NDF_PREC_FP32, NDF_PREC_SPLIT_BF16, NDF_PREC_BF16, NDF_PREC_FP8_E4M3 = 0, 1, 2, 3
 NDF_OP_PEARSON_FIELD, NDF_OP_KSG_FIELD, NDF_OP_TRAIN, NDF_OP_INFER, NDF_OP_KSG_PAIRS = 1, 2, 3, 4, 5
+NDF_OP_KSG_POINTS = 6
 NDF_FLAG_NONFINITE, NDF_FLAG_CONSTANT = 1, 2
 
 EXPORTED = [
@@ -29,6 +30,7 @@ EXPORTED = [
     "ndf_infer_latent_bytes", "ndf_infer_latents", "ndf_infer_field_cached",
     "ndf_net_swap_encoders", "ndf_infer_points", "ndf_infer_field_difference",
     "ndf_pearson_points", "ndf_net_forward_at", "ndf_net_grad_at", "ndf_train_step_at",
+    "ndf_ksg_mi_points",
 ]
 
 
@@ -73,6 +75,8 @@ def lib():
                                                 _SZ, _VP]),
             "ndf_pearson_pairs": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _VP, _VP]),
             "ndf_pearson_points": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _VP, _VP]),
+            "ndf_ksg_mi_points": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _I32, _VP, _VP, _VP,
+                                                 _SZ, _VP]),
             "ndf_ksg_mi_pairs": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _I32, _VP, _VP, _VP,
                                                 _SZ, _VP]),
             "ndf_net_param_bytes": (_SZ, [C]),
@@ -244,6 +248,27 @@ def pearson_points(ens, pos, var_a=0, var_b=0, stream=None):
     out = torch.empty(pos.shape[0], dtype=torch.float32, device=ens.device)
     ndf_pearson_points(ens, var_a, var_b, pos, out, stream)
     return out
+
+
+def ndf_ksg_mi_points(ens, var_a, var_b, pos, k, out, counts, ws, stream=None):
+    _check_pos_pairs(pos, "ndf_ksg_mi_points")
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < pos.shape[0]:
+        raise NdfError("ndf_ksg_mi_points: out must be a contiguous float32 [B] tensor")
+    _check(lib().ndf_ksg_mi_points(ctypes.byref(ens.c), var_a, var_b, _p(pos), pos.shape[0], k,
+                                   _p(out), _p(counts), _p(ws), ws.numel(), _stream(stream)),
+           "ndf_ksg_mi_points")
+
+
+def ksg_points(ens, pos, k=4, counts=False, var_a=0, var_b=0, stream=None):
+    """KSG MI between the interpolated samples at pos[b][0] and pos[b][1]."""
+    pos = torch.as_tensor(pos, dtype=torch.float32, device=ens.device).contiguous()
+    B = pos.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=ens.device)
+    cnt = (torch.empty((B, 2, ens.n_members), dtype=torch.int32, device=ens.device)
+           if counts else None)
+    ws = _ws(ndf_workspace_bytes(NDF_OP_KSG_POINTS, ens, None, max(B, 1), 0), ens.device)
+    ndf_ksg_mi_points(ens, var_a, var_b, pos, k, out, cnt, ws, stream)
+    return (out, cnt) if counts else out
 
 
 def ksg_pairs(ens, pairs, k=4, counts=False, var_a=0, var_b=0, stream=None):

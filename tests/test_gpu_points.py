@@ -197,3 +197,37 @@ def test_training_at_positions_learns():
     const = float(np.mean(np.abs(truth - np.median(truth))))
     _log(f"training at positions: MAE init {mae0:.4f} trained {mae1:.4f} best-constant {const:.4f}")
     assert mae1 < 0.5 * mae0 and mae1 < 0.6 * const
+
+
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+def test_ksg_points_parity(name):
+    """KSG targets at continuous positions: the interpolated columns' codes and
+    neighbour counts bit-exact against the FP64 oracle, |dI| <= 1e-4, within and
+    across variables, including positions outside the domain and NaN
+    coordinates; at vertex positions the estimate is the vertex pair's."""
+    cfg = dataclasses.replace(gen.CONFIGS[name], n_vars=2)
+    e = _ens(cfg)
+    x = e.x.cpu().numpy()
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    pos = np.concatenate([_pos_pairs(150, seed=61), _pos_pairs(20, seed=62, spread=1.3)])
+    pos[-2:, 0, 1] = np.nan
+    for va, vb in ((0, 0), (1, 0)):
+        mi, cnt = ndf.ksg_points(e, pos, k=4, counts=True, var_a=va, var_b=vb)
+        mi, cnt = mi.cpu().numpy(), cnt.cpu().numpy()
+        want, wcnt = pt.ksg_points(x[va], x[vb], dims, pos, 4, counts=True)
+        err = np.max(np.abs(mi - want))
+        _log(f"ksg points {name} vars ({va},{vb}): max|dI| {err:.2e}, "
+             f"counts equal {np.array_equal(cnt, wcnt)}")
+        assert np.array_equal(cnt, wcnt)
+        assert err <= 1e-4
+    # the domain's corners are exactly the grid's corner vertices (in FP32 too)
+    signs = np.array([[sx, sy, sz] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)],
+                     dtype=np.float32)
+    vert = np.array([(0 if sx < 0 else cfg.nx - 1) + cfg.nx * ((0 if sy < 0 else cfg.ny - 1)
+                     + cfg.ny * (0 if sz < 0 else cfg.nz - 1)) for sx, sy, sz in signs])
+    ia, ib = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    cpos = np.stack([signs[ia.ravel()], signs[ib.ravel()]], axis=1)
+    pairs = np.stack([vert[ia.ravel()], vert[ib.ravel()]], axis=1)
+    got = ndf.ksg_points(e, cpos, k=4).cpu().numpy()
+    want = ndf.ksg_pairs(e, pairs, k=4).cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-6

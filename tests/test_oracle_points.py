@@ -121,3 +121,45 @@ def test_zero_weight_corner_does_not_contribute():
     np.testing.assert_array_equal(pt.interpolate_members(x, DIMS, p)[:, 0], x[:, 0])
     q = np.array([[2.0 / (DIMS[0] - 1) - 1.0 + 0.01, -1.0, -1.0]])
     assert np.isnan(pt.interpolate_members(x, DIMS, q)[3, 0])
+
+
+def test_interpolated_codes_at_vertices_are_vertex_codes():
+    """At a vertex's own position the interpolated column is the vertex column, so
+    its codes are the C oracle's vertex codes and the KSG estimate is the vertex
+    pair's; halfway between two vertices the codes follow from the mean column."""
+    cfg = gen.CONFIGS["tiny"]
+    x = gen.make_ensemble(cfg, device="cpu")[0].numpy()
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    pairs = gen.random_pairs(cfg.n_vertices, 12, seed=7)
+    ijk = _grid_coords(dims)
+    pos = (2.0 * ijk[pairs] / (np.array(dims) - 1) - 1.0)
+    codes, bad, flat = pt.interpolated_codes(x, dims, pos[:, 0])
+    assert not bad.any() and not flat.any()
+    for i, v in enumerate(pairs[:, 0]):
+        want, _ = direct.ksg_codes(x[:, v])
+        assert np.array_equal(codes[:, i], want)
+    got = pt.ksg_points(x, x, dims, pos, 4)
+    want = np.array([direct.ksg_field(x[:, a], x[:, b:b + 1], 4)[0] for a, b in pairs])
+    np.testing.assert_array_equal(got, want)
+    # midpoint: the column is (x_a + x_b) / 2 exactly (weights 1/2 in FP64)
+    v0 = 3 + cfg.nx * (2 + cfg.ny * 1)
+    mid = 2.0 * (ijk[v0] + np.array([0.5, 0.0, 0.0])) / (np.array(dims) - 1) - 1.0
+    m = 0.5 * x[:, v0].astype(np.float64) + 0.5 * x[:, v0 + 1].astype(np.float64)
+    lo, hi = m.min(), m.max()
+    want = np.rint((m - lo) * (8388608.0 / (hi - lo))).astype(np.int32)
+    c, _, _ = pt.interpolated_codes(x, dims, mid[None, :])
+    assert np.array_equal(c[:, 0], want)
+
+
+def test_ksg_points_flags():
+    """A constant interpolated column gives 0, a non-finite one NaN."""
+    rng = np.random.default_rng(8)
+    V = DIMS[0] * DIMS[1] * DIMS[2]
+    x = rng.standard_normal((16, V))
+    x[:, V - 1] = 1.5
+    x[2, 0] = np.inf
+    pos = np.array([[[1.0, 1.0, 1.0], [0.1, 0.2, 0.3]],
+                    [[-1.0, -1.0, -1.0], [0.1, 0.2, 0.3]],
+                    [[0.3, -0.2, 0.5], [0.1, 0.2, 0.3]]])
+    out = pt.ksg_points(x, x, DIMS, pos, 3)
+    assert out[0] == 0.0 and np.isnan(out[1]) and np.isfinite(out[2])
