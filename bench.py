@@ -18,9 +18,10 @@ Workload: synthetic paper-shaped ensemble (1000 members on 250x352x20 =
 
 After the timed steps the calls beyond that path are timed on their own
 (`next_rows`, not part of a step): the same field at 1.76M sample positions along
-rays, the difference of two fields from the latent cache, Pearson and KSG-MI
-targets for 2^18 pairs of continuous positions (trilinear interpolation of the
-ensemble) and a training step on them.
+rays, the difference of two fields from the latent cache, the field of a network
+whose finest level is a 2^19-cell hash table, Pearson and KSG-MI targets for 2^18
+pairs of continuous positions (trilinear interpolation of the ensemble) and a
+training step on them.
 
 `value` is the learned-field ms per field (the paper's headline quantity);
 `fields` gives every row.  All launches go on torch's current stream and are
@@ -45,6 +46,7 @@ N_BATCH = 64
 K_NN = 4
 LR = 1e-3
 PREP_TRAIN_STEPS = 300
+HASH_T = 19          # hash-table size 2^T of the hashed-grid row
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
@@ -68,7 +70,8 @@ def _parse():
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
                          "targets, train_step, ndf_field, ndf_field_fp8, ndf_field_cached, "
                          "or one of the next rows: ndf_points_rays, ndf_field_difference, "
-                         "pearson_points, ksg_points, train_step_at) W+K times and exit")
+                         "pearson_points, ksg_points, train_step_at, ndf_field_hash) W+K "
+                         "times and exit")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip timing the calls beyond the hot path")
     ap.add_argument("--copy-probe", action="store_true",
@@ -251,6 +254,15 @@ def main():
                                                     0), dtype=torch.uint8, device=dev)
         P_at, opt_at = P.clone(), opt.clone()
         step_at = [step_no[0]]
+        # the same network shape with the finest level as a 2^19-cell hash table
+        lay_h = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, log2_hashmap=HASH_T)
+        net_h = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay_h.res, log2_hashmap=HASH_T)
+        P_h = torch.empty(lay_h.n_floats, device=dev)
+        ndf.ndf_net_init(net_h, P_h, None, 2352)
+        qp_h = torch.empty(ndf.ndf_net_qparam_bytes(net_h, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                           device=dev)
+        ndf.ndf_net_quantize(net_h, P_h, ndf.NDF_PREC_BF16, qp_h)
+        out_h = torch.empty((1, V), device=dev)
 
         def rays(it):
             ndf.ndf_infer_points(net, qp, ndf.NDF_PREC_BF16, [ref], ray_pos, out_rp, ws_i)
@@ -260,6 +272,9 @@ def main():
 
         def ppoints(it):
             ndf.ndf_pearson_points(ens_t, 0, 0, pos_sets[it % 4], t_pp)
+
+        def hashed(it):
+            ndf.ndf_infer_field(net_h, qp_h, ndf.NDF_PREC_BF16, [ref], out_h, ws_i)
 
         def kpoints(it):
             ndf.ndf_ksg_mi_points(ens_t, 0, 0, pos_sets[it % 4], K_NN, t_kp, None, ws_kq)
@@ -271,7 +286,7 @@ def main():
 
         ppoints(0)
         return {"ndf_points_rays": rays, "ndf_field_difference": diff,
-                "pearson_points": ppoints, "ksg_points": kpoints,
+                "pearson_points": ppoints, "ksg_points": kpoints, "ndf_field_hash": hashed,
                 "train_step_at": train_at}, ray_pos.shape[0]
 
     def time_rows(fns, warmup, steps):
@@ -429,6 +444,7 @@ def main():
                    "ndf_field_difference_from_cache": nm["ndf_field_difference"],
                    "pearson_points_targets_2^18_pairs": nm["pearson_points"],
                    "ksg_points_targets_2^18_pairs": nm["ksg_points"],
+                   "ndf_field_bf16_hash_table_2^19": nm["ndf_field_hash"],
                    "train_step_at_positions_2^18_pairs": nm["train_step_at"]},
             "rooflines": nroof,
             "workload": f"{n_ray} samples on {n_ray // 256} rays x 256 steps; two references "

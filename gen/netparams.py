@@ -4,7 +4,9 @@ Flat FP32 parameter layout (the format the C library documents for
 ``ndf_net_param_bytes``): for each encoder e in 0..n_enc-1 (n_enc = 1 when the
 reference and query share one encoder and grid, Sec. 4.1, else 2):
 
-    grid_e level l, l = 0..L-1 : float[cells_l][F]   cells_l = Rx*Ry*Rz, cell = x + Rx*(y + Ry*z)
+    grid_e level l, l = 0..L-1 : float[cells_l][F]   cells_l = Rx*Ry*Rz, cell = x + Rx*(y + Ry*z),
+                                 or cells_l = 2^T for a level hashed into a table of
+                                 2^T cells (T = log2_hashmap > 0, Rx*Ry*Rz > 2^T)
     W1_e float[H][L*F], b1_e float[H]
     W2_e float[H][H],   b2_e float[H]
     W3_e float[H][H],   b3_e float[H]
@@ -45,11 +47,18 @@ class NetLayout:
     feats: int = 8
     width: int = 128
     n_enc: int = 1        # 1: shared encoder + grid (self field), 2: separate
+    log2_hashmap: int = 0  # T > 0: levels larger than 2^T cells are hash tables of 2^T
 
     @staticmethod
-    def for_grid(nx, ny, nz, n_levels=4, feats=8, width=128, n_enc=1):
+    def for_grid(nx, ny, nz, n_levels=4, feats=8, width=128, n_enc=1, log2_hashmap=0):
         return NetLayout(nx, ny, nz, tuple(level_resolutions(nx, ny, nz, n_levels)),
-                         feats, width, n_enc)
+                         feats, width, n_enc, log2_hashmap)
+
+    def cells(self, l):
+        rx, ry, rz = self.res[l]
+        dense = rx * ry * rz
+        T = self.log2_hashmap
+        return (1 << T) if T and dense > (1 << T) else dense
 
     @property
     def n_levels(self):
@@ -60,8 +69,8 @@ class NetLayout:
         H, F, L = self.width, self.feats, self.n_levels
         out = []
         for e in range(self.n_enc):
-            for l, (rx, ry, rz) in enumerate(self.res):
-                out.append((f"grid{e}_{l}", (rx * ry * rz, F)))
+            for l in range(self.n_levels):
+                out.append((f"grid{e}_{l}", (self.cells(l), F)))
             out += [(f"W1_{e}", (H, L * F)), (f"b1_{e}", (H,)),
                     (f"W2_{e}", (H, H)), (f"b2_{e}", (H,)),
                     (f"W3_{e}", (H, H)), (f"b3_{e}", (H,))]

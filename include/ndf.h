@@ -93,7 +93,13 @@ typedef struct ndf_ensemble {
  * implement n_levels = 4, feats = 8, width = 128.  Limits (NDF_E_UNSUPPORTED
  * beyond them): nx*ny*nz < 2^24, each of nx, ny, nz <= 65535, and
  * (n-1)*(R-1) < 2^24 for every axis and level (the lookup's exact integer
- * arithmetic). */
+ * arithmetic); a dense level holds fewer than 2^28 cells.
+ * Hash grids (Sec. 4.2): with log2_hashmap = T in [8, 24], a level whose dense
+ * size Rx*Ry*Rz exceeds 2^T is stored as a table of 2^T cells indexed by the
+ * spatial hash (x * 1 xor y * 2654435761 xor z * 805459861) mod 2^T of the
+ * corner (x, y, z) (32-bit unsigned arithmetic; the hash of the grids the paper
+ * builds on, Mueller et al. 2022); coarser levels stay dense.  Colliding
+ * corners share a cell (their gradients add).  T = 0: every level dense. */
 typedef struct ndf_net_config {
     int32_t nx, ny, nz;      /* data grid whose vertices are evaluated            */
     int32_t n_levels;        /* 4                                                 */
@@ -101,6 +107,8 @@ typedef struct ndf_net_config {
     int32_t feats;           /* 8                                                 */
     int32_t width;           /* 128                                               */
     int32_t n_enc;           /* 1 or 2                                            */
+    int32_t log2_hashmap;    /* 0 (dense levels) or T in [8, 24]: hash tables of
+                                2^T cells for the levels larger than that        */
 } ndf_net_config;
 
 /* Human-readable name of a status code (static storage). */
@@ -192,9 +200,10 @@ int ndf_ksg_mi_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, con
                       size_t ws_bytes, void *stream);
 
 /* Bytes of the FP32 parameter vector (layout: for each encoder its grid levels
- * float[Rx*Ry*Rz][feats], then W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3; then
- * W4[W][W], b4, W5[W][W], b5, w6[W], b6[1]; every tensor starts at a multiple of
- * 64 floats, gaps zero) and of the Adam state (m then v, same layout). */
+ * float[cells][feats] with cells = Rx*Ry*Rz, or 2^T for a hashed level, then
+ * W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3; then W4[W][W], b4, W5[W][W], b5,
+ * w6[W], b6[1]; every tensor starts at a multiple of 64 floats, gaps zero) and
+ * of the Adam state (m then v, same layout). */
 size_t ndf_net_param_bytes(const ndf_net_config *cfg);
 size_t ndf_net_optstate_bytes(const ndf_net_config *cfg);
 

@@ -16,6 +16,10 @@ Readings where the paper is silent (the GPU path uses the same ones):
   (the paper's p = 2u - 1 in [-1,1]^3, corners aligned);
 * level l with sizes R: c = u*(R-1), base = clamp(floor(c), 0, R-2), f = c - base,
   eight corners (dx,dy,dz) weighted by prod(f or 1-f); cell = x + Rx*(y + Ry*z);
+* hash grids (Sec. 4.2, T > 0): a level with more than 2^T dense cells is a table
+  of 2^T cells indexed by the spatial hash of the encoding the paper uses
+  (xor of x*1, y*2654435761, z*805459861, modulo 2^T); smaller levels stay dense
+  (the paper's table is large enough that no level of its grids is hashed);
 * encoder: 3 layers, ReLU after the first two, linear latent; decoder: two ReLU
   layers and a linear scalar output; weights row-major [out][in];
 * L1 loss gradient uses sign(y - t) with sign(0) = 0.
@@ -34,9 +38,10 @@ ALIGN = 64
 class Net:
     """Named float64 views over a copy of a flat parameter vector."""
 
-    def __init__(self, flat, dims, res, feats=8, width=128, n_enc=1):
+    def __init__(self, flat, dims, res, feats=8, width=128, n_enc=1, log2_hashmap=0):
         self.nx, self.ny, self.nz = dims
         self.res = [tuple(r) for r in res]
+        self.T = log2_hashmap
         self.F = feats
         self.H = width
         self.n_enc = n_enc
@@ -52,8 +57,8 @@ class Net:
             pos += (n + ALIGN - 1) // ALIGN * ALIGN
 
         for e in range(n_enc):
-            for l, (rx, ry, rz) in enumerate(self.res):
-                take(("grid", e, l), (rx * ry * rz, feats))
+            for l, R in enumerate(self.res):
+                take(("grid", e, l), (level_cells(R, log2_hashmap), feats))
             take(("W1", e), (width, L * feats))
             take(("b1", e), (width,))
             take(("W2", e), (width, width))
@@ -91,8 +96,35 @@ def vertex_positions(v, dims):
     return np.stack([i / (nx - 1), j / (ny - 1), k / (nz - 1)], axis=-1).astype(np.float64)
 
 
-def trilinear(u, R):
-    """Corner cells (n,8) and weights (n,8) of positions u (n,3) on a level of size R."""
+# Primes of the spatial hash of multi-resolution hash grids (Mueller et al. 2022),
+# the encoding Sec. 4.2 builds on: one per axis, the first 1 so that x maps to itself.
+HASH_PRIMES = (1, 2654435761, 805459861)
+
+
+def level_hashed(R, T):
+    """A level is a hash table of 2^T cells when T > 0 and its dense size exceeds it."""
+    return T > 0 and int(np.prod(R)) > (1 << T)
+
+
+def level_cells(R, T):
+    return (1 << T) if level_hashed(R, T) else int(np.prod(R))
+
+
+def hash_cell(p, T):
+    """Spatial hash of integer corners p (n,3): xor over axes of p_a * prime_a,
+    modulo 2^T (the primes' products taken modulo 2^64; the low T bits are those
+    of the exact integers)."""
+    p = np.asarray(p, dtype=np.uint64)
+    h = np.zeros(p.shape[0], dtype=np.uint64)
+    for a in range(3):
+        h ^= p[:, a] * np.uint64(HASH_PRIMES[a])
+    return (h & np.uint64((1 << T) - 1)).astype(np.int64)
+
+
+def trilinear(u, R, T=0):
+    """Corner cells (n,8) and weights (n,8) of positions u (n,3) on a level of size
+    R; the cells are hashed when the level is a hash table (T > 0)."""
+    hashed = level_hashed(R, T)
     R = np.asarray(R, dtype=np.int64)
     c = u * (R - 1)
     base = np.clip(np.floor(c), 0, R - 2).astype(np.int64)
@@ -102,7 +134,8 @@ def trilinear(u, R):
     for corner in range(8):
         d = np.array([corner & 1, (corner >> 1) & 1, (corner >> 2) & 1])
         p = base + d
-        idx[:, corner] = p[:, 0] + R[0] * (p[:, 1] + R[1] * p[:, 2])
+        idx[:, corner] = (hash_cell(p, T) if hashed
+                          else p[:, 0] + R[0] * (p[:, 1] + R[1] * p[:, 2]))
         w[:, corner] = np.prod(np.where(d == 1, f, 1.0 - f), axis=1)
     return idx, w
 
@@ -111,7 +144,7 @@ def grid_encode(net, e, u):
     """Concatenated per-level trilinear features h0 (n, L*F)."""
     parts = []
     for l, R in enumerate(net.res):
-        idx, w = trilinear(u, R)
+        idx, w = trilinear(u, R, net.T)
         g = net[("grid", e, l)]
         parts.append(np.einsum("nc,ncf->nf", w, g[idx]))
     return np.concatenate(parts, axis=1)
@@ -121,7 +154,7 @@ def grid_scatter(net, e, u, dh0, grads):
     """Adjoint of grid_encode: add the gradient of h0 into the grid gradients."""
     F = net.F
     for l, R in enumerate(net.res):
-        idx, w = trilinear(u, R)
+        idx, w = trilinear(u, R, net.T)
         g = grads[("grid", e, l)]
         contrib = w[:, :, None] * dh0[:, None, l * F:(l + 1) * F]
         np.add.at(g, idx.reshape(-1), contrib.reshape(-1, F))

@@ -36,7 +36,22 @@ inline int check_net_config(const ndf_net_config *c) {
     for (int l = 0; l < kL; ++l)
         for (int a = 0; a < 3; ++a)
             if ((int64_t)(n[a] - 1) * (c->res[l][a] - 1) >= (1 << 24)) return NDF_E_UNSUPPORTED;
+    // hash tables of 2^T entries (T = log2_hashmap, 0: every level dense)
+    const int T = c->log2_hashmap;
+    if (T != 0 && (T < 8 || T > 24)) return NDF_E_ARG;
+    for (int l = 0; l < kL; ++l) {
+        const int64_t dense = (int64_t)c->res[l][0] * c->res[l][1] * c->res[l][2];
+        const bool hashed = T != 0 && dense > ((int64_t)1 << T);
+        if (!hashed && dense >= ((int64_t)1 << 28)) return NDF_E_UNSUPPORTED;  // int32 cell offsets
+    }
     return NDF_OK;
+}
+
+// Level l is stored as a hash table of 2^T entries when its dense size exceeds
+// that (the multi-resolution hash grid of Sec. 4.2), else densely.
+inline bool level_hashed(const ndf_net_config *c, int l) {
+    const int64_t dense = (int64_t)c->res[l][0] * c->res[l][1] * c->res[l][2];
+    return c->log2_hashmap != 0 && dense > ((int64_t)1 << c->log2_hashmap);
 }
 
 inline NetOffsets net_offsets(const ndf_net_config *c) {
@@ -47,7 +62,9 @@ inline NetOffsets net_offsets(const ndf_net_config *c) {
         pos += (n + kAlign - 1) / kAlign * kAlign;
         return at;
     };
-    for (int l = 0; l < kL; ++l) o.cells[l] = (int64_t)c->res[l][0] * c->res[l][1] * c->res[l][2];
+    for (int l = 0; l < kL; ++l)
+        o.cells[l] = level_hashed(c, l) ? ((int64_t)1 << c->log2_hashmap)
+                                        : (int64_t)c->res[l][0] * c->res[l][1] * c->res[l][2];
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) o.grid[e][l] = take(o.cells[l] * kF);
         o.W1[e] = take(kH * kK0);
@@ -80,6 +97,7 @@ struct GridGeom {
     float inv[3];        // 1 / (n - 1) per axis
     uint64_t md[3];      // ceil(2^40 / (n - 1)) per axis
     uint64_t mx, my;     // ceil(2^40 / nx), ceil(2^40 / ny)
+    uint32_t hmask[kL];  // table entries - 1 for a hashed level, 0 for a dense one
 };
 
 inline GridGeom grid_geom(const ndf_net_config *c) {
@@ -96,7 +114,26 @@ inline GridGeom grid_geom(const ndf_net_config *c) {
     }
     g.mx = ((1ull << 40) + (uint64_t)c->nx - 1) / (uint64_t)c->nx;
     g.my = ((1ull << 40) + (uint64_t)c->ny - 1) / (uint64_t)c->ny;
+    for (int l = 0; l < kL; ++l)
+        g.hmask[l] = level_hashed(c, l) ? (uint32_t)((1u << c->log2_hashmap) - 1) : 0u;
     return g;
+}
+
+// Cell of level corner (x, y, z): dense x + Rx (y + Ry z), or on a hashed level
+// (hm = table entries - 1) the spatial hash of the hash grids that Sec. 4.2
+// builds on (Mueller et al. 2022): (x * 1 xor y * 2654435761 xor z * 805459861)
+// mod 2^T in 32-bit unsigned arithmetic.  HASH = false compiles the dense form
+// only (every level dense).
+template <bool HASH>
+__device__ __forceinline__ int cell_index(int x, int y, int z, const int R[3], uint32_t hm) {
+    const uint32_t dense = (uint32_t)x + (uint32_t)R[0] * ((uint32_t)y + (uint32_t)R[1] * (uint32_t)z);
+    if (!HASH) return (int)dense;
+    const uint32_t h = (uint32_t)x ^ ((uint32_t)y * 2654435761u) ^ ((uint32_t)z * 805459861u);
+    return (int)(hm ? (h & hm) : dense);
+}
+
+__device__ __forceinline__ uint32_t level_hmask(const GridGeom &g, int l) {
+    return l == 0 ? g.hmask[0] : (l == 1 ? g.hmask[1] : (l == 2 ? g.hmask[2] : g.hmask[3]));
 }
 
 // Level sizes of level l (l may differ between lanes: selects instead of an
@@ -112,8 +149,9 @@ __device__ __forceinline__ void level_dims(const GridGeom &g, int l, int R[3]) {
 // rounded division i (R - 1) / (n - 1) (exact whenever c is an integer);
 // base = clamp(floor(c), 0, R - 2), f = c - base; corner (dx,dy,dz) = bit 0,1,2.
 // Vertex and cell indices fit in 32 bits (V, cells < 2^31).
+template <bool HASH = false>
 __device__ __forceinline__ void corners_R32(const GridGeom &g, const int R[3], int64_t v64,
-                                            int idx[8], float w[8]) {
+                                            int idx[8], float w[8], uint32_t hm = 0) {
     const uint32_t v = (uint32_t)v64;
     const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
     // exact divisions by multiply-high: numerators < 2^24, divisors < 2^16
@@ -137,7 +175,7 @@ __device__ __forceinline__ void corners_R32(const GridGeom &g, const int R[3], i
 #pragma unroll
     for (int cn = 0; cn < 8; ++cn) {
         const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
-        idx[cn] = (b[0] + dx) + R[0] * ((b[1] + dy) + R[1] * (b[2] + dz));
+        idx[cn] = cell_index<HASH>(b[0] + dx, b[1] + dy, b[2] + dz, R, hm);
         w[cn] = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) * (dz ? f[2] : 1.f - f[2]);
     }
 }
@@ -148,8 +186,9 @@ __device__ __forceinline__ void corners_R32(const GridGeom &g, const int R[3], i
 // the max turns into 0) take the boundary's value; base = min(floor(c), R - 2),
 // f = c - base.  The position 2 i/(n - 1) - 1 of vertex i gives the vertex lookup's
 // cell, with weights equal up to the rounding of c.
+template <bool HASH = false>
 __device__ __forceinline__ void corners_pos32(const int R[3], const float p[3], int idx[8],
-                                              float w[8]) {
+                                              float w[8], uint32_t hm = 0) {
     int b[3];
     float f[3];
 #pragma unroll
@@ -163,7 +202,7 @@ __device__ __forceinline__ void corners_pos32(const int R[3], const float p[3], 
 #pragma unroll
     for (int cn = 0; cn < 8; ++cn) {
         const int dx = cn & 1, dy = (cn >> 1) & 1, dz = (cn >> 2) & 1;
-        idx[cn] = (b[0] + dx) + R[0] * ((b[1] + dy) + R[1] * (b[2] + dz));
+        idx[cn] = cell_index<HASH>(b[0] + dx, b[1] + dy, b[2] + dz, R, hm);
         w[cn] = (dx ? f[0] : 1.f - f[0]) * (dy ? f[1] : 1.f - f[1]) * (dz ? f[2] : 1.f - f[2]);
     }
 }

@@ -254,11 +254,12 @@ struct InferArgs {
 constexpr int kFragW1 = 4 * 2 * 64;   // bf16x8 elements
 constexpr int kFragW = 4 * 8 * 64;
 
-// Corner cells (int32) and weights of vertex v on level l; same arithmetic as
-// the training lookup.
+// Corner cells (int32) and weights of vertex v on a level of sizes R; same
+// arithmetic as the training lookup.  HASH: the level may be hashed (hm != 0).
+template <bool HASH>
 __device__ __forceinline__ void corners32(const GridGeom &g, const int R[3], int64_t v, int idx[8],
-                                          float w[8]) {
-    corners_R32(g, R, v, idx, w);
+                                          float w[8], uint32_t hm) {
+    corners_R32<HASH>(g, R, v, idx, w, hm);
 }
 
 enum { LAY_RELU = 0, LAY_LATENT = 1, LAY_HEAD = 2, LAY_LATENT_OUT = 3, LAY_LATENT_CACHE = 4 };
@@ -393,7 +394,8 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 // vertices in qlist (lat_out[n][128], bf16-rounded values stored as FP32);
 // MODE 2: latents of vertices 0 .. nq-1 into the query-latent cache (out);
 // MODE 3: field at the continuous positions qpos[n][3] in [-1, 1]^3.
-template <int MODE>
+// HASH: some grid level is a hash table (compiled out when every level is dense).
+template <int MODE, bool HASH>
 __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const int64_t *__restrict__ qlist,
                                                               int64_t nq,
@@ -449,14 +451,15 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             int R[3];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
+            const uint32_t hm = HASH ? (h ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 int idx[8];
                 float w[8];
                 if (MODE == 3)
-                    corners_pos32(R, pq[q], idx, w);
+                    corners_pos32<HASH>(R, pq[q], idx, w, hm);
                 else
-                    corners32(A.g, R, vq[q], idx, w);
+                    corners32<HASH>(A.g, R, vq[q], idx, w, hm);
                 float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int cn = 0; cn < 8; ++cn) {
@@ -695,7 +698,7 @@ __device__ __forceinline__ void dense_layer_fp8(
 
 // MODE 0: field (out[v] = Phi(ref, v)); MODE 1: latents of the vertices in
 // qlist (FP32); MODE 3: field at the continuous positions qpos[n][3].
-template <int MODE>
+template <int MODE, bool HASH>
 __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   const int64_t *__restrict__ qlist,
                                                                   int64_t nq,
@@ -750,14 +753,15 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
             int R[3];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
+            const uint32_t hm = HASH ? (h ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 int idx[8];
                 float w[8];
                 if (MODE == 3)
-                    corners_pos32(R, pq[q], idx, w);
+                    corners_pos32<HASH>(R, pq[q], idx, w, hm);
                 else
-                    corners32(A.g, R, vq[q], idx, w);
+                    corners32<HASH>(A.g, R, vq[q], idx, w, hm);
                 float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int cn = 0; cn < 8; ++cn) {
@@ -918,6 +922,12 @@ static InferArgs make_args(const ndf_net_config *c, const QLayout &q, const char
     return a;
 }
 
+static bool any_hashed(const ndf_net_config *c) {
+    for (int l = 0; l < kL; ++l)
+        if (level_hashed(c, l)) return true;
+    return false;
+}
+
 static unsigned infer_blocks(int64_t nq) {
     const int64_t tiles = ceil_div(nq, 64);
     const int64_t b = ceil_div(tiles, kInferWaves);
@@ -930,15 +940,21 @@ size_t net_latent_cache_bytes(const ndf_net_config *c) {
 }
 
 int launch_infer_latents(const ndf_net_config *c, const void *qp, void *cache, hipStream_t st) {
+    const bool hash = any_hashed(c);
     const QLayout q = qlayout(c);
     const InferArgs a = make_args(c, q, (const char *)qp, c->n_enc - 1);
-    hipLaunchKernelGGL(infer_kernel<2>, dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
-                       nullptr, a.V, nullptr, (float *)cache, nullptr);
+    if (hash)
+        hipLaunchKernelGGL((infer_kernel<2, true>), dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
+                           nullptr, a.V, nullptr, (float *)cache, nullptr);
+    else
+        hipLaunchKernelGGL((infer_kernel<2, false>), dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
+                           nullptr, a.V, nullptr, (float *)cache, nullptr);
     return status_of_launch();
 }
 
 int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int64_t *ref_v,
                               int n_ref, const void *cache, float *out, void *ws, hipStream_t st) {
+    const bool hash = any_hashed(c);
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
@@ -947,8 +963,12 @@ int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int
         hipSuccess)
         return NDF_E_HIP;
     const InferArgs a0 = make_args(c, q, Q, 0);
-    hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                       refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    if (hash)
+        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    else
+        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     for (int r = 0; r < n_ref; ++r)
         hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
@@ -959,6 +979,7 @@ int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int
 
 int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const int64_t *ref_v,
                        int n_ref, float *out, void *ws, hipStream_t st) {
+    const bool hash = any_hashed(c);
     if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
@@ -969,31 +990,49 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
         return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
-        hipLaunchKernelGGL(infer_fp8_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                           st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        if (hash)
+            hipLaunchKernelGGL((infer_fp8_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        else
+            hipLaunchKernelGGL((infer_fp8_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
         const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
         const int64_t V = (int64_t)c->nx * c->ny * c->nz;
         for (int r = 0; r < n_ref; ++r)
-            hipLaunchKernelGGL(infer_fp8_kernel<0>, dim3(infer_blocks(V)), dim3(kInferThreads), 0,
-                               st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V,
-                               nullptr);
+            if (hash)
+                hipLaunchKernelGGL((infer_fp8_kernel<0, true>), dim3(infer_blocks(V)), dim3(kInferThreads), 0,
+                                   st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V,
+                                   nullptr);
+            else
+                hipLaunchKernelGGL((infer_fp8_kernel<0, false>), dim3(infer_blocks(V)), dim3(kInferThreads), 0,
+                                   st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V,
+                                   nullptr);
         return status_of_launch();
     }
     // reference latents with encoder 0 (p1), queries with the last encoder (p2)
     const InferArgs a0 = make_args(c, q, Q, 0);
-    hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                       refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    if (hash)
+        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    else
+        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     const int64_t V = a1.V;
     for (int r = 0; r < n_ref; ++r)
-        hipLaunchKernelGGL(infer_kernel<0>, dim3(infer_blocks(V)), dim3(kInferThreads), 0, st, a1,
-                           nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V, nullptr);
+        if (hash)
+            hipLaunchKernelGGL((infer_kernel<0, true>), dim3(infer_blocks(V)), dim3(kInferThreads), 0, st, a1,
+                               nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V, nullptr);
+        else
+            hipLaunchKernelGGL((infer_kernel<0, false>), dim3(infer_blocks(V)), dim3(kInferThreads), 0, st, a1,
+                               nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V, nullptr);
     return status_of_launch();
 }
 
 int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const int64_t *ref_v,
                         int n_ref, const float *pos, int64_t n, float *out, void *ws,
                         hipStream_t st) {
+    const bool hash = any_hashed(c);
     if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
@@ -1004,27 +1043,45 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
         return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
-        hipLaunchKernelGGL(infer_fp8_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                           st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        if (hash)
+            hipLaunchKernelGGL((infer_fp8_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        else
+            hipLaunchKernelGGL((infer_fp8_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
         const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
         for (int r = 0; r < n_ref; ++r)
-            hipLaunchKernelGGL(infer_fp8_kernel<3>, dim3(infer_blocks(n)), dim3(kInferThreads), 0,
-                               st, a1, nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n,
-                               pos);
+            if (hash)
+                hipLaunchKernelGGL((infer_fp8_kernel<3, true>), dim3(infer_blocks(n)), dim3(kInferThreads), 0,
+                                   st, a1, nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n,
+                                   pos);
+            else
+                hipLaunchKernelGGL((infer_fp8_kernel<3, false>), dim3(infer_blocks(n)), dim3(kInferThreads), 0,
+                                   st, a1, nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n,
+                                   pos);
         return status_of_launch();
     }
     const InferArgs a0 = make_args(c, q, Q, 0);
-    hipLaunchKernelGGL(infer_kernel<1>, dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                       refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    if (hash)
+        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    else
+        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
+                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     for (int r = 0; r < n_ref; ++r)
-        hipLaunchKernelGGL(infer_kernel<3>, dim3(infer_blocks(n)), dim3(kInferThreads), 0, st, a1,
-                           nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n, pos);
+        if (hash)
+            hipLaunchKernelGGL((infer_kernel<3, true>), dim3(infer_blocks(n)), dim3(kInferThreads), 0, st, a1,
+                               nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n, pos);
+        else
+            hipLaunchKernelGGL((infer_kernel<3, false>), dim3(infer_blocks(n)), dim3(kInferThreads), 0, st, a1,
+                               nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n, pos);
     return status_of_launch();
 }
 
 int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref_a, int64_t ref_b,
                             const void *cache, float *out, void *ws, hipStream_t st) {
+    const bool hash = any_hashed(c);
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
@@ -1033,8 +1090,12 @@ int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref
     if (hipMemcpyAsync(refs, both, sizeof(both), hipMemcpyHostToDevice, st) != hipSuccess)
         return NDF_E_HIP;
     const InferArgs a0 = make_args(c, q, Q, 0);
-    hipLaunchKernelGGL(infer_kernel<1>, dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
-                       nullptr, lat, nullptr);
+    if (hash)
+        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
+                           nullptr, lat, nullptr);
+    else
+        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
+                           nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
                        st, a1, (const u32x4 *)cache, a1.V, lat, out);

@@ -73,20 +73,23 @@ __device__ __forceinline__ const float *row_pos(const float *pos, int64_t B, int
     return pos + 3 * (n < B ? 2 * n : 2 * (n - B) + 1);
 }
 
-// Trilinear corners of row n on a level of sizes R: from its vertex index
-// (pairs) or its continuous position (pos, when non-null).
-__device__ __forceinline__ void row_corners(const GridGeom &g, const int R[3],
-                                            const int64_t *pairs, const float *pos, int64_t B,
-                                            int64_t n, int idx[8], float w[8]) {
+// Trilinear corners of row n on level l: from its vertex index (pairs) or its
+// continuous position (pos, when non-null); cells hashed on hashed levels.
+__device__ __forceinline__ void row_corners(const GridGeom &g, int l, const int64_t *pairs,
+                                            const float *pos, int64_t B, int64_t n, int idx[8],
+                                            float w[8]) {
+    int R[3];
+    level_dims(g, l, R);
+    const uint32_t hm = level_hmask(g, l);
     if (pos) {
         const float *p = row_pos(pos, B, n);
         const float pp[3] = {p[0], p[1], p[2]};
-        corners_pos32(R, pp, idx, w);
+        corners_pos32<true>(R, pp, idx, w, hm);
     } else {
         int64_t v = row_vertex(pairs, B, n);
         const int64_t V = (int64_t)g.nx * g.ny * g.nz;
         v = v < 0 ? 0 : (v >= V ? V - 1 : v);  // out-of-range pairs are clamped
-        corners_R32(g, R, v, idx, w);
+        corners_R32<true>(g, R, v, idx, w, hm);
     }
 }
 
@@ -102,11 +105,9 @@ __global__ __launch_bounds__(kThreads) void grid_fwd_kernel(const float *__restr
     const int64_t n = t / kL;
     const int l = (int)(t % kL);
     const int e = (n_enc == 2 && n >= B) ? 1 : 0;
-    int R[3];
-    level_dims(g, l, R);
     int idx[8];
     float w[8];
-    row_corners(g, R, pairs, pos, B, n, idx, w);
+    row_corners(g, l, pairs, pos, B, n, idx, w);
     const f32x4 *grid = reinterpret_cast<const f32x4 *>(params + grid_off(go, e, l));
     f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
 #pragma unroll
@@ -139,11 +140,9 @@ __global__ __launch_bounds__(kThreads) void grid_bwd_kernel(float *__restrict__ 
         const int64_t n = row0 + it / kL;
         const int l = (int)(it % kL);
         const int e = (n_enc == 2 && n >= B) ? 1 : 0;
-        int R[3];
-        level_dims(g, l, R);
         int idx[8];
         float w[8];
-        row_corners(g, R, pairs, pos, B, n, idx, w);
+        row_corners(g, l, pairs, pos, B, n, idx, w);
         int ic = idx[0];
         float wc = w[0];
 #pragma unroll

@@ -200,3 +200,24 @@ def test_positions_entry_points_reject_bad_arguments():
     assert L.ndf_pearson_points(E, 0, 0, None, 10, FAKE, None) == ndf.NDF_E_ARG
     assert L.ndf_pearson_points(E, 0, 0, FAKE, -1, FAKE, None) == ndf.NDF_E_ARG
     assert L.ndf_pearson_points(E, 0, 0, None, 0, None, None) == ndf.NDF_OK
+
+
+def test_hash_grid_config():
+    """Hash tables (Sec. 4.2): T in [8, 24]; the parameter layout matches the
+    generator's (2^T cells for the levels larger than that); a dense level of
+    2^28 cells or more needs hashing."""
+    import gen
+    L = ndf.lib()
+    FAKE = ctypes.c_void_p(0x1000)
+    lay = gen.NetLayout.for_grid(250, 352, 20, log2_hashmap=19)
+    cfg = ndf.net_config(250, 352, 20, lay.res, log2_hashmap=19)
+    assert ndf.ndf_net_param_bytes(cfg) == 4 * lay.n_floats
+    assert lay.cells(3) == 1 << 19 and lay.cells(2) == 157 * 222 * 13
+    dense = gen.NetLayout.for_grid(250, 352, 20)
+    assert lay.n_floats < dense.n_floats
+    for T in (5, 25, -1):
+        bad = ndf.net_config(250, 352, 20, lay.res, log2_hashmap=T)
+        assert L.ndf_net_init(ctypes.byref(bad), FAKE, None, 1, None) == ndf.NDF_E_ARG
+    huge = [[4096, 4096, 16]] * 4                    # 2^28 cells per level
+    assert ndf.ndf_net_param_bytes(ndf.net_config(2048, 2048, 2, huge)) == 0
+    assert ndf.ndf_net_param_bytes(ndf.net_config(2048, 2048, 2, huge, log2_hashmap=20)) > 0

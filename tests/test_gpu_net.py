@@ -502,3 +502,89 @@ def test_infer_field_difference():
     _log(f"difference field: max|d| {err:.3g} field rms {scale:.3g}")
     assert err <= 0.2 * scale
     assert np.linalg.norm(got - want) <= 2e-2 * (np.linalg.norm(fa) + np.linalg.norm(fb))
+
+
+# --------------------------------------------------------------- hash grids ----
+def _setup_hash(name, n_enc, T, seed):
+    cfg = gen.CONFIGS[name]
+    lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, n_enc=n_enc, log2_hashmap=T)
+    flat = gen.make_net_params(lay, seed=seed, grid_scale=0.5, bias_scale=0.1)
+    c = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay.res, n_enc=n_enc, log2_hashmap=T)
+    P = torch.from_numpy(flat).cuda()
+    net = nn.Net(flat, (cfg.nx, cfg.ny, cfg.nz), lay.res, 8, 128, n_enc, T)
+    return cfg, lay, c, P, net
+
+
+@pytest.mark.parametrize("n_enc", [1, 2])
+def test_hash_grid_forward_and_gradient(n_enc):
+    """Hash-table levels (Sec. 4.2; T = 10 hashes every level of the mid grid
+    above 1024 cells): the training forward and adjoint against the FP64 network
+    with the same hash, at vertex pairs and at continuous positions (the
+    vertex-pair tests' bars)."""
+    cfg, lay, c, P, net = _setup_hash("mid", n_enc, 10, 2342)
+    assert any(lay.cells(l) == 1024 for l in range(4))
+    pairs = gen.random_pairs(cfg.n_vertices, 3000, seed=71)
+    _check_bf16(_forward_gpu(c, P, pairs), nn.forward(net, pairs[:, 0], pairs[:, 1])[0],
+                f"hash forward n_enc={n_enc}")
+    pos = gen.random_positions(2 * 2048, seed=72).reshape(2048, 2, 3)
+    y = nn.forward_points(net, pos)
+    t = y + 1.0
+    loss_o, g_o, _ = nn.loss_and_grad_points(net, pos, t)
+    g = torch.empty_like(P)
+    loss = torch.empty(1, device="cuda")
+    ws = torch.empty(ndf.train_ws_bytes(c, len(pos)), dtype=torch.uint8, device="cuda")
+    ndf.ndf_net_grad_at(c, P, torch.as_tensor(pos, device="cuda"),
+                        torch.as_tensor(t.astype(np.float32), device="cuda"), g, loss, ws)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - loss_o) <= 1e-2 * loss_o
+    for name_t, _shape in lay.tensors():
+        a = lay.view(g, name_t).ravel()
+        b = lay.view(g_o.flat, name_t).ravel()
+        nb = np.linalg.norm(b)
+        rel = np.linalg.norm(a - b) / nb
+        cos = float(np.dot(a, b) / (np.linalg.norm(a) * nb))
+        _log(f"hash grad {name_t}: relL2 {rel:.2e} cos {cos:.5f}")
+        assert rel <= 1e-1 and cos >= 0.995, name_t
+
+
+@pytest.mark.parametrize("n_enc", [1, 2])
+def test_hash_grid_inference(n_enc):
+    """Fused inference with hash-table levels: BF16 and FP8 fields and the field
+    at continuous positions against the FP64 network; the cached-latent field
+    bit for bit equal to the fused one."""
+    cfg, lay, c, P, net = _setup_hash("mid", n_enc, 10, 2343)
+    V = cfg.n_vertices
+    refs = [cfg.ref_v, 0]
+    q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
+    out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
+    for i, r in enumerate(refs):
+        want = nn.field(net, r)
+        _check_bf16(out16[i].cpu().numpy(), want, f"hash infer n_enc={n_enc} ref={r}")
+        assert np.linalg.norm(out8[i] - want) / np.linalg.norm(want) <= 0.2
+    pos = gen.random_positions(2000, seed=73)
+    pts = _points_gpu(c, q, refs[:1], pos, ndf.NDF_PREC_BF16)
+    _check_bf16(pts[0], nn.field_points(net, refs[0], pos.astype(np.float64)),
+                f"hash points n_enc={n_enc}")
+    cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
+    ndf.ndf_infer_latents(c, q, cache)
+    oc = torch.empty((len(refs), V), device="cuda")
+    ws = torch.empty(ndf.infer_ws_bytes(c, len(refs), ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                     device="cuda")
+    ndf.ndf_infer_field_cached(c, q, refs, cache, oc, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(oc, out16)
+
+
+def test_hash_grid_paper_size_sampled():
+    """The paper's grid with a 2^19-cell table: the finest level (1.76M cells) is
+    hashed, the others dense; sampled vertices against the FP64 network."""
+    cfg, lay, c, P, net = _setup_hash("paper", 1, 19, 2344)
+    assert lay.cells(3) == 1 << 19
+    V = cfg.n_vertices
+    q = _qparams(c, P)
+    out = _infer_gpu(c, q, [cfg.ref_v], V)
+    sample = gen.random_vertices(V, 3000, seed=74)
+    g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
+    _check_bf16(g, want, "hash infer paper")

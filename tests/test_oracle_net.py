@@ -273,3 +273,76 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(p1, p - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-14)
     np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-14)
+
+
+# --------------------------------------------------------------- hash grids ----
+RES_H = [(8, 8, 8), (16, 12, 8), (20, 16, 10), (24, 20, 12)]
+DIMS_H = (24, 20, 12)
+
+
+def test_hash_definition_values():
+    """The spatial hash of Sec. 4.2's hash grids: xor of the corner coordinates
+    times one prime per axis, the first prime 1, modulo 2^T.  Values worked by
+    hand from the primes' hex forms 0x9E3779B1 and 0x30025795."""
+    T = 10
+    p = np.array([[5, 0, 0], [1029, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]])
+    np.testing.assert_array_equal(nn.hash_cell(p, T), [5, 5, 0x1B1, 0x395, 0x225])
+    assert nn.level_hashed((16, 12, 8), 10) and not nn.level_hashed((8, 8, 8), 10)
+    assert nn.level_cells((16, 12, 8), 10) == 1024 and nn.level_cells((8, 8, 8), 10) == 512
+
+
+def test_hashed_level_lookup_end_to_end():
+    """Table entry i holding the value i in feature 0: at the position of a level
+    vertex (weight one on that corner) the feature is the corner's hash; on a
+    dense level it is the dense cell index."""
+    T = 10
+    L = gen.NetLayout(DIMS_H[0], DIMS_H[1], DIMS_H[2], tuple(RES_H), 8, 128, 1, T)
+    net = nn.Net(gen.make_net_params(L), DIMS_H, RES_H, 8, 128, 1, T)
+    for l, R in enumerate(RES_H):
+        g = np.zeros((nn.level_cells(R, T), 8))
+        g[:, 0] = np.arange(g.shape[0])
+        net[("grid", 0, l)] = g
+    rng = np.random.default_rng(3)
+    for l, R in enumerate(RES_H):
+        c = np.stack([rng.integers(0, r, 50) for r in R], axis=1)
+        u = c / (np.array(R) - 1.0)
+        h0 = nn.grid_encode(net, 0, u)[:, 8 * l]
+        if nn.level_hashed(R, T):
+            want = nn.hash_cell(c, T)
+        else:
+            want = c[:, 0] + R[0] * (c[:, 1] + R[1] * c[:, 2])
+        np.testing.assert_allclose(h0, want, rtol=0, atol=1e-9)
+
+
+def test_hashed_gather_scatter_adjoint_with_collisions():
+    """The adjoint identity holds on hashed levels, where corners collide and
+    their contributions add into one cell."""
+    T = 9
+    L = gen.NetLayout(DIMS_H[0], DIMS_H[1], DIMS_H[2], tuple(RES_H), 8, 128, 1, T)
+    net = nn.Net(gen.make_net_params(L, grid_scale=1.0), DIMS_H, RES_H, 8, 128, 1, T)
+    rng = np.random.default_rng(4)
+    u = rng.uniform(0, 1, (400, 3))
+    idx, _ = nn.trilinear(u, RES_H[3], T)
+    assert len(np.unique(idx)) < len(np.unique(nn.trilinear(u, RES_H[3])[0]))  # collisions
+    G = net.zeros_like()
+    for l in range(4):
+        G[("grid", 0, l)] = rng.standard_normal(G[("grid", 0, l)].shape)
+    y = rng.standard_normal((400, 32))
+    probe = nn.Net(G.flat, DIMS_H, RES_H, 8, 128, 1, T)
+    lhs = np.sum(nn.grid_encode(probe, 0, u) * y)
+    S = net.zeros_like()
+    nn.grid_scatter(net, 0, u, y, S)
+    rhs = sum(np.sum(G[("grid", 0, l)] * S[("grid", 0, l)]) for l in range(4))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_large_table_is_the_dense_grid():
+    """A table at least as large as every level leaves every level dense: the same
+    layout and the same field as T = 0."""
+    L0 = gen.NetLayout(DIMS_H[0], DIMS_H[1], DIMS_H[2], tuple(RES_H), 8, 128, 2, 0)
+    L1 = gen.NetLayout(DIMS_H[0], DIMS_H[1], DIMS_H[2], tuple(RES_H), 8, 128, 2, 13)
+    assert L0.offsets() == L1.offsets()
+    flat = gen.make_net_params(L0, grid_scale=1.0, bias_scale=0.1)
+    a = nn.Net(flat, DIMS_H, RES_H, 8, 128, 2, 0)
+    b = nn.Net(flat, DIMS_H, RES_H, 8, 128, 2, 13)
+    np.testing.assert_array_equal(nn.field(a, 17), nn.field(b, 17))
