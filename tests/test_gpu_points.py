@@ -231,3 +231,21 @@ def test_ksg_points_parity(name):
     got = ndf.ksg_points(e, cpos, k=4).cpu().numpy()
     want = ndf.ksg_pairs(e, pairs, k=4).cpu().numpy()
     assert np.max(np.abs(got - want)) <= 1e-6
+
+
+def test_points_ragged_members():
+    """N = 37 members (not a multiple of 4: the scalar-load paths) and a 3-member
+    edge case: Pearson and KSG at positions against the oracle."""
+    for n_members, k in ((37, 4), (3, 1)):
+        cfg = dataclasses.replace(gen.CONFIGS["tiny"], n_members=n_members)
+        e = _ens(cfg)
+        x = e.x[0].cpu().numpy()
+        dims = (cfg.nx, cfg.ny, cfg.nz)
+        pos = _pos_pairs(203, seed=81)
+        r = ndf.pearson_points(e, pos).cpu().numpy()
+        assert np.max(np.abs(r - pt.pearson_points(x, x, dims, pos))) <= PEARSON_TOL
+        mi, cnt = ndf.ksg_points(e, pos, k=k, counts=True)
+        want, wcnt = pt.ksg_points(x, x, dims, pos, k, counts=True)
+        assert np.array_equal(cnt.cpu().numpy(), wcnt)
+        assert np.max(np.abs(mi.cpu().numpy() - want)) <= 1e-4
+        _log(f"ragged N={n_members}: pearson and KSG at positions match")
