@@ -21,7 +21,8 @@ LIB = PKG / "libndf.so"
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "prepare.hip", "pearson.hip", "ksg.hip", "net_train.hip", "net_infer.hip"]
+SOURCES = ["api.hip", "prepare.hip", "pearson.hip", "ksg.hip", "points.hip", "net_train.hip",
+           "net_infer.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fno-fast-math",
@@ -31,7 +32,8 @@ COMMON = [
     "-Wno-unused-result",
 ]
 # exact IEEE double arithmetic for the KSG codes and the harmonic sums
-PER_FILE = {"prepare.hip": ["-ffp-contract=off"], "ksg.hip": ["-ffp-contract=off"]}
+PER_FILE = {"prepare.hip": ["-ffp-contract=off"], "ksg.hip": ["-ffp-contract=off"],
+            "points.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> Path:

@@ -1106,93 +1106,4 @@ int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t 
     return status_of_launch();
 }
 
-// ------------------------------------------------ continuous positions ----
-// KSG targets between the interpolated samples at two continuous positions
-// (Sec. 4.3).  points_codes_kernel turns each interpolated column into a column
-// of integer codes exactly as ndf_prepare does for a vertex (min-max onto
-// [0, 2^23], IEEE double, round-half-even): column b is p1 of pair b (variable
-// a), column B + b is p2 (variable b).  The samples are sum_c w_c x_m(v_c) over
-// the corners of nonzero weight in corner order, in FP64 without contraction, so
-// the codes are reproducible bit for bit; at a vertex's own position they equal
-// that vertex's codes.  The pairs kernel then runs on these 2B columns with
-// pairs (b, B + b), sorting each column itself (there are no stored orders).
-__global__ __launch_bounds__(256) void points_codes_kernel(
-    const float *__restrict__ xt_a, const float *__restrict__ xt_b, int N, int nx, int ny,
-    int nz, const float *__restrict__ pos, int64_t B, int32_t *__restrict__ code,
-    int32_t *__restrict__ flags, int64_t *__restrict__ pairs) {
-    const int lane = threadIdx.x & 63;
-    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (col >= 2 * B) return;
-    const int side = col >= B ? 1 : 0;
-    const int64_t b = col - side * B;
-    const float *xt = side ? xt_b : xt_a;
-    int64_t v[8];
-    double w[8];
-    data_cell(pos + 6 * b + 3 * side, nx, ny, nz, v, w);
-    auto value = [&](int m) {
-        double a = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (w[c] != 0.0) a += w[c] * (double)xt[v[c] * N + m];
-        return a;
-    };
-    double lo = INFINITY, hi = -INFINITY;
-    int bad = 0;
-    for (int m = lane; m < N; m += 64) {
-        const double a = value(m);
-        bad |= !isfinite(a);
-        lo = fmin(lo, a);
-        hi = fmax(hi, a);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = fmin(lo, __shfl_xor(lo, off, 64));
-        hi = fmax(hi, __shfl_xor(hi, off, 64));
-        bad |= __shfl_xor(bad, off, 64);
-    }
-    const bool flat = !(hi > lo);
-    const double scale = flat ? 0.0 : 8388608.0 / (hi - lo);
-    int32_t *dst = code + col * N;
-    for (int m = lane; m < N; m += 64)
-        dst[m] = (flat || bad) ? 0 : (int32_t)__builtin_rint((value(m) - lo) * scale);
-    if (lane == 0) {
-        flags[col] = (bad ? NDF_FLAG_NONFINITE : 0) | (flat ? NDF_FLAG_CONSTANT : 0);
-        if (!side) {
-            pairs[2 * b] = b;
-            pairs[2 * b + 1] = B + b;
-        }
-    }
-}
-
-size_t ksg_points_ws_bytes(int N, int64_t B) {
-    return ksg_pairs_ws_bytes(N) + align_up((size_t)B * 2 * sizeof(int64_t), 256) +
-           align_up((size_t)B * 2 * sizeof(int32_t), 256) +
-           align_up((size_t)B * 2 * N * sizeof(int32_t), 256);
-}
-
-int launch_ksg_points(const ndf_ensemble *e, int var_a, int var_b, const float *pos, int64_t B,
-                      int k, float *out, int32_t *counts, void *ws, hipStream_t st) {
-    const int N = e->n_members;
-    const int64_t V = (int64_t)e->nx * e->ny * e->nz;
-    char *w = (char *)ws;
-    double *H = (double *)w;
-    w += ksg_pairs_ws_bytes(N);
-    int64_t *pairs = (int64_t *)w;
-    w += align_up((size_t)B * 2 * sizeof(int64_t), 256);
-    int32_t *flags = (int32_t *)w;
-    w += align_up((size_t)B * 2 * sizeof(int32_t), 256);
-    int32_t *code = (int32_t *)w;
-    hipLaunchKernelGGL(points_codes_kernel, dim3((unsigned)ceil_div(2 * B, 4)), dim3(256), 0, st,
-                       e->xt + (int64_t)var_a * V * N, e->xt + (int64_t)var_b * V * N, N, e->nx,
-                       e->ny, e->nz, pos, B, code, flags, pairs);
-    // the 2B columns as a one-variable ensemble of 2B "vertices" without stored orders
-    ndf_ensemble cols = *e;
-    cols.nx = (int32_t)(2 * B);
-    cols.ny = 1;
-    cols.nz = 1;
-    cols.code = code;
-    cols.flags = flags;
-    cols.order = nullptr;
-    return launch_ksg_pairs(&cols, 0, 0, pairs, B, k, out, counts, H, st);
-}
-
 }  // namespace ndf
