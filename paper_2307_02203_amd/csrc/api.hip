@@ -59,6 +59,28 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
+namespace ndf {
+
+struct RefBatch {
+    int64_t v[64];
+};
+
+__global__ void put_refs_kernel(RefBatch rb, int n, int64_t *__restrict__ dst) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = rb.v[threadIdx.x];
+}
+
+int put_refs(const int64_t *ref_v, int n_ref, int64_t *dst, hipStream_t st) {
+    for (int r0 = 0; r0 < n_ref; r0 += 64) {
+        RefBatch rb{};
+        const int n = n_ref - r0 < 64 ? n_ref - r0 : 64;
+        for (int i = 0; i < n; ++i) rb.v[i] = ref_v[r0 + i];
+        hipLaunchKernelGGL(put_refs_kernel, dim3(1), dim3(64), 0, st, rb, n, dst + r0);
+    }
+    return status_of_launch();
+}
+
+}  // namespace ndf
+
 extern "C" {
 
 const char *ndf_status_string(int s) {

@@ -1051,9 +1051,7 @@ int launch_ksg_field(const ndf_ensemble *e, int var_ref, int var_qry, const int6
     uint16_t *perm = (uint16_t *)w;
     w += align_up((size_t)n_ref * N * sizeof(uint16_t), 256);
     uint16_t *invp = (uint16_t *)w;
-    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-        return NDF_E_HIP;
+    if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     const int P = p2(N);
     const int32_t *cr = e->code + (int64_t)var_ref * V * N;
     const int32_t *cq = e->code + (int64_t)var_qry * V * N;

@@ -872,8 +872,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
         for (int q = 0; q < 2; ++q) {
             const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
             if (h == 0 && ok[q]) {
-                float *o = out + row0 + q * 32 + jl;
-                *o = SUB ? *o - y : y;
+                if (SUB)
+                    out[row0 + q * 32 + jl] -= y;
+                else
+                    out[row0 + q * 32 + jl] = y;
             }
         }
     }
@@ -959,9 +961,7 @@ int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
-    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-        return NDF_E_HIP;
+    if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     const InferArgs a0 = make_args(c, q, Q, 0);
     if (hash)
         hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
@@ -985,9 +985,7 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
-    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-        return NDF_E_HIP;
+    if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
         if (hash)
@@ -1038,9 +1036,7 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
-    if (hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-        return NDF_E_HIP;
+    if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
         if (hash)
@@ -1087,8 +1083,7 @@ int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)2 * kH * sizeof(float), 256));
     const int64_t both[2] = {ref_a, ref_b};
-    if (hipMemcpyAsync(refs, both, sizeof(both), hipMemcpyHostToDevice, st) != hipSuccess)
-        return NDF_E_HIP;
+    if (put_refs(both, 2, refs, st) != NDF_OK) return NDF_E_HIP;
     const InferArgs a0 = make_args(c, q, Q, 0);
     if (hash)
         hipLaunchKernelGGL((infer_kernel<1, true>), dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,

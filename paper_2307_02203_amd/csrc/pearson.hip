@@ -365,9 +365,7 @@ int launch_pearson_field(const ndf_ensemble *e, int var_ref, int var_qry, const 
     w += align_up((size_t)n_ref * kpad * sizeof(float), 256);
     int64_t *refs = (int64_t *)w;
     w += align_up((size_t)n_ref * sizeof(int64_t), 256);
-    hipError_t err = hipMemcpyAsync(refs, ref_v, (size_t)n_ref * sizeof(int64_t),
-                                    hipMemcpyHostToDevice, st);
-    if (err != hipSuccess) return NDF_E_HIP;
+    if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     const float *xr = e->x + (int64_t)var_ref * N * V;
     const float *xq = e->x + (int64_t)var_qry * N * V;
     hipLaunchKernelGGL(pearson_refcols_kernel, dim3(n_ref), dim3(256), 0, st, xr,
