@@ -248,6 +248,8 @@ struct InferArgs {
     const float *b6;
     GridGeom g;
     int64_t V;
+    int64_t fuse_ref;  // field modes: reference vertex whose latent the workgroup computes
+                       // itself (shared encoder), or -1: read it from ref_lat
 };
 
 // LDS plan (bytes): W1 8K | W2..W5 4 x 32K | b1..b5 5 x 512 | w6 512 | ref latent 512
@@ -415,13 +417,56 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
+    const bool fuse = kField && A.fuse_ref >= 0;
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
-        s_ref[i] = kField ? ref_lat[i] : 0.f;
+        s_ref[i] = kField && !fuse ? ref_lat[i] : 0.f;
     }
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    if (fuse) {
+        // The reference latent with the shared encoder (same layers, same packing
+        // as the latent mode, so the same bits): wave 0 runs the reference as the
+        // only valid row of one tile and leaves its 128 latents in s_ref.
+        if (wave == 0) {
+            int h4 = 4 * h;
+            const bool ok[2] = {jl == 0, false};
+            bf16x8 a[8][2], b[8][2];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
+                int R[3];
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
+                const uint32_t hm = HASH ? (h ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
+                int idx[8];
+                float w[8];
+                corners32<HASH>(A.g, R, A.fuse_ref, idx, w, hm);
+                float sf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int cn = 0; cn < 8; ++cn) {
+                    const i32x4 raw = *reinterpret_cast<const i32x4 *>(grid + (int64_t)idx[cn] * kF);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const uint32_t u = (uint32_t)raw[p];
+                        sf[2 * p] = fmaf(w[cn], __uint_as_float(u << 16), sf[2 * p]);
+                        sf[2 * p + 1] = fmaf(w[cn], __uint_as_float(u & 0xffff0000u), sf[2 * p + 1]);
+                    }
+                }
+                bf16x8 t;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) t[e] = f2bf(sf[e]);
+                a[kb][0] = a[kb][1] = t;
+            }
+            float part[2] = {0.f, 0.f};
+            dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok, lane, h4);
+            dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0, ok, lane, h4);
+            dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref, 0, ok,
+                                           lane, h4);
+        }
+        __syncthreads();
+    }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
     for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
@@ -921,6 +966,7 @@ static InferArgs make_args(const ndf_net_config *c, const QLayout &q, const char
     a.b6 = (const float *)(Q + q.b6);
     a.g = grid_geom(c);
     a.V = (int64_t)c->nx * c->ny * c->nz;
+    a.fuse_ref = -1;
     return a;
 }
 
@@ -985,6 +1031,22 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    if (prec == NDF_PREC_BF16 && c->n_enc == 1) {
+        // shared encoder: each workgroup computes the reference latent itself
+        InferArgs a = make_args(c, q, Q, 0);
+        for (int r = 0; r < n_ref; ++r) {
+            a.fuse_ref = ref_v[r];
+            if (hash)
+                hipLaunchKernelGGL((infer_kernel<0, true>), dim3(infer_blocks(a.V)),
+                                   dim3(kInferThreads), 0, st, a, nullptr, a.V, nullptr,
+                                   out + (int64_t)r * a.V, nullptr);
+            else
+                hipLaunchKernelGGL((infer_kernel<0, false>), dim3(infer_blocks(a.V)),
+                                   dim3(kInferThreads), 0, st, a, nullptr, a.V, nullptr,
+                                   out + (int64_t)r * a.V, nullptr);
+        }
+        return status_of_launch();
+    }
     if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
