@@ -94,8 +94,8 @@ def _copy_probe(a):
 def main():
     a = _parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(the multi-GPU sharding is a design note only)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                          "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     if a.copy_probe:
         _copy_probe(a)
