@@ -616,6 +616,7 @@ struct InferArgs8 {
     const float *w6;
     const float *b6;
     GridGeom g;
+    int64_t fuse_ref;  // as in InferArgs
 };
 
 constexpr int kFrag8 = 4 * 2 * 64;  // i32x8 per 128x128 fp8 layer
@@ -766,13 +767,60 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     for (int i = tid; i < 4 * kH * 4; i += kInferThreads)
         s_e[i / (kH * 4)][i % (kH * 4)] = A.se[i / (kH * 4)][i % (kH * 4)];
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
+    const bool fuse = kField && A.fuse_ref >= 0;
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
-        s_ref[i] = kField ? ref_lat[i] : 0.f;
+        s_ref[i] = kField && !fuse ? ref_lat[i] : 0.f;
     }
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    if (fuse) {
+        // the reference latent with the shared encoder, as the latent mode computes
+        // it (the only valid row of one tile), left in s_ref by wave 0
+        if (wave == 0) {
+            const int h4 = 4 * h;
+            const bool ok[2] = {jl == 0, false};
+            bf16x8 g16[2][2];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
+                int R[3];
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
+                const uint32_t hm = HASH ? (h ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
+                int idx[8];
+                float w[8];
+                corners32<HASH>(A.g, R, A.fuse_ref, idx, w, hm);
+                float sf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int cn = 0; cn < 8; ++cn) {
+                    const i32x4 raw = *reinterpret_cast<const i32x4 *>(grid + (int64_t)idx[cn] * kF);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const uint32_t u = (uint32_t)raw[p];
+                        sf[2 * p] = fmaf(w[cn], __uint_as_float(u << 16), sf[2 * p]);
+                        sf[2 * p + 1] = fmaf(w[cn], __uint_as_float(u & 0xffff0000u), sf[2 * p + 1]);
+                    }
+                }
+                bf16x8 t;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) t[e] = f2bf(sf[e]);
+                g16[kb][0] = g16[kb][1] = t;
+            }
+            i32x8 a8[2][2], b8[2][2];
+            int sa[2][2], sb[2][2];
+            float part[2] = {0.f, 0.f};
+            dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8,
+                                            sb, a8, sa, part, nullptr, 0, ok, lane, h4);
+            dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16,
+                                             a8, sa, b8, sb, part, nullptr, 0, ok, lane, h4);
+            dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6,
+                                                   g16, b8, sb, a8, sa, part, s_ref, 0, ok, lane,
+                                                   h4);
+        }
+        __syncthreads();
+    }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
     for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
@@ -946,6 +994,7 @@ static InferArgs8 make_args8(const ndf_net_config *c, const QLayout &q, const ch
     a.w6 = (const float *)(Q + q.w6);
     a.b6 = (const float *)(Q + q.b6);
     a.g = grid_geom(c);
+    a.fuse_ref = -1;
     return a;
 }
 
@@ -1031,6 +1080,23 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    if (prec == NDF_PREC_FP8_E4M3 && c->n_enc == 1) {
+        // shared encoder: each workgroup computes the reference latent itself
+        InferArgs8 a = make_args8(c, q, Q, 0);
+        const int64_t V = (int64_t)c->nx * c->ny * c->nz;
+        for (int r = 0; r < n_ref; ++r) {
+            a.fuse_ref = ref_v[r];
+            if (hash)
+                hipLaunchKernelGGL((infer_fp8_kernel<0, true>), dim3(infer_blocks(V)),
+                                   dim3(kInferThreads), 0, st, a, nullptr, V, nullptr,
+                                   out + (int64_t)r * V, nullptr);
+            else
+                hipLaunchKernelGGL((infer_fp8_kernel<0, false>), dim3(infer_blocks(V)),
+                                   dim3(kInferThreads), 0, st, a, nullptr, V, nullptr,
+                                   out + (int64_t)r * V, nullptr);
+        }
+        return status_of_launch();
+    }
     if (prec == NDF_PREC_BF16 && c->n_enc == 1) {
         // shared encoder: each workgroup computes the reference latent itself
         InferArgs a = make_args(c, q, Q, 0);
