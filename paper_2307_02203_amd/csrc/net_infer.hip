@@ -1164,6 +1164,36 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    if (c->n_enc == 1) {  // shared encoder: the reference latent in each workgroup
+        if (prec == NDF_PREC_FP8_E4M3) {
+            InferArgs8 a = make_args8(c, q, Q, 0);
+            for (int r = 0; r < n_ref; ++r) {
+                a.fuse_ref = ref_v[r];
+                if (hash)
+                    hipLaunchKernelGGL((infer_fp8_kernel<3, true>), dim3(infer_blocks(n)),
+                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
+                                       out + (int64_t)r * n, pos);
+                else
+                    hipLaunchKernelGGL((infer_fp8_kernel<3, false>), dim3(infer_blocks(n)),
+                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
+                                       out + (int64_t)r * n, pos);
+            }
+        } else {
+            InferArgs a = make_args(c, q, Q, 0);
+            for (int r = 0; r < n_ref; ++r) {
+                a.fuse_ref = ref_v[r];
+                if (hash)
+                    hipLaunchKernelGGL((infer_kernel<3, true>), dim3(infer_blocks(n)),
+                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
+                                       out + (int64_t)r * n, pos);
+                else
+                    hipLaunchKernelGGL((infer_kernel<3, false>), dim3(infer_blocks(n)),
+                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
+                                       out + (int64_t)r * n, pos);
+            }
+        }
+        return status_of_launch();
+    }
     if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
