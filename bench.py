@@ -481,11 +481,16 @@ def _roofline_of(dominant, roof, med, N, V):
         r["note"] = ("peak = brute-force pair evaluations/s at the 32-bit VALU peak "
                      f"({PEAK_ALU_TOPS:.1f} T lane-ops/s / {KSG_OPS_PER_PAIR} ops); the kernel "
                      "prunes the neighbour search, so frac > 1 is the pruning gain; its own "
-                     "VALU issue rate (rocprofv3 SQ_INSTS_VALU) is recorded in profiles/")
+                     "VALU issue rate and lane occupancy (rocprofv3 SQ counters, profiles/) "
+                     "are valu_issue_frac and valu_lanes_active_frac")
     else:
         r = {"bound": "mixed", "achieved": None, "peak": None, "unit": None, "frac": None}
     r["kernel"] = dominant
     r["traffic"] = _measured_traffic(dominant)
+    issue = _measured_issue(dominant)
+    if issue is not None:
+        # the kernel's own VALU issue and lane occupancy (rocprofv3 SQ counters)
+        r["valu_issue_frac"], r["valu_lanes_active_frac"] = issue
     return r
 
 
@@ -498,7 +503,9 @@ _PMC_TRAFFIC = {
 }
 
 
-def _measured_traffic(row):
+def _profile_text(row):
+    """The counter profile of `row` while its kernel source still matches the hash
+    recorded there (at measurement, or after a comment-only edit), else None."""
     import hashlib
     import re
     if row not in _PMC_TRAFFIC:
@@ -509,13 +516,30 @@ def _measured_traffic(row):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    # the prefix of the measured source, plus those of later comment-only edits
     shas = re.findall(r"sha256 prefix (?:at measurement|after a comment-only edit): "
                       r"([0-9a-f]+)", text)
-    m_val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
-    if not (shas and m_val) or not any(sha.startswith(h) for h in shas):
+    if not shas or not any(sha.startswith(h) for h in shas):
         return None
-    return float(m_val.group(1))
+    return text
+
+
+def _measured_traffic(row):
+    import re
+    text = _profile_text(row)
+    m_val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text) if text else None
+    return float(m_val.group(1)) if m_val else None
+
+
+def _measured_issue(row):
+    import re
+    text = _profile_text(row)
+    if not text:
+        return None
+    m_i = re.search(r"VALU issue: .*= (\d+)% of the kernel's cycles", text)
+    m_l = re.search(r"VALU lanes active: .*= (\d+)%", text)
+    if not (m_i and m_l):
+        return None
+    return int(m_i.group(1)) / 100.0, int(m_l.group(1)) / 100.0
 
 
 N_MI_SAMPLE = 400   # vertices of the oracle KSG-MI comparison (brute force on the host)

@@ -54,3 +54,12 @@ def test_recorded_ksg_traffic_matches_the_current_source():
     """The committed counter profile belongs to the committed KSG source."""
     t = bench._measured_traffic("ksg_field")
     assert t is not None and 1.0e10 < t < 1.3e10
+
+
+def test_recorded_ksg_issue_rates():
+    """The dominant kernel's measured VALU issue and lane occupancy come from the
+    same hash-checked counter profile."""
+    issue, lanes = bench._measured_issue("ksg_field")
+    assert 0.5 < issue <= 1.0 and 0.5 < lanes <= 1.0
+    r = bench._roofline_of("ksg_field", {}, {"ksg_field": 48.0}, 1000, 1_760_000)
+    assert r["valu_issue_frac"] == issue and r["valu_lanes_active_frac"] == lanes
