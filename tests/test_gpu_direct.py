@@ -366,3 +366,37 @@ def test_cross_variable_fields():
     mi = ndf.ksg_pairs(e, pairs, k=4, var_a=1, var_b=0).cpu().numpy()
     want = np.array([direct.ksg_field(xh[1][:, a], xh[0][:, b:b + 1], 4)[0] for a, b in pairs])
     assert np.max(np.abs(mi - want)) <= MI_TOL
+
+
+def test_maximum_member_counts():
+    """The largest ensembles the calls accept: KSG at N = 2048 (its limit; the stored
+    orders come from the block sort, counts exact on sampled queries) and Pearson at
+    N = 4096 (its limit); a KSG call beyond 2048 members is refused on the host."""
+    cfg = gen.CONFIGS["tiny"].with_members(2048)
+    e = _ens(cfg)
+    V = cfg.n_vertices
+    x = e.x[0].cpu().numpy()
+    ref = cfg.ref_v
+    sample = np.unique(np.concatenate([gen.random_vertices(V, 40, seed=91), [ref]]))
+    mi, cnt = ndf.ksg_field(e, [ref], k=4, counts=True)
+    s_t = torch.as_tensor(sample, device="cuda")
+    mi = mi[0, s_t].cpu().numpy()
+    cnt = cnt[0, s_t].cpu().numpy()
+    want, wnx, wny = direct.ksg_field(x[:, ref], x[:, sample], 4, counts=True)
+    assert np.array_equal(cnt[:, 0], wnx) and np.array_equal(cnt[:, 1], wny)
+    err = np.max(np.abs(mi - want))
+    _log(f"KSG N=2048 sampled: max|dI| {err:.2e}")
+    assert err <= MI_TOL
+    cfg4 = gen.CONFIGS["tiny"].with_members(4096)
+    x4 = gen.make_ensemble(cfg4, device="cuda")
+    e4 = ndf.Ensemble(x4, cfg4.nx, cfg4.ny, cfg4.nz, orders=False)
+    ndf.ndf_prepare(e4)
+    xh4 = x4[0].cpu().numpy()
+    for prec in (ndf.NDF_PREC_FP32, ndf.NDF_PREC_SPLIT_BF16):
+        got = ndf.pearson_field(e4, [ref, 0], prec=prec).cpu().numpy()
+        for i, r in enumerate([ref, 0]):
+            e_ = np.max(np.abs(got[i] - direct.pearson_field(xh4[:, r], xh4)))
+            _log(f"Pearson N=4096 prec={prec} ref={r}: max|dr| {e_:.2e}")
+            assert e_ <= PEARSON_TOL
+    with pytest.raises(ndf.NdfError):
+        ndf.ksg_field(e4, [ref], k=4)
