@@ -202,8 +202,10 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
 
 // Vertex-major copy xt[v][m] of the member-major ensemble x[m][v] (for the
 // reads of a few scattered vertices' full columns, as interpolation at
-// continuous positions does): 64 x 64 tiles through LDS, 256-byte coalesced
-// reads and writes.
+// continuous positions does): 64 x 64 tiles through LDS.  VEC (V and N multiples
+// of 4): 16-byte loads of four vertices of a member row and 16-byte stores of
+// four members of a vertex row, 16 threads per 256-byte row segment.
+template <bool VEC>
 __global__ __launch_bounds__(256) void transpose_kernel(const float *__restrict__ x, int N,
                                                         int64_t V, float *__restrict__ xt) {
     __shared__ float tile[64][65];
@@ -212,6 +214,33 @@ __global__ __launch_bounds__(256) void transpose_kernel(const float *__restrict_
     float *tv = xt + (int64_t)var * V * N;
     const int64_t v0 = (int64_t)blockIdx.x * 64;
     const int m0 = blockIdx.y * 64;
+    if (VEC) {
+        const int c4 = threadIdx.x & 15, r = threadIdx.x >> 4;  // 16 rows of 16 x 16 B
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + r + 16 * i;
+            const int64_t v = v0 + 4 * c4;
+            f32x4 q = {0.f, 0.f, 0.f, 0.f};
+            if (m < N && v < V)
+                q = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(xv + (int64_t)m * V + v));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tile[r + 16 * i][4 * c4 + e] = q[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int vl = r + 16 * i;
+            const int64_t v = v0 + vl;
+            const int m = m0 + 4 * c4;
+            if (v < V && m < N) {
+                f32x4 q;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) q[e] = tile[4 * c4 + e][vl];
+                *reinterpret_cast<f32x4 *>(tv + v * N + m) = q;
+            }
+        }
+        return;
+    }
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int i = ty; i < 64; i += 4) {
         const int m = m0 + i;
@@ -234,7 +263,12 @@ int launch_prepare(const ndf_ensemble *e, hipStream_t st) {
     if (e->xt) {
         dim3 tg((unsigned)ceil_div(V, 64), (unsigned)ceil_div(e->n_members, 64),
                 (unsigned)e->n_vars);
-        hipLaunchKernelGGL(transpose_kernel, tg, dim3(256), 0, st, e->x, e->n_members, V, e->xt);
+        if (V % 4 == 0 && e->n_members % 4 == 0)
+            hipLaunchKernelGGL(transpose_kernel<true>, tg, dim3(256), 0, st, e->x, e->n_members, V,
+                               e->xt);
+        else
+            hipLaunchKernelGGL(transpose_kernel<false>, tg, dim3(256), 0, st, e->x, e->n_members,
+                               V, e->xt);
     }
     return status_of_launch();
 }
