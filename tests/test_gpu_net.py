@@ -588,3 +588,44 @@ def test_hash_grid_paper_size_sampled():
     g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
     want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
     _check_bf16(g, want, "hash infer paper")
+
+
+def test_field_calls_capture_into_a_graph():
+    """A field call enqueues only kernels (no host copies, no memsets), so it can be
+    captured into a graph: the fused field and the cached-latent field, each replayed
+    three times with eager library work and synchronisations in between, equal the
+    eager results bit for bit on every replay."""
+    cfg, lay, c, P, net = _setup("mid", 1, seed=2345)
+    V = cfg.n_vertices
+    q = _qparams(c, P)
+    ref, other = cfg.ref_v, 17
+    want = _infer_gpu(c, q, [ref], V)
+    cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
+    ndf.ndf_infer_latents(c, q, cache)
+    ws = torch.empty(ndf.infer_ws_bytes(c, 1, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                     device="cuda")
+    want_c = torch.empty((1, V), device="cuda")
+    ndf.ndf_infer_field_cached(c, q, [ref], cache, want_c, ws)
+    out = torch.empty((1, V), device="cuda")
+    out_c = torch.empty((1, V), device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        ndf.ndf_infer_field(c, q, ndf.NDF_PREC_BF16, [ref], out, ws)
+        ndf.ndf_infer_field_cached(c, q, [ref], cache, out_c, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ndf.ndf_infer_field(c, q, ndf.NDF_PREC_BF16, [ref], out, ws)
+        ndf.ndf_infer_field_cached(c, q, [ref], cache, out_c, ws)
+    for i in range(3):
+        out.fill_(float("nan"))
+        out_c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), i
+        assert torch.equal(out_c, want_c), i
+        _infer_gpu(c, q, [other], V)  # eager work between replays
+        torch.cuda.synchronize()
