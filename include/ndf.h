@@ -193,8 +193,9 @@ int ndf_pearson_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, co
  * vertex's.  out float[B]; counts (nullable) int32[B][2][N] in member order; 0
  * for a constant interpolated column, NaN for a non-finite one.  1 <= k <= 8,
  * k < N <= 2048, B <= 2^29.  ws: ndf_workspace_bytes(NDF_OP_KSG_POINTS, ens,
- * NULL, B, 0) bytes (the 2B code columns, 8 B x N per pair, plus small
- * tables).  Reads ens->xt (NDF_E_ARG when NULL).  B = 0 enqueues nothing. */
+ * NULL, B, 0) bytes (the 2B code columns and their sorted member orders,
+ * 12 B x N per pair, plus small tables).  Reads ens->xt (NDF_E_ARG when NULL).
+ * B = 0 enqueues nothing. */
 int ndf_ksg_mi_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, const float *pos,
                       int64_t B, int32_t k, float *out, int32_t *counts, void *ws,
                       size_t ws_bytes, void *stream);

@@ -10,8 +10,8 @@
 // codes.  One wave per column reads its eight corner rows of the vertex-major
 // copy once (16-byte loads when N % 4 == 0) and keeps the column's samples in
 // registers (N <= 2048: 32 per lane) for the min/max and the coding pass.  The
-// KSG pairs kernel then runs on these 2B columns with pairs (b, B + b), sorting
-// each column itself (interpolated columns have no stored orders).
+// sorted-order kernel of ndf_prepare then sorts the 2B columns once each, and the
+// KSG pairs kernel runs on them with pairs (b, B + b) exactly as on vertices.
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -20,6 +20,7 @@ namespace ndf {
 
 int launch_ksg_pairs(const ndf_ensemble *e, int var_a, int var_b, const int64_t *pairs, int64_t B,
                      int k, float *out, int32_t *counts, double *H, hipStream_t st);
+int launch_ksg_orders(const ndf_ensemble *e, hipStream_t st);
 size_t ksg_pairs_ws_bytes(int N);
 
 constexpr int kPtsPerLane = 32;  // 2048 members / 64 lanes
@@ -103,7 +104,8 @@ __global__ __launch_bounds__(256) void points_codes_kernel(
 size_t ksg_points_ws_bytes(int N, int64_t B) {
     return ksg_pairs_ws_bytes(N) + align_up((size_t)B * 2 * sizeof(int64_t), 256) +
            align_up((size_t)B * 2 * sizeof(int32_t), 256) +
-           align_up((size_t)B * 2 * N * sizeof(int32_t), 256);
+           align_up((size_t)B * 2 * N * sizeof(int32_t), 256) +
+           align_up((size_t)B * 2 * N * sizeof(uint16_t), 256);
 }
 
 int launch_ksg_points(const ndf_ensemble *e, int var_a, int var_b, const float *pos, int64_t B,
@@ -119,6 +121,8 @@ int launch_ksg_points(const ndf_ensemble *e, int var_a, int var_b, const float *
     int32_t *flags = (int32_t *)w;
     w += align_up((size_t)B * 2 * sizeof(int32_t), 256);
     int32_t *code = (int32_t *)w;
+    w += align_up((size_t)B * 2 * N * sizeof(int32_t), 256);
+    uint16_t *order = (uint16_t *)w;
     const float *xa = e->xt + (int64_t)var_a * V * N, *xb = e->xt + (int64_t)var_b * V * N;
     const dim3 g((unsigned)ceil_div(2 * B, 4));
     if (N % 4 == 0)
@@ -127,14 +131,17 @@ int launch_ksg_points(const ndf_ensemble *e, int var_a, int var_b, const float *
     else
         hipLaunchKernelGGL(points_codes_kernel<false>, g, dim3(256), 0, st, xa, xb, N, e->nx,
                            e->ny, e->nz, pos, B, code, flags, pairs);
-    // the 2B columns as a one-variable ensemble of 2B "vertices" without stored orders
+    // the 2B columns as a one-variable ensemble of 2B "vertices" with their orders
     ndf_ensemble cols = *e;
+    cols.n_vars = 1;
     cols.nx = (int32_t)(2 * B);
     cols.ny = 1;
     cols.nz = 1;
     cols.code = code;
     cols.flags = flags;
-    cols.order = nullptr;
+    cols.order = order;
+    const int s = launch_ksg_orders(&cols, st);
+    if (s != NDF_OK) return s;
     return launch_ksg_pairs(&cols, 0, 0, pairs, B, k, out, counts, H, st);
 }
 
