@@ -207,21 +207,6 @@ __device__ __forceinline__ void corners_pos32(const int R[3], const float p[3], 
     }
 }
 
-__device__ __forceinline__ void corners_R(const GridGeom &g, const int R[3], int64_t v,
-                                          int64_t idx[8], float w[8]) {
-    int i32[8];
-    corners_R32(g, R, v, i32, w);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) idx[c] = i32[c];
-}
-
-__device__ __forceinline__ void corners(const GridGeom &g, int l, int64_t v, int64_t idx[8],
-                                        float w[8]) {
-    int R[3];
-    level_dims(g, l, R);
-    corners_R(g, R, v, idx, w);
-}
-
 size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B);
 size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec);
 size_t net_qparam_bytes(const ndf_net_config *c, int prec);
