@@ -31,13 +31,8 @@ __device__ __forceinline__ int d_row(int r, int lane) { return 8 * (r >> 2) + 4 
 __device__ __forceinline__ __bf16 f2bf(float f) { return static_cast<__bf16>(f); }
 __device__ __forceinline__ uint16_t f2bf_bits(float f) { return __builtin_bit_cast(uint16_t, f2bf(f)); }
 __device__ __forceinline__ float bf_bits2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ float bf2f(__bf16 b) { return bf_bits2f(__builtin_bit_cast(uint16_t, b)); }
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-__device__ __forceinline__ float wave_sum_f32(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
