@@ -268,10 +268,10 @@ int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t pre
 /* Learned dependence field (Sec. 5): out[r][v] = Phi(p_ref[r], p_v) at every grid
  * vertex v, for ref_v [host] int64[n_ref] (out float[n_ref][V], device).  Every
  * query is encoded, multiplied with the reference latent and decoded in one fused
- * kernel (grid gather + MFMA MLP) per reference.  With a shared encoder
- * (n_enc = 1) that kernel also computes the reference latent (once per
- * workgroup, before its tiles), so a field is a single launch; with two encoders
- * a separate launch computes the reference latents with encoder 0.  The call
+ * kernel (grid gather + MFMA MLP) per reference.  That kernel also computes the
+ * reference latent (once per workgroup, before its tiles; with two encoders from
+ * encoder 0's layers), so a BF16 field is a single launch; FP8 with two encoders
+ * computes the reference latents in a separate launch first.  The call
  * enqueues kernels only (no copies or memsets), so it can be captured into a
  * graph.  ws: ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, n_ref, prec) bytes.
  * NDF_E_ARG for a null pointer, n_ref < 1 or a reference outside [0, V). */

@@ -249,7 +249,11 @@ struct InferArgs {
     GridGeom g;
     int64_t V;
     int64_t fuse_ref;  // field modes: reference vertex whose latent the workgroup computes
-                       // itself (shared encoder), or -1: read it from ref_lat
+                       // itself, or -1: read it from ref_lat
+    // SEP (two encoders): the reference encoder's grids, W1..W3 and b1..b3
+    const uint16_t *rgrid[kL];
+    const bf16x8 *rw[3];
+    const float *rb[3];
 };
 
 // LDS plan (bytes): W1 8K | W2..W5 4 x 32K | b1..b5 5 x 512 | w6 512 | ref latent 512
@@ -397,7 +401,10 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 // MODE 2: latents of vertices 0 .. nq-1 into the query-latent cache (out);
 // MODE 3: field at the continuous positions qpos[n][3] in [-1, 1]^3.
 // HASH: some grid level is a hash table (compiled out when every level is dense).
-template <int MODE, bool HASH>
+// SEP: a field mode of a two-encoder network that computes the reference latent in
+// the prologue: the reference encoder's layers are staged first, then replaced
+// by the query encoder's.
+template <int MODE, bool HASH, bool SEP = false>
 __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const int64_t *__restrict__ qlist,
                                                               int64_t nq,
@@ -412,11 +419,13 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
 
     const int tid = threadIdx.x;
-    for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
+    for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = (SEP ? A.rw[0] : A.w[0])[i];
     const int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
     for (int L = 0; L < nlay; ++L)
-        for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
-    for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
+        for (int i = tid; i < kFragW; i += kInferThreads)
+            s_w[L][i] = (SEP && L < 2 ? A.rw[L + 1] : A.w[L + 1])[i];
+    for (int i = tid; i < 5 * kH; i += kInferThreads)
+        s_b[i / kH][i % kH] = (SEP && i < 3 * kH ? A.rb[i / kH] : A.b[i / kH])[i % kH];
     const bool fuse = kField && A.fuse_ref >= 0;
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
@@ -435,7 +444,8 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             bf16x8 a[8][2], b[8][2];
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb) {
-                const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
+                const uint16_t *const *G = SEP ? A.rgrid : A.grid;
+                const uint16_t *grid = h ? G[2 * kb + 1] : G[2 * kb];
                 int R[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
@@ -466,6 +476,14 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                            lane, h4);
         }
         __syncthreads();
+        if (SEP) {  // the query encoder's layers replace the reference encoder's
+            for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
+            for (int L = 0; L < 2; ++L)
+                for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
+            for (int i = tid; i < 3 * kH; i += kInferThreads)
+                s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
+            __syncthreads();
+        }
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
@@ -1019,6 +1037,24 @@ static InferArgs make_args(const ndf_net_config *c, const QLayout &q, const char
     return a;
 }
 
+// Field arguments of the query encoder (the last one) with the reference vertex
+// whose latent the kernel computes itself; with two encoders the reference
+// encoder's (encoder 0's) grids and layers go along (SEP launches).
+static InferArgs fused_args(const ndf_net_config *c, const QLayout &q, const char *Q,
+                            int64_t ref) {
+    InferArgs a = make_args(c, q, Q, c->n_enc - 1);
+    a.fuse_ref = ref;
+    if (c->n_enc == 2) {
+        const InferArgs r = make_args(c, q, Q, 0);
+        for (int l = 0; l < kL; ++l) a.rgrid[l] = r.grid[l];
+        for (int i = 0; i < 3; ++i) {
+            a.rw[i] = r.w[i];
+            a.rb[i] = r.b[i];
+        }
+    }
+    return a;
+}
+
 static bool any_hashed(const ndf_net_config *c) {
     for (int l = 0; l < kL; ++l)
         if (level_hashed(c, l)) return true;
@@ -1097,19 +1133,25 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
         }
         return status_of_launch();
     }
-    if (prec == NDF_PREC_BF16 && c->n_enc == 1) {
-        // shared encoder: each workgroup computes the reference latent itself
-        InferArgs a = make_args(c, q, Q, 0);
+    if (prec == NDF_PREC_BF16) {
+        // each workgroup computes the reference latent itself (SEP: with encoder 0)
+        const bool sep = c->n_enc == 2;
         for (int r = 0; r < n_ref; ++r) {
-            a.fuse_ref = ref_v[r];
-            if (hash)
-                hipLaunchKernelGGL((infer_kernel<0, true>), dim3(infer_blocks(a.V)),
-                                   dim3(kInferThreads), 0, st, a, nullptr, a.V, nullptr,
-                                   out + (int64_t)r * a.V, nullptr);
+            const InferArgs a = fused_args(c, q, Q, ref_v[r]);
+            const dim3 g(infer_blocks(a.V)), b(kInferThreads);
+            float *o = out + (int64_t)r * a.V;
+            if (sep && hash)
+                hipLaunchKernelGGL((infer_kernel<0, true, true>), g, b, 0, st, a, nullptr, a.V,
+                                   nullptr, o, nullptr);
+            else if (sep)
+                hipLaunchKernelGGL((infer_kernel<0, false, true>), g, b, 0, st, a, nullptr, a.V,
+                                   nullptr, o, nullptr);
+            else if (hash)
+                hipLaunchKernelGGL((infer_kernel<0, true>), g, b, 0, st, a, nullptr, a.V, nullptr,
+                                   o, nullptr);
             else
-                hipLaunchKernelGGL((infer_kernel<0, false>), dim3(infer_blocks(a.V)),
-                                   dim3(kInferThreads), 0, st, a, nullptr, a.V, nullptr,
-                                   out + (int64_t)r * a.V, nullptr);
+                hipLaunchKernelGGL((infer_kernel<0, false>), g, b, 0, st, a, nullptr, a.V, nullptr,
+                                   o, nullptr);
         }
         return status_of_launch();
     }
@@ -1179,9 +1221,8 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
                                        out + (int64_t)r * n, pos);
             }
         } else {
-            InferArgs a = make_args(c, q, Q, 0);
             for (int r = 0; r < n_ref; ++r) {
-                a.fuse_ref = ref_v[r];
+                const InferArgs a = fused_args(c, q, Q, ref_v[r]);
                 if (hash)
                     hipLaunchKernelGGL((infer_kernel<3, true>), dim3(infer_blocks(n)),
                                        dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
