@@ -221,3 +221,29 @@ def test_hash_grid_config():
     huge = [[4096, 4096, 16]] * 4                    # 2^28 cells per level
     assert ndf.ndf_net_param_bytes(ndf.net_config(2048, 2048, 2, huge)) == 0
     assert ndf.ndf_net_param_bytes(ndf.net_config(2048, 2048, 2, huge, log2_hashmap=20)) > 0
+
+
+def test_ksg_points_workspace_and_limits():
+    """Workspace of the KSG targets at positions: the 2B code columns (4 B per member)
+    and their sorted orders (2 B per member) dominate; B is limited to 2^29 and the
+    call refuses more than 2048 members like the other KSG calls."""
+    L = ndf.lib()
+    e = ndf.ndf_ensemble(1000, 250, 352, 20, 1, 0x1000, 0x2000, 0x3000, 0x4000, 0x5000, None,
+                         0x6000)
+    B = 1 << 18
+    ws = ndf.ndf_workspace_bytes(ndf.NDF_OP_KSG_POINTS, type("E", (), {"c": e})(), None, B, 0)
+    cols = 2 * B * 1000
+    assert cols * 6 <= ws <= cols * 6 + 2 * B * 12 + (1 << 16)
+    assert ndf.ndf_workspace_bytes(ndf.NDF_OP_KSG_POINTS, type("E", (), {"c": e})(), None,
+                                   (1 << 29) + 1, 0) == 0
+    E = ctypes.byref(e)
+    FAKE = ctypes.c_void_p(0x7000)
+    assert (L.ndf_ksg_mi_points(E, 0, 0, FAKE, (1 << 29) + 1, 4, FAKE, None, FAKE, 1 << 40, None)
+            == ndf.NDF_E_ARG)
+    assert L.ndf_ksg_mi_points(E, 0, 0, FAKE, 16, 9, FAKE, None, FAKE, 1 << 40, None) == \
+        ndf.NDF_E_UNSUPPORTED
+    assert L.ndf_ksg_mi_points(E, 0, 0, FAKE, 16, 4, FAKE, None, FAKE, 16, None) == \
+        ndf.NDF_E_WORKSPACE
+    e.n_members = 4096
+    assert L.ndf_ksg_mi_points(E, 0, 0, FAKE, 16, 4, FAKE, None, FAKE, 1 << 40, None) == \
+        ndf.NDF_E_UNSUPPORTED
