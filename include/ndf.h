@@ -41,7 +41,9 @@ enum {
     NDF_E_ARG = -1,          /* null pointer, index or size out of range          */
     NDF_E_WORKSPACE = -2,    /* ws NULL or ws_bytes below ndf_workspace_bytes()   */
     NDF_E_HIP = -3,          /* a kernel launch failed                            */
-    NDF_E_UNSUPPORTED = -5   /* valid request outside what the kernels implement  */
+    NDF_E_UNSUPPORTED = -5,  /* valid request outside what the kernels implement  */
+    NDF_E_SCRATCH = -6       /* request larger than the static device scratch of
+                                ndf_ksg_mi_field_noalloc                          */
 };
 
 enum {
@@ -153,6 +155,25 @@ int ndf_pearson_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
 int ndf_ksg_mi_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
                      const int64_t *ref_v, int32_t n_ref, int32_t k, float *out,
                      int32_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* ndf_ksg_mi_field without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * ndf_ksg_mi_field (bit for bit); the workspace lives in a static device array
+ * of ndf_ksg_scratch_bytes() bytes (1 MiB) that the library holds on every
+ * device it runs on until the process ends.  The call allocates nothing; its
+ * first call on a device looks up that device's scratch address (no
+ * allocation).  Requests whose workspace, ndf_workspace_bytes(NDF_OP_KSG_FIELD,
+ * ens, NULL, n_ref, 0), exceeds the scratch return NDF_E_SCRATCH with nothing
+ * enqueued (at N = 1000 members up to 129 references per call; at N = 2048, 62).
+ * All calls on one device share the scratch: calls that overlap in time on one
+ * device (other streams, other host threads) race and must be serialised by the
+ * caller.  Each call writes every scratch byte it reads, so stale contents of
+ * an earlier call do not matter. */
+size_t ndf_ksg_scratch_bytes(void);
+int ndf_ksg_mi_field_noalloc(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
+                             const int64_t *ref_v, int32_t n_ref, int32_t k, float *out,
+                             int32_t *counts, void *stream);
 
 /* Direct estimates for B vertex pairs (training targets of Eq. 3, Sec. 4.3):
  * out[b] = r or MI between e^{var_a}(pairs[b][0]) and e^{var_b}(pairs[b][1]),

@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "net.hpp"
 
@@ -29,6 +31,38 @@ int launch_ksg_points(const ndf_ensemble *e, int var_a, int var_b, const float *
 }  // namespace ndf
 
 using namespace ndf;
+
+// ------------------------------------------- field without allocation ----
+// Device scratch of the no-allocation KSG field call: the workspace of
+// launch_ksg_field (harmonic table, reference list, sorted reference columns)
+// for requests up to kKsgScratchBytes.  Every device holds its own copy for the
+// life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is not a device
+// address in host code).  Calls on one device share the array, so calls that
+// overlap in time on one device race; each call writes every byte it reads.
+namespace {
+
+constexpr size_t kKsgScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kKsgScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // per device, set once by the first call there
+
+int ksg_scratch_ptr(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NDF_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NDF_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NDF_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -90,6 +124,7 @@ const char *ndf_status_string(int s) {
         case NDF_E_WORKSPACE: return "workspace missing or too small";
         case NDF_E_HIP: return "HIP launch failed";
         case NDF_E_UNSUPPORTED: return "unsupported configuration";
+        case NDF_E_SCRATCH: return "request exceeds the library's static device scratch";
         default: return "unknown status";
     }
 }
@@ -153,6 +188,26 @@ int ndf_ksg_mi_field(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
     if (!out || k < 1 || k >= ens->n_members) return NDF_E_ARG;
     if (k > 8 || ens->n_members > kMaxMembersKsg) return NDF_E_UNSUPPORTED;
     if (!ws || ws_bytes < ksg_field_ws_bytes(ens->n_members, n_ref)) return NDF_E_WORKSPACE;
+    return launch_ksg_field(ens, var_ref, var_qry, ref_v, n_ref, k, out, counts, ws, S(stream));
+}
+
+size_t ndf_ksg_scratch_bytes(void) { return kKsgScratchBytes; }
+
+int ndf_ksg_mi_field_noalloc(const ndf_ensemble *ens, int32_t var_ref, int32_t var_qry,
+                             const int64_t *ref_v, int32_t n_ref, int32_t k, float *out,
+                             int32_t *counts, void *stream) {
+    int s = check_ensemble(ens, true);
+    if (s == NDF_OK) s = check_var(ens, var_ref);
+    if (s == NDF_OK) s = check_var(ens, var_qry);
+    if (s == NDF_OK) s = check_refs(ens, ref_v, n_ref);
+    if (s != NDF_OK) return s;
+    if (!out || k < 1 || k >= ens->n_members) return NDF_E_ARG;
+    if (k > 8 || ens->n_members > kMaxMembersKsg) return NDF_E_UNSUPPORTED;
+    if (n_ref > (1 << 20) || ksg_field_ws_bytes(ens->n_members, n_ref) > kKsgScratchBytes)
+        return NDF_E_SCRATCH;
+    void *ws = nullptr;
+    s = ksg_scratch_ptr(&ws);
+    if (s != NDF_OK) return s;
     return launch_ksg_field(ens, var_ref, var_qry, ref_v, n_ref, k, out, counts, ws, S(stream));
 }
 

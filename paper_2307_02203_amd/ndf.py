@@ -17,6 +17,7 @@ import torch
 _LIB_PATH = Path(__file__).resolve().parent / "libndf.so"
 
 NDF_OK, NDF_E_ARG, NDF_E_WORKSPACE, NDF_E_HIP, NDF_E_UNSUPPORTED = 0, -1, -2, -3, -5
+NDF_E_SCRATCH = -6
 NDF_PREC_FP32, NDF_PREC_SPLIT_BF16, NDF_PREC_BF16, NDF_PREC_FP8_E4M3 = 0, 1, 2, 3
 NDF_OP_PEARSON_FIELD, NDF_OP_KSG_FIELD, NDF_OP_TRAIN, NDF_OP_INFER, NDF_OP_KSG_PAIRS = 1, 2, 3, 4, 5
 NDF_OP_KSG_POINTS = 6
@@ -30,7 +31,7 @@ EXPORTED = [
     "ndf_infer_latent_bytes", "ndf_infer_latents", "ndf_infer_field_cached",
     "ndf_net_swap_encoders", "ndf_infer_points", "ndf_infer_field_difference",
     "ndf_pearson_points", "ndf_net_forward_at", "ndf_net_grad_at", "ndf_train_step_at",
-    "ndf_ksg_mi_points",
+    "ndf_ksg_mi_points", "ndf_ksg_scratch_bytes", "ndf_ksg_mi_field_noalloc",
 ]
 
 
@@ -74,6 +75,9 @@ def lib():
                                                  _VP]),
             "ndf_ksg_mi_field": (ctypes.c_int, [E, _I32, _I32, _VP, _I32, _I32, _VP, _VP, _VP,
                                                 _SZ, _VP]),
+            "ndf_ksg_scratch_bytes": (_SZ, []),
+            "ndf_ksg_mi_field_noalloc": (ctypes.c_int, [E, _I32, _I32, _VP, _I32, _I32, _VP, _VP,
+                                                        _VP]),
             "ndf_pearson_pairs": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _VP, _VP]),
             "ndf_pearson_points": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _VP, _VP]),
             "ndf_ksg_mi_points": (ctypes.c_int, [E, _I32, _I32, _VP, _I64, _I32, _VP, _VP, _VP,
@@ -194,6 +198,17 @@ def ndf_ksg_mi_field(ens, var_ref, var_qry, ref_v, k, out, counts, ws, stream=No
     _check(lib().ndf_ksg_mi_field(ctypes.byref(ens.c), var_ref, var_qry, rp, len(refs), k,
                                   _p(out), _p(counts), _p(ws), ws.numel(), _stream(stream)),
            "ndf_ksg_mi_field")
+
+
+def ndf_ksg_scratch_bytes() -> int:
+    return int(lib().ndf_ksg_scratch_bytes())
+
+
+def ndf_ksg_mi_field_noalloc(ens, var_ref, var_qry, ref_v, k, out, counts, stream=None):
+    refs, rp = _host_i64(ref_v)
+    _check(lib().ndf_ksg_mi_field_noalloc(ctypes.byref(ens.c), var_ref, var_qry, rp, len(refs),
+                                          k, _p(out), _p(counts), _stream(stream)),
+           "ndf_ksg_mi_field_noalloc")
 
 
 def ndf_pearson_pairs(ens, var_a, var_b, pairs, out, stream=None):

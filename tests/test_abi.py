@@ -81,6 +81,29 @@ def test_field_calls_validate_before_launch():
     assert L.ndf_pearson_pairs(E, 0, 0, None, 5, FAKE, None) == ndf.NDF_E_ARG
 
 
+def test_noalloc_field_validates_and_bounds_the_scratch():
+    # argument errors and requests beyond the static scratch are refused on the host
+    L = ndf.lib()
+    cap = L.ndf_ksg_scratch_bytes()
+    assert cap == 1 << 20
+    e = _ens(N=1000, nx=250, ny=352, nz=20)
+    E = ctypes.byref(e)
+    n_max = max(n for n in range(1, 400)
+                if L.ndf_workspace_bytes(ndf.NDF_OP_KSG_FIELD, E, None, n, 0) <= cap)
+    assert n_max == 129
+    refs = np.zeros(n_max + 1, dtype=np.int64)
+    rp = refs.ctypes.data_as(ctypes.c_void_p)
+    assert L.ndf_ksg_mi_field_noalloc(E, 0, 0, rp, n_max + 1, 4, FAKE, None, None) == ndf.NDF_E_SCRATCH
+    assert b"scratch" in L.ndf_status_string(ndf.NDF_E_SCRATCH)
+    assert L.ndf_ksg_mi_field_noalloc(E, 0, 0, rp, 1, 0, FAKE, None, None) == ndf.NDF_E_ARG
+    assert L.ndf_ksg_mi_field_noalloc(E, 0, 0, rp, 1, 4, None, None, None) == ndf.NDF_E_ARG
+    assert L.ndf_ksg_mi_field_noalloc(E, 0, 0, rp, 1, 9, FAKE, None, None) == ndf.NDF_E_UNSUPPORTED
+    big = _ens(N=2048, nx=250, ny=352, nz=20)
+    B = ctypes.byref(big)
+    assert max(n for n in range(1, 400)
+               if L.ndf_workspace_bytes(ndf.NDF_OP_KSG_FIELD, B, None, n, 0) <= cap) == 62
+
+
 def test_workspace_sizes_grow_with_references():
     L = ndf.lib()
     e = ctypes.byref(_ens(N=1000, nx=250, ny=352, nz=20))
