@@ -140,12 +140,14 @@ def trilinear(u, R, T=0):
     return idx, w
 
 
-def grid_encode(net, e, u):
+def grid_encode(net, e, u, rnd=None):
     """Concatenated per-level trilinear features h0 (n, L*F)."""
     parts = []
     for l, R in enumerate(net.res):
         idx, w = trilinear(u, R, net.T)
         g = net[("grid", e, l)]
+        if rnd is not None and rnd.grid is not None:
+            g = rnd.grid(g)
         parts.append(np.einsum("nc,ncf->nf", w, g[idx]))
     return np.concatenate(parts, axis=1)
 
@@ -164,12 +166,128 @@ def relu(a):
     return np.maximum(a, 0.0)
 
 
-def encoder(net, e, h0):
-    a1 = h0 @ net[("W1", e)].T + net[("b1", e)]
+# ----------------------------------------------------- operand rounding ----
+# The network oracle is exact FP64.  To measure how much of a reduced-precision
+# implementation's deviation from it is caused by rounding alone, every matrix
+# product below takes an optional `rnd` (an Operands instance) that rounds the
+# two factors as they enter the product and accumulates in FP64.  With
+# rnd=None every product is the plain FP64 product.
+
+def round_bf16(a):
+    """Nearest bfloat16 (8 significand bits, ties to even) of float32(a), as float64."""
+    x = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    b = x.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_split_bf16(a):
+    """hi + lo with hi = bf16(a) and lo = bf16(a - hi): a float32 to about 16 bits."""
+    a32 = np.asarray(a, dtype=np.float32).astype(np.float64)
+    hi = round_bf16(a32)
+    return hi + round_bf16(a32 - hi)
+
+
+E4M3_MAX = 448.0  # largest finite OCP E4M3 value, 1.75 * 2^8
+
+
+def round_e4m3(a):
+    """Nearest OCP E4M3 value (3 significand bits, exponent bias 7, normals down to
+    2^-6, subnormal spacing 2^-9; ties to even), saturated at +-448."""
+    a = np.asarray(a, dtype=np.float64)
+    mag = np.abs(a)
+    _, ex = np.frexp(mag)                       # mag = f * 2^ex, f in [0.5, 1)
+    e = np.maximum(ex - 1, -6)                  # exponent of the leading bit
+    q = np.ldexp(1.0, e - 3)                    # spacing of E4M3 values there
+    r = np.minimum(np.round(mag / q) * q, E4M3_MAX)  # np.round: half to even
+    return np.where(mag == 0, 0.0, np.copysign(r, a))
+
+
+def e4m3_scale_exp(m):
+    """Smallest e with m / 2^e <= 448 for block maxima m >= 0 (2^-126 for m = 0):
+    the power-of-two (E8M0) scale of a microscaling block."""
+    m = np.asarray(m, dtype=np.float64)
+    _, ex = np.frexp(np.where(m > 0, m, 1.0))
+    e = ex - 1 - 8                              # 448 * 2^e >= m for e >= this + 1 at worst
+    e = np.where(m > E4M3_MAX * np.ldexp(1.0, e), e + 1, e)
+    return np.where(m > 0, np.maximum(e, -126), -126)
+
+
+def round_mx_e4m3(a, block=32):
+    """Microscaled E4M3 along the last axis: every run of `block` values shares the
+    power-of-two scale 2^e of e4m3_scale_exp(its max |value|); each value becomes
+    2^e * round_e4m3(value / 2^e)."""
+    a = np.asarray(a, dtype=np.float64)
+    k = a.shape[-1]
+    assert k % block == 0
+    b = a.reshape(a.shape[:-1] + (k // block, block))
+    s = np.ldexp(1.0, e4m3_scale_exp(np.max(np.abs(b), axis=-1)))[..., None]
+    return (round_e4m3(b / s) * s).reshape(a.shape)
+
+
+class Operands:
+    """Rounding of the factors of each product, per layer (1..3 encoder, 4..5
+    decoder): act(x, layer) for activations entering a forward layer (rows are
+    positions, the last axis is the layer's input), weight(W, layer) for W[out][in]
+    (both directions), grad(g) for the gradient operand of the adjoint products,
+    latent(e) for the two latents before their product and grid(table) for the
+    stored grid features (None: unrounded)."""
+
+    def __init__(self, act=None, weight=None, grad=None, latent=None, grid=None):
+        bf = lambda x, layer=0: round_bf16(x)  # noqa: E731
+        self.act = act or bf
+        self.weight = weight or bf
+        self.grad = grad or (lambda x: round_bf16(x))
+        self.latent = latent
+        self.grid = grid
+
+
+def bf16_inference_operands():
+    """The learned-field inference path in BF16: bf16 grid features, every layer's
+    operands bf16 and the latents rounded to bf16 before their product."""
+    return Operands(latent=round_bf16, grid=round_bf16)
+
+
+def fp8_inference_operands():
+    """Inference with the first layer in BF16 and layers 2..5 in microscaled E4M3
+    (blocks of 32 along each product's input axis, for weights per output row),
+    bf16 grid features, latents rounded to bf16 before their product."""
+    def act(x, layer):
+        return round_bf16(x) if layer == 1 else round_mx_e4m3(x)
+
+    def weight(W, layer):
+        return round_bf16(W) if layer == 1 else round_mx_e4m3(W)
+
+    return Operands(act=act, weight=weight, latent=round_bf16, grid=round_bf16)
+
+
+def _lin(x, W, layer, rnd):
+    """x @ W.T with the operands rounded as rnd says for this layer."""
+    if rnd is None:
+        return x @ W.T
+    return rnd.act(x, layer) @ rnd.weight(W, layer).T
+
+
+def _adj(g, W, layer, rnd):
+    """Data adjoint g @ W of a layer."""
+    if rnd is None:
+        return g @ W
+    return rnd.grad(g) @ rnd.weight(W, layer)
+
+
+def _wgrad(g, x, layer, rnd):
+    """Weight gradient g.T @ x of a layer."""
+    if rnd is None:
+        return g.T @ x
+    return rnd.grad(g).T @ rnd.act(x, layer)
+
+
+def encoder(net, e, h0, rnd=None):
+    a1 = _lin(h0, net[("W1", e)], 1, rnd) + net[("b1", e)]
     h1 = relu(a1)
-    a2 = h1 @ net[("W2", e)].T + net[("b2", e)]
+    a2 = _lin(h1, net[("W2", e)], 2, rnd) + net[("b2", e)]
     h2 = relu(a2)
-    lat = h2 @ net[("W3", e)].T + net[("b3", e)]
+    lat = _lin(h2, net[("W3", e)], 3, rnd) + net[("b3", e)]
     return {"h0": h0, "a1": a1, "h1": h1, "a2": a2, "h2": h2, "lat": lat}
 
 
@@ -187,41 +305,44 @@ def domain_to_unit(p):
     return np.where(np.isnan(p), 0.0, u)
 
 
-def forward(net, v1, v2):
+def forward(net, v1, v2, rnd=None):
     """Phi(p1, p2) for vertex pairs; returns (y, cache)."""
     dims = (net.nx, net.ny, net.nz)
-    return forward_unit(net, vertex_positions(v1, dims), vertex_positions(v2, dims))
+    return forward_unit(net, vertex_positions(v1, dims), vertex_positions(v2, dims), rnd)
 
 
-def forward_unit(net, u1, u2):
+def forward_unit(net, u1, u2, rnd=None):
     """Phi(p1, p2) for positions given as u in [0,1]^3 (n,3); returns (y, cache)."""
     ea, eb = _enc_index(net, 0), _enc_index(net, 1)
-    A = encoder(net, ea, grid_encode(net, ea, u1))
-    B = encoder(net, eb, grid_encode(net, eb, u2))
-    m = A["lat"] * B["lat"]
-    a4 = m @ net["W4"].T + net["b4"]
+    A = encoder(net, ea, grid_encode(net, ea, u1, rnd), rnd)
+    B = encoder(net, eb, grid_encode(net, eb, u2, rnd), rnd)
+    if rnd is not None and rnd.latent is not None:
+        m = rnd.latent(A["lat"]) * rnd.latent(B["lat"])
+    else:
+        m = A["lat"] * B["lat"]
+    a4 = _lin(m, net["W4"], 4, rnd) + net["b4"]
     d1 = relu(a4)
-    a5 = d1 @ net["W5"].T + net["b5"]
+    a5 = _lin(d1, net["W5"], 5, rnd) + net["b5"]
     d2 = relu(a5)
     y = d2 @ net["w6"] + net["b6"][0]
     return y, {"u1": u1, "u2": u2, "A": A, "B": B, "m": m, "a4": a4, "d1": d1, "a5": a5,
                "d2": d2, "y": y}
 
 
-def field(net, ref_v, dims_v=None):
+def field(net, ref_v, dims_v=None, rnd=None):
     """phi(p) = Phi(p_ref, p) at every grid vertex (Sec. 5)."""
     V = net.nx * net.ny * net.nz
     v = np.arange(V, dtype=np.int64) if dims_v is None else np.asarray(dims_v)
-    y, _ = forward(net, np.full(v.shape, ref_v, dtype=np.int64), v)
+    y, _ = forward(net, np.full(v.shape, ref_v, dtype=np.int64), v, rnd)
     return y
 
 
-def field_points(net, ref_v, pos):
+def field_points(net, ref_v, pos, rnd=None):
     """Phi(p_ref, p) at continuous positions pos (n,3) in [-1,1]^3, the positions a
     ray marcher samples (Sec. 5)."""
     u2 = domain_to_unit(pos)
     u1 = vertex_positions(np.full(u2.shape[0], ref_v, dtype=np.int64), (net.nx, net.ny, net.nz))
-    y, _ = forward_unit(net, u1, u2)
+    y, _ = forward_unit(net, u1, u2, rnd)
     return y
 
 
@@ -229,44 +350,46 @@ def l1_loss(y, t):
     return float(np.mean(np.abs(y - t)))
 
 
-def _encoder_backward(net, e, c, dlat, grads):
-    grads[("W3", e)] += dlat.T @ c["h2"]
+def _encoder_backward(net, e, c, dlat, grads, rnd=None):
+    grads[("W3", e)] += _wgrad(dlat, c["h2"], 3, rnd)
     grads[("b3", e)] += dlat.sum(0)
-    dh2 = dlat @ net[("W3", e)]
+    dh2 = _adj(dlat, net[("W3", e)], 3, rnd)
     da2 = dh2 * (c["a2"] > 0)
-    grads[("W2", e)] += da2.T @ c["h1"]
+    grads[("W2", e)] += _wgrad(da2, c["h1"], 2, rnd)
     grads[("b2", e)] += da2.sum(0)
-    dh1 = da2 @ net[("W2", e)]
+    dh1 = _adj(da2, net[("W2", e)], 2, rnd)
     da1 = dh1 * (c["a1"] > 0)
-    grads[("W1", e)] += da1.T @ c["h0"]
+    grads[("W1", e)] += _wgrad(da1, c["h0"], 1, rnd)
     grads[("b1", e)] += da1.sum(0)
-    return da1 @ net[("W1", e)]
+    return _adj(da1, net[("W1", e)], 1, rnd)
 
 
-def loss_and_grad(net, v1, v2, t):
+def loss_and_grad(net, v1, v2, t, rnd=None):
     """Mean L1 loss (Eq. 3 with d = L1) and its gradient w.r.t. every parameter."""
     dims = (net.nx, net.ny, net.nz)
-    return loss_and_grad_unit(net, vertex_positions(v1, dims), vertex_positions(v2, dims), t)
+    return loss_and_grad_unit(net, vertex_positions(v1, dims), vertex_positions(v2, dims), t,
+                              rnd)
 
 
-def loss_and_grad_points(net, pos, t):
+def loss_and_grad_points(net, pos, t, rnd=None):
     """loss_and_grad for pairs of continuous positions pos (B,2,3) in [-1,1]^3
     (the training pairs of Sec. 4.3)."""
     pos = np.asarray(pos, dtype=np.float64)
-    return loss_and_grad_unit(net, domain_to_unit(pos[:, 0]), domain_to_unit(pos[:, 1]), t)
+    return loss_and_grad_unit(net, domain_to_unit(pos[:, 0]), domain_to_unit(pos[:, 1]), t,
+                              rnd)
 
 
-def forward_points(net, pos):
+def forward_points(net, pos, rnd=None):
     """Phi(p1, p2) for pairs of continuous positions pos (B,2,3)."""
     pos = np.asarray(pos, dtype=np.float64)
-    y, _ = forward_unit(net, domain_to_unit(pos[:, 0]), domain_to_unit(pos[:, 1]))
+    y, _ = forward_unit(net, domain_to_unit(pos[:, 0]), domain_to_unit(pos[:, 1]), rnd)
     return y
 
 
-def loss_and_grad_unit(net, u1, u2, t):
+def loss_and_grad_unit(net, u1, u2, t, rnd=None):
     """loss_and_grad for positions given as u in [0,1]^3."""
     t = np.asarray(t, dtype=np.float64)
-    y, c = forward_unit(net, u1, u2)
+    y, c = forward_unit(net, u1, u2, rnd)
     n = y.shape[0]
     gy = np.sign(y - t) / n
     g = net.zeros_like()
@@ -274,18 +397,18 @@ def loss_and_grad_unit(net, u1, u2, t):
     g["b6"][:] += gy.sum()
     dd2 = gy[:, None] * net["w6"][None, :]
     da5 = dd2 * (c["a5"] > 0)
-    g["W5"][:] += da5.T @ c["d1"]
+    g["W5"][:] += _wgrad(da5, c["d1"], 5, rnd)
     g["b5"][:] += da5.sum(0)
-    dd1 = da5 @ net["W5"]
+    dd1 = _adj(da5, net["W5"], 5, rnd)
     da4 = dd1 * (c["a4"] > 0)
-    g["W4"][:] += da4.T @ c["m"]
+    g["W4"][:] += _wgrad(da4, c["m"], 4, rnd)
     g["b4"][:] += da4.sum(0)
-    dm = da4 @ net["W4"]
+    dm = _adj(da4, net["W4"], 4, rnd)
     dla = dm * c["B"]["lat"]
     dlb = dm * c["A"]["lat"]
     ea, eb = _enc_index(net, 0), _enc_index(net, 1)
-    dh0a = _encoder_backward(net, ea, c["A"], dla, g)
-    dh0b = _encoder_backward(net, eb, c["B"], dlb, g)
+    dh0a = _encoder_backward(net, ea, c["A"], dla, g, rnd)
+    dh0b = _encoder_backward(net, eb, c["B"], dlb, g, rnd)
     grid_scatter(net, ea, c["u1"], dh0a, g)
     grid_scatter(net, eb, c["u2"], dh0b, g)
     return l1_loss(y, t), g, y

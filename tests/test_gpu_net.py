@@ -2,9 +2,18 @@
 C ABI: initialisation, forward, adjoint (gradients), Adam, fused inference, and
 training convergence.
 
-BF16 MFMA with FP32 accumulate is compared with FP64: forward outputs within
-2e-2 of the output scale, gradients within 3e-2 relative L2 per tensor, the
-hand-built network within its bf16 input rounding; Adam exactly where the
+Bars.  BF16 MFMA operands with FP32 accumulate (and, for a11, microscaled E4M3)
+cannot match FP64 exactly; how far they may deviate is measured on the CPU by the
+same FP64 oracle with its products' operands rounded as the kernels round them
+(oracle.ndf_net.Operands: bf16 weights, activations and gradient operands in
+training; bf16 latents before the merge in inference; E4M3 with power-of-two
+block scales for FP8 layers 2-5; bf16 grid features in inference).  Each GPU
+result must stay within 1.25 times that emulated floor (relative L2 per output
+vector or per gradient tensor, plus 1e-3 for results whose floor is near zero),
+and its largest element error within 2 times the emulated one (plus 1e-3 of the
+RMS); tests/floors.py holds the bars.  A kernel that rounds where the arithmetic
+says it does passes, one with a wrong or missing term does not.  The
+hand-built network is held to its bf16 input rounding; Adam exactly where the
 gradient sign is unambiguous.  Parameters and pairs come from the seeded
 generators; the oracle never sees a value produced by the GPU path.
 """
@@ -24,6 +33,8 @@ pytestmark = pytest.mark.gpu
 
 sys.path.insert(0, __file__.rsplit("/", 1)[0])
 from test_oracle_net import hand_built_params, hand_built_value, DIMS as HB_DIMS, RES as HB_RES  # noqa: E402
+from floors import (BF16_OPS, FP8_OPS, TRAIN_OPS, check_floor as _check_floor,  # noqa: E402
+                    check_grad_floor)
 
 
 def _log(*a):
@@ -40,16 +51,6 @@ def _setup(name, n_enc=1, seed=2320, grid_scale=0.5, bias_scale=0.1):
     return cfg, lay, c, P, net
 
 
-def _check_bf16(got, want, what):
-    """BF16 operands (unit roundoff 2^-9) through six layers whose output is a
-    small difference of larger terms: relative L2 error <= 2e-2 and every
-    element within 0.1 of the output's RMS."""
-    got = np.asarray(got, dtype=np.float64)
-    rms = np.sqrt(np.mean(want ** 2))
-    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
-    mx = np.max(np.abs(got - want))
-    _log(f"{what}: rms={rms:.3g} relL2={rel:.2e} max|d|={mx:.3g}")
-    assert rel <= 2e-2 and mx <= 0.1 * rms
 
 
 def _forward_gpu(c, P, pairs):
@@ -132,19 +133,19 @@ def test_forward_parity(name, n_enc):
     pairs = gen.random_pairs(cfg.n_vertices, 3000, seed=11)
     y = _forward_gpu(c, P, pairs)
     want, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
-    _check_bf16(y, want, f"forward {name} n_enc={n_enc}")
+    emul, _ = nn.forward(net, pairs[:, 0], pairs[:, 1], TRAIN_OPS)
+    _check_floor(y, want, emul, f"forward {name} n_enc={n_enc}")
 
 
 @pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 2)])
 @pytest.mark.parametrize("signs", ["same", "random"])
 def test_gradient_parity(name, n_enc, signs):
-    """Adjoint kernels vs the FP64 adjoint.  With one residual sign for every pair
-    the per-pair gradients add up and each tensor must match to 1e-1 relative L2
-    with cosine >= 0.995 (measured: 2e-2 on coarse levels up to 8e-2 on the finest
-    grid level, whose cells see ~2 rows each; bf16 rounding through five layers).
-    With random signs the batch gradient is a sum with heavy cancellation, which
-    amplifies the bf16 operand rounding (measured 4e-2..1e-1 relative L2); there
-    the direction (cosine >= 0.99) and the norm (within 3 %) must match."""
+    """Adjoint kernels vs the FP64 adjoint, every parameter tensor held to 1.25 times
+    the error of the FP64 adjoint with the kernels' bf16 operand rounding.  With
+    one residual sign for every pair the per-pair gradients add up; with random
+    signs the batch gradient is a sum with heavy cancellation and its floor is
+    near 1e-1 in every tensor (rounding flips ReLU masks; the rounding of the
+    gradient operand itself contributes only a few 1e-3)."""
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2321)
     pairs = gen.random_pairs(cfg.n_vertices, 2048, seed=12)
     y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
@@ -154,24 +155,10 @@ def test_gradient_parity(name, n_enc, signs):
         s = np.where(np.random.default_rng(5).random(len(pairs)) < 0.5, -1.0, 1.0)
     t = y - s            # residual y - t = s: fixed sign, far from the L1 kink
     loss_o, g_o, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    _, g_e, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t, TRAIN_OPS)
     g, loss = _grad_gpu(c, P, pairs, t.astype(np.float32))
     assert abs(loss - loss_o) <= 1e-2 * loss_o
-    for name_t, _shape in lay.tensors():
-        a = lay.view(g, name_t).ravel()
-        b = lay.view(g_o.flat, name_t).ravel()
-        nb = np.linalg.norm(b)
-        if nb == 0:
-            assert np.all(a == 0), name_t
-            continue
-        rel = np.linalg.norm(a - b) / nb
-        cos = float(np.dot(a, b) / (np.linalg.norm(a) * nb))
-        ratio = np.linalg.norm(a) / nb
-        _log(f"grad[{signs}] {name_t}: relL2 {rel:.2e} cos {cos:.5f} norm ratio {ratio:.4f}")
-        if signs == "same":
-            # finest level: ~2 rows per cell, so each cell shows one row's error
-            assert rel <= 1e-1 and cos >= 0.995, name_t
-        else:
-            assert cos >= 0.99 and abs(ratio - 1.0) <= 0.03, name_t
+    check_grad_floor(lay, g, g_o.flat, g_e.flat, f"grad[{signs}] {name} n_enc={n_enc}")
 
 
 def test_train_step_adam_parity():
@@ -214,7 +201,8 @@ def test_infer_field_parity(name, n_enc):
     out = _infer_gpu(c, q, refs, V).cpu().numpy()
     for i, r in enumerate(refs):
         want = nn.field(net, r)
-        _check_bf16(out[i], want, f"infer {name} n_enc={n_enc} ref={r}")
+        _check_floor(out[i], want, nn.field(net, r, rnd=BF16_OPS),
+                     f"infer {name} n_enc={n_enc} ref={r}")
 
 
 @pytest.mark.parametrize("name,n_enc", [("mid", 1), ("mid", 2)])
@@ -283,7 +271,8 @@ def test_infer_paper_size_sampled():
     sample = np.unique(np.concatenate([gen.random_vertices(V, 3000, seed=31), [0, V - 1]]))
     g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
     want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
-    _check_bf16(g, want, "infer paper")
+    emul, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample, BF16_OPS)
+    _check_floor(g, want, emul, "infer paper")
 
 
 def test_training_learns_pearson_field():
@@ -339,10 +328,10 @@ def test_training_learns_pearson_field():
 
 @pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 1), ("mid", 2)])
 def test_infer_field_fp8_parity(name, n_enc):
-    """MXFP8 layers 2..5 (E4M3, 3 mantissa bits: unit roundoff 2^-4) on random
-    weights, whose output is a small difference of O(1) terms: relative L2 error
-    <= 0.2 against the FP64 oracle (measured 0.10..0.14; BF16 of the same packed
-    parameters 0.01).  The trained-network error is checked in the training test."""
+    """FP8 layers 2..5 (E4M3, 3 mantissa bits: unit roundoff 2^-4) on random
+    weights, whose output is a small difference of O(1) terms, held to the FP64
+    oracle with the same E4M3 operand rounding; BF16 of the same packed parameters
+    to its bf16 floor.  The trained-network error is checked in the training test."""
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2326)
     V = cfg.n_vertices
     refs = [cfg.ref_v, 0, V - 1]
@@ -351,11 +340,10 @@ def test_infer_field_fp8_parity(name, n_enc):
     out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16).cpu().numpy()
     for i, r in enumerate(refs):
         want = nn.field(net, r)
-        rel8 = np.linalg.norm(out8[i] - want) / np.linalg.norm(want)
-        rel16 = np.linalg.norm(out16[i] - want) / np.linalg.norm(want)
-        _log(f"fp8 {name} n_enc={n_enc} ref={r}: relL2 fp8 {rel8:.3e} bf16 {rel16:.3e}")
-        assert rel8 <= 0.2
-        assert rel16 <= 2e-2
+        _check_floor(out8[i], want, nn.field(net, r, rnd=FP8_OPS),
+                     f"fp8 {name} n_enc={n_enc} ref={r}")
+        _check_floor(out16[i], want, nn.field(net, r, rnd=BF16_OPS),
+                     f"bf16 of fp8 blob {name} n_enc={n_enc} ref={r}")
 
 
 def test_infer_fp8_paper_size_sampled():
@@ -367,9 +355,8 @@ def test_infer_fp8_paper_size_sampled():
     sample = gen.random_vertices(V, 3000, seed=32)
     g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
     want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
-    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
-    _log(f"fp8 paper: relL2 {rel:.3e}")
-    assert rel <= 0.2
+    emul, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample, FP8_OPS)
+    _check_floor(g, want, emul, "fp8 paper")
 
 
 def test_correlation_volume_matrix_two_variables():
@@ -444,8 +431,8 @@ def test_infer_points_parity(name, n_enc):
     """The learned field at continuous positions, as a ray marcher samples it
     (Sec. 5): uniform positions in the domain, positions outside it (clamped),
     equally spaced samples along rays and the positions of grid vertices, 4517 in
-    all (a ragged last tile).  BF16 against the FP64 oracle to the BF16 bar, FP8
-    to relative L2 0.2; at vertex positions the BF16 values equal the vertex
+    all (a ragged last tile).  BF16 and FP8 against the FP64 oracle, each held to
+    its emulated rounding floor; at vertex positions the BF16 values equal the vertex
     field up to the FP32 rounding of the position (within 2% of the field RMS)."""
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2330)
     V = cfg.n_vertices
@@ -460,11 +447,12 @@ def test_infer_points_parity(name, n_enc):
     out16 = _points_gpu(c, q, refs, pos, ndf.NDF_PREC_BF16)
     out8 = _points_gpu(c, q, refs, pos, ndf.NDF_PREC_FP8_E4M3)
     for i, r in enumerate(refs):
-        want = nn.field_points(net, r, pos.astype(np.float64))
-        _check_bf16(out16[i], want, f"points {name} n_enc={n_enc} ref={r}")
-        rel8 = np.linalg.norm(out8[i] - want) / np.linalg.norm(want)
-        _log(f"points fp8 {name} n_enc={n_enc} ref={r}: relL2 {rel8:.3e}")
-        assert rel8 <= 0.2
+        p64 = pos.astype(np.float64)
+        want = nn.field_points(net, r, p64)
+        _check_floor(out16[i], want, nn.field_points(net, r, p64, BF16_OPS),
+                     f"points {name} n_enc={n_enc} ref={r}")
+        _check_floor(out8[i], want, nn.field_points(net, r, p64, FP8_OPS),
+                     f"points fp8 {name} n_enc={n_enc} ref={r}")
     field = _infer_gpu(c, q, refs, V).cpu().numpy()[:, vs]
     for i in range(len(refs)):
         rms = np.sqrt(np.mean(field[i] ** 2))
@@ -494,14 +482,9 @@ def test_infer_field_difference():
     same = torch.full((V,), float("nan"), device="cuda")
     ndf.ndf_infer_field_difference(c, q, a, a, cache, same, ws)
     assert torch.equal(same, torch.zeros_like(same))
-    fa, fb = nn.field(net, a), nn.field(net, b)
-    want = fa - fb
-    got = out.cpu().numpy().astype(np.float64)
-    scale = max(np.sqrt(np.mean(fa ** 2)), np.sqrt(np.mean(fb ** 2)))
-    err = np.max(np.abs(got - want))
-    _log(f"difference field: max|d| {err:.3g} field rms {scale:.3g}")
-    assert err <= 0.2 * scale
-    assert np.linalg.norm(got - want) <= 2e-2 * (np.linalg.norm(fa) + np.linalg.norm(fb))
+    want = nn.field(net, a) - nn.field(net, b)
+    emul = nn.field(net, a, rnd=BF16_OPS) - nn.field(net, b, rnd=BF16_OPS)
+    _check_floor(out.cpu().numpy(), want, emul, "difference field")
 
 
 # --------------------------------------------------------------- hash grids ----
@@ -524,12 +507,14 @@ def test_hash_grid_forward_and_gradient(n_enc):
     cfg, lay, c, P, net = _setup_hash("mid", n_enc, 10, 2342)
     assert any(lay.cells(l) == 1024 for l in range(4))
     pairs = gen.random_pairs(cfg.n_vertices, 3000, seed=71)
-    _check_bf16(_forward_gpu(c, P, pairs), nn.forward(net, pairs[:, 0], pairs[:, 1])[0],
-                f"hash forward n_enc={n_enc}")
+    _check_floor(_forward_gpu(c, P, pairs), nn.forward(net, pairs[:, 0], pairs[:, 1])[0],
+                 nn.forward(net, pairs[:, 0], pairs[:, 1], TRAIN_OPS)[0],
+                 f"hash forward n_enc={n_enc}")
     pos = gen.random_positions(2 * 2048, seed=72).reshape(2048, 2, 3)
     y = nn.forward_points(net, pos)
     t = y + 1.0
     loss_o, g_o, _ = nn.loss_and_grad_points(net, pos, t)
+    _, g_e, _ = nn.loss_and_grad_points(net, pos, t, TRAIN_OPS)
     g = torch.empty_like(P)
     loss = torch.empty(1, device="cuda")
     ws = torch.empty(ndf.train_ws_bytes(c, len(pos)), dtype=torch.uint8, device="cuda")
@@ -537,14 +522,7 @@ def test_hash_grid_forward_and_gradient(n_enc):
                         torch.as_tensor(t.astype(np.float32), device="cuda"), g, loss, ws)
     g = g.cpu().numpy().astype(np.float64)
     assert abs(loss.item() - loss_o) <= 1e-2 * loss_o
-    for name_t, _shape in lay.tensors():
-        a = lay.view(g, name_t).ravel()
-        b = lay.view(g_o.flat, name_t).ravel()
-        nb = np.linalg.norm(b)
-        rel = np.linalg.norm(a - b) / nb
-        cos = float(np.dot(a, b) / (np.linalg.norm(a) * nb))
-        _log(f"hash grad {name_t}: relL2 {rel:.2e} cos {cos:.5f}")
-        assert rel <= 1e-1 and cos >= 0.995, name_t
+    check_grad_floor(lay, g, g_o.flat, g_e.flat, f"hash grad n_enc={n_enc}")
 
 
 @pytest.mark.parametrize("n_enc", [1, 2])
@@ -560,12 +538,15 @@ def test_hash_grid_inference(n_enc):
     out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
     for i, r in enumerate(refs):
         want = nn.field(net, r)
-        _check_bf16(out16[i].cpu().numpy(), want, f"hash infer n_enc={n_enc} ref={r}")
-        assert np.linalg.norm(out8[i] - want) / np.linalg.norm(want) <= 0.2
+        _check_floor(out16[i].cpu().numpy(), want, nn.field(net, r, rnd=BF16_OPS),
+                     f"hash infer n_enc={n_enc} ref={r}")
+        _check_floor(out8[i], want, nn.field(net, r, rnd=FP8_OPS),
+                     f"hash infer fp8 n_enc={n_enc} ref={r}")
     pos = gen.random_positions(2000, seed=73)
     pts = _points_gpu(c, q, refs[:1], pos, ndf.NDF_PREC_BF16)
-    _check_bf16(pts[0], nn.field_points(net, refs[0], pos.astype(np.float64)),
-                f"hash points n_enc={n_enc}")
+    p64 = pos.astype(np.float64)
+    _check_floor(pts[0], nn.field_points(net, refs[0], p64),
+                 nn.field_points(net, refs[0], p64, BF16_OPS), f"hash points n_enc={n_enc}")
     cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
     ndf.ndf_infer_latents(c, q, cache)
     oc = torch.empty((len(refs), V), device="cuda")
@@ -587,7 +568,8 @@ def test_hash_grid_paper_size_sampled():
     sample = gen.random_vertices(V, 3000, seed=74)
     g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
     want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
-    _check_bf16(g, want, "hash infer paper")
+    emul, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample, BF16_OPS)
+    _check_floor(g, want, emul, "hash infer paper")
 
 
 def test_field_calls_capture_into_a_graph():

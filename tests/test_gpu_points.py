@@ -7,7 +7,7 @@ through the C ABI:
   and the edge cases: a non-finite corner (NaN unless its weight is 0), a
   constant column (r = 0);
 * ndf_net_forward_at / ndf_net_grad_at against the FP64 network at the same
-  positions (the BF16 bars of the vertex-pair tests);
+  positions, held to the emulated bf16 rounding floor (tests/floors.py);
 * ndf_train_step_at on targets from ndf_pearson_points learns the field.
 """
 import dataclasses
@@ -23,6 +23,9 @@ from oracle import points as pt
 from paper_2307_02203_amd import ndf
 
 pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from floors import TRAIN_OPS, check_floor, check_grad_floor  # noqa: E402
 
 PEARSON_TOL = 1e-5
 
@@ -123,23 +126,20 @@ def test_forward_at_parity(name, n_enc):
     ws = torch.empty(ndf.train_ws_bytes(c, len(pos)), dtype=torch.uint8, device="cuda")
     ndf.ndf_net_forward_at(c, P, pos_t, y, ws)
     got = y.cpu().numpy().astype(np.float64)
-    want = nn.forward_points(net, pos)
-    rms = np.sqrt(np.mean(want ** 2))
-    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
-    mx = np.max(np.abs(got - want))
-    _log(f"forward_at {name} n_enc={n_enc}: rms={rms:.3g} relL2={rel:.2e} max|d|={mx:.3g}")
-    assert rel <= 2e-2 and mx <= 0.1 * rms
+    check_floor(got, nn.forward_points(net, pos), nn.forward_points(net, pos, TRAIN_OPS),
+                f"forward_at {name} n_enc={n_enc}")
 
 
 @pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 2)])
 def test_gradient_at_parity(name, n_enc):
-    """The adjoint at continuous positions, one residual sign for every pair (the
-    vertex-pair test's bar: relative L2 <= 1e-1 and cosine >= 0.995 per tensor)."""
+    """The adjoint at continuous positions, one residual sign for every pair, held
+    to the emulated bf16 floor per tensor like the vertex-pair adjoint."""
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2341)
     pos = _pos_pairs(2048, seed=57)
     y = nn.forward_points(net, pos)
     t = y + 1.0
     loss_o, g_o, _ = nn.loss_and_grad_points(net, pos, t)
+    _, g_e, _ = nn.loss_and_grad_points(net, pos, t, TRAIN_OPS)
     pos_t = torch.as_tensor(pos, device="cuda")
     t_t = torch.as_tensor(t.astype(np.float32), device="cuda")
     g = torch.empty_like(P)
@@ -148,17 +148,7 @@ def test_gradient_at_parity(name, n_enc):
     ndf.ndf_net_grad_at(c, P, pos_t, t_t, g, loss, ws)
     g = g.cpu().numpy().astype(np.float64)
     assert abs(loss.item() - loss_o) <= 1e-2 * loss_o
-    for name_t, _shape in lay.tensors():
-        a = lay.view(g, name_t).ravel()
-        b = lay.view(g_o.flat, name_t).ravel()
-        nb = np.linalg.norm(b)
-        if nb == 0:
-            assert np.all(a == 0), name_t
-            continue
-        rel = np.linalg.norm(a - b) / nb
-        cos = float(np.dot(a, b) / (np.linalg.norm(a) * nb))
-        _log(f"grad_at {name_t}: relL2 {rel:.2e} cos {cos:.5f}")
-        assert rel <= 1e-1 and cos >= 0.995, name_t
+    check_grad_floor(lay, g, g_o.flat, g_e.flat, f"grad_at {name} n_enc={n_enc}")
 
 
 def test_training_at_positions_learns():

@@ -346,3 +346,105 @@ def test_large_table_is_the_dense_grid():
     a = nn.Net(flat, DIMS_H, RES_H, 8, 128, 2, 0)
     b = nn.Net(flat, DIMS_H, RES_H, 8, 128, 2, 13)
     np.testing.assert_array_equal(nn.field(a, 17), nn.field(b, 17))
+
+
+# ------------------------------------------------------- operand rounding ----
+def test_round_bf16_matches_library_and_ties_to_even():
+    import torch
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(size=5000) * 10.0 ** rng.integers(-20, 20, 5000),
+                        [0.0, -0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8)]])
+    want = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(nn.round_bf16(x), want)
+    # halfway cases go to the even significand
+    assert nn.round_bf16(1 + 2 ** -8) == 1.0
+    assert nn.round_bf16(1 + 3 * 2 ** -8) == 1 + 2 ** -6
+    hi_lo = nn.round_split_bf16(np.float32(np.pi))
+    assert abs(hi_lo - np.float32(np.pi)) <= 2.0 ** -16 * np.pi
+
+
+def test_round_e4m3_matches_library_on_its_range():
+    import torch
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.uniform(-448, 448, 4000), rng.normal(size=4000) * 2.0 ** -7,
+                        [0.0, 448.0, -448.0, 2 ** -6, 2 ** -9, 2 ** -10, 3 * 2 ** -10, 1.0625,
+                         1.1875, 240.0, 232.0]])
+    want = torch.tensor(x, dtype=torch.float32).to(torch.float8_e4m3fn).double().numpy()
+    np.testing.assert_array_equal(nn.round_e4m3(x), want)
+    assert nn.round_e4m3(1.0625) == 1.0          # tie between 1 and 1.125: even
+    assert nn.round_e4m3(1.1875) == 1.25         # tie between 1.125 and 1.25: even
+    assert nn.round_e4m3(2 ** -10) == 0.0 and nn.round_e4m3(3 * 2 ** -10) == 2 ** -8
+    assert nn.round_e4m3(1000.0) == 448.0        # saturates
+
+
+def test_e4m3_block_scale():
+    # smallest e with m / 2^e <= 448
+    for m, e in [(448.0, 0), (448.0001, 1), (1.75, -8), (1.76, -7), (1.0, -8), (0.0, -126),
+                 (1e-30, -108), (3.0e6, 13)]:
+        got = int(nn.e4m3_scale_exp(m))
+        assert got == e, (m, got, e)
+        if m > 0 and e > -126:
+            assert m / 2.0 ** e <= 448 < m / 2.0 ** (e - 1)
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(7, 64)) * 3.0
+    q = nn.round_mx_e4m3(a)
+    # scaling a block by a power of two scales its rounding exactly
+    np.testing.assert_array_equal(nn.round_mx_e4m3(a * 2.0 ** 9), q * 2.0 ** 9)
+    # values already on a block's E4M3 grid are kept
+    np.testing.assert_array_equal(nn.round_mx_e4m3(q), q)
+    # each block's largest magnitude lands within E4M3's relative spacing 2^-4
+    b = np.abs(a).reshape(7, 2, 32).max(-1)
+    bq = np.abs(q).reshape(7, 2, 32).max(-1)
+    assert np.all(np.abs(bq - b) <= 2.0 ** -4 * b)
+
+
+def test_unrounded_operands_reproduce_the_fp64_oracle():
+    """An Operands whose every rounding is the identity gives the plain FP64 network
+    and gradients bit for bit, so the rounding hooks change no arithmetic."""
+    ident = lambda x, layer=0: np.asarray(x, dtype=np.float64)  # noqa: E731
+    I = nn.Operands(act=ident, weight=ident, grad=ident, latent=None)
+    for n_enc in (1, 2):
+        L = _layout(n_enc=n_enc)
+        net = _net(gen.make_net_params(L, seed=9, grid_scale=0.5, bias_scale=0.1), n_enc=n_enc)
+        V = DIMS[0] * DIMS[1] * DIMS[2]
+        pairs = gen.random_pairs(V, 300, seed=3)
+        t = np.linspace(-1, 1, 300)
+        l0, g0, y0 = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+        l1, g1, y1 = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t, I)
+        assert l0 == l1
+        np.testing.assert_array_equal(y0, y1)
+        np.testing.assert_array_equal(g0.flat, g1.flat)
+
+
+def test_bf16_operand_rounding_floor():
+    """The error that bf16 operands alone cause in the learned field's outputs and
+    gradients (the floor a BF16 MFMA implementation is held to): forward outputs
+    within a few 1e-3 relative L2, gradients within about 1e-1 per tensor.  Rounding
+    the gradient operand contributes little (<= 5e-3); the forward weights and
+    activations dominate, through the ReLU masks they flip and, for gradients that
+    are sums of terms of both signs, through cancellation."""
+    cfg = gen.CONFIGS["tiny"]
+    lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz)
+    net = nn.Net(gen.make_net_params(lay, seed=2321, grid_scale=0.5, bias_scale=0.1),
+                 (cfg.nx, cfg.ny, cfg.nz), lay.res)
+    pairs = gen.random_pairs(cfg.n_vertices, 2048, seed=12)
+    y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    ye, _ = nn.forward(net, pairs[:, 0], pairs[:, 1], nn.Operands())
+    rel_y = np.linalg.norm(ye - y) / np.linalg.norm(y)
+    assert 1e-4 < rel_y < 1e-2
+    s = np.where(np.random.default_rng(5).random(len(pairs)) < 0.5, -1.0, 1.0)
+    t = y - s
+    _, g0, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    _, gb, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t, nn.Operands())
+    ident = lambda x, layer=0: np.asarray(x, dtype=np.float64)  # noqa: E731
+    _, gg, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t,
+                                nn.Operands(act=ident, weight=ident))
+    for name, _shape in lay.tensors():
+        b = lay.view(g0.flat, name)
+        nb = np.linalg.norm(b)
+        if nb == 0:
+            continue
+        rel_all = np.linalg.norm(lay.view(gb.flat, name) - b) / nb
+        rel_g = np.linalg.norm(lay.view(gg.flat, name) - b) / nb
+        assert rel_all < 0.15, name
+        assert rel_g < 5e-3, name
