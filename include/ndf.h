@@ -22,6 +22,12 @@
  *    NDF_E_HIP means a launch failed (hipGetLastError after the launch).
  *  - Vertex index v = i + nx*(j + ny*k); V = nx*ny*nz.
  *  - Calls that share a workspace must not overlap in time.
+ *  - Device-side conditions cannot be returned by a call that only enqueues, so
+ *    the calls that can meet them (ndf_prepare, the training calls) keep a
+ *    device status word: the int32 at the start of their workspace `ws`.  The
+ *    call resets it to NDF_OK first (a kernel, not a memset) and its kernels set
+ *    it to NDF_E_NONFINITE when they meet a non-finite input value or loss; read
+ *    it after the stream has passed the call.
  *
  * Build: libndf.so (hipcc --offload-arch=gfx950).  No function needs a GPU to be
  * looked up; every compute call needs one to run.
@@ -41,6 +47,8 @@ enum {
     NDF_E_ARG = -1,          /* null pointer, index or size out of range          */
     NDF_E_WORKSPACE = -2,    /* ws NULL or ws_bytes below ndf_workspace_bytes()   */
     NDF_E_HIP = -3,          /* a kernel launch failed                            */
+    NDF_E_NONFINITE = -4,    /* device status word only: a non-finite input value
+                                (ndf_prepare) or training loss was met            */
     NDF_E_UNSUPPORTED = -5,  /* valid request outside what the kernels implement  */
     NDF_E_SCRATCH = -6       /* request larger than the static device scratch of
                                 ndf_ksg_mi_field_noalloc                          */
@@ -59,7 +67,8 @@ enum {                       /* `op` of ndf_workspace_bytes                     
     NDF_OP_TRAIN = 3,
     NDF_OP_INFER = 4,
     NDF_OP_KSG_PAIRS = 5,
-    NDF_OP_KSG_POINTS = 6
+    NDF_OP_KSG_POINTS = 6,
+    NDF_OP_PREPARE = 7
 };
 
 enum {                       /* per-vertex flags written by ndf_prepare           */
@@ -130,8 +139,11 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
  * the column min/max, all in IEEE double (0 for a constant column).  When
  * ens->order is non-NULL it also writes each vertex's members sorted by code
  * (ties by member index): the sorted orders the KSG neighbour search walks,
- * built once per ensemble instead of once per (reference, query) pair. */
-int ndf_prepare(const ndf_ensemble *ens, void *stream);
+ * built once per ensemble instead of once per (reference, query) pair.
+ * ws (nullable): ndf_workspace_bytes(NDF_OP_PREPARE, ens, NULL, 0, 0) bytes;
+ * its status word becomes NDF_E_NONFINITE when any member value is NaN or
+ * infinite (those vertices carry NDF_FLAG_NONFINITE).  NULL: no status word. */
+int ndf_prepare(const ndf_ensemble *ens, void *ws, size_t ws_bytes, void *stream);
 
 /* Direct Pearson field (Sec. 3.1, Eq. 1; Table 1 "Pearson"):
  * out[r][v] = r(e^{var_ref}(ref_v[r]), e^{var_qry}(v)) for r < n_ref, v < V.
@@ -239,7 +251,9 @@ int ndf_net_init(const ndf_net_config *cfg, float *params, float *opt_state, uin
  * respect to every parameter (float[param_bytes/4], overwritten), by the
  * library's forward and adjoint kernels (BF16 MFMA, FP32 accumulate, FP32
  * atomic scatter into the grids).  pairs int64[B][2] (device), targets
- * float[B]; loss_out float[1] (device). */
+ * float[B]; loss_out float[1] (device).  The workspace's status word becomes
+ * NDF_E_NONFINITE when the loss is not finite (a NaN or infinite target or
+ * output). */
 int ndf_net_grad(const ndf_net_config *cfg, const float *params, const int64_t *pairs,
                  const float *targets, int64_t B, float *grad_out, float *loss_out,
                  void *ws, size_t ws_bytes, void *stream);
@@ -247,7 +261,9 @@ int ndf_net_grad(const ndf_net_config *cfg, const float *params, const int64_t *
 /* One training step of Eq. 3 (Sec. 4.3): ndf_net_grad followed by Adam
  * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; `step` counts from 1).
  * opt_state holds m then v.  ws needs ndf_workspace_bytes(NDF_OP_TRAIN, .., B, ..)
- * plus the parameter bytes rounded up to 256; the gradient is left there. */
+ * plus the parameter bytes rounded up to 256; the gradient is left there.  A
+ * step whose loss is not finite sets the status word to NDF_E_NONFINITE and
+ * leaves params and opt_state unchanged (the Adam kernel reads the word). */
 int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
                    const int64_t *pairs, const float *targets, int64_t B, float lr,
                    float *loss_out, void *ws, size_t ws_bytes, void *stream);
@@ -278,10 +294,11 @@ int ndf_train_step_at(const ndf_net_config *cfg, float *params, float *opt_state
 int ndf_net_swap_encoders(const ndf_net_config *cfg, const float *params, float *params_out,
                           void *stream);
 
-/* Inference parameters for `prec` (NDF_PREC_BF16 or NDF_PREC_FP8_E4M3) packed
- * from the FP32 parameters: BF16 grids, weights in MFMA operand order, FP32
- * biases; FP8 adds E8M0 scales per output row and block of 32 inputs.  One
- * packed blob serves both precisions. */
+/* Reduced-precision inference parameters (Sec. 5 evaluates the trained network
+ * with 16-bit arithmetic): packed for `prec` (NDF_PREC_BF16 or
+ * NDF_PREC_FP8_E4M3) from the FP32 parameters: BF16 grids, weights in MFMA
+ * operand order, FP32 biases; FP8 adds E8M0 scales per output row and block of
+ * 32 inputs.  One packed blob serves both precisions. */
 size_t ndf_net_qparam_bytes(const ndf_net_config *cfg, int32_t prec);
 int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t prec,
                      void *qparams, void *stream);
@@ -318,10 +335,11 @@ int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const
  * out[v] = Phi(p_a, p_v) - Phi(p_b, p_v) at every grid vertex v, for reference
  * vertices ref_a, ref_b in [0, V).  cache holds the query latents written by
  * ndf_infer_latents for the same qparams; ws needs
- * ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, 2, NDF_PREC_BF16) bytes.  One
- * pass over the cache decodes both fields per
- * tile; the result equals the FP32 difference of the two ndf_infer_field_cached
- * fields bit for bit.  NDF_E_ARG for a null pointer or a vertex out of range. */
+ * ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, 2, NDF_PREC_BF16) bytes.  Two
+ * launches over the cache: the first writes the field of ref_a into out, the
+ * second decodes ref_b and subtracts its field from out in place; the result
+ * equals the FP32 difference of the two ndf_infer_field_cached fields bit for
+ * bit.  NDF_E_ARG for a null pointer or a vertex out of range. */
 int ndf_infer_field_difference(const ndf_net_config *cfg, const void *qparams, int64_t ref_a,
                                int64_t ref_b, const void *cache, float *out, void *ws,
                                size_t ws_bytes, void *stream);

@@ -10,7 +10,7 @@
 #include "net.hpp"
 
 namespace ndf {
-int launch_prepare(const ndf_ensemble *e, hipStream_t st);
+int launch_prepare(const ndf_ensemble *e, int32_t *status, hipStream_t st);
 size_t pearson_ws_bytes(int N, int n_ref, int prec);
 int launch_pearson_field(const ndf_ensemble *e, int var_ref, int var_qry, const int64_t *ref_v,
                          int n_ref, float *out, int prec, void *ws, hipStream_t st);
@@ -124,6 +124,7 @@ const char *ndf_status_string(int s) {
         case NDF_E_WORKSPACE: return "workspace missing or too small";
         case NDF_E_HIP: return "HIP launch failed";
         case NDF_E_UNSUPPORTED: return "unsupported configuration";
+        case NDF_E_NONFINITE: return "non-finite value (input or loss)";
         case NDF_E_SCRATCH: return "request exceeds the library's static device scratch";
         default: return "unknown status";
     }
@@ -148,6 +149,8 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
         case NDF_OP_TRAIN:
             if (check_net_config(net) != NDF_OK || n < 1) return 0;
             return net_train_ws_bytes(net, n);
+        case NDF_OP_PREPARE:
+            return check_ensemble(ens, false) == NDF_OK ? kStatusBytes : 0;
         case NDF_OP_INFER:
             if (check_net_config(net) != NDF_OK || n < 1 || n > (1 << 20)) return 0;
             return net_infer_ws_bytes(net, n, prec);
@@ -155,10 +158,11 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
     }
 }
 
-int ndf_prepare(const ndf_ensemble *ens, void *stream) {
+int ndf_prepare(const ndf_ensemble *ens, void *ws, size_t ws_bytes, void *stream) {
     int s = check_ensemble(ens, true);
     if (s != NDF_OK) return s;
-    s = launch_prepare(ens, S(stream));
+    if (ws && ws_bytes < kStatusBytes) return NDF_E_WORKSPACE;
+    s = launch_prepare(ens, (int32_t *)ws, S(stream));
     if (s == NDF_OK && ens->order) s = launch_ksg_orders(ens, S(stream));
     return s;
 }
@@ -330,7 +334,7 @@ int ndf_train_step(const ndf_net_config *cfg, float *params, float *opt_state, i
     float *grad = (float *)((char *)ws + net_train_ws_bytes(cfg, B));
     s = launch_net_grad(cfg, params, pairs, nullptr, targets, B, grad, loss_out, ws, S(stream));
     if (s != NDF_OK) return s;
-    return launch_adam(cfg, params, opt_state, grad, step, lr, S(stream));
+    return launch_adam(cfg, params, opt_state, grad, step, lr, (const int32_t *)ws, S(stream));
 }
 
 int ndf_train_step_at(const ndf_net_config *cfg, float *params, float *opt_state, int64_t step,
@@ -347,7 +351,7 @@ int ndf_train_step_at(const ndf_net_config *cfg, float *params, float *opt_state
     float *grad = (float *)((char *)ws + net_train_ws_bytes(cfg, B));
     s = launch_net_grad(cfg, params, nullptr, pos, targets, B, grad, loss_out, ws, S(stream));
     if (s != NDF_OK) return s;
-    return launch_adam(cfg, params, opt_state, grad, step, lr, S(stream));
+    return launch_adam(cfg, params, opt_state, grad, step, lr, (const int32_t *)ws, S(stream));
 }
 
 size_t ndf_net_qparam_bytes(const ndf_net_config *cfg, int32_t prec) {

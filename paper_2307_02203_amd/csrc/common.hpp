@@ -69,6 +69,11 @@ __device__ __forceinline__ void data_cell(const float *p, int nx, int ny, int nz
 // would make the host wait for the stream; stream-ordered like any launch.
 int put_refs(const int64_t *ref_v, int n_ref, int64_t *dst, hipStream_t st);
 
+// Bytes at the start of a workspace that hold the int32 device status word
+// (NDF_OK, or NDF_E_NONFINITE once a call has met a non-finite input or loss).
+constexpr size_t kStatusBytes = 256;
+int launch_status_clear(int32_t *status, hipStream_t st);
+
 inline int status_of_launch() { return hipGetLastError() == hipSuccess ? NDF_OK : NDF_E_HIP; }
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

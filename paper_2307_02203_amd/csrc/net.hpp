@@ -221,7 +221,7 @@ int launch_net_grad(const ndf_net_config *c, const float *params, const int64_t 
 int launch_net_forward(const ndf_net_config *c, const float *params, const int64_t *pairs,
                        const float *pos, int64_t B, float *y, void *ws, hipStream_t st);
 int launch_adam(const ndf_net_config *c, float *params, float *opt, const float *grad,
-                int64_t step, float lr, hipStream_t st);
+                int64_t step, float lr, const int32_t *status, hipStream_t st);
 int launch_net_quantize(const ndf_net_config *c, const float *params, int prec, void *q,
                         hipStream_t st);
 int launch_net_swap_encoders(const ndf_net_config *c, const float *in, float *out,

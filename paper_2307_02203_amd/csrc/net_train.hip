@@ -408,8 +408,10 @@ __global__ __launch_bounds__(kThreads) void head_fwd_kernel(
     }
 }
 
+// Mean of the per-block sums; a non-finite loss (a NaN or infinite target or
+// output) sets the call's status word, which stops the optimiser step.
 __global__ void loss_reduce_kernel(const double *__restrict__ partial, int n, int64_t B,
-                                   float *__restrict__ loss) {
+                                   float *__restrict__ loss, int32_t *__restrict__ status) {
     __shared__ double s[64];
     double t = 0.0;
     for (int i = threadIdx.x; i < n; i += 64) t += partial[i];
@@ -418,7 +420,9 @@ __global__ void loss_reduce_kernel(const double *__restrict__ partial, int n, in
     if (threadIdx.x == 0) {
         double a = 0.0;
         for (int i = 0; i < 64; ++i) a += s[i];
-        loss[0] = (float)(a / (double)B);
+        const float l = (float)(a / (double)B);
+        loss[0] = l;
+        if (!isfinite(l)) status[0] = NDF_E_NONFINITE;
     }
 }
 
@@ -450,8 +454,10 @@ __global__ __launch_bounds__(kThreads) void head_bwd_kernel(const float *__restr
 }
 
 __global__ void adam_kernel(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
-                            const float *__restrict__ g, int64_t n, float lr, float c1, float c2) {
+                            const float *__restrict__ g, int64_t n, float lr, float c1, float c2,
+                            const int32_t *__restrict__ status) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    if (status[0] != NDF_OK) return;  // the step's loss was not finite: keep p, m, v
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
@@ -467,6 +473,7 @@ __global__ void adam_kernel(float *__restrict__ p, float *__restrict__ m, float 
 namespace {
 
 struct TrainWS {
+    int32_t *status;
     float *H0, *H1, *H2, *E, *M, *D1, *D2, *y, *gy, *dA, *dB, *dH0;
     double *partial;
     size_t bytes;
@@ -482,6 +489,7 @@ TrainWS carve(void *ws, int64_t B) {
         pos += align_up(n, 256);
         return p;
     };
+    t.status = (int32_t *)take(kStatusBytes);
     t.H0 = (float *)take(R * kK0 * 4);
     t.H1 = (float *)take(R * kH * 4);
     t.H2 = (float *)take(R * kH * 4);
@@ -593,11 +601,13 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
     const NetOffsets o = net_offsets(c);
     const TrainWS t = carve(ws, B);
     const int64_t R = 2 * B;
+    launch_status_clear(t.status, st);
     hipLaunchKernelGGL(fill_kernel, dim3(gs_blocks(o.total)), dim3(kThreads), 0, st, G, o.total,
                        0.f);
     forward(c, o, P, pairs, pos, targets, B, t, st);
     const int nparts = (int)ceil_div(B, kThreads);
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, st, t.partial, nparts, B, loss);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, st, t.partial, nparts, B, loss,
+                       t.status);
     // decoder adjoint
     {
         int64_t hb = ceil_div(B, 2);
@@ -647,12 +657,12 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
 }
 
 int launch_adam(const ndf_net_config *c, float *params, float *opt, const float *grad,
-                int64_t step, float lr, hipStream_t st) {
+                int64_t step, float lr, const int32_t *status, hipStream_t st) {
     const NetOffsets o = net_offsets(c);
     const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
     const double c2 = 1.0 / (1.0 - pow(0.999, (double)step));
     hipLaunchKernelGGL(adam_kernel, dim3(gs_blocks(o.total)), dim3(kThreads), 0, st, params, opt,
-                       opt + o.total, grad, o.total, lr, (float)c1, (float)c2);
+                       opt + o.total, grad, o.total, lr, (float)c1, (float)c2, status);
     return status_of_launch();
 }
 

@@ -29,7 +29,8 @@ constexpr int kPrepThreads = kPrepG * kPrepPh;
 
 __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
     const float *__restrict__ x, int N, int64_t V, double *__restrict__ mean,
-    double *__restrict__ inv_std, int32_t *__restrict__ code, int32_t *__restrict__ flags) {
+    double *__restrict__ inv_std, int32_t *__restrict__ code, int32_t *__restrict__ flags,
+    int32_t *__restrict__ status) {
     const int var = blockIdx.y;
     const float *xv = x + (int64_t)var * N * V;
     const int t = threadIdx.x;
@@ -196,6 +197,8 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(
             inv_std[(int64_t)var * V + v] = (var_pop > 0.0 && !flat[j]) ? 1.0 / sqrt(var_pop) : 0.0;
             flags[(int64_t)var * V + v] =
                 (bad[j] ? NDF_FLAG_NONFINITE : 0) | (flat[j] ? NDF_FLAG_CONSTANT : 0);
+            // every writer stores the same value, so the unordered stores agree
+            if (bad[j] && status) *status = NDF_E_NONFINITE;
         }
     }
 }
@@ -255,11 +258,19 @@ __global__ __launch_bounds__(256) void transpose_kernel(const float *__restrict_
     }
 }
 
-int launch_prepare(const ndf_ensemble *e, hipStream_t st) {
+__global__ void status_clear_kernel(int32_t *status) { *status = NDF_OK; }
+
+int launch_status_clear(int32_t *status, hipStream_t st) {
+    hipLaunchKernelGGL(status_clear_kernel, dim3(1), dim3(1), 0, st, status);
+    return status_of_launch();
+}
+
+int launch_prepare(const ndf_ensemble *e, int32_t *status, hipStream_t st) {
     const int64_t V = (int64_t)e->nx * e->ny * e->nz;
+    if (status) launch_status_clear(status, st);
     dim3 grid((unsigned)ceil_div(V, kPrepV), (unsigned)e->n_vars);
     hipLaunchKernelGGL(prepare_kernel, grid, dim3(kPrepThreads), 0, st, e->x, e->n_members, V,
-                       e->mean, e->inv_std, e->code, e->flags);
+                       e->mean, e->inv_std, e->code, e->flags, status);
     if (e->xt) {
         dim3 tg((unsigned)ceil_div(V, 64), (unsigned)ceil_div(e->n_members, 64),
                 (unsigned)e->n_vars);

@@ -17,10 +17,10 @@ import torch
 _LIB_PATH = Path(__file__).resolve().parent / "libndf.so"
 
 NDF_OK, NDF_E_ARG, NDF_E_WORKSPACE, NDF_E_HIP, NDF_E_UNSUPPORTED = 0, -1, -2, -3, -5
-NDF_E_SCRATCH = -6
+NDF_E_NONFINITE, NDF_E_SCRATCH = -4, -6
 NDF_PREC_FP32, NDF_PREC_SPLIT_BF16, NDF_PREC_BF16, NDF_PREC_FP8_E4M3 = 0, 1, 2, 3
 NDF_OP_PEARSON_FIELD, NDF_OP_KSG_FIELD, NDF_OP_TRAIN, NDF_OP_INFER, NDF_OP_KSG_PAIRS = 1, 2, 3, 4, 5
-NDF_OP_KSG_POINTS = 6
+NDF_OP_KSG_POINTS, NDF_OP_PREPARE = 6, 7
 NDF_FLAG_NONFINITE, NDF_FLAG_CONSTANT = 1, 2
 
 EXPORTED = [
@@ -70,7 +70,7 @@ def lib():
         sig = {
             "ndf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "ndf_workspace_bytes": (_SZ, [_I32, E, C, _I64, _I32]),
-            "ndf_prepare": (ctypes.c_int, [E, _VP]),
+            "ndf_prepare": (ctypes.c_int, [E, _VP, _SZ, _VP]),
             "ndf_pearson_field": (ctypes.c_int, [E, _I32, _I32, _VP, _I32, _VP, _I32, _VP, _SZ,
                                                  _VP]),
             "ndf_ksg_mi_field": (ctypes.c_int, [E, _I32, _I32, _VP, _I32, _I32, _VP, _VP, _VP,
@@ -182,8 +182,15 @@ def ndf_workspace_bytes(op, ens=None, net=None, n=1, prec=0) -> int:
     return int(lib().ndf_workspace_bytes(op, e, c, int(n), int(prec)))
 
 
-def ndf_prepare(ens: Ensemble, stream=None):
-    _check(lib().ndf_prepare(ctypes.byref(ens.c), _stream(stream)), "ndf_prepare")
+def ndf_prepare(ens: Ensemble, ws=None, stream=None):
+    """ws (optional uint8 device tensor): receives the device status word."""
+    n = 0 if ws is None else ws.numel()
+    _check(lib().ndf_prepare(ctypes.byref(ens.c), _p(ws), n, _stream(stream)), "ndf_prepare")
+
+
+def status_word(ws) -> int:
+    """The device status word at the start of a call's workspace (after a sync)."""
+    return int(ws[:4].view(torch.int32).item())
 
 
 def ndf_pearson_field(ens, var_ref, var_qry, ref_v, out, prec, ws, stream=None):

@@ -42,8 +42,14 @@ def _ens(N=64, nx=16, ny=16, nz=8, n_vars=1, stats=True):
 def test_prepare_rejects_bad_shapes():
     L = ndf.lib()
     for e in (_ens(N=1), _ens(nx=1), _ens(n_vars=0), _ens(stats=False), _ens(N=5000)):
-        assert L.ndf_prepare(ctypes.byref(e), None) == ndf.NDF_E_ARG
-    assert L.ndf_prepare(None, None) == ndf.NDF_E_ARG
+        assert L.ndf_prepare(ctypes.byref(e), None, 0, None) == ndf.NDF_E_ARG
+    assert L.ndf_prepare(None, None, 0, None) == ndf.NDF_E_ARG
+    # the status word needs its workspace bytes
+    e = _ens()
+    need = L.ndf_workspace_bytes(ndf.NDF_OP_PREPARE, ctypes.byref(e), None, 0, 0)
+    assert need == 256
+    assert L.ndf_prepare(ctypes.byref(e), FAKE, need - 1, None) == ndf.NDF_E_WORKSPACE
+    assert b"non-finite" in L.ndf_status_string(ndf.NDF_E_NONFINITE)
 
 
 def test_field_calls_validate_before_launch():

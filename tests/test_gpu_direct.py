@@ -77,7 +77,11 @@ def test_prepare_flags_constant_and_nonfinite():
     x[0, :, 7] = 2.5                     # constant column
     x[0, 3, 9] = float("nan")            # non-finite sample
     e = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz)
-    ndf.ndf_prepare(e)
+    ws = torch.full((ndf.ndf_workspace_bytes(ndf.NDF_OP_PREPARE, e),), 0x55, dtype=torch.uint8,
+                    device="cuda")
+    ndf.ndf_prepare(e, ws)
+    torch.cuda.synchronize()
+    assert ndf.status_word(ws) == ndf.NDF_E_NONFINITE     # the device status word
     f = e.flags[0].cpu().numpy()
     assert f[7] == ndf.NDF_FLAG_CONSTANT and f[9] & ndf.NDF_FLAG_NONFINITE
     assert np.sum(f != 0) == 2
@@ -90,6 +94,11 @@ def test_prepare_flags_constant_and_nonfinite():
     assert math.isnan(r[9]) and math.isnan(r7[9])
     mi = ndf.ksg_field(e, [1160])[0].cpu().numpy()
     assert mi[7] == 0.0 and math.isnan(mi[9])
+    # a finite ensemble (a constant column is finite) leaves the word at NDF_OK
+    x[0, 3, 9] = 1.0
+    ndf.ndf_prepare(e, ws)
+    torch.cuda.synchronize()
+    assert ndf.status_word(ws) == ndf.NDF_OK
 
 
 @pytest.mark.parametrize("name", ["tiny", "mid"])

@@ -192,6 +192,39 @@ def test_train_step_adam_parity():
     np.testing.assert_allclose(m[strong], 0.1 * g_o.flat[strong], rtol=5e-2, atol=0)
 
 
+def test_nonfinite_loss_sets_status_and_skips_the_step():
+    """A NaN target makes the loss non-finite: the workspace's status word becomes
+    NDF_E_NONFINITE and Adam leaves parameters and moments as they were; the next
+    step with finite targets clears the word and updates them."""
+    cfg, lay, c, P, net = _setup("tiny", 1, seed=2329)
+    B = 512
+    pairs = torch.as_tensor(gen.random_pairs(cfg.n_vertices, B, seed=14), device="cuda")
+    t = torch.zeros(B, device="cuda")
+    t[17] = float("nan")
+    opt = torch.zeros(2 * P.numel(), device="cuda")
+    ws = torch.empty(ndf.train_ws_bytes(c, B) + P.numel() * 4 + 256, dtype=torch.uint8,
+                     device="cuda")
+    loss = torch.empty(1, device="cuda")
+    P0 = P.clone()
+    ndf.ndf_train_step(c, P, opt, 1, pairs, t, 1e-3, loss, ws)
+    torch.cuda.synchronize()
+    assert ndf.status_word(ws) == ndf.NDF_E_NONFINITE
+    assert math.isnan(loss.item())
+    assert torch.equal(P, P0) and torch.all(opt == 0)
+    t[17] = 0.0
+    ndf.ndf_train_step(c, P, opt, 1, pairs, t, 1e-3, loss, ws)
+    torch.cuda.synchronize()
+    assert ndf.status_word(ws) == ndf.NDF_OK
+    assert math.isfinite(loss.item()) and not torch.equal(P, P0)
+    # the gradient call reports through its own workspace too
+    t[3] = float("inf")
+    g = torch.empty_like(P)
+    wsg = torch.empty(ndf.train_ws_bytes(c, B), dtype=torch.uint8, device="cuda")
+    ndf.ndf_net_grad(c, P, pairs, t, g, loss, wsg)
+    torch.cuda.synchronize()
+    assert ndf.status_word(wsg) == ndf.NDF_E_NONFINITE
+
+
 @pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 1), ("mid", 2)])
 def test_infer_field_parity(name, n_enc):
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2323)
