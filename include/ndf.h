@@ -68,7 +68,8 @@ enum {                       /* `op` of ndf_workspace_bytes                     
     NDF_OP_INFER = 4,
     NDF_OP_KSG_PAIRS = 5,
     NDF_OP_KSG_POINTS = 6,
-    NDF_OP_PREPARE = 7
+    NDF_OP_PREPARE = 7,
+    NDF_OP_INFER_CACHED = 8  /* ndf_infer_field_cached, ndf_infer_field_difference */
 };
 
 enum {                       /* per-vertex flags written by ndf_prepare           */
@@ -304,15 +305,21 @@ int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t pre
                      void *qparams, void *stream);
 
 /* Learned dependence field (Sec. 5): out[r][v] = Phi(p_ref[r], p_v) at every grid
- * vertex v, for ref_v [host] int64[n_ref] (out float[n_ref][V], device).  Every
- * query is encoded, multiplied with the reference latent and decoded in one fused
- * kernel (grid gather + MFMA MLP) per reference.  That kernel also computes the
+ * vertex v, for ref_v [host] int64[n_ref] (out float[n_ref][V], device).  One
+ * reference: every query is encoded, multiplied with the reference latent and
+ * decoded in one fused kernel (grid gather + MFMA MLP), which also computes the
  * reference latent (once per workgroup, before its tiles; with two encoders from
  * encoder 0's layers), so a BF16 field is a single launch; FP8 with two encoders
- * computes the reference latents in a separate launch first.  The call
- * enqueues kernels only (no copies or memsets), so it can be captured into a
- * graph.  ws: ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, n_ref, prec) bytes.
- * NDF_E_ARG for a null pointer, n_ref < 1 or a reference outside [0, V). */
+ * computes the reference latents in a separate launch first.  BF16 with
+ * n_ref >= 2: the query latents of all vertices are computed once into the
+ * workspace (ndf_infer_latents) and every launch then decodes up to 32
+ * references per read of them (ndf_infer_field_cached); the fields are the
+ * single-reference fields bit for bit.  FP8 runs one fused pass per reference.
+ * The call enqueues kernels only (no copies or memsets), so it can be captured
+ * into a graph.  ws: ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, n_ref, prec)
+ * bytes (BF16, n_ref >= 2: includes ndf_infer_latent_bytes(cfg) for the query
+ * latents).  NDF_E_ARG for a null pointer, n_ref < 1 or a reference outside
+ * [0, V). */
 int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec,
                     const int64_t *ref_v, int32_t n_ref, float *out, void *ws,
                     size_t ws_bytes, void *stream);
@@ -323,8 +330,10 @@ int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec
  * encoder for every grid vertex into `cache` (device, ndf_infer_latent_bytes
  * bytes, caller-owned; the fused kernel's register order, 256 bytes per
  * vertex); ndf_infer_field_cached then runs only the merge and the decoder per
- * reference and gives the same values as ndf_infer_field with NDF_PREC_BF16,
- * bit for bit.  ws as for ndf_infer_field (BF16). */
+ * reference, up to 32 references per launch, each launch reading every cached
+ * latent once, and gives the same values as ndf_infer_field with NDF_PREC_BF16,
+ * bit for bit.  ws: ndf_workspace_bytes(NDF_OP_INFER_CACHED, NULL, cfg, n_ref,
+ * NDF_PREC_BF16) bytes (the reference latents). */
 size_t ndf_infer_latent_bytes(const ndf_net_config *cfg);
 int ndf_infer_latents(const ndf_net_config *cfg, const void *qparams, void *cache, void *stream);
 int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const int64_t *ref_v,
@@ -335,11 +344,10 @@ int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const
  * out[v] = Phi(p_a, p_v) - Phi(p_b, p_v) at every grid vertex v, for reference
  * vertices ref_a, ref_b in [0, V).  cache holds the query latents written by
  * ndf_infer_latents for the same qparams; ws needs
- * ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, 2, NDF_PREC_BF16) bytes.  Two
- * launches over the cache: the first writes the field of ref_a into out, the
- * second decodes ref_b and subtracts its field from out in place; the result
- * equals the FP32 difference of the two ndf_infer_field_cached fields bit for
- * bit.  NDF_E_ARG for a null pointer or a vertex out of range. */
+ * ndf_workspace_bytes(NDF_OP_INFER_CACHED, NULL, cfg, 2, NDF_PREC_BF16) bytes.
+ * One launch reads each cached latent once and decodes both fields from it;
+ * the result equals the FP32 difference of the two ndf_infer_field_cached
+ * fields bit for bit.  NDF_E_ARG for a null pointer or a vertex out of range. */
 int ndf_infer_field_difference(const ndf_net_config *cfg, const void *qparams, int64_t ref_a,
                                int64_t ref_b, const void *cache, float *out, void *ws,
                                size_t ws_bytes, void *stream);

@@ -154,6 +154,9 @@ size_t ndf_workspace_bytes(int32_t op, const ndf_ensemble *ens, const ndf_net_co
         case NDF_OP_INFER:
             if (check_net_config(net) != NDF_OK || n < 1 || n > (1 << 20)) return 0;
             return net_infer_ws_bytes(net, n, prec);
+        case NDF_OP_INFER_CACHED:
+            if (check_net_config(net) != NDF_OK || n < 1 || n > (1 << 20)) return 0;
+            return net_infer_lat_ws_bytes(n);
         default: return 0;
     }
 }
@@ -411,7 +414,7 @@ int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     for (int r = 0; r < n_ref; ++r)
         if (ref_v[r] < 0 || ref_v[r] >= V) return NDF_E_ARG;
-    if (!ws || ws_bytes < net_infer_ws_bytes(cfg, n_ref, NDF_PREC_BF16)) return NDF_E_WORKSPACE;
+    if (!ws || ws_bytes < net_infer_lat_ws_bytes(n_ref)) return NDF_E_WORKSPACE;
     return launch_infer_field_cached(cfg, qparams, ref_v, n_ref, cache, out, ws, S(stream));
 }
 
@@ -438,7 +441,7 @@ int ndf_infer_field_difference(const ndf_net_config *cfg, const void *qparams, i
     if (!qparams || !cache || !out) return NDF_E_ARG;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     if (ref_a < 0 || ref_a >= V || ref_b < 0 || ref_b >= V) return NDF_E_ARG;
-    if (!ws || ws_bytes < net_infer_ws_bytes(cfg, 2, NDF_PREC_BF16)) return NDF_E_WORKSPACE;
+    if (!ws || ws_bytes < net_infer_lat_ws_bytes(2)) return NDF_E_WORKSPACE;
     return launch_infer_difference(cfg, qparams, ref_a, ref_b, cache, out, ws, S(stream));
 }
 

@@ -209,6 +209,7 @@ __device__ __forceinline__ void corners_pos32(const int R[3], const float p[3], 
 
 size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B);
 size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec);
+size_t net_infer_lat_ws_bytes(int64_t n_ref);
 size_t net_qparam_bytes(const ndf_net_config *c, int prec);
 
 int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t seed,

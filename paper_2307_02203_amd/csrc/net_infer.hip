@@ -88,11 +88,21 @@ size_t net_qparam_bytes(const ndf_net_config *c, int prec) {
     return (size_t)qlayout(c).total;
 }
 
-size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec) {
-    (void)c;
-    (void)prec;
+// Workspace of the calls that decode from given or cached query latents: the
+// reference latents [n_ref][128] FP32 and the reference list.
+size_t net_infer_lat_ws_bytes(int64_t n_ref) {
     return align_up((size_t)n_ref * kH * sizeof(float), 256) +
            align_up((size_t)n_ref * sizeof(int64_t), 256);
+}
+
+size_t net_latent_cache_bytes(const ndf_net_config *c);
+
+// ndf_infer_field: a BF16 call with several references also holds the query
+// latents of every vertex (they are computed once and decoded per reference).
+size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec) {
+    size_t b = net_infer_lat_ws_bytes(n_ref);
+    if (prec == NDF_PREC_BF16 && n_ref >= 2) b += align_up(net_latent_cache_bytes(c), 256);
+    return b;
 }
 
 // ----------------------------------------------------------- quantize ----
@@ -920,30 +930,40 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     }
 }
 
-// The field from cached query latents: per 64-vertex tile, 16 loads of the bf16
-// latents, the product with the reference latent (the same packed arithmetic as
-// the uncached kernel, so both give the same bits), then layers 4, 5 and w6.
-// Only W4 and W5 (64 KB) live in LDS.  SUB: subtract the field from out instead
-// of storing it (the difference of two fields, Sec. 6.4, in two launches; each
-// lane reads back only what it stored itself).
-template <bool SUB>
+// Fields from cached query latents, several references per pass: per 64-vertex
+// tile the wave loads the tile's bf16 latents once (16 loads, kept in registers),
+// then for each reference of the launch forms the product with that reference's
+// latent (the same packed arithmetic as the uncached kernel, so both give the
+// same bits) and runs layers 4, 5 and w6.  A launch decodes up to kMultiRefs
+// references; the cache is read once per launch instead of once per field.
+// Only W4, W5 (64 KB) and the launch's reference latents live in LDS.
+// DIFF: two references, out[v] = Phi(ref 0, v) - Phi(ref 1, v) (the difference
+// of two fields, Sec. 6.4), both decoded from one read of the tile.
+constexpr int kMultiRefs = 16;
+constexpr int kLatLds = 5;  // k-blocks of the tile latents held in LDS
+
+template <bool DIFF>
 __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A,
                                                                       const u32x4 *__restrict__ cache,
                                                                       int64_t nq,
                                                                       const float *__restrict__ ref_lat,
-                                                                      float *__restrict__ out) {
+                                                                      int n_ref,
+                                                                      float *__restrict__ out,
+                                                                      int64_t ld_out) {
     __shared__ bf16x8 s_w[2][kFragW];
     __shared__ __attribute__((aligned(16))) float s_b[2][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
-    __shared__ __attribute__((aligned(16))) float s_ref[kH];
+    __shared__ __attribute__((aligned(16))) float s_ref[kMultiRefs][kH];
+    // k-blocks 0..kLatLds-1 of each wave's tile latents (the others stay in
+    // registers: all eight plus layer 4's 128 accumulators would not fit in 256
+    // VGPRs)
+    __shared__ u32x4 s_lat[kInferWaves][kLatLds][2][64];
     const int tid = threadIdx.x;
     for (int L = 0; L < 2; ++L)
         for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 3][i];
     for (int i = tid; i < 2 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[3 + i / kH][i % kH];
-    for (int i = tid; i < kH; i += kInferThreads) {
-        s_w6[i] = A.w6[i];
-        s_ref[i] = ref_lat[i];
-    }
+    for (int i = tid; i < kH; i += kInferThreads) s_w6[i] = A.w6[i];
+    for (int i = tid; i < n_ref * kH; i += kInferThreads) s_ref[i / kH][i % kH] = ref_lat[i];
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
@@ -957,36 +977,95 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
         bool ok[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) ok[q] = row0 + q * 32 + jl < nq;
-        const float *ref_h = s_ref + h4;
-        bf16x8 a[8][2], b[8][2];
+        // each lane writes and later reads only its own LDS entries (in order
+        // within the wave), so no barrier is needed
+        u32x4 lat[8 - kLatLds][2];
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const u32x4 lat = __builtin_nontemporal_load(cache + cache_chunk(tile, kb, q, lane));
-                // k-block kb = 2 ob + s holds rows r = 8 s + 2 e2, r + 1 of output block ob
-                const int ob = kb >> 1, sb = kb & 1;
-                u32x4 t;
-#pragma unroll
-                for (int e2 = 0; e2 < 4; ++e2) {
-                    const int r = 8 * sb + 2 * e2;
-                    const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
-                    const f32x2 rv = *reinterpret_cast<const f32x2 *>(ref_h + ic);
-                    t[e2] = pack_bf16x2(bf_lo(lat[e2]) * rv[0], bf_hi(lat[e2]) * rv[1]);
-                }
-                b[kb][q] = __builtin_bit_cast(bf16x8, t);
-            }
-        float part[2] = {0.f, 0.f};
-        dense_layer<8, LAY_RELU>(s_w[0], s_b[0], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
-        dense_layer<8, LAY_HEAD>(s_w[1], s_b[1], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
-            if (h == 0 && ok[q]) {
-                if (SUB)
-                    out[row0 + q * 32 + jl] -= y;
+                const u32x4 v = __builtin_nontemporal_load(cache + cache_chunk(tile, kb, q, lane));
+                if (kb < kLatLds)
+                    s_lat[wave][kb][q][lane] = v;
                 else
-                    out[row0 + q * 32 + jl] = y;
+                    lat[kb - kLatLds][q] = v;
+            }
+        float y0[2] = {0.f, 0.f};
+#pragma unroll 1
+        for (int r = 0; r < n_ref; ++r) {
+            // opaque per reference, so the LDS reads of weights and biases stay
+            // inside the loop instead of being hoisted out of it into registers
+            asm volatile("" : "+v"(h4));
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const float *ref_h = &s_ref[r][0] + h4;
+            // layer 4 with the k-blocks outermost, so each product operand is
+            // formed once and used by all four output blocks (each accumulator
+            // still sums its k-blocks in order: the bits of dense_layer)
+            f32x16 acc[4][2];
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4 bv = *reinterpret_cast<const f32x4 *>(&s_b[0][0] + h4 + 32 * ob + 8 * g);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[ob][0][4 * g + i] = acc[ob][1][4 * g + i] = bv[i];
+                }
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                // k-block kb = 2 ob + s holds rows r = 8 s + 2 e2, r + 1 of output block ob
+                const int obk = kb >> 1, sb = kb & 1;
+                bf16x8 bq[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const u32x4 lv = kb < kLatLds ? s_lat[wave][kb][q][ln] : lat[kb - kLatLds][q];
+                    u32x4 t;
+#pragma unroll
+                    for (int e2 = 0; e2 < 4; ++e2) {
+                        const int rr = 8 * sb + 2 * e2;
+                        const int ic = 32 * obk + 8 * (rr >> 2) + (rr & 3);
+                        const f32x2 rv = *reinterpret_cast<const f32x2 *>(ref_h + ic);
+                        t[e2] = pack_bf16x2(bf_lo(lv[e2]) * rv[0], bf_hi(lv[e2]) * rv[1]);
+                    }
+                    bq[q] = __builtin_bit_cast(bf16x8, t);
+                }
+#pragma unroll
+                for (int ob = 0; ob < 4; ++ob) {
+                    const bf16x8 w = s_w[0][(ob * 8 + kb) * 64 + ln];
+                    acc[ob][0] = mfma32(w, bq[0], acc[ob][0]);
+                    acc[ob][1] = mfma32(w, bq[1], acc[ob][1]);
+                }
+                // keep each k-block's weight reads with its MFMAs (128 accumulators
+                // and 64 cached-latent registers are live here)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            bf16x8 a[8][2], b[8][2];
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+                for (int sb = 0; sb < 2; ++sb) {
+                    u32x4 t0, t1;
+#pragma unroll
+                    for (int e2 = 0; e2 < 4; ++e2) {
+                        const int rr = 8 * sb + 2 * e2;
+                        t0[e2] = relu_bf16x2(pack_bf16x2(acc[ob][0][rr], acc[ob][0][rr + 1]));
+                        t1[e2] = relu_bf16x2(pack_bf16x2(acc[ob][1][rr], acc[ob][1][rr + 1]));
+                    }
+                    a[2 * ob + sb][0] = __builtin_bit_cast(bf16x8, t0);
+                    a[2 * ob + sb][1] = __builtin_bit_cast(bf16x8, t1);
+                }
+            float part[2] = {0.f, 0.f};
+            dense_layer<8, LAY_HEAD>(s_w[1], s_b[1], &s_ref[r][0], s_w6, a, b, part, nullptr, row0,
+                                     ok, ln, h4);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
+                if (DIFF) {
+                    if (r == 0) y0[q] = y;
+                    else if (h == 0 && ok[q]) out[row0 + q * 32 + jl] = y0[q] - y;
+                } else if (h == 0 && ok[q]) {
+                    out[(int64_t)r * ld_out + row0 + q * 32 + jl] = y;
+                }
             }
         }
     }
@@ -1085,6 +1164,20 @@ int launch_infer_latents(const ndf_net_config *c, const void *qp, void *cache, h
     return status_of_launch();
 }
 
+// Fields of n_ref references (latents lat[n_ref][128]) from the query-latent
+// cache, kMultiRefs per launch.
+static void decode_cached(const ndf_net_config *c, const QLayout &q, const char *Q,
+                          const void *cache, const float *lat, int n_ref, float *out,
+                          hipStream_t st) {
+    const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
+    for (int r0 = 0; r0 < n_ref; r0 += kMultiRefs) {
+        const int n = n_ref - r0 < kMultiRefs ? n_ref - r0 : kMultiRefs;
+        hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)),
+                           dim3(kInferThreads), 0, st, a1, (const u32x4 *)cache, a1.V,
+                           lat + (int64_t)r0 * kH, n, out + (int64_t)r0 * a1.V, a1.V);
+    }
+}
+
 int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int64_t *ref_v,
                               int n_ref, const void *cache, float *out, void *ws, hipStream_t st) {
     const bool hash = any_hashed(c);
@@ -1100,11 +1193,7 @@ int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int
     else
         hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
                            refs, (int64_t)n_ref, nullptr, lat, nullptr);
-    const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
-    for (int r = 0; r < n_ref; ++r)
-        hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
-                           st, a1, (const u32x4 *)cache, a1.V, lat + (int64_t)r * kH,
-                           out + (int64_t)r * a1.V);
+    decode_cached(c, q, Q, cache, lat, n_ref, out, st);
     return status_of_launch();
 }
 
@@ -1131,6 +1220,23 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
                                    dim3(kInferThreads), 0, st, a, nullptr, V, nullptr,
                                    out + (int64_t)r * V, nullptr);
         }
+        return status_of_launch();
+    }
+    if (prec == NDF_PREC_BF16 && n_ref >= 2) {
+        // the query latents once into the workspace, then every reference decoded
+        // from them, kMultiRefs references per pass over the cache (bit for bit
+        // the fused single-reference field)
+        if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
+        void *cache = (char *)ws + net_infer_lat_ws_bytes(n_ref);
+        const InferArgs a0 = make_args(c, q, Q, 0);
+        if (hash)
+            hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        else
+            hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
+                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        if (launch_infer_latents(c, qp, cache, st) != NDF_OK) return NDF_E_HIP;
+        decode_cached(c, q, Q, cache, lat, n_ref, out, st);
         return status_of_launch();
     }
     if (prec == NDF_PREC_BF16) {
@@ -1291,10 +1397,8 @@ int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref
         hipLaunchKernelGGL((infer_kernel<1, false>), dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
                            nullptr, lat, nullptr);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
-    hipLaunchKernelGGL(infer_cached_kernel<false>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
-                       st, a1, (const u32x4 *)cache, a1.V, lat, out);
     hipLaunchKernelGGL(infer_cached_kernel<true>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
-                       st, a1, (const u32x4 *)cache, a1.V, lat + kH, out);
+                       st, a1, (const u32x4 *)cache, a1.V, lat, 2, out, a1.V);
     return status_of_launch();
 }
 

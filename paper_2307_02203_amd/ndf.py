@@ -20,7 +20,7 @@ NDF_OK, NDF_E_ARG, NDF_E_WORKSPACE, NDF_E_HIP, NDF_E_UNSUPPORTED = 0, -1, -2, -3
 NDF_E_NONFINITE, NDF_E_SCRATCH = -4, -6
 NDF_PREC_FP32, NDF_PREC_SPLIT_BF16, NDF_PREC_BF16, NDF_PREC_FP8_E4M3 = 0, 1, 2, 3
 NDF_OP_PEARSON_FIELD, NDF_OP_KSG_FIELD, NDF_OP_TRAIN, NDF_OP_INFER, NDF_OP_KSG_PAIRS = 1, 2, 3, 4, 5
-NDF_OP_KSG_POINTS, NDF_OP_PREPARE = 6, 7
+NDF_OP_KSG_POINTS, NDF_OP_PREPARE, NDF_OP_INFER_CACHED = 6, 7, 8
 NDF_FLAG_NONFINITE, NDF_FLAG_CONSTANT = 1, 2
 
 EXPORTED = [
@@ -438,3 +438,8 @@ def ndf_infer_field_difference(cfg, qparams, ref_a, ref_b, cache, out, ws, strea
 
 def infer_ws_bytes(cfg, n_ref, prec):
     return ndf_workspace_bytes(NDF_OP_INFER, None, cfg, n_ref, prec)
+
+
+def cached_ws_bytes(cfg, n_ref):
+    """Workspace of ndf_infer_field_cached / ndf_infer_field_difference."""
+    return ndf_workspace_bytes(NDF_OP_INFER_CACHED, None, cfg, n_ref, NDF_PREC_BF16)

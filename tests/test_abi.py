@@ -194,7 +194,10 @@ def test_net_config_validation_and_param_bytes():
     assert L.ndf_infer_field_difference(C, FAKE, 0, V, FAKE, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
     assert L.ndf_infer_field_difference(C, FAKE, -1, 0, FAKE, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
     assert L.ndf_infer_field_difference(C, FAKE, 0, 1, None, FAKE, FAKE, 1 << 30, None) == ndf.NDF_E_ARG
-    need2 = ndf.infer_ws_bytes(cfg, 2, BF)
+    need2 = ndf.cached_ws_bytes(cfg, 2)
+    # a BF16 field of several references also holds the query latents of every vertex
+    assert ndf.infer_ws_bytes(cfg, 2, BF) >= need2 + L.ndf_infer_latent_bytes(C)
+    assert ndf.infer_ws_bytes(cfg, 1, BF) == ndf.cached_ws_bytes(cfg, 1)
     assert (L.ndf_infer_field_difference(C, FAKE, 0, 1, FAKE, FAKE, FAKE, need2 - 1, None)
             == ndf.NDF_E_WORKSPACE)
 

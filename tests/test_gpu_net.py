@@ -240,20 +240,24 @@ def test_infer_field_parity(name, n_enc):
 
 @pytest.mark.parametrize("name,n_enc", [("mid", 1), ("mid", 2)])
 def test_infer_field_cached_latents_bitwise(name, n_enc):
-    """Fields from the query-latent cache equal the fused field bit for bit."""
+    """Fields from the query-latent cache, 35 references (a launch of 32 and a
+    ragged one of 3), equal the fused single-reference fields bit for bit; so do
+    the fields of one multi-reference ndf_infer_field call, which decodes from a
+    latent cache in its workspace."""
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2328)
     V = cfg.n_vertices
-    refs = [cfg.ref_v, 0, V - 1]
+    refs = np.concatenate([[cfg.ref_v, 0, V - 1], gen.random_vertices(V, 32, seed=15)])
     q = _qparams(c, P, ndf.NDF_PREC_BF16)
-    want = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
+    want = torch.cat([_infer_gpu(c, q, [r], V, ndf.NDF_PREC_BF16) for r in refs])
     cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
     ndf.ndf_infer_latents(c, q, cache)
-    out = torch.empty((len(refs), V), device="cuda")
-    ws = torch.empty(ndf.infer_ws_bytes(c, len(refs), ndf.NDF_PREC_BF16), dtype=torch.uint8,
-                     device="cuda")
+    out = torch.full((len(refs), V), float("nan"), device="cuda")
+    ws = torch.empty(ndf.cached_ws_bytes(c, len(refs)), dtype=torch.uint8, device="cuda")
     ndf.ndf_infer_field_cached(c, q, refs, cache, out, ws)
     torch.cuda.synchronize()
     assert torch.equal(out, want)
+    multi = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
+    assert torch.equal(multi, want)
 
 
 def test_infer_self_field_symmetric_bitwise():
@@ -505,8 +509,7 @@ def test_infer_field_difference():
     ndf.ndf_infer_latents(c, q, cache)
     a, b = cfg.ref_v, 5
     fields = torch.empty((2, V), device="cuda")
-    ws = torch.empty(ndf.infer_ws_bytes(c, 2, ndf.NDF_PREC_BF16), dtype=torch.uint8,
-                     device="cuda")
+    ws = torch.empty(ndf.cached_ws_bytes(c, 2), dtype=torch.uint8, device="cuda")
     ndf.ndf_infer_field_cached(c, q, [a, b], cache, fields, ws)
     out = torch.full((V,), float("nan"), device="cuda")
     ndf.ndf_infer_field_difference(c, q, a, b, cache, out, ws)
@@ -583,11 +586,11 @@ def test_hash_grid_inference(n_enc):
     cache = torch.empty(ndf.ndf_infer_latent_bytes(c), dtype=torch.uint8, device="cuda")
     ndf.ndf_infer_latents(c, q, cache)
     oc = torch.empty((len(refs), V), device="cuda")
-    ws = torch.empty(ndf.infer_ws_bytes(c, len(refs), ndf.NDF_PREC_BF16), dtype=torch.uint8,
-                     device="cuda")
+    ws = torch.empty(ndf.cached_ws_bytes(c, len(refs)), dtype=torch.uint8, device="cuda")
     ndf.ndf_infer_field_cached(c, q, refs, cache, oc, ws)
+    single = torch.cat([_infer_gpu(c, q, [r], V, ndf.NDF_PREC_BF16) for r in refs])
     torch.cuda.synchronize()
-    assert torch.equal(oc, out16)
+    assert torch.equal(oc, single) and torch.equal(out16, single)
 
 
 def test_hash_grid_paper_size_sampled():
