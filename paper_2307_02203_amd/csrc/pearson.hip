@@ -205,6 +205,143 @@ __global__ __launch_bounds__(256) void pearson_gemm_kernel(
         }
 }
 
+// Many references in one read of the ensemble: a workgroup of four waves takes
+// 128 vertices and 256 references, wave w the references 64 w .. 64 w + 63 for
+// all 128 vertices (four 32-vertex tiles, 128 accumulators: the reference
+// fragments, read from L2, are the per-MFMA traffic, so each is used for as
+// many vertices as the registers allow).  Each k-step (16 members) the
+// workgroup loads the 16 x 128 block of x once (16-byte loads, one member row
+// segment per 16 threads), standardises and splits it into hi/lo bf16 and
+// stages it in LDS in MFMA B-operand order; all four waves read their B
+// operands from there (double-buffered, one barrier per k-step), and the next
+// k-step's x values and reference fragments are loaded during the MFMAs.  The
+// per-element arithmetic and the order of the MFMAs match pearson_gemm_kernel,
+// so both give the same bits.
+constexpr int kWideVerts = 128;
+constexpr int kWideTiles = kWideVerts / 32;
+constexpr int kWideRefs = 256;
+
+__global__ __launch_bounds__(256, 2) void pearson_gemm_wide_kernel(
+    const float *__restrict__ x, const double *__restrict__ mean,
+    const double *__restrict__ inv_std, int N, int64_t V, const bf16x8 *__restrict__ afrag,
+    int n_ib_total, int n_ref, float *__restrict__ out) {
+    __shared__ bf16x8 s_bop[2][kWideTiles][2][64];  // [buffer][vertex tile][hi, lo][lane]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, jl = lane & 31;
+    const int64_t vbase = (int64_t)blockIdx.x * kWideVerts;
+    const int ib0 = blockIdx.y * (kWideRefs / 32) + 2 * wave;  // this wave's two 32-ref blocks
+    const bool active = ib0 * 32 < n_ref;
+
+    // loader role: vertex vj of the block, members 8 mh .. 8 mh + 7 of the k-step
+    // (each load instruction reads 512 contiguous bytes of a member row over 128
+    // threads); the thread then owns one 16-byte B-operand slot per part, so
+    // the LDS writes of a wave are conflict-free.  Loads past the last member or
+    // vertex read the last one instead (clamped addresses, no branches) and are
+    // zeroed when staged.
+    const int vj = tid & (kWideVerts - 1);
+    const int mh = __builtin_amdgcn_readfirstlane(tid >> 7);  // uniform per wave
+    const int64_t vg = vbase + vj;
+    const bool okv = vg < V;
+    const int vgc = (int)(okv ? vg : V - 1);
+    const float mu = (float)mean[vgc], is = (float)inv_std[vgc];
+    auto load = [&](int ks, float (&xv)[8]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int m = min(ks * 16 + 8 * mh + e, N - 1);
+            xv[e] = __builtin_nontemporal_load(x + (int64_t)m * V + vgc);
+        }
+    };
+    // B operand element (member k, vertex j): tile j / 32, lane 32 (k / 8) + j % 32,
+    // position k % 8
+    auto stage = [&](int ks, const float (&xv)[8], int buf) {
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float zz = (xv[e] - mu) * is;
+            const float z = (okv && ks * 16 + 8 * mh + e < N) ? zz : 0.f;
+            const __bf16 hb = f2bf(z);
+            hi[e] = hb;
+            lo[e] = f2bf(z - (float)hb);
+        }
+        const int t = vj >> 5, ln = 32 * mh + (vj & 31);
+        s_bop[buf][t][0][ln] = hi;
+        s_bop[buf][t][1][ln] = lo;
+    };
+    auto afetch = [&](int ks, bf16x8 (&a)[2][2]) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t fb = (((int64_t)ks * n_ib_total + ib0 + i) * 2) * 64;
+            a[i][0] = afrag[fb + lane];
+            a[i][1] = afrag[fb + 64 + lane];
+        }
+    };
+
+    f32x16 acc[2][kWideTiles];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int t = 0; t < kWideTiles; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][t][r] = 0.f;
+
+    const int ksteps = (N + 15) / 16;
+    // raw x of two k-steps in flight: at the start of step ks, xr[ks & 1] is free
+    // (staged) and xr[(ks + 1) & 1] holds step ks + 1, loaded a full step earlier
+    float xr0[8], xr1[8];
+    bf16x8 acur[2][2], anxt[2][2];
+    load(0, xr0);
+    if (ksteps > 1) load(1, xr1);
+    if (active) afetch(0, acur);
+    stage(0, xr0, 0);
+    __syncthreads();
+    auto step = [&](int ks, float (&xfree)[8], const float (&xnext)[8]) {
+        const int buf = ks & 1;
+        if (ks + 2 < ksteps) load(ks + 2, xfree);
+        if (ks + 1 < ksteps && active) afetch(ks + 1, anxt);
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < kWideTiles; ++t) {
+                const bf16x8 bhi = s_bop[buf][t][0][lane];
+                const bf16x8 blo = s_bop[buf][t][1][lane];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    acc[i][t] = mfma32(acur[i][0], bhi, acc[i][t]);
+                    acc[i][t] = mfma32(acur[i][0], blo, acc[i][t]);
+                    acc[i][t] = mfma32(acur[i][1], bhi, acc[i][t]);
+                }
+            }
+        }
+        // the other buffer was last read in step ks - 1, before the previous barrier
+        if (ks + 1 < ksteps) {
+            stage(ks + 1, xnext, buf ^ 1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                acur[i][0] = anxt[i][0];
+                acur[i][1] = anxt[i][1];
+            }
+        }
+        __syncthreads();
+    };
+    for (int ks = 0; ks < ksteps; ks += 2) {
+        step(ks, xr0, xr1);
+        if (ks + 1 < ksteps) step(ks + 1, xr1, xr0);
+    }
+    if (!active) return;
+    const float invN = 1.0f / (float)N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int ref = (ib0 + i) * 32 + d_row(r, lane);
+            if (ref >= n_ref) continue;
+#pragma unroll
+            for (int t = 0; t < kWideTiles; ++t) {
+                const int64_t v = vbase + 32 * t + jl;
+                if (v < V) out[(int64_t)ref * V + v] = acc[i][t][r] * invN;
+            }
+        }
+}
+
 // --------------------------------------------------------------- pairs ----
 // Training targets for random vertex pairs.  A pair's two member columns are
 // strided rows of the member-major ensemble (one 128-byte line per value), so
@@ -395,7 +532,12 @@ int launch_pearson_field(const ndf_ensemble *e, int var_ref, int var_qry, const 
     // 8-byte accesses need every member row 8-byte aligned: V even
     const bool vec = (V % 2) == 0;
     const bf16x8 *af = (const bf16x8 *)frag;
-    if (n_ref <= 32) {
+    if (n_ref > 64) {
+        // one read of the ensemble per 256 references
+        const dim3 g((unsigned)ceil_div(V, kWideVerts), (unsigned)ceil_div(n_ref, kWideRefs));
+        hipLaunchKernelGGL(pearson_gemm_wide_kernel, g, dim3(256), 0, st, xq, mq, iq, N, V, af,
+                           n_ib, n_ref, out);
+    } else if (n_ref <= 32) {
         const dim3 g(nbx, 1);
         if (vec)
             hipLaunchKernelGGL((pearson_gemm_kernel<1, true>), g, dim3(256), 0, st, xq, mq, iq, N,

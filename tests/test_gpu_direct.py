@@ -101,6 +101,29 @@ def test_prepare_flags_constant_and_nonfinite():
     assert ndf.status_word(ws) == ndf.NDF_OK
 
 
+@pytest.mark.parametrize("n_ref", [100, 300])
+def test_pearson_many_references_one_pass(mid, n_ref):
+    """More than 64 references run as one read of the ensemble per 256 references
+    (four waves share each staged block of members): every field of a ragged
+    batch (100: two of the four waves partly idle; 300: a second pass of 44) on
+    the mid ensemble (11803 vertices, no 16-byte row alignment) against the
+    oracle, and bit for bit equal to the same references in calls of 64."""
+    V = mid.n_vertices
+    refs = gen.random_vertices(V, n_ref, seed=16 + n_ref)
+    _log(f"split-BF16 Pearson, {n_ref} references, mid")
+    got = ndf.pearson_field(mid, refs, prec=ndf.NDF_PREC_SPLIT_BF16)
+    x = mid.x[0].cpu().numpy()
+    g = got.cpu().numpy()
+    worst = 0.0
+    for i in range(0, n_ref, 7):
+        worst = max(worst, float(np.max(np.abs(g[i] - direct.pearson_field(x[:, refs[i]], x)))))
+    _log(f"{n_ref} refs: max|dr| {worst:.2e}")
+    assert worst <= PEARSON_TOL
+    for r0 in range(0, n_ref, 64):
+        part = ndf.pearson_field(mid, refs[r0:r0 + 64], prec=ndf.NDF_PREC_SPLIT_BF16)
+        assert torch.equal(part, got[r0:r0 + 64]), r0
+
+
 @pytest.mark.parametrize("name", ["tiny", "mid"])
 @pytest.mark.parametrize("prec", [ndf.NDF_PREC_FP32, ndf.NDF_PREC_SPLIT_BF16])
 def test_pearson_field_full(name, prec, request):
