@@ -57,6 +57,16 @@ def lib():
         L.ndf_oracle_ksg_field.restype = None
         L.ndf_oracle_ksg_field.argtypes = [_f32p, ctypes.c_int64, _f32p, ctypes.c_int64,
                                            ctypes.c_int64, ctypes.c_int, _f64p, _i32p, _i32p]
+        L.ndf_oracle_pearson_pairs.restype = None
+        L.ndf_oracle_pearson_pairs.argtypes = [_f32p, _f32p, ctypes.c_int64, ctypes.c_int64,
+                                               _f64p]
+        L.ndf_oracle_ksg_pairs.restype = None
+        L.ndf_oracle_ksg_pairs.argtypes = [_f32p, _f32p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int, _f64p]
+        L.ndf_oracle_set_threads.restype = None
+        L.ndf_oracle_set_threads.argtypes = [ctypes.c_int]
+        L.ndf_oracle_max_threads.restype = ctypes.c_int
+        L.ndf_oracle_max_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -136,3 +146,34 @@ def ksg_field(ref_col, q, k, counts=False):
     if counts:
         return out, nx, ny
     return out
+
+
+def pearson_pairs(a, b) -> np.ndarray:
+    """r(a[:, p], b[:, p]) for the columns p of two member-major blocks [N][np]."""
+    a = _f32(a)
+    b = _f32(b)
+    assert a.shape == b.shape and a.ndim == 2
+    n, npairs = a.shape
+    out = np.empty(npairs, dtype=np.float64)
+    lib().ndf_oracle_pearson_pairs(_ptr(a, _f32p), _ptr(b, _f32p), npairs, n, _ptr(out, _f64p))
+    return out
+
+
+def ksg_pairs(a, b, k) -> np.ndarray:
+    """KSG MI(a[:, p], b[:, p]) (nats) for the columns p of two blocks [N][np]."""
+    a = _f32(a)
+    b = _f32(b)
+    assert a.shape == b.shape and a.ndim == 2
+    n, npairs = a.shape
+    out = np.empty(npairs, dtype=np.float64)
+    lib().ndf_oracle_ksg_pairs(_ptr(a, _f32p), _ptr(b, _f32p), npairs, n, int(k),
+                               _ptr(out, _f64p))
+    return out
+
+
+def set_threads(n: int) -> None:
+    lib().ndf_oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().ndf_oracle_max_threads())

@@ -204,3 +204,45 @@ void ndf_oracle_ksg_field(const float *ref, int64_t sref, const float *q, int64_
     free(h);
     free(cref);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pairs of columns (training targets, Sec. 4.3, and held-out evaluation):     */
+/* column p of the member-major blocks a[N][np] and b[N][np] forms pair p.     */
+/* ------------------------------------------------------------------------ */
+void ndf_oracle_pearson_pairs(const float *a, const float *b, int64_t np, int64_t n,
+                              double *out)
+{
+    int64_t p;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (p = 0; p < np; ++p)
+        out[p] = ndf_oracle_pearson(a + p, np, b + p, np, n);
+}
+
+void ndf_oracle_ksg_pairs(const float *a, const float *b, int64_t np, int64_t n, int k,
+                          double *out)
+{
+    double *h = harmonic_table(n);
+    int64_t p;
+#pragma omp parallel
+    {
+        int32_t *ca = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *cb = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int64_t *best = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 4)
+        for (p = 0; p < np; ++p) {
+            int fa = ndf_oracle_ksg_codes(a + p, np, n, ca);
+            int fb = ndf_oracle_ksg_codes(b + p, np, n, cb);
+            out[p] = (fa || fb) ? 0.0 : ksg_core(ca, cb, n, k, h, NULL, NULL, best);
+        }
+        free(best);
+        free(cb);
+        free(ca);
+    }
+    free(h);
+}
+
+/* Threads of the parallel loops above (the CPU baseline times one and all). */
+extern void omp_set_num_threads(int);
+extern int omp_get_max_threads(void);
+void ndf_oracle_set_threads(int n) { omp_set_num_threads(n); }
+int ndf_oracle_max_threads(void) { return omp_get_max_threads(); }

@@ -1,12 +1,15 @@
 """Host logic of bench.py (no GPU): the one-GPU guard, the roofline arithmetic of
-the dominant kernel, and the rule that recorded counter traffic is reported only
-while the kernel source still hashes to the value recorded with it."""
+the learned-field kernel behind `value` and of the KSG field kernel, the
+percentile summary, the coarse-grid interpolation of the equal-time baseline,
+and the rule that recorded counter figures are reported only while the kernel
+sources still hash to the values recorded with them."""
 import hashlib
 import json
 import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -21,14 +24,41 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
-def test_ksg_roofline_arithmetic():
+def test_value_roofline_is_the_learned_field_kernel():
+    r = bench._value_roofline({"ndf_field": 0.25})
+    flops = 2.0 * 69760 * 1_760_000
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 2500.0
+    assert r["achieved"] == pytest.approx(flops / 0.25e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 2500.0) and 0 < r["frac"] < 1
+
+
+def test_ksg_roofline_is_a_lane_op_fraction():
     V, N, ms = 1_760_000, 1000, 48.0
-    r = bench._roofline_of("ksg_field", {}, {"ksg_field": ms}, N, V)
-    pairs = V * N * (N - 1)
-    assert r["bound"] == "alu" and r["kernel"] == "ksg_field"
-    assert r["achieved"] == pytest.approx(pairs / (ms * 1e-3) / 1e12)
-    assert r["peak"] == pytest.approx(256 * 4 * 16 * 2.4e9 / 1e12 / 8)
+    r = bench._ksg_roofline(ms, N, V)
+    assert r["bound"] == "alu" and r["unit"] == "T lane-ops/s"
+    assert r["peak"] == pytest.approx(256 * 4 * 16 * 2.4e9 / 1e12)
+    assert r["brute_force_equivalent_pair_evals_per_s"] == pytest.approx(V * N * (N - 1) / 48e-3)
+    # the lane operations come from the hash-checked counter profile
+    assert r["achieved"] is not None and 0 < r["frac"] <= 1
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    assert 0 < r["lds_bank_conflict_frac"] < 1
+
+
+def test_stats_and_coarse_upsampling():
+    st = bench._stats(list(range(1, 101)))
+    assert st["median"] == 50.5 and st["p10"] == pytest.approx(10.9) and st["n"] == 100
+    # trilinear upsampling reproduces a field affine in (i, j, k) exactly
+    import gen
+    cfg = gen.CONFIGS["mid"]
+    axes = [bench._coarse_axis(cfg.nx, 5), bench._coarse_axis(cfg.ny, 5),
+            bench._coarse_axis(cfg.nz, 5)]
+    assert axes[0][0] == 0 and axes[0][-1] == cfg.nx - 1
+    iz, iy, ix = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    f = (0.5 * ix - 2.0 * iy + 3.0 * iz + 1.0).reshape(-1)
+    v = np.arange(cfg.n_vertices)
+    i, j, k = v % cfg.nx, (v // cfg.nx) % cfg.ny, v // (cfg.nx * cfg.ny)
+    np.testing.assert_allclose(bench._upsample(f, axes, v, cfg),
+                               0.5 * i - 2.0 * j + 3.0 * k + 1.0, atol=1e-12)
 
 
 def test_traffic_follows_the_source_hash(tmp_path, monkeypatch):
@@ -39,7 +69,7 @@ def test_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     prof.write_text(f"k.hip sha256 prefix at measurement: {sha[:16]}.\n"
                     "  traffic_bytes_per_launch: 1.5e+09   (algorithmic ...)\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "_PMC_TRAFFIC", {"k": ("p.txt", "k.hip")})
+    monkeypatch.setattr(bench, "_PMC_TRAFFIC", {"k": ("p.txt", ["k.hip"])})
     assert bench._measured_traffic("k") == pytest.approx(1.5e9)
     assert bench._measured_traffic("other") is None
     src.write_text("kernel v2\n")                       # source changed since the counters
@@ -57,9 +87,9 @@ def test_recorded_ksg_traffic_matches_the_current_source():
 
 
 def test_recorded_ksg_issue_rates():
-    """The dominant kernel's measured VALU issue and lane occupancy come from the
-    same hash-checked counter profile."""
+    """The KSG kernel's measured VALU issue and lane occupancy come from the same
+    hash-checked counter profile."""
     issue, lanes = bench._measured_issue("ksg_field")
     assert 0.5 < issue <= 1.0 and 0.5 < lanes <= 1.0
-    r = bench._roofline_of("ksg_field", {}, {"ksg_field": 48.0}, 1000, 1_760_000)
+    r = bench._ksg_roofline(48.0, 1000, 1_760_000)
     assert r["valu_issue_frac"] == issue and r["valu_lanes_active_frac"] == lanes

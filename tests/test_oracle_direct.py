@@ -220,3 +220,18 @@ def test_ksg_bivariate_gaussian_closed_form(rho):
     # non-strict count or a shifted psi argument move the mean by >= 0.1 nats
     bias_allowance = 0.01 if rho < 0.8 else 0.02
     assert abs(est.mean() - truth) < bias_allowance + 3 * se
+
+
+def test_pair_batches_equal_the_single_pair_oracle():
+    """The batched pair entry points (held-out evaluation) give, column by column,
+    the values of the pinned single-column functions bit for bit."""
+    rng = np.random.default_rng(17)
+    a = rng.normal(size=(40, 23)).astype(np.float32)
+    b = (0.6 * a + rng.normal(size=(40, 23))).astype(np.float32)
+    b[:, 5] = 1.5                                    # a constant column: r = 0, MI = 0
+    r = direct.pearson_pairs(a, b)
+    mi = direct.ksg_pairs(a, b, 3)
+    for p in range(23):
+        assert r[p] == direct.pearson(a[:, p], b[:, p])
+        assert mi[p] == direct.ksg_field(a[:, p], b[:, p:p + 1], 3)[0]
+    assert r[5] == 0.0 and mi[5] == 0.0
