@@ -51,11 +51,13 @@ B_PAIRS = 1 << 18
 N_BATCH = 64
 N_REF5 = 256         # references of the batched two-variable workload
 K_NN = 4
-LR = 1e-3
-PREP_TRAIN_STEPS = 300
-MI_TRAIN_STEPS = 600
-CROSS_TRAIN_STEPS = 150
-LOSS_EVERY = 10
+LR = 3e-3            # peak learning rate (cosine schedule over each training run)
+LR_GRID_ONLY = 1e-2  # the grid-only ablation trains best at a higher rate
+PREP_TRAIN_STEPS = 1000
+MI_TRAIN_STEPS = 1500
+GRID_ONLY_STEPS = 1000
+CROSS_TRAIN_STEPS = 300
+LOSS_EVERY = 25
 N_HELD = 1_000_000   # held-out Pearson pairs (oracle)
 N_HELD_MI = 2000     # held-out KSG-MI pairs (brute-force oracle on the host)
 N_SAMPLE = 2000      # sampled vertices of the one-reference fields (oracle)
@@ -133,8 +135,10 @@ def _timed(fn, reps, warmup=1):
     return ms
 
 
-def _train(ndf, net, P, opt, steps, make_targets, pairs_seed, ws_t, loss, dev, log, what):
-    """`steps` Adam steps on fresh 2^18-pair batches; loss every LOSS_EVERY steps."""
+def _train(ndf, net, P, opt, steps, make_targets, pairs_seed, ws_t, loss, dev, log, what,
+           lr0=LR):
+    """`steps` Adam steps on fresh 2^18-pair batches with a cosine learning-rate
+    schedule from lr0; the loss every LOSS_EVERY steps."""
     import torch
     import gen
     V = net.nx * net.ny * net.nz
@@ -144,14 +148,16 @@ def _train(ndf, net, P, opt, steps, make_targets, pairs_seed, ws_t, loss, dev, l
     for s in range(1, steps + 1):
         pr = torch.as_tensor(gen.random_pairs(V, B_PAIRS, seed=pairs_seed + s), device=dev)
         t = make_targets(pr)
-        ndf.ndf_train_step(net, P, opt, s, pr, t, LR, loss, ws_t)
+        lr = lr0 * 0.5 * (1.0 + math.cos(math.pi * (s - 1) / steps))
+        ndf.ndf_train_step(net, P, opt, s, pr, t, lr, loss, ws_t)
         hist[s - 1] = loss[0]
     torch.cuda.synchronize()
     sec = time.time() - t0
     st = ndf.status_word(ws_t)
     h = hist.cpu().numpy()
     curve = [[s, float(h[s - 1])] for s in range(1, steps + 1) if s == 1 or s % LOSS_EVERY == 0]
-    return {"steps": steps, "seconds": sec, "batch": B_PAIRS, "lr": LR,
+    return {"steps": steps, "seconds": sec, "batch": B_PAIRS, "lr_peak": lr0,
+            "lr_schedule": "cosine",
             "final_l1_loss": float(h[steps - 1]) if steps else None,
             "loss_curve": curve, "status_word": st}
 
@@ -469,7 +475,8 @@ def main():
         log("bench: held-out errors of the trained fields")
         result["config3"]["held_out"] = _held_out(ens, cfg, net, P, P_mi, ws_t, log)
         log("bench: gain of the trained field over the method without it")
-        result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log)
+        result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log,
+                               pearson_targets)
     if not a.no_config5:
         del out_b, cache
         torch.cuda.empty_cache()
@@ -763,7 +770,7 @@ def _equal_time_coarse(ens, cfg, budget_ms, measure, log, what):
     return None
 
 
-def _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log):
+def _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log, pearson_targets):
     """What the trained field gains over the method without it, on the sampled
     vertices of one reference's field against the FP64 oracle: the untrained
     (initialised) field, the best constant predictor, and the direct estimator at
@@ -797,7 +804,30 @@ def _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log):
     ndf.ndf_infer_field(net, qp0, ndf.NDF_PREC_BF16, [cfg.ref_v], y0, ws_i)
     y0 = y0[0, idx].cpu().numpy().astype(np.float64)
     out["ndf_untrained_mae"] = mae(y0)
-    del P0, qp0, ws_i
+    del P0, qp0
+
+    # the grid-only network (encoder MLP omitted, Sec. 6.3, Fig. 6), same targets
+    lay_g = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, grid_only=True)
+    net_g = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay_g.res, grid_only=True)
+    P_g = torch.empty(lay_g.n_floats, device="cuda")
+    opt_g = torch.empty(2 * lay_g.n_floats, device="cuda")
+    ndf.ndf_net_init(net_g, P_g, opt_g, 2320)
+    ws_g = torch.empty(ndf.train_ws_bytes(net_g, B_PAIRS) + lay_g.n_floats * 4 + 256,
+                       dtype=torch.uint8, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    tr_g = _train(ndf, net_g, P_g, opt_g, GRID_ONLY_STEPS, pearson_targets, 5000, ws_g, loss,
+                  "cuda", log, "grid-only Pearson", lr0=LR_GRID_ONLY)
+    qp_g = torch.empty(ndf.ndf_net_qparam_bytes(net_g, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                       device="cuda")
+    ndf.ndf_net_quantize(net_g, P_g, ndf.NDF_PREC_BF16, qp_g)
+    y_g = torch.empty((1, V), device="cuda")
+    ms_g = _timed(lambda it: ndf.ndf_infer_field(net_g, qp_g, ndf.NDF_PREC_BF16, [cfg.ref_v], y_g,
+                                                 ws_i), 5, 1)
+    out["grid_only_network"] = {
+        "mae": mae(y_g[0, idx].cpu().numpy()), "ms_per_field": float(np.median(ms_g)),
+        "training": {k: tr_g[k] for k in ("steps", "lr_peak", "final_l1_loss", "seconds")},
+        "note": "encoder MLP omitted: the latent is the 32 grid features (Sec. 6.3 ablation)"}
+    del P_g, opt_g, ws_g, qp_g, y_g, ws_i
 
     # equal time, fewer members: the direct cost is linear in N
     m_eq = int(max(8, min(N, round(N * t_ndf / med["pearson_fp32"]))))

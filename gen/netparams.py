@@ -2,7 +2,9 @@
 
 Flat FP32 parameter layout (the format the C library documents for
 ``ndf_net_param_bytes``): for each encoder e in 0..n_enc-1 (n_enc = 1 when the
-reference and query share one encoder and grid, Sec. 4.1, else 2):
+reference and query share one encoder and grid, Sec. 4.1, else 2; a grid-only
+network, the ablation of Sec. 6.3 with the encoder MLP omitted, has no W1..b3
+and its W4 is float[H][L*F]):
 
     grid_e level l, l = 0..L-1 : float[cells_l][F]   cells_l = Rx*Ry*Rz, cell = x + Rx*(y + Ry*z),
                                  or cells_l = 2^T for a level hashed into a table of
@@ -48,11 +50,13 @@ class NetLayout:
     width: int = 128
     n_enc: int = 1        # 1: shared encoder + grid (self field), 2: separate
     log2_hashmap: int = 0  # T > 0: levels larger than 2^T cells are hash tables of 2^T
+    grid_only: bool = False  # encoder MLP omitted: the latent is the grid features
 
     @staticmethod
-    def for_grid(nx, ny, nz, n_levels=4, feats=8, width=128, n_enc=1, log2_hashmap=0):
+    def for_grid(nx, ny, nz, n_levels=4, feats=8, width=128, n_enc=1, log2_hashmap=0,
+                 grid_only=False):
         return NetLayout(nx, ny, nz, tuple(level_resolutions(nx, ny, nz, n_levels)),
-                         feats, width, n_enc, log2_hashmap)
+                         feats, width, n_enc, log2_hashmap, grid_only)
 
     def cells(self, l):
         rx, ry, rz = self.res[l]
@@ -71,11 +75,12 @@ class NetLayout:
         for e in range(self.n_enc):
             for l in range(self.n_levels):
                 out.append((f"grid{e}_{l}", (self.cells(l), F)))
-            out += [(f"W1_{e}", (H, L * F)), (f"b1_{e}", (H,)),
-                    (f"W2_{e}", (H, H)), (f"b2_{e}", (H,)),
-                    (f"W3_{e}", (H, H)), (f"b3_{e}", (H,))]
-        out += [("W4", (H, H)), ("b4", (H,)), ("W5", (H, H)), ("b5", (H,)),
-                ("w6", (H,)), ("b6", (1,))]
+            if not self.grid_only:
+                out += [(f"W1_{e}", (H, L * F)), (f"b1_{e}", (H,)),
+                        (f"W2_{e}", (H, H)), (f"b2_{e}", (H,)),
+                        (f"W3_{e}", (H, H)), (f"b3_{e}", (H,))]
+        out += [("W4", (H, L * F if self.grid_only else H)), ("b4", (H,)), ("W5", (H, H)),
+                ("b5", (H,)), ("w6", (H,)), ("b6", (1,))]
         return out
 
     def offsets(self):

@@ -111,7 +111,14 @@ typedef struct ndf_ensemble {
  * spatial hash (x * 1 xor y * 2654435761 xor z * 805459861) mod 2^T of the
  * corner (x, y, z) (32-bit unsigned arithmetic; the hash of the grids the paper
  * builds on, Mueller et al. 2022); coarser levels stay dense.  Colliding
- * corners share a cell (their gradients add).  T = 0: every level dense. */
+ * corners share a cell (their gradients add).  T = 0: every level dense.
+ * Grid-only network (grid_only = 1; the TensoRF-like ablation of Sec. 6.3,
+ * Fig. 6: the encoder MLP omitted, predictions from the input embedding alone):
+ * the latent of a position is its L*F = 32 grid features, the merge multiplies
+ * the two 32-vectors and the decoder's first layer W4 is W x (L*F).  The
+ * training, forward and BF16 field calls support it (ndf_infer_field with one
+ * fused pass per reference, ndf_infer_points); FP8 and the query-latent calls
+ * return NDF_E_UNSUPPORTED. */
 typedef struct ndf_net_config {
     int32_t nx, ny, nz;      /* data grid whose vertices are evaluated            */
     int32_t n_levels;        /* 4                                                 */
@@ -121,6 +128,7 @@ typedef struct ndf_net_config {
     int32_t n_enc;           /* 1 or 2                                            */
     int32_t log2_hashmap;    /* 0 (dense levels) or T in [8, 24]: hash tables of
                                 2^T cells for the levels larger than that        */
+    int32_t grid_only;       /* 0: full network; 1: encoder MLP omitted          */
 } ndf_net_config;
 
 /* Human-readable name of a status code (static storage). */
@@ -236,9 +244,10 @@ int ndf_ksg_mi_points(const ndf_ensemble *ens, int32_t var_a, int32_t var_b, con
 
 /* Bytes of the FP32 parameter vector (layout: for each encoder its grid levels
  * float[cells][feats] with cells = Rx*Ry*Rz, or 2^T for a hashed level, then
- * W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3; then W4[W][W], b4, W5[W][W], b5,
- * w6[W], b6[1]; every tensor starts at a multiple of 64 floats, gaps zero) and
- * of the Adam state (m then v, same layout). */
+ * W1[W][L*F], b1, W2[W][W], b2, W3[W][W], b3 (absent for a grid-only network);
+ * then W4[W][W] (grid-only: W4[W][L*F]), b4, W5[W][W], b5, w6[W], b6[1]; every
+ * tensor starts at a multiple of 64 floats, gaps zero) and of the Adam state
+ * (m then v, same layout). */
 size_t ndf_net_param_bytes(const ndf_net_config *cfg);
 size_t ndf_net_optstate_bytes(const ndf_net_config *cfg);
 

@@ -22,6 +22,10 @@ Readings where the paper is silent (the GPU path uses the same ones):
   (the paper's table is large enough that no level of its grids is hashed);
 * encoder: 3 layers, ReLU after the first two, linear latent; decoder: two ReLU
   layers and a linear scalar output; weights row-major [out][in];
+* grid-only network (the TensoRF-like ablation of Sec. 6.3, Fig. 6: the encoder
+  MLP omitted, predictions from the input embedding alone): the latent of a
+  position is its concatenated grid features, so the merge multiplies two
+  L*F-vectors and the decoder's first layer is W4[width][L*F];
 * L1 loss gradient uses sign(y - t) with sign(0) = 0.
 
 The flat parameter layout is parsed here from its documented description (each
@@ -38,10 +42,12 @@ ALIGN = 64
 class Net:
     """Named float64 views over a copy of a flat parameter vector."""
 
-    def __init__(self, flat, dims, res, feats=8, width=128, n_enc=1, log2_hashmap=0):
+    def __init__(self, flat, dims, res, feats=8, width=128, n_enc=1, log2_hashmap=0,
+                 grid_only=False):
         self.nx, self.ny, self.nz = dims
         self.res = [tuple(r) for r in res]
         self.T = log2_hashmap
+        self.grid_only = grid_only
         self.F = feats
         self.H = width
         self.n_enc = n_enc
@@ -59,13 +65,16 @@ class Net:
         for e in range(n_enc):
             for l, R in enumerate(self.res):
                 take(("grid", e, l), (level_cells(R, log2_hashmap), feats))
+            if grid_only:
+                continue
             take(("W1", e), (width, L * feats))
             take(("b1", e), (width,))
             take(("W2", e), (width, width))
             take(("b2", e), (width,))
             take(("W3", e), (width, width))
             take(("b3", e), (width,))
-        for name, shape in (("W4", (width, width)), ("b4", (width,)), ("W5", (width, width)),
+        w4_in = L * feats if grid_only else width
+        for name, shape in (("W4", (width, w4_in)), ("b4", (width,)), ("W5", (width, width)),
                             ("b5", (width,)), ("w6", (width,)), ("b6", (1,))):
             take(name, shape)
         self.n_floats = pos
@@ -283,6 +292,8 @@ def _wgrad(g, x, layer, rnd):
 
 
 def encoder(net, e, h0, rnd=None):
+    if net.grid_only:  # the encoder MLP omitted: the latent is the embedding itself
+        return {"h0": h0, "lat": h0}
     a1 = _lin(h0, net[("W1", e)], 1, rnd) + net[("b1", e)]
     h1 = relu(a1)
     a2 = _lin(h1, net[("W2", e)], 2, rnd) + net[("b2", e)]
@@ -351,6 +362,8 @@ def l1_loss(y, t):
 
 
 def _encoder_backward(net, e, c, dlat, grads, rnd=None):
+    if net.grid_only:
+        return dlat
     grads[("W3", e)] += _wgrad(dlat, c["h2"], 3, rnd)
     grads[("b3", e)] += dlat.sum(0)
     dh2 = _adj(dlat, net[("W3", e)], 3, rnd)

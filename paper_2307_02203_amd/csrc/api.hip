@@ -377,6 +377,7 @@ int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t pre
     if (s != NDF_OK) return s;
     if (!params || !qparams) return NDF_E_ARG;
     if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
+    if (cfg->grid_only && prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
     return launch_net_quantize(cfg, params, prec, qparams, S(stream));
 }
 
@@ -387,6 +388,7 @@ int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec
     if (s != NDF_OK) return s;
     if (!qparams || !out || !ref_v || n_ref < 1) return NDF_E_ARG;
     if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
+    if (cfg->grid_only && prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     for (int r = 0; r < n_ref; ++r)
         if (ref_v[r] < 0 || ref_v[r] >= V) return NDF_E_ARG;
@@ -402,6 +404,7 @@ int ndf_infer_latents(const ndf_net_config *cfg, const void *qparams, void *cach
     int s = check_net_config(cfg);
     if (s != NDF_OK) return s;
     if (!qparams || !cache) return NDF_E_ARG;
+    if (cfg->grid_only) return NDF_E_UNSUPPORTED;
     return launch_infer_latents(cfg, qparams, cache, S(stream));
 }
 
@@ -411,6 +414,7 @@ int ndf_infer_field_cached(const ndf_net_config *cfg, const void *qparams, const
     int s = check_net_config(cfg);
     if (s != NDF_OK) return s;
     if (!qparams || !cache || !out || !ref_v || n_ref < 1) return NDF_E_ARG;
+    if (cfg->grid_only) return NDF_E_UNSUPPORTED;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     for (int r = 0; r < n_ref; ++r)
         if (ref_v[r] < 0 || ref_v[r] >= V) return NDF_E_ARG;
@@ -425,6 +429,7 @@ int ndf_infer_points(const ndf_net_config *cfg, const void *qparams, int32_t pre
     if (s != NDF_OK) return s;
     if (!qparams || !ref_v || n_ref < 1 || n < 0 || (n > 0 && (!pos || !out))) return NDF_E_ARG;
     if (prec != NDF_PREC_BF16 && prec != NDF_PREC_FP8_E4M3) return NDF_E_UNSUPPORTED;
+    if (cfg->grid_only && prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     for (int r = 0; r < n_ref; ++r)
         if (ref_v[r] < 0 || ref_v[r] >= V) return NDF_E_ARG;
@@ -439,6 +444,7 @@ int ndf_infer_field_difference(const ndf_net_config *cfg, const void *qparams, i
     int s = check_net_config(cfg);
     if (s != NDF_OK) return s;
     if (!qparams || !cache || !out) return NDF_E_ARG;
+    if (cfg->grid_only) return NDF_E_UNSUPPORTED;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     if (ref_a < 0 || ref_a >= V || ref_b < 0 || ref_b >= V) return NDF_E_ARG;
     if (!ws || ws_bytes < net_infer_lat_ws_bytes(2)) return NDF_E_WORKSPACE;

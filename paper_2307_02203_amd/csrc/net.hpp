@@ -29,6 +29,7 @@ inline int check_net_config(const ndf_net_config *c) {
     if ((int64_t)c->nx * c->ny * c->nz >= (1 << 24)) return NDF_E_UNSUPPORTED;
     if (c->n_levels != kL || c->feats != kF || c->width != kH) return NDF_E_UNSUPPORTED;
     if (c->n_enc != 1 && c->n_enc != 2) return NDF_E_ARG;
+    if (c->grid_only != 0 && c->grid_only != 1) return NDF_E_ARG;
     for (int l = 0; l < kL; ++l)
         for (int a = 0; a < 3; ++a)
             if (c->res[l][a] < 2 || c->res[l][a] > (1 << 16)) return NDF_E_ARG;
@@ -67,6 +68,7 @@ inline NetOffsets net_offsets(const ndf_net_config *c) {
                                         : (int64_t)c->res[l][0] * c->res[l][1] * c->res[l][2];
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) o.grid[e][l] = take(o.cells[l] * kF);
+        if (c->grid_only) continue;  // no encoder MLP (W1..b3 offsets stay 0, unused)
         o.W1[e] = take(kH * kK0);
         o.b1[e] = take(kH);
         o.W2[e] = take(kH * kH);
@@ -80,7 +82,7 @@ inline NetOffsets net_offsets(const ndf_net_config *c) {
         o.W2[1] = o.W2[0]; o.b2[1] = o.b2[0];
         o.W3[1] = o.W3[0]; o.b3[1] = o.b3[0];
     }
-    o.W4 = take(kH * kH);
+    o.W4 = take(kH * (c->grid_only ? kK0 : kH));
     o.b4 = take(kH);
     o.W5 = take(kH * kH);
     o.b5 = take(kH);

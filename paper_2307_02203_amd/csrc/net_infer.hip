@@ -48,6 +48,7 @@ static QLayout qlayout(const ndf_net_config *c) {
     const NetOffsets o = net_offsets(c);
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) q.grid[e][l] = take(o.cells[l] * kF * 2);
+        if (c->grid_only) continue;  // no encoder MLP
         q.w1[e] = take(kH * kK0 * 2);
         q.w2[e] = take(kH * kH * 2);
         q.w3[e] = take(kH * kH * 2);
@@ -60,12 +61,16 @@ static QLayout qlayout(const ndf_net_config *c) {
         q.w1[1] = q.w1[0]; q.w2[1] = q.w2[0]; q.w3[1] = q.w3[0];
         q.b1[1] = q.b1[0]; q.b2[1] = q.b2[0]; q.b3[1] = q.b3[0];
     }
-    q.w4 = take(kH * kH * 2);
+    q.w4 = take(kH * (c->grid_only ? kK0 : kH) * 2);
     q.w5 = take(kH * kH * 2);
     q.b4 = take(kH * 4);
     q.b5 = take(kH * 4);
     q.w6 = take(kH * 4);
     q.b6 = take(4);
+    if (c->grid_only) {  // BF16 only: no FP8 copies
+        q.total = pos;
+        return q;
+    }
     for (int e = 0; e < c->n_enc; ++e) {
         q.q2[e] = take(kH * kH);
         q.q3[e] = take(kH * kH);
@@ -211,6 +216,7 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
             hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256),
                                0, st, P + o.grid[e][l], n, (uint16_t *)(Q + q.grid[e][l]));
         }
+        if (c->grid_only) continue;
         hipLaunchKernelGGL(pack_frag_kernel, dim3(16), dim3(256), 0, st, P + o.W1[e], kK0, 0,
                            (uint16_t *)(Q + q.w1[e]));
         hipLaunchKernelGGL(pack_frag_kernel, dim3(64), dim3(256), 0, st, P + o.W2[e], kH, 1,
@@ -224,8 +230,12 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
         hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(128), 0, st, P + o.b3[e], kH,
                            (float *)(Q + q.b3[e]));
     }
-    hipLaunchKernelGGL(pack_frag_kernel, dim3(64), dim3(256), 0, st, P + o.W4, kH, 1,
-                       (uint16_t *)(Q + q.w4));
+    if (c->grid_only)  // W4 [128][32] on the merged grid features, natural input order
+        hipLaunchKernelGGL(pack_frag_kernel, dim3(16), dim3(256), 0, st, P + o.W4, kK0, 0,
+                           (uint16_t *)(Q + q.w4));
+    else
+        hipLaunchKernelGGL(pack_frag_kernel, dim3(64), dim3(256), 0, st, P + o.W4, kH, 1,
+                           (uint16_t *)(Q + q.w4));
     hipLaunchKernelGGL(pack_frag_kernel, dim3(64), dim3(256), 0, st, P + o.W5, kH, 1,
                        (uint16_t *)(Q + q.w5));
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(128), 0, st, P + o.b4, kH,
@@ -235,6 +245,7 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(128), 0, st, P + o.w6, kH,
                        (float *)(Q + q.w6));
     hipLaunchKernelGGL(copy_f32_kernel, dim3(1), dim3(1), 0, st, P + o.b6, 1, (float *)(Q + q.b6));
+    if (c->grid_only) return status_of_launch();
     // FP8 copies of the 128x128 layers (both precisions share one packed blob)
     auto fp8 = [&](const float *W, int64_t qoff, int64_t soff) {
         hipLaunchKernelGGL(pack_fp8_kernel, dim3(1), dim3(kH), 0, st, W, (uint32_t *)(Q + qoff),
@@ -414,7 +425,11 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 // SEP: a field mode of a two-encoder network that computes the reference latent in
 // the prologue: the reference encoder's layers are staged first, then replaced
 // by the query encoder's.
-template <int MODE, bool HASH, bool SEP = false>
+// GO: a grid-only network (the encoder MLP omitted): the latent is the gathered
+// grid features (32, in the gather's natural feature order 16 kb + 8 h + e), the
+// product with the reference's feeds W4 [128][32] (held in s_w1) and W5 sits in
+// s_w[3]; field modes only, shared grid or separate grids alike.
+template <int MODE, bool HASH, bool SEP = false, bool GO = false>
 __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const int64_t *__restrict__ qlist,
                                                               int64_t nq,
@@ -429,13 +444,20 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
 
     const int tid = threadIdx.x;
-    for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = (SEP ? A.rw[0] : A.w[0])[i];
-    const int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
-    for (int L = 0; L < nlay; ++L)
-        for (int i = tid; i < kFragW; i += kInferThreads)
-            s_w[L][i] = (SEP && L < 2 ? A.rw[L + 1] : A.w[L + 1])[i];
-    for (int i = tid; i < 5 * kH; i += kInferThreads)
-        s_b[i / kH][i % kH] = (SEP && i < 3 * kH ? A.rb[i / kH] : A.b[i / kH])[i % kH];
+    if (GO) {
+        for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[3][i];
+        for (int i = tid; i < kFragW; i += kInferThreads) s_w[3][i] = A.w[4][i];
+        for (int i = tid; i < 2 * kH; i += kInferThreads)
+            s_b[3 + i / kH][i % kH] = A.b[3 + i / kH][i % kH];
+    } else {
+        for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = (SEP ? A.rw[0] : A.w[0])[i];
+        const int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
+        for (int L = 0; L < nlay; ++L)
+            for (int i = tid; i < kFragW; i += kInferThreads)
+                s_w[L][i] = (SEP && L < 2 ? A.rw[L + 1] : A.w[L + 1])[i];
+        for (int i = tid; i < 5 * kH; i += kInferThreads)
+            s_b[i / kH][i % kH] = (SEP && i < 3 * kH ? A.rb[i / kH] : A.b[i / kH])[i % kH];
+    }
     const bool fuse = kField && A.fuse_ref >= 0;
     for (int i = tid; i < kH; i += kInferThreads) {
         s_w6[i] = A.w6[i];
@@ -478,15 +500,21 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
 #pragma unroll
                 for (int e = 0; e < 8; ++e) t[e] = f2bf(sf[e]);
                 a[kb][0] = a[kb][1] = t;
+                if (GO && jl == 0) {  // the latent is the rounded grid features
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) s_ref[16 * kb + 8 * h + e] = (float)t[e];
+                }
             }
             float part[2] = {0.f, 0.f};
+            if (!GO) {
             dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok, lane, h4);
             dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0, ok, lane, h4);
             dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref, 0, ok,
                                            lane, h4);
+            }
         }
         __syncthreads();
-        if (SEP) {  // the query encoder's layers replace the reference encoder's
+        if (SEP && !GO) {  // the query encoder's layers replace the reference encoder's
             for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
             for (int L = 0; L < 2; ++L)
                 for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
@@ -551,6 +579,21 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             }
         }
         float part[2] = {0.f, 0.f};
+        if (GO) {
+            // product of the query's and the reference's grid features (exact in
+            // FP32 for bf16 values, then rounded to bf16), decoder on top
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        b[kb][q][e] = f2bf((float)a[kb][q][e] * s_ref[16 * kb + 8 * h + e]);
+            dense_layer<2, LAY_RELU>(s_w1, s_b[3], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane,
+                                     h4);
+            dense_layer<8, LAY_HEAD>(s_w[3], s_b[4], s_ref, s_w6, a, b, part, nullptr, row0, ok,
+                                     lane, h4);
+        } else {
         dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
         dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
         if (MODE == 1) {
@@ -567,6 +610,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                    lane, h4);
         dense_layer<8, LAY_RELU>(s_w[2], s_b[3], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
         dense_layer<8, LAY_HEAD>(s_w[3], s_b[4], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
@@ -1222,6 +1266,25 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
         }
         return status_of_launch();
     }
+    if (c->grid_only) {
+        // grid-only network: one fused pass per reference (BF16; the reference's
+        // grid features gathered in each workgroup's prologue)
+        if (prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
+        const bool sep = c->n_enc == 2;
+        for (int r = 0; r < n_ref; ++r) {
+            const InferArgs a = fused_args(c, q, Q, ref_v[r]);
+            const dim3 g(infer_blocks(a.V)), b(kInferThreads);
+            float *o = out + (int64_t)r * a.V;
+#define NDF_GO_FIELD(H, S) \
+    hipLaunchKernelGGL((infer_kernel<0, H, S, true>), g, b, 0, st, a, nullptr, a.V, nullptr, o, nullptr)
+            if (hash && sep) NDF_GO_FIELD(true, true);
+            else if (hash) NDF_GO_FIELD(true, false);
+            else if (sep) NDF_GO_FIELD(false, true);
+            else NDF_GO_FIELD(false, false);
+#undef NDF_GO_FIELD
+        }
+        return status_of_launch();
+    }
     if (prec == NDF_PREC_BF16 && n_ref >= 2) {
         // the query latents once into the workspace, then every reference decoded
         // from them, kMultiRefs references per pass over the cache (bit for bit
@@ -1312,6 +1375,23 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    if (c->grid_only) {  // BF16, one fused pass per reference
+        if (prec != NDF_PREC_BF16) return NDF_E_UNSUPPORTED;
+        const bool sep = c->n_enc == 2;
+        for (int r = 0; r < n_ref; ++r) {
+            const InferArgs a = fused_args(c, q, Q, ref_v[r]);
+            const dim3 g(infer_blocks(n)), b(kInferThreads);
+            float *o = out + (int64_t)r * n;
+#define NDF_GO_POINTS(H, S) \
+    hipLaunchKernelGGL((infer_kernel<3, H, S, true>), g, b, 0, st, a, nullptr, n, nullptr, o, pos)
+            if (hash && sep) NDF_GO_POINTS(true, true);
+            else if (hash) NDF_GO_POINTS(true, false);
+            else if (sep) NDF_GO_POINTS(false, true);
+            else NDF_GO_POINTS(false, false);
+#undef NDF_GO_POINTS
+        }
+        return status_of_launch();
+    }
     if (c->n_enc == 1) {  // shared encoder: the reference latent in each workgroup
         if (prec == NDF_PREC_FP8_E4M3) {
             InferArgs8 a = make_args8(c, q, Q, 0);

@@ -340,10 +340,13 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const float *__restrict
 }
 
 // ------------------------------------------------------- small kernels ----
-__global__ void merge_fwd_kernel(const float *__restrict__ E, int64_t B, float *__restrict__ M) {
-    const int64_t n4 = B * kH / 4;
+// M[b] = E[b] * E[B + b] over latents of `width` features (128, or the 32 grid
+// features of a grid-only network)
+__global__ void merge_fwd_kernel(const float *__restrict__ E, int64_t B, float *__restrict__ M,
+                                 int width) {
+    const int64_t n4 = B * width / 4;
     const f32x4 *a = reinterpret_cast<const f32x4 *>(E);
-    const f32x4 *b = reinterpret_cast<const f32x4 *>(E + B * kH);
+    const f32x4 *b = reinterpret_cast<const f32x4 *>(E + B * width);
     f32x4 *m = reinterpret_cast<f32x4 *>(M);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -351,13 +354,13 @@ __global__ void merge_fwd_kernel(const float *__restrict__ E, int64_t B, float *
 }
 
 __global__ void merge_bwd_kernel(const float *__restrict__ dM, const float *__restrict__ E,
-                                 int64_t B, float *__restrict__ dE) {
-    const int64_t n4 = B * kH / 4;
+                                 int64_t B, float *__restrict__ dE, int width) {
+    const int64_t n4 = B * width / 4;
     const f32x4 *d = reinterpret_cast<const f32x4 *>(dM);
     const f32x4 *a = reinterpret_cast<const f32x4 *>(E);
-    const f32x4 *b = reinterpret_cast<const f32x4 *>(E + B * kH);
+    const f32x4 *b = reinterpret_cast<const f32x4 *>(E + B * width);
     f32x4 *da = reinterpret_cast<f32x4 *>(dE);
-    f32x4 *dbp = reinterpret_cast<f32x4 *>(dE + B * kH);
+    f32x4 *dbp = reinterpret_cast<f32x4 *>(dE + B * width);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x) {
         const f32x4 g = d[i];
@@ -523,6 +526,9 @@ GridOffs grid_offs(const NetOffsets &o) {
     return g;
 }
 
+void encode_merge_layer4(const ndf_net_config *c, const NetOffsets &o, const float *P, int64_t B,
+                         const TrainWS &t, hipStream_t st);
+
 // Forward pass into the workspace; with targets also the loss and gy.
 void forward(const ndf_net_config *c, const NetOffsets &o, const float *P, const int64_t *pairs,
              const float *pos, const float *targets, int64_t B, const TrainWS &t,
@@ -532,6 +538,26 @@ void forward(const ndf_net_config *c, const NetOffsets &o, const float *P, const
     const GridOffs go = grid_offs(o);
     hipLaunchKernelGGL(grid_fwd_kernel, dim3((unsigned)ceil_div(R * kL, kThreads)), dim3(kThreads),
                        0, st, P, go, g, c->n_enc, pairs, pos, B, t.H0);
+    if (c->grid_only) {
+        // the grid features are the latents: merge them and decode (W4 is [128][32])
+        hipLaunchKernelGGL(merge_fwd_kernel, dim3(gs_blocks(B * kK0 / 4)), dim3(kThreads), 0, st,
+                           t.H0, B, t.M, kK0);
+        hipLaunchKernelGGL((rows_mma_kernel<kK0, kH, EPI_BIAS_RELU>), dim3(mma_blocks(B)),
+                           dim3(kThreads), 0, st, t.M, B, P + o.W4, kK0, 1, P + o.b4, nullptr,
+                           t.D1);
+    } else {
+        encode_merge_layer4(c, o, P, B, t, st);
+    }
+    hipLaunchKernelGGL((rows_mma_kernel<kH, kH, EPI_BIAS_RELU>), dim3(mma_blocks(B)),
+                       dim3(kThreads), 0, st, t.D1, B, P + o.W5, kH, 1, P + o.b5, nullptr, t.D2);
+    hipLaunchKernelGGL(head_fwd_kernel, dim3((unsigned)ceil_div(B, kThreads)), dim3(kThreads), 0,
+                       st, t.D2, P + o.w6, P + o.b6, targets, B, t.y, t.gy, t.partial);
+}
+
+// Encoder layers of both endpoints, the latent product and decoder layer 4.
+void encode_merge_layer4(const ndf_net_config *c, const NetOffsets &o, const float *P, int64_t B,
+                         const TrainWS &t, hipStream_t st) {
+    const int64_t R = 2 * B;
     const int n_enc = c->n_enc;
     for (int e = 0; e < n_enc; ++e) {
         const int64_t r0 = n_enc == 1 ? 0 : e * B, rows = n_enc == 1 ? R : B;
@@ -546,13 +572,9 @@ void forward(const ndf_net_config *c, const NetOffsets &o, const float *P, const
                            P + o.b3[e], nullptr, t.E + r0 * kH);
     }
     hipLaunchKernelGGL(merge_fwd_kernel, dim3(gs_blocks(B * kH / 4)), dim3(kThreads), 0, st, t.E, B,
-                       t.M);
+                       t.M, kH);
     hipLaunchKernelGGL((rows_mma_kernel<kH, kH, EPI_BIAS_RELU>), dim3(mma_blocks(B)),
                        dim3(kThreads), 0, st, t.M, B, P + o.W4, kH, 1, P + o.b4, nullptr, t.D1);
-    hipLaunchKernelGGL((rows_mma_kernel<kH, kH, EPI_BIAS_RELU>), dim3(mma_blocks(B)),
-                       dim3(kThreads), 0, st, t.D1, B, P + o.W5, kH, 1, P + o.b5, nullptr, t.D2);
-    hipLaunchKernelGGL(head_fwd_kernel, dim3((unsigned)ceil_div(B, kThreads)), dim3(kThreads), 0,
-                       st, t.D2, P + o.w6, P + o.b6, targets, B, t.y, t.gy, t.partial);
 }
 
 }  // namespace
@@ -576,11 +598,13 @@ int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t
     };
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) uni(o.grid[e][l], o.cells[l] * kF, 1e-4f);
+        if (c->grid_only) continue;
         uni(o.W1[e], kH * kK0, sqrtf(6.f / kK0));
         uni(o.W2[e], kH * kH, sqrtf(6.f / kH));
         uni(o.W3[e], kH * kH, sqrtf(6.f / kH));
     }
-    uni(o.W4, kH * kH, sqrtf(6.f / kH));
+    const int k4 = c->grid_only ? kK0 : kH;  // inputs of the first decoder layer
+    uni(o.W4, kH * k4, sqrtf(6.f / k4));
     uni(o.W5, kH * kH, sqrtf(6.f / kH));
     uni(o.w6, kH, sqrtf(6.f / kH));
     return status_of_launch();
@@ -618,17 +642,37 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
                        G + o.W5, G + o.b5);
     hipLaunchKernelGGL((rows_mma_kernel<kH, kH, EPI_MASK>), dim3(mma_blocks(B)), dim3(kThreads), 0,
                        st, t.dA, B, P + o.W5, 1, kH, nullptr, t.D1, t.dB);
+    const GridGeom g = grid_geom(c);
+    const GridOffs go = grid_offs(o);
+    const int n_enc = c->n_enc;
+    if (c->grid_only) {
+        // W4 [128][32] on the merged grid features; the product rule gives the
+        // grid features' gradient directly
+        hipLaunchKernelGGL(wgrad_kernel<kK0>, dim3(wgrad_blocks(B)), dim3(kThreads), 0, st, t.dB,
+                           t.M, B, G + o.W4, G + o.b4);
+        hipLaunchKernelGGL((rows_mma_kernel<kH, kK0, EPI_PLAIN>), dim3(mma_blocks(B)),
+                           dim3(kThreads), 0, st, t.dB, B, P + o.W4, 1, kK0, nullptr, nullptr,
+                           t.dA);
+        hipLaunchKernelGGL(merge_bwd_kernel, dim3(gs_blocks(B * kK0 / 4)), dim3(kThreads), 0, st,
+                           t.dA, t.H0, B, t.dH0, kK0);
+        for (int e = 0; e < n_enc; ++e) {
+            const int64_t r0 = n_enc == 1 ? 0 : e * B, rows = n_enc == 1 ? R : B;
+            const int64_t items = rows * kL, per_block = kThreads / 64;
+            const int64_t gb = ceil_div(items, per_block);
+            hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)(gb < 16384 ? gb : 16384)),
+                               dim3(kThreads), 0, st, G, go, g, n_enc, pairs, pos, B, r0, rows,
+                               t.dH0);
+        }
+        return status_of_launch();
+    }
     hipLaunchKernelGGL(wgrad_kernel<kH>, dim3(wgrad_blocks(B)), dim3(kThreads), 0, st, t.dB, t.M, B,
                        G + o.W4, G + o.b4);
     hipLaunchKernelGGL((rows_mma_kernel<kH, kH, EPI_PLAIN>), dim3(mma_blocks(B)), dim3(kThreads), 0,
                        st, t.dB, B, P + o.W4, 1, kH, nullptr, nullptr, t.dA);
     // product rule across the merge: dE[b] = dM[b] * E[B+b], dE[B+b] = dM[b] * E[b]
     hipLaunchKernelGGL(merge_bwd_kernel, dim3(gs_blocks(B * kH / 4)), dim3(kThreads), 0, st, t.dA,
-                       t.E, B, t.dB);
+                       t.E, B, t.dB, kH);
     // encoder adjoint(s): with a shared encoder both branches accumulate into one set
-    const GridGeom g = grid_geom(c);
-    const GridOffs go = grid_offs(o);
-    const int n_enc = c->n_enc;
     for (int e = 0; e < n_enc; ++e) {
         const int64_t r0 = n_enc == 1 ? 0 : e * B, rows = n_enc == 1 ? R : B;
         float *dE = t.dB + r0 * kH, *dP2 = t.dA + r0 * kH, *dP1 = t.dB + r0 * kH;

@@ -647,3 +647,57 @@ def test_field_calls_capture_into_a_graph():
         assert torch.equal(out_c, want_c), i
         _infer_gpu(c, q, [other], V)  # eager work between replays
         torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------- grid-only network --
+@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 2)])
+def test_grid_only_network(name, n_enc):
+    """The grid-only network (encoder MLP omitted; the ablation of Sec. 6.3): its
+    parameter layout, initialisation, training forward and adjoint, and BF16
+    field and position inference against the FP64 oracle of the same network, to
+    the emulated rounding floors; FP8 and the query-latent calls are refused."""
+    cfg = gen.CONFIGS[name]
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    lay = gen.NetLayout.for_grid(*dims, n_enc=n_enc, grid_only=True)
+    flat = gen.make_net_params(lay, seed=2345, grid_scale=0.5, bias_scale=0.1)
+    c = ndf.net_config(*dims, lay.res, n_enc=n_enc, grid_only=True)
+    assert ndf.ndf_net_param_bytes(c) == 4 * lay.n_floats
+    net = nn.Net(flat, dims, lay.res, 8, 128, n_enc, grid_only=True)
+    P = torch.from_numpy(flat).cuda()
+    # initialisation: W4 He-uniform over its 32 inputs, no encoder tensors
+    P0 = torch.empty_like(P)
+    ndf.ndf_net_init(c, P0, None, 11)
+    w4 = lay.view(P0.cpu().numpy(), "W4")
+    assert w4.shape == (128, 32) and np.all(np.abs(w4) <= math.sqrt(6.0 / 32))
+    assert w4.std() > 0.5 * math.sqrt(6.0 / 32) / math.sqrt(3)
+    pairs = gen.random_pairs(cfg.n_vertices, 2048, seed=77)
+    y = _forward_gpu(c, P, pairs)
+    want, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    _check_floor(y, want, nn.forward(net, pairs[:, 0], pairs[:, 1], TRAIN_OPS)[0],
+                 f"grid-only forward {name} n_enc={n_enc}")
+    s = np.where(np.random.default_rng(6).random(len(pairs)) < 0.5, -1.0, 1.0)
+    t = want - s
+    loss_o, g_o, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    _, g_e, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t, TRAIN_OPS)
+    g, loss = _grad_gpu(c, P, pairs, t.astype(np.float32))
+    assert abs(loss - loss_o) <= 1e-2 * loss_o
+    check_grad_floor(lay, g, g_o.flat, g_e.flat, f"grid-only grad {name} n_enc={n_enc}")
+    V = cfg.n_vertices
+    refs = [cfg.ref_v, 0, V - 1]
+    q = _qparams(c, P, ndf.NDF_PREC_BF16)
+    out = _infer_gpu(c, q, refs, V).cpu().numpy()
+    for i, r in enumerate(refs):
+        _check_floor(out[i], nn.field(net, r), nn.field(net, r, rnd=BF16_OPS),
+                     f"grid-only field {name} n_enc={n_enc} ref={r}")
+    pos = gen.random_positions(1500, seed=78)
+    pts = _points_gpu(c, q, refs[:1], pos, ndf.NDF_PREC_BF16)
+    p64 = pos.astype(np.float64)
+    _check_floor(pts[0], nn.field_points(net, refs[0], p64),
+                 nn.field_points(net, refs[0], p64, BF16_OPS), f"grid-only points {name}")
+    with pytest.raises(ndf.NdfError):
+        _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    with pytest.raises(ndf.NdfError):
+        _infer_gpu(c, q, refs[:1], V, ndf.NDF_PREC_FP8_E4M3)
+    cache = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ndf.NdfError):
+        ndf.ndf_infer_latents(c, q, cache)

@@ -22,12 +22,12 @@ DIMS = (5, 4, 3)
 RES = [(2, 2, 2), (3, 3, 2), (4, 3, 3), (5, 4, 3)]
 
 
-def _layout(width=128, n_enc=1, dims=DIMS, res=RES):
-    return gen.NetLayout(dims[0], dims[1], dims[2], tuple(res), 8, width, n_enc)
+def _layout(width=128, n_enc=1, dims=DIMS, res=RES, grid_only=False):
+    return gen.NetLayout(dims[0], dims[1], dims[2], tuple(res), 8, width, n_enc, 0, grid_only)
 
 
-def _net(flat, width=128, n_enc=1, dims=DIMS, res=RES):
-    return nn.Net(flat, dims, res, 8, width, n_enc)
+def _net(flat, width=128, n_enc=1, dims=DIMS, res=RES, grid_only=False):
+    return nn.Net(flat, dims, res, 8, width, n_enc, grid_only=grid_only)
 
 
 def _cell_positions(R):
@@ -227,12 +227,12 @@ def test_two_encoder_swap_identity():
     assert np.max(np.abs(y - y_fwd)) > 1e-6           # the field itself is not symmetric
 
 
-@pytest.mark.parametrize("n_enc", [1, 2])
-def test_adjoint_vs_finite_differences(n_enc):
+@pytest.mark.parametrize("n_enc,grid_only", [(1, False), (2, False), (1, True), (2, True)])
+def test_adjoint_vs_finite_differences(n_enc, grid_only):
     width = 16
-    L = _layout(width=width, n_enc=n_enc)
+    L = _layout(width=width, n_enc=n_enc, grid_only=grid_only)
     flat = gen.make_net_params(L, seed=9, grid_scale=0.5, bias_scale=0.2).astype(np.float64)
-    net = _net(flat, width=width, n_enc=n_enc)
+    net = _net(flat, width=width, n_enc=n_enc, grid_only=grid_only)
     pairs = gen.random_pairs(60, 64, seed=8)
     y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
     t = y - 10.0                      # every residual positive: L = mean(y) + 10, smooth
@@ -244,10 +244,10 @@ def test_adjoint_vs_finite_differences(n_enc):
         n = int(np.prod(shape))
         d = np.zeros_like(flat)
         d[o:o + n] = rng.standard_normal(n)
-        lp = nn.l1_loss(nn.forward(_net(flat + h * d, width=width, n_enc=n_enc),
-                                   pairs[:, 0], pairs[:, 1])[0], t)
-        lm = nn.l1_loss(nn.forward(_net(flat - h * d, width=width, n_enc=n_enc),
-                                   pairs[:, 0], pairs[:, 1])[0], t)
+        lp = nn.l1_loss(nn.forward(_net(flat + h * d, width=width, n_enc=n_enc,
+                                        grid_only=grid_only), pairs[:, 0], pairs[:, 1])[0], t)
+        lm = nn.l1_loss(nn.forward(_net(flat - h * d, width=width, n_enc=n_enc,
+                                        grid_only=grid_only), pairs[:, 0], pairs[:, 1])[0], t)
         fd = (lp - lm) / (2 * h)
         an = float(np.dot(g.flat, d))
         assert abs(fd - an) <= 1e-6 * max(1e-3, abs(an)) + 1e-9, (key, fd, an)
@@ -448,3 +448,47 @@ def test_bf16_operand_rounding_floor():
         rel_g = np.linalg.norm(lay.view(gg.flat, name) - b) / nb
         assert rel_all < 0.15, name
         assert rel_g < 5e-3, name
+
+
+def test_grid_only_is_the_full_network_with_an_identity_encoder():
+    """The grid-only network (encoder MLP omitted, Sec. 6.3) equals a full network
+    whose encoder passes the grid features through unchanged: W1 = [I; -I; 0]
+    (so h1 = [relu(h0), relu(-h0)]), W2 = I on those 64 units, W3 = [I, -I] into
+    the first 32 latent units (relu(a) - relu(-a) = a exactly), and W4 of the
+    full network = the grid-only W4 on those units.  Outputs and the gradients of
+    the shared parameters (grids and decoder) agree."""
+    width, K = 128, 32
+    Lg = _layout(width=width, grid_only=True)
+    Lf = _layout(width=width)
+    fg = gen.make_net_params(Lg, seed=21, grid_scale=0.5, bias_scale=0.2).astype(np.float64)
+    ng = _net(fg, width=width, grid_only=True)
+    nf = _net(np.zeros(Lf.n_floats), width=width)
+    for l in range(4):
+        nf[("grid", 0, l)] = ng[("grid", 0, l)]
+    W1 = np.zeros((width, K))
+    W1[:K] = np.eye(K)
+    W1[K:2 * K] = -np.eye(K)
+    W2 = np.zeros((width, width))
+    W2[:2 * K, :2 * K] = np.eye(2 * K)
+    W3 = np.zeros((width, width))
+    W3[:K, :K] = np.eye(K)
+    W3[:K, K:2 * K] = -np.eye(K)
+    W4 = np.zeros((width, width))
+    W4[:, :K] = ng["W4"]
+    nf[("W1", 0)], nf[("W2", 0)], nf[("W3", 0)], nf["W4"] = W1, W2, W3, W4
+    for name in ("b4", "W5", "b5", "w6", "b6"):
+        nf[name] = ng[name]
+    V = DIMS[0] * DIMS[1] * DIMS[2]
+    pairs = gen.random_pairs(V, 200, seed=4)
+    yg, _ = nn.forward(ng, pairs[:, 0], pairs[:, 1])
+    yf, _ = nn.forward(nf, pairs[:, 0], pairs[:, 1])
+    np.testing.assert_allclose(yg, yf, rtol=1e-12, atol=1e-12)
+    t = yg - 1.0
+    _, gg, _ = nn.loss_and_grad(ng, pairs[:, 0], pairs[:, 1], t)
+    _, gf, _ = nn.loss_and_grad(nf, pairs[:, 0], pairs[:, 1], t)
+    for l in range(4):
+        np.testing.assert_allclose(gg[("grid", 0, l)], gf[("grid", 0, l)], rtol=1e-9,
+                                   atol=1e-12)
+    np.testing.assert_allclose(gg["W4"], gf["W4"][:, :K], rtol=1e-9, atol=1e-12)
+    for name in ("b4", "W5", "b5", "w6", "b6"):
+        np.testing.assert_allclose(gg[name], gf[name], rtol=1e-9, atol=1e-12)
