@@ -473,7 +473,11 @@ def main():
                                            refs64, cfg, out_nc)
         result["accuracy"] = acc
         log("bench: held-out errors of the trained fields")
-        result["config3"]["held_out"] = _held_out(ens, cfg, net, P, P_mi, ws_t, log)
+        result["config3"]["held_out"], held, r_held = _held_out(ens, cfg, net, P, P_mi, ws_t,
+                                                                 log)
+        log("bench: capacity sweep over the hash-table size")
+        result["capacity_sweep"] = _capacity_sweep(cfg, held, r_held, pearson_targets, ws_i,
+                                                   log)
         log("bench: gain of the trained field over the method without it")
         result["gain"] = _gain(ens, cfg, net, lay, sample, r_o, mi_o, out_n, out_mi, med, log,
                                pearson_targets)
@@ -720,7 +724,55 @@ def _held_out(ens, cfg, net, P, P_mi, ws_t, log):
             "ndf_max_abs_err_vs_oracle": float(np.max(np.abs(ym - mi_o))),
             "direct_gpu_targets_max_abs_err_vs_oracle": float(np.max(np.abs(dm - mi_o))),
             "best_constant_mae_vs_oracle": float(np.mean(np.abs(mi_o - np.median(mi_o))))}
-    return out
+    return out, held, r_o
+
+
+SWEEP_T = (14, 16, 18, 20, 22)
+SWEEP_STEPS = 600
+
+
+def _capacity_sweep(cfg, held, r_o, pearson_targets, ws_i, log):
+    """Model size against accuracy (Sec. 6.3, Fig. 5) on the synthetic ensemble:
+    the network with hash tables of 2^T cells (levels larger than that hashed; at
+    T = 22 every level of this grid is dense), each trained for SWEEP_STEPS steps
+    on the same Pearson targets, and its error on the 10^6 held-out pairs against
+    the FP64 oracle.  The MLP widths are fixed by the kernels (5 x 128), so only
+    the table size varies."""
+    import torch
+    import gen
+    from paper_2307_02203_amd import ndf
+    V = cfg.n_vertices
+    out = []
+    loss = torch.empty(1, device="cuda")
+    for T in SWEEP_T:
+        lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, log2_hashmap=T)
+        net = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay.res, log2_hashmap=T)
+        P = torch.empty(lay.n_floats, device="cuda")
+        opt = torch.empty(2 * lay.n_floats, device="cuda")
+        ndf.ndf_net_init(net, P, opt, 2320)
+        ws = torch.empty(ndf.train_ws_bytes(net, B_PAIRS) + lay.n_floats * 4 + 256,
+                         dtype=torch.uint8, device="cuda")
+        tr = _train(ndf, net, P, opt, SWEEP_STEPS, pearson_targets, 5000, ws, loss, "cuda", log,
+                    f"T={T}")
+        y = torch.empty(len(held), device="cuda")
+        for c0 in range(0, len(held), B_PAIRS):
+            pr = torch.as_tensor(held[c0:c0 + B_PAIRS], device="cuda")
+            ndf.ndf_net_forward(net, P, pr, y[c0:c0 + len(pr)], ws)
+        y = y.cpu().numpy().astype(np.float64)
+        q = torch.empty(ndf.ndf_net_qparam_bytes(net, ndf.NDF_PREC_BF16), dtype=torch.uint8,
+                        device="cuda")
+        ndf.ndf_net_quantize(net, P, ndf.NDF_PREC_BF16, q)
+        f = torch.empty((1, V), device="cuda")
+        ms = _timed(lambda it: ndf.ndf_infer_field(net, q, ndf.NDF_PREC_BF16, [cfg.ref_v], f,
+                                                   ws_i), 5, 1)
+        out.append({"log2_hashmap": T, "cells_per_level": [lay.cells(l) for l in range(4)],
+                    "param_mb": 4.0 * lay.n_floats / 1e6,
+                    "inference_param_mb": ndf.ndf_net_qparam_bytes(net, ndf.NDF_PREC_BF16) / 1e6,
+                    "held_out_mae_vs_oracle": float(np.mean(np.abs(y - r_o))),
+                    "final_l1_loss": tr["final_l1_loss"], "field_ms": float(np.median(ms))})
+        del P, opt, ws, q, f
+    return {"steps_per_model": SWEEP_STEPS, "lr_peak": LR, "held_out_pairs": len(held),
+            "models": out}
 
 
 # ------------------------------------------------------------------------ gain --
