@@ -307,8 +307,16 @@ int ndf_net_swap_encoders(const ndf_net_config *cfg, const float *params, float 
 /* Reduced-precision inference parameters (Sec. 5 evaluates the trained network
  * with 16-bit arithmetic): packed for `prec` (NDF_PREC_BF16 or
  * NDF_PREC_FP8_E4M3) from the FP32 parameters: BF16 grids, weights in MFMA
- * operand order, FP32 biases; FP8 adds E8M0 scales per output row and block of
- * 32 inputs.  One packed blob serves both precisions. */
+ * operand order, FP32 biases; FP8 adds E4M3 copies of layers 2..5 with E8M0
+ * scales per output row and block of 32 inputs, and one static power-of-two
+ * scale per layer input: the call runs the BF16 network on a fixed calibration
+ * set (32 references x 2048 queries, vertex (2 i + 1) V / (2 n) for i < n) and
+ * keeps M_l, the largest |input| of layer l = 2..5 (query-encoder activations,
+ * latent product, first decoder activation); inference then scales layer l's
+ * inputs by 2^-e_l, e_l the smallest exponent with 2 M_l <= 448 * 2^e_l, and
+ * clamps them to +-448 * 2^e_l.  The four M_l (FP32 bits) are the first 16
+ * bytes of the blob's last 256.  One packed blob serves both precisions
+ * (grid-only networks: BF16 only, NDF_E_UNSUPPORTED for FP8). */
 size_t ndf_net_qparam_bytes(const ndf_net_config *cfg, int32_t prec);
 int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t prec,
                      void *qparams, void *stream);
@@ -321,7 +329,7 @@ int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t pre
  * encoder 0's layers), so a BF16 field is a single launch; FP8 with two encoders
  * computes the reference latents in a separate launch first.  BF16 with
  * n_ref >= 2: the query latents of all vertices are computed once into the
- * workspace (ndf_infer_latents) and every launch then decodes up to 32
+ * workspace (ndf_infer_latents) and every launch then decodes up to 16
  * references per read of them (ndf_infer_field_cached); the fields are the
  * single-reference fields bit for bit.  FP8 runs one fused pass per reference.
  * The call enqueues kernels only (no copies or memsets), so it can be captured
@@ -339,7 +347,7 @@ int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec
  * encoder for every grid vertex into `cache` (device, ndf_infer_latent_bytes
  * bytes, caller-owned; the fused kernel's register order, 256 bytes per
  * vertex); ndf_infer_field_cached then runs only the merge and the decoder per
- * reference, up to 32 references per launch, each launch reading every cached
+ * reference, up to 16 references per launch, each launch reading every cached
  * latent once, and gives the same values as ndf_infer_field with NDF_PREC_BF16,
  * bit for bit.  ws: ndf_workspace_bytes(NDF_OP_INFER_CACHED, NULL, cfg, n_ref,
  * NDF_PREC_BF16) bytes (the reference latents). */

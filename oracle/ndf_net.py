@@ -257,17 +257,57 @@ def bf16_inference_operands():
     return Operands(latent=round_bf16, grid=round_bf16)
 
 
-def fp8_inference_operands():
-    """Inference with the first layer in BF16 and layers 2..5 in microscaled E4M3
-    (blocks of 32 along each product's input axis, for weights per output row),
-    bf16 grid features, latents rounded to bf16 before their product."""
+CAL_REFS = 32       # calibration set of the static E4M3 activation scales
+CAL_QUERIES = 2048
+
+
+def calibration_vertices(n, V):
+    """n vertices spread evenly over [0, V): (2 i + 1) V / (2 n), i < n (floor)."""
+    i = np.arange(n, dtype=np.int64)
+    return ((2 * i + 1) * V) // (2 * n)
+
+
+def fp8_activation_maxima(net):
+    """Largest |input| of layers 2..5 (query encoder's h1 and h2, the latent
+    product m, the decoder's d1) over the calibration set (CAL_REFS references
+    x CAL_QUERIES queries), run through the BF16 inference operands and read
+    as the BF16 values those layers pass on."""
+    V = net.nx * net.ny * net.nz
+    refs = calibration_vertices(CAL_REFS, V)
+    qs = calibration_vertices(CAL_QUERIES, V)
+    ops = bf16_inference_operands()
+    m = np.zeros(4)
+    for r in refs:
+        _, c = forward(net, np.full(qs.shape, r, dtype=np.int64), qs, ops)
+        for i, x in enumerate((c["B"]["h1"], c["B"]["h2"], c["m"], c["d1"])):
+            m[i] = max(m[i], float(np.max(np.abs(round_bf16(x)))))
+    return m
+
+
+def fp8_activation_scales(maxima):
+    """Static power-of-two scales 2^e of the layer inputs: e the smallest exponent
+    with twice the calibrated maximum within E4M3's range (headroom for inputs
+    beyond the calibration set, which saturate at +-448 2^e)."""
+    return np.ldexp(1.0, e4m3_scale_exp(2.0 * np.asarray(maxima, dtype=np.float64)))
+
+
+def fp8_inference_operands(net, maxima=None):
+    """Inference with the first layer in BF16 and layers 2..5 in E4M3: weights
+    microscaled (blocks of 32 inputs per output row), activations with one static
+    scale s_l per layer input (fp8_activation_scales of the calibrated maxima):
+    x -> s_l round_e4m3(x / s_l), saturating; bf16 grid features, FP32 latents
+    (their rounding is far below E4M3's and is not emulated)."""
+    s = fp8_activation_scales(fp8_activation_maxima(net) if maxima is None else maxima)
+
     def act(x, layer):
-        return round_bf16(x) if layer == 1 else round_mx_e4m3(x)
+        if layer == 1:
+            return round_bf16(x)
+        return s[layer - 2] * round_e4m3(x / s[layer - 2])
 
     def weight(W, layer):
         return round_bf16(W) if layer == 1 else round_mx_e4m3(W)
 
-    return Operands(act=act, weight=weight, latent=round_bf16, grid=round_bf16)
+    return Operands(act=act, weight=weight, grid=round_bf16)
 
 
 def _lin(x, W, layer, rnd):

@@ -34,6 +34,7 @@ struct QLayout {
     // FP8 (OCP E4M3) copies of W2..W5 in 32x32x64 operand order + per-row scales
     int64_t q2[2], q3[2], q4, q5;  // fp8 fragments, 16 KB each
     int64_t s2[2], s3[2], s4, s5;  // int32 [128][4] E8M0 scale bytes per row and 32-k block
+    int64_t amax;                  // int32 [4]: calibrated max |input| of layers 2..5
     int64_t total;
 };
 
@@ -84,6 +85,7 @@ static QLayout qlayout(const ndf_net_config *c) {
     q.q5 = take(kH * kH);
     q.s4 = take(kH * 4 * 4);
     q.s5 = take(kH * 4 * 4);
+    q.amax = take(4 * 4);
     q.total = pos;
     return q;
 }
@@ -198,6 +200,12 @@ __global__ void pack_fp8_kernel(const float *__restrict__ W, uint32_t *__restric
     pack_row_fp8(W + (int64_t)o * kH, o, frag, se);
 }
 
+static void launch_calibrate(const ndf_net_config *c, const QLayout &q, char *Q, hipStream_t st);
+
+__global__ void zero_i32_kernel(int *__restrict__ p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 __global__ void copy_f32_kernel(const float *__restrict__ src, int n, float *__restrict__ dst) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -257,6 +265,9 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
     }
     fp8(P + o.W4, q.q4, q.s4);
     fp8(P + o.W5, q.q5, q.s5);
+    // static activation scales: the largest |input| of layers 2..5 over the
+    // calibration set, measured with the BF16 layers just packed
+    launch_calibrate(c, q, Q, st);
     return status_of_launch();
 }
 
@@ -425,6 +436,32 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 // SEP: a field mode of a two-encoder network that computes the reference latent in
 // the prologue: the reference encoder's layers are staged first, then replaced
 // by the query encoder's.
+// Calibration set of the FP8 activation scales (MODE 4): kCalRefs references and
+// kCalQueries queries spread evenly over the vertex range, v = (2 i + 1) V / (2 n).
+constexpr int kCalRefs = 32;
+constexpr int kCalQueries = 2048;
+__host__ __device__ inline int64_t cal_vertex(int64_t i, int64_t n, int64_t V) {
+    return ((2 * i + 1) * V) / (2 * n);
+}
+
+// Largest |value| of a wave's bf16 operands (the rows of valid queries), folded
+// into *dst with an integer max on the float bits (non-negative floats order
+// like their bits).
+template <int KB>
+__device__ __forceinline__ void wave_max_into(const bf16x8 (&v)[8][2], const bool (&ok)[2],
+                                              int *__restrict__ dst) {
+    float m = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (ok[q]) m = fmaxf(m, fabsf((float)v[kb][q][e]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(dst, __float_as_int(m));
+}
+
 // GO: a grid-only network (the encoder MLP omitted): the latent is the gathered
 // grid features (32, in the gather's natural feature order 16 kb + 8 h + e), the
 // product with the reference's feeds W4 [128][32] (held in s_w1) and W5 sits in
@@ -436,12 +473,16 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const float *__restrict__ ref_lat,
                                                               float *__restrict__ out,
                                                               const float *__restrict__ qpos) {
-    constexpr bool kField = MODE == 0 || MODE == 3;
+    // MODE 4: calibration of the FP8 activation scales: workgroup w takes reference
+    // cal_vertex(w, gridDim.x) against the nq calibration queries and folds the
+    // largest |input| of layers 2..5 into ((int *)out)[0..3]
+    constexpr bool kField = MODE == 0 || MODE == 3 || MODE == 4;
     __shared__ bf16x8 s_w1[kFragW1];
     __shared__ bf16x8 s_w[4][kFragW];
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
+    const int64_t fref = MODE == 4 ? cal_vertex(blockIdx.x, gridDim.x, A.V) : A.fuse_ref;
 
     const int tid = threadIdx.x;
     if (GO) {
@@ -484,7 +525,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                 const uint32_t hm = HASH ? (h ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
                 int idx[8];
                 float w[8];
-                corners32<HASH>(A.g, R, A.fuse_ref, idx, w, hm);
+                corners32<HASH>(A.g, R, fref, idx, w, hm);
                 float sf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int cn = 0; cn < 8; ++cn) {
@@ -525,8 +566,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
-    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
-         tile += (int64_t)gridDim.x * kInferWaves) {
+    // MODE 4: every workgroup takes all calibration tiles (against its own reference)
+    const int64_t t0 = MODE == 4 ? wave : (int64_t)blockIdx.x * kInferWaves + wave;
+    const int64_t tstep = MODE == 4 ? kInferWaves : (int64_t)gridDim.x * kInferWaves;
+    for (int64_t tile = t0; tile < ntiles; tile += tstep) {
         const int64_t row0 = tile * 64;
         // opaque per tile, so the per-lane LDS addresses derived from it are
         // formed inside the loop (base + immediate) instead of hoisted and spilled
@@ -539,7 +582,9 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         for (int q = 0; q < 2; ++q) {
             const int64_t n = row0 + q * 32 + jl;
             ok[q] = n < nq;
-            vq[q] = ok[q] && MODE != 3 ? (qlist ? qlist[n] : n) : 0;
+            vq[q] = ok[q] && MODE != 3 ? (MODE == 4 ? cal_vertex(n, nq, A.V)
+                                                    : (qlist ? qlist[n] : n))
+                                      : 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) pq[q][a] = MODE == 3 && ok[q] ? qpos[3 * n + a] : 0.f;
         }
@@ -593,6 +638,21 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                      h4);
             dense_layer<8, LAY_HEAD>(s_w[3], s_b[4], s_ref, s_w6, a, b, part, nullptr, row0, ok,
                                      lane, h4);
+        } else if (MODE == 4) {
+            int *amax = reinterpret_cast<int *>(out);
+            dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok,
+                                     lane, h4);
+            wave_max_into<8>(b, ok, amax + 0);
+            dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok,
+                                     lane, h4);
+            wave_max_into<8>(a, ok, amax + 1);
+            dense_layer<8, LAY_LATENT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, nullptr, row0, ok,
+                                       lane, h4);
+            wave_max_into<8>(b, ok, amax + 2);
+            dense_layer<8, LAY_RELU>(s_w[2], s_b[3], s_ref, s_w6, b, a, part, nullptr, row0, ok,
+                                     lane, h4);
+            wave_max_into<8>(a, ok, amax + 3);
+            continue;
         } else {
         dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
         dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
@@ -654,29 +714,42 @@ __device__ __forceinline__ int cvt_fp8x2(int w, float a, float b, float s) {
 }
 
 // The 32 values of one lane (f(o, r) = output block 2 kb + o, row r of the lane;
-// byte t = 16 o + r) -> E4M3 with one E8M0 scale per output block: the block's
-// 32 rows sit 16 in lane l and 16 in lane l ^ 32, which share the block maximum.
-// mbits[o]: the lane's max |value| of block o as float bits (non-negative).  The
-// lane half h supplies the MFMA scale of block o = h (the hardware's scale block
-// h is bytes 16 h .. 16 h + 15 of both lane halves).
+// byte t = 16 o + r) -> E4M3 with the layer's static activation scale s (the
+// conversion divides by s; the caller has clamped the values to [-448 s, 448 s],
+// so none overflows).
 template <typename F>
-__device__ __forceinline__ void quant_block(F f, int (&mbits)[2], int h, i32x8 &out,
-                                            int &sbyte) {
-    float s[2];
-    int e[2];
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        const int m = max(mbits[o], __shfl_xor(mbits[o], 32, 64));
-        e[o] = e4m3_block_exp(__int_as_float(m));
-        s[o] = __uint_as_float((uint32_t)(e[o] + 127) << 23);
-    }
+__device__ __forceinline__ void quant_static(F f, float s, i32x8 &out) {
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         const int o = d >> 2, r = 4 * (d & 3);
-        const int w = cvt_fp8x2<false>(0, f(o, r), f(o, r + 1), s[o]);
-        out[d] = cvt_fp8x2<true>(w, f(o, r + 2), f(o, r + 3), s[o]);
+        const int w = cvt_fp8x2<false>(0, f(o, r), f(o, r + 1), s);
+        out[d] = cvt_fp8x2<true>(w, f(o, r + 2), f(o, r + 3), s);
+        // pinned here: left free, the conversions sink to their uses in the next
+        // layer and keep all the FP32 accumulators alive until then
+        asm volatile("" : "+v"(out[d]));
     }
-    sbyte = (h ? e[1] : e[0]) + 127;
+}
+
+// Static activation scales of the FP8 layers (inputs of layers 2..5): 2^e with e
+// the smallest exponent for which twice the calibrated maximum |activation| stays
+// within E4M3's 448 (ndf_net_quantize measures the maxima on a fixed calibration
+// set; twice leaves headroom for inputs beyond it, which are clamped).
+struct ActScales {
+    float s[4];    // 2^e per layer input (layers 2, 3, 4, 5)
+    float clip[4]; // 448 * s
+    int sbyte[4];  // E8M0 byte 127 + e (the MFMA's B-operand scale)
+};
+
+__device__ __forceinline__ ActScales act_scales(const int *__restrict__ amax) {
+    ActScales a;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int e = e4m3_block_exp(2.0f * __int_as_float(amax[l]));
+        a.s[l] = __uint_as_float((uint32_t)(e + 127) << 23);
+        a.clip[l] = 448.0f * a.s[l];
+        a.sbyte[l] = e + 127;
+    }
+    return a;
 }
 
 struct InferArgs8 {
@@ -684,6 +757,7 @@ struct InferArgs8 {
     const bf16x8 *w1;
     const i32x8 *q[4];    // W2..W5 fp8 fragments
     const int *se[4];     // their E8M0 bytes [128][4] (row, 32-input block)
+    const int *amax;      // calibrated max |input| of layers 2..5 (float bits)
     const float *b[5];
     const float *w6;
     const float *b6;
@@ -697,9 +771,11 @@ template <int KIND, bool BF16IN>
 __device__ __forceinline__ void dense_layer_fp8(
     const bf16x8 *__restrict__ w16, const i32x8 *__restrict__ w8, const int *__restrict__ se,
     const float *__restrict__ bias, const float *__restrict__ ref, const float *__restrict__ w6,
-    const bf16x8 (&in16)[2][2], const i32x8 (&in8)[2][2], const int (&sin)[2][2],
-    i32x8 (&out8)[2][2], int (&sout)[2][2], float (&part)[2], float *__restrict__ lat_out,
-    int64_t row0, const bool (&ok)[2], int lane, int h4) {
+    const bf16x8 (&in16)[2][2], const i32x8 (&in8)[2][2], int sin, i32x8 (&out8)[2][2],
+    float so, float clip, float (&part)[2], float *__restrict__ lat_out, int64_t row0,
+    const bool (&ok)[2], int lane, int h4) {
+    // sin: the E8M0 scale byte of this layer's inputs; so, clip: the scale of the
+    // next layer's inputs and 448 so
     __builtin_amdgcn_sched_barrier(0);
     const float *bias_h = bias + h4;
     const float *ref_h = ref + h4;
@@ -722,7 +798,7 @@ __device__ __forceinline__ void dense_layer_fp8(
 #pragma unroll
                 for (int kb = 0; kb < 2; ++kb)
                     acc = mfma_fp8(w8[(ob * 2 + kb) * 64 + lane], se[(32 * ob + il) * 4 + 2 * kb + hh],
-                                   in8[kb][q], sin[kb][q], acc);
+                                   in8[kb][q], sin, acc);
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const f32x4 wv = *reinterpret_cast<const f32x4 *>(w6_h + 32 * ob + 8 * g);
@@ -762,8 +838,8 @@ __device__ __forceinline__ void dense_layer_fp8(
                 for (int kb = 0; kb < 2; ++kb) {
                     const i32x8 a = w8[(ob * 2 + kb) * 64 + lane];
                     const int sa = se[(32 * ob + il) * 4 + 2 * kb + hh];
-                    acc[o][0] = mfma_fp8(a, sa, in8[kb][0], sin[kb][0], acc[o][0]);
-                    acc[o][1] = mfma_fp8(a, sa, in8[kb][1], sin[kb][1], acc[o][1]);
+                    acc[o][0] = mfma_fp8(a, sa, in8[kb][0], sin, acc[o][0]);
+                    acc[o][1] = mfma_fp8(a, sa, in8[kb][1], sin, acc[o][1]);
                 }
             }
             // fetch one output block's weights at a time (32 registers, not 64)
@@ -781,17 +857,11 @@ __device__ __forceinline__ void dense_layer_fp8(
                             dst[32 * (2 * op + o) + 8 * (r >> 2) + (r & 3)] = acc[o][q][r];
                 }
             } else if (KIND == LAY_RELU) {
-                // max of the ReLU outputs straight from the raw bits: negative
-                // floats are negative integers and lose against the initial 0
-                int mb[2] = {0, 0};
-#pragma unroll
-                for (int o = 0; o < 2; ++o)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) mb[o] = max(mb[o], __float_as_int(acc[o][q][r]));
-                quant_block([&](int o, int r) { return relu_f32(acc[o][q][r]); }, mb, hh,
-                            out8[op][q], sout[op][q]);
+                // ReLU and the clamp to the E4M3 range in one median of three
+                quant_static([&](int o, int r) {
+                    return __builtin_amdgcn_fmed3f(acc[o][q][r], 0.f, clip);
+                }, so, out8[op][q]);
             } else {  // LAY_LATENT: product with the reference latent
-                int mb[2] = {0, 0};
 #pragma unroll
                 for (int o = 0; o < 2; ++o)
 #pragma unroll
@@ -799,14 +869,11 @@ __device__ __forceinline__ void dense_layer_fp8(
                         const f32x4 rv = *reinterpret_cast<const f32x4 *>(
                             ref_h + 32 * (2 * op + o) + 8 * g);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const float y = acc[o][q][4 * g + i] * rv[i];
-                            acc[o][q][4 * g + i] = y;
-                            mb[o] = max(mb[o], __float_as_int(y) & 0x7fffffff);
-                        }
+                        for (int i = 0; i < 4; ++i)
+                            acc[o][q][4 * g + i] = __builtin_amdgcn_fmed3f(
+                                acc[o][q][4 * g + i] * rv[i], -clip, clip);
                     }
-                quant_block([&](int o, int r) { return acc[o][q][r]; }, mb, hh, out8[op][q],
-                            sout[op][q]);
+                quant_static([&](int o, int r) { return acc[o][q][r]; }, so, out8[op][q]);
             }
             // one query half at a time (keeps the epilogue's temporaries few)
             __builtin_amdgcn_sched_barrier(0);
@@ -844,6 +911,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         s_w6[i] = A.w6[i];
         s_ref[i] = kField && !fuse ? ref_lat[i] : 0.f;
     }
+    const ActScales as = act_scales(A.amax);
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
@@ -881,15 +949,16 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                 g16[kb][0] = g16[kb][1] = t;
             }
             i32x8 a8[2][2], b8[2][2];
-            int sa[2][2], sb[2][2];
             float part[2] = {0.f, 0.f};
             dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8,
-                                            sb, a8, sa, part, nullptr, 0, ok, lane, h4);
+                                            0, a8, as.s[0], as.clip[0], part, nullptr, 0, ok,
+                                            lane, h4);
             dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16,
-                                             a8, sa, b8, sb, part, nullptr, 0, ok, lane, h4);
+                                             a8, as.sbyte[0], b8, as.s[1], as.clip[1], part,
+                                             nullptr, 0, ok, lane, h4);
             dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6,
-                                                   g16, b8, sb, a8, sa, part, s_ref, 0, ok, lane,
-                                                   h4);
+                                                   g16, b8, as.sbyte[1], a8, 0.f, 0.f, part,
+                                                   s_ref, 0, ok, lane, h4);
         }
         __syncthreads();
     }
@@ -946,26 +1015,31 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
             }
         }
         i32x8 a8[2][2], b8[2][2];
-        int sa[2][2], sb[2][2];
         float part[2] = {0.f, 0.f};
-        dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8, sb,
-                                        a8, sa, part, nullptr, row0, ok, lane, h4);
+        dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8, 0,
+                                        a8, as.s[0], as.clip[0], part, nullptr, row0, ok, lane,
+                                        h4);
         if (MODE == 1) {
             dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16,
-                                             a8, sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+                                             a8, as.sbyte[0], b8, as.s[1], as.clip[1], part,
+                                             nullptr, row0, ok, lane, h4);
             dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6,
-                                                   g16, b8, sb, a8, sa, part, out, row0, ok, lane,
-                                                   h4);
+                                                   g16, b8, as.sbyte[1], a8, 0.f, 0.f, part, out,
+                                                   row0, ok, lane, h4);
             continue;
         }
         dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16, a8,
-                                         sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+                                         as.sbyte[0], b8, as.s[1], as.clip[1], part, nullptr, row0,
+                                         ok, lane, h4);
         dense_layer_fp8<LAY_LATENT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6, g16, b8,
-                                           sb, a8, sa, part, nullptr, row0, ok, lane, h4);
+                                           as.sbyte[1], a8, as.s[2], as.clip[2], part, nullptr,
+                                           row0, ok, lane, h4);
         dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[2], s_e[2], s_b[3], s_ref, s_w6, g16, a8,
-                                         sa, b8, sb, part, nullptr, row0, ok, lane, h4);
+                                         as.sbyte[2], b8, as.s[3], as.clip[3], part, nullptr, row0,
+                                         ok, lane, h4);
         dense_layer_fp8<LAY_HEAD, false>(nullptr, s_q[3], s_e[3], s_b[4], s_ref, s_w6, g16, b8,
-                                         sb, a8, sa, part, nullptr, row0, ok, lane, h4);
+                                         as.sbyte[3], a8, 0.f, 0.f, part, nullptr, row0, ok, lane,
+                                         h4);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
@@ -1127,6 +1201,7 @@ static InferArgs8 make_args8(const ndf_net_config *c, const QLayout &q, const ch
     a.se[1] = (const int *)(Q + q.s3[e]);
     a.se[2] = (const int *)(Q + q.s4);
     a.se[3] = (const int *)(Q + q.s5);
+    a.amax = (const int *)(Q + q.amax);
     a.b[0] = (const float *)(Q + q.b1[e]);
     a.b[1] = (const float *)(Q + q.b2[e]);
     a.b[2] = (const float *)(Q + q.b3[e]);
@@ -1182,6 +1257,25 @@ static bool any_hashed(const ndf_net_config *c) {
     for (int l = 0; l < kL; ++l)
         if (level_hashed(c, l)) return true;
     return false;
+}
+
+// Static activation scales of the E4M3 layers: the largest |input| of layers
+// 2..5 over a fixed calibration set (kCalRefs references x kCalQueries
+// queries spread evenly over the grid), run through the BF16 layers.
+static void launch_calibrate(const ndf_net_config *c, const QLayout &q, char *Q, hipStream_t st) {
+    int *amax = (int *)(Q + q.amax);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, amax, 4);
+    const InferArgs a = fused_args(c, q, Q, 0);
+    const dim3 g(kCalRefs), b(kInferThreads);
+    const bool hash = any_hashed(c), sep = c->n_enc == 2;
+#define NDF_CAL(H, S) \
+    hipLaunchKernelGGL((infer_kernel<4, H, S>), g, b, 0, st, a, nullptr, (int64_t)kCalQueries, \
+                       nullptr, (float *)amax, nullptr)
+    if (hash && sep) NDF_CAL(true, true);
+    else if (hash) NDF_CAL(true, false);
+    else if (sep) NDF_CAL(false, true);
+    else NDF_CAL(false, false);
+#undef NDF_CAL
 }
 
 static unsigned infer_blocks(int64_t nq) {

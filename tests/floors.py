@@ -23,7 +23,12 @@ MAX_FACTOR = 2.0     # largest element error against the emulation's largest
 
 TRAIN_OPS = nn.Operands()                    # training kernels: bf16 operands
 BF16_OPS = nn.bf16_inference_operands()      # inference: also bf16 latents
-FP8_OPS = nn.fp8_inference_operands()        # inference, layers 2-5 in MX E4M3
+
+
+def fp8_ops(net):
+    """Inference with layers 2-5 in E4M3 (static activation scales from the
+    network's own calibration)."""
+    return nn.fp8_inference_operands(net)
 
 
 def _log(*a):

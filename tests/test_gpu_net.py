@@ -33,7 +33,7 @@ pytestmark = pytest.mark.gpu
 
 sys.path.insert(0, __file__.rsplit("/", 1)[0])
 from test_oracle_net import hand_built_params, hand_built_value, DIMS as HB_DIMS, RES as HB_RES  # noqa: E402
-from floors import (BF16_OPS, FP8_OPS, TRAIN_OPS, check_floor as _check_floor,  # noqa: E402
+from floors import (BF16_OPS, TRAIN_OPS, fp8_ops, check_floor as _check_floor,  # noqa: E402
                     check_grad_floor)
 
 
@@ -373,11 +373,18 @@ def test_infer_field_fp8_parity(name, n_enc):
     V = cfg.n_vertices
     refs = [cfg.ref_v, 0, V - 1]
     q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    # the calibrated maxima of layers 2..5 (the blob's last 256 bytes start with
+    # them) against the oracle's, up to one bf16 step (FP32 summation order)
+    m_gpu = q[-256:-240].cpu().numpy().view(np.float32).astype(np.float64)
+    m_o = nn.fp8_activation_maxima(net)
+    _log(f"calibrated maxima gpu {m_gpu} oracle {m_o}")
+    assert np.all(np.abs(m_gpu - m_o) <= 2.0 ** -7 * m_o)
+    ops8 = nn.fp8_inference_operands(net, m_gpu)
     out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
     out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16).cpu().numpy()
     for i, r in enumerate(refs):
         want = nn.field(net, r)
-        _check_floor(out8[i], want, nn.field(net, r, rnd=FP8_OPS),
+        _check_floor(out8[i], want, nn.field(net, r, rnd=ops8),
                      f"fp8 {name} n_enc={n_enc} ref={r}")
         _check_floor(out16[i], want, nn.field(net, r, rnd=BF16_OPS),
                      f"bf16 of fp8 blob {name} n_enc={n_enc} ref={r}")
@@ -392,7 +399,7 @@ def test_infer_fp8_paper_size_sampled():
     sample = gen.random_vertices(V, 3000, seed=32)
     g = out[0, torch.as_tensor(sample, device="cuda")].cpu().numpy()
     want, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample)
-    emul, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample, FP8_OPS)
+    emul, _ = nn.forward(net, np.full(len(sample), cfg.ref_v), sample, fp8_ops(net))
     _check_floor(g, want, emul, "fp8 paper")
 
 
@@ -483,12 +490,13 @@ def test_infer_points_parity(name, n_enc):
     q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
     out16 = _points_gpu(c, q, refs, pos, ndf.NDF_PREC_BF16)
     out8 = _points_gpu(c, q, refs, pos, ndf.NDF_PREC_FP8_E4M3)
+    ops8 = fp8_ops(net)
     for i, r in enumerate(refs):
         p64 = pos.astype(np.float64)
         want = nn.field_points(net, r, p64)
         _check_floor(out16[i], want, nn.field_points(net, r, p64, BF16_OPS),
                      f"points {name} n_enc={n_enc} ref={r}")
-        _check_floor(out8[i], want, nn.field_points(net, r, p64, FP8_OPS),
+        _check_floor(out8[i], want, nn.field_points(net, r, p64, ops8),
                      f"points fp8 {name} n_enc={n_enc} ref={r}")
     field = _infer_gpu(c, q, refs, V).cpu().numpy()[:, vs]
     for i in range(len(refs)):
@@ -572,11 +580,12 @@ def test_hash_grid_inference(n_enc):
     q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
     out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
     out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
+    ops8 = fp8_ops(net)
     for i, r in enumerate(refs):
         want = nn.field(net, r)
         _check_floor(out16[i].cpu().numpy(), want, nn.field(net, r, rnd=BF16_OPS),
                      f"hash infer n_enc={n_enc} ref={r}")
-        _check_floor(out8[i], want, nn.field(net, r, rnd=FP8_OPS),
+        _check_floor(out8[i], want, nn.field(net, r, rnd=ops8),
                      f"hash infer fp8 n_enc={n_enc} ref={r}")
     pos = gen.random_positions(2000, seed=73)
     pts = _points_gpu(c, q, refs[:1], pos, ndf.NDF_PREC_BF16)

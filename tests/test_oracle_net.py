@@ -398,6 +398,57 @@ def test_e4m3_block_scale():
     assert np.all(np.abs(bq - b) <= 2.0 ** -4 * b)
 
 
+def test_calibration_vertices():
+    v = nn.calibration_vertices(4, 100)
+    np.testing.assert_array_equal(v, [12, 37, 62, 87])   # (2 i + 1) * 100 / 8
+    v = nn.calibration_vertices(2048, 1_760_000)
+    assert v[0] == 429 and v[-1] == 1_759_570 and np.all(np.diff(v) > 0)
+
+
+def test_fp8_static_activation_scales():
+    """Static E4M3 activation scales: s_l = 2^e with e the smallest exponent for
+    which twice the calibrated maximum fits in 448 s_l, so no calibration input
+    saturates; values beyond 448 s_l saturate.  Moving a power of two from W2 into
+    W1 and b1 (ReLU is positively homogeneous) multiplies the first calibrated
+    maximum by it, leaves the others, and leaves the emulated E4M3 field bit for
+    bit as it was, which fails if a layer's scale is applied to another layer's
+    input or the maxima are taken from the wrong activations."""
+    cfg = gen.CONFIGS["tiny"]
+    lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz)
+    flat = gen.make_net_params(lay, seed=2329, grid_scale=0.5, bias_scale=0.1)
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    net = nn.Net(flat, dims, lay.res)
+    M = nn.fp8_activation_maxima(net)
+    assert np.all(M > 0)
+    s = nn.fp8_activation_scales(M)
+    assert np.all(2 * M <= 448 * s) and np.all(448 * s < 4 * M)
+    ops = nn.fp8_inference_operands(net, M)
+    x = np.array([0.0, 100 * s[1], 448 * s[1], 449 * s[1], -1e9])
+    np.testing.assert_array_equal(ops.act(x, 3),
+                                  [0.0, 96 * s[1], 448 * s[1], 448 * s[1], -448 * s[1]])
+    k = 2.0 ** 3
+    f2 = flat.copy()
+    lay.view(f2, "W1_0")[:] *= k
+    lay.view(f2, "b1_0")[:] *= k
+    lay.view(f2, "W2_0")[:] /= k
+    net2 = nn.Net(f2, dims, lay.res)
+    M2 = nn.fp8_activation_maxima(net2)
+    np.testing.assert_array_equal(M2, M * np.array([k, 1, 1, 1]))
+    ref = cfg.ref_v
+    y1 = nn.field(net, ref, rnd=ops)
+    y2 = nn.field(net2, ref, rnd=nn.fp8_inference_operands(net2, M2))
+    np.testing.assert_array_equal(y1, y2)
+    # a different scale for layer 2 (the maxima of another layer) changes the field
+    y3 = nn.field(net2, ref, rnd=nn.fp8_inference_operands(net2, M))
+    assert not np.array_equal(y1, y3)
+    # and the emulated error is an E4M3 error: well above BF16's, well below O(1)
+    y = nn.field(net, ref)
+    rel = np.linalg.norm(y1 - y) / np.linalg.norm(y)
+    rel16 = np.linalg.norm(nn.field(net, ref, rnd=nn.bf16_inference_operands()) - y) / \
+        np.linalg.norm(y)
+    assert 2 * rel16 < rel < 0.2
+
+
 def test_unrounded_operands_reproduce_the_fp64_oracle():
     """An Operands whose every rounding is the identity gives the plain FP64 network
     and gradients bit for bit, so the rounding hooks change no arithmetic."""
