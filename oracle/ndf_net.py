@@ -238,7 +238,8 @@ class Operands:
     """Rounding of the factors of each product, per layer (1..3 encoder, 4..5
     decoder): act(x, layer) for activations entering a forward layer (rows are
     positions, the last axis is the layer's input), weight(W, layer) for W[out][in]
-    (both directions), grad(g) for the gradient operand of the adjoint products,
+    (both directions), grad(g) for the gradient operand of the adjoint products
+    and of the weight and bias gradients (and d2 in the head's weight gradient),
     latent(e) for the two latents before their product and grid(table) for the
     stored grid features (None: unrounded)."""
 
@@ -324,6 +325,14 @@ def _adj(g, W, layer, rnd):
     return rnd.grad(g) @ rnd.weight(W, layer)
 
 
+def _bgrad(g, rnd):
+    """Bias gradient sum_rows g: the weight gradient of a constant input 1, so its
+    G operand is rounded like that of the layer's weight gradient."""
+    if rnd is None:
+        return g.sum(0)
+    return rnd.grad(g).sum(0)
+
+
 def _wgrad(g, x, layer, rnd):
     """Weight gradient g.T @ x of a layer."""
     if rnd is None:
@@ -405,15 +414,15 @@ def _encoder_backward(net, e, c, dlat, grads, rnd=None):
     if net.grid_only:
         return dlat
     grads[("W3", e)] += _wgrad(dlat, c["h2"], 3, rnd)
-    grads[("b3", e)] += dlat.sum(0)
+    grads[("b3", e)] += _bgrad(dlat, rnd)
     dh2 = _adj(dlat, net[("W3", e)], 3, rnd)
     da2 = dh2 * (c["a2"] > 0)
     grads[("W2", e)] += _wgrad(da2, c["h1"], 2, rnd)
-    grads[("b2", e)] += da2.sum(0)
+    grads[("b2", e)] += _bgrad(da2, rnd)
     dh1 = _adj(da2, net[("W2", e)], 2, rnd)
     da1 = dh1 * (c["a1"] > 0)
     grads[("W1", e)] += _wgrad(da1, c["h0"], 1, rnd)
-    grads[("b1", e)] += da1.sum(0)
+    grads[("b1", e)] += _bgrad(da1, rnd)
     return _adj(da1, net[("W1", e)], 1, rnd)
 
 
@@ -446,16 +455,18 @@ def loss_and_grad_unit(net, u1, u2, t, rnd=None):
     n = y.shape[0]
     gy = np.sign(y - t) / n
     g = net.zeros_like()
-    g["w6"][:] += c["d2"].T @ gy
+    # the head's weight gradient takes d2 as a gradient-product operand (the loss
+    # gradient gy = +-1/n stays exact)
+    g["w6"][:] += (c["d2"] if rnd is None else rnd.grad(c["d2"])).T @ gy
     g["b6"][:] += gy.sum()
     dd2 = gy[:, None] * net["w6"][None, :]
     da5 = dd2 * (c["a5"] > 0)
     g["W5"][:] += _wgrad(da5, c["d1"], 5, rnd)
-    g["b5"][:] += da5.sum(0)
+    g["b5"][:] += _bgrad(da5, rnd)
     dd1 = _adj(da5, net["W5"], 5, rnd)
     da4 = dd1 * (c["a4"] > 0)
     g["W4"][:] += _wgrad(da4, c["m"], 4, rnd)
-    g["b4"][:] += da4.sum(0)
+    g["b4"][:] += _bgrad(da4, rnd)
     dm = _adj(da4, net["W4"], 4, rnd)
     dla = dm * c["B"]["lat"]
     dlb = dm * c["A"]["lat"]

@@ -209,6 +209,36 @@ __device__ __forceinline__ void corners_pos32(const int R[3], const float p[3], 
     }
 }
 
+// ------------------------------------------- packed bf16 helpers (MFMA epilogues) ----
+typedef __attribute__((ext_vector_type(2))) short s16x2;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// Two floats -> packed bf16 pair (a in the low half), round to nearest even.  A
+// two-element vector conversion maps to the two-source v_cvt_pk_bf16_f32; the
+// scalar form would convert each value on its own and merge the halves.  (No
+// inline asm here: the compiler does not see an asm statement's reads of MFMA
+// results and would not insert the wait states they need.)
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+// ReLU of a packed bf16 pair: a bf16 is negative iff its sign bit is set, so a
+// signed 16-bit max with 0 (one v_pk_max_i16) clamps both halves.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+    const s16x2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), z));
+}
+// max(x, 0) as a signed integer max on the bit pattern: negative floats have
+// the sign bit set, so they compare below 0 and map to +0.  (fmaxf would first
+// quiet NaNs with an extra max per value.)
+__device__ __forceinline__ float relu_f32(float x) {
+    return __int_as_float(max(__float_as_int(x), 0));
+}
+__device__ __forceinline__ float bf_lo(uint32_t v) { return __uint_as_float(v << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
+
 size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B);
 size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec);
 size_t net_infer_lat_ws_bytes(int64_t n_ref);

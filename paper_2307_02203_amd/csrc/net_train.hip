@@ -122,36 +122,48 @@ __global__ __launch_bounds__(kThreads) void grid_fwd_kernel(const float *__restr
 }
 
 // ----------------------------------------------------------- grid bwd ----
-// Scatter-add of dL/dh0 into the grid gradient: one wave per (row, level) item,
-// lane = (corner c, feature f), so each atomic instruction of a wave updates the
-// eight features of eight corner cells (eight 32-byte runs) instead of 64 scattered
-// floats.  Every lane evaluates the trilinear lookup of the forward pass and keeps
-// its own corner, so the weights are the forward's bit for bit.
+// Scatter-add of dL/dh0 into the grid gradient: a wave takes four (row, level)
+// items, lane = (item i, corner bit dx, feature f).  Each lane evaluates its
+// item's trilinear lookup (the forward's arithmetic, so the same weights bit for
+// bit) and issues one atomic per corner pair (dx = 0, 1 at equal dy, dz): on a
+// dense level the two cells are neighbours in memory, so every atomic
+// instruction of the wave adds four 64-byte runs.
 __global__ __launch_bounds__(kThreads) void grid_bwd_kernel(float *__restrict__ grad, GridOffs go,
                                                             GridGeom g, int n_enc,
                                                             const int64_t *__restrict__ pairs,
                                                             const float *__restrict__ pos,
                                                             int64_t B, int64_t row0, int64_t rows,
                                                             const float *__restrict__ dH0) {
-    const int lane = threadIdx.x & 63, c = lane >> 3, f = lane & 7;
+    const int lane = threadIdx.x & 63, i = lane >> 4, dx = (lane >> 3) & 1, f = lane & 7;
+    const int64_t items = rows * kL;
     const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t it = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); it < rows * kL;
-         it += waves) {
+    for (int64_t w0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 4;
+         w0 < items; w0 += waves * 4) {
+        const int64_t it = w0 + i;
+        if (it >= items) continue;
         const int64_t n = row0 + it / kL;
         const int l = (int)(it % kL);
         const int e = (n_enc == 2 && n >= B) ? 1 : 0;
         int idx[8];
         float w[8];
         row_corners(g, l, pairs, pos, B, n, idx, w);
-        int ic = idx[0];
-        float wc = w[0];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) {
-            ic = c == k ? idx[k] : ic;
-            wc = c == k ? w[k] : wc;
-        }
         const float d = dH0[n * kK0 + l * kF + f];
-        if (wc != 0.f) unsafeAtomicAdd(grad + grid_off(go, e, l) + (int64_t)ic * kF + f, wc * d);
+        float *gl = grad + grid_off(go, e, l) + f;
+        // this lane's corner of each pair by bit blending (a select between two
+        // elements is turned into a lane-dependent index, which moves idx and w
+        // to memory)
+        const int m = -dx;
+        int ic[4];
+        float wc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ic[c] = idx[2 * c] ^ (m & (idx[2 * c] ^ idx[2 * c + 1]));
+            wc[c] = __int_as_float(__float_as_int(w[2 * c]) ^
+                                   (m & (__float_as_int(w[2 * c]) ^ __float_as_int(w[2 * c + 1]))));
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (wc[c] != 0.f) unsafeAtomicAdd(gl + (int64_t)ic[c] * kF, wc[c] * d);
     }
 }
 
@@ -297,7 +309,7 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(const float *__restrict
             const int row = s * 8 + (tid >> 5);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                bsum[e] += gv[s][e];
+                bsum[e] += (float)f2bf(gv[s][e]);  // the bf16 G that the MFMA takes
                 s_g[(4 * c4 + e) * kLD + row] = f2bf(gv[s][e]);
             }
         }
@@ -446,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void head_bwd_kernel(const float *__restr
         const float g = gy[b];
         const float d = D2[b * kH + c];
         dpre[b * kH + c] = d > 0.f ? g * wc : 0.f;
-        acc = fmaf(g, d, acc);
+        acc = fmaf(g, (float)f2bf(d), acc);  // d2 as a bf16 operand, like every weight grad
         accb += g;
     }
     s_red[ph][c] = acc;
@@ -514,6 +526,10 @@ unsigned mma_blocks(int64_t rows) {
     int64_t b = ceil_div(ceil_div(rows, 64), 4);
     return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
 }
+int64_t grid_bwd_blocks(int64_t rows) {
+    const int64_t b = ceil_div(rows * kL, 4 * (kThreads / 64));  // 4 items per wave
+    return b < 8192 ? (b > 0 ? b : 1) : 8192;
+}
 unsigned wgrad_blocks(int64_t rows) {
     int64_t b = ceil_div(rows, 64);
     return (unsigned)(b < 512 ? (b > 0 ? b : 1) : 512);  // 2 per CU: 222 -> 156 us at 2^19 rows
@@ -577,11 +593,780 @@ void encode_merge_layer4(const ndf_net_config *c, const NetOffsets &o, const flo
                        dim3(kThreads), 0, st, t.M, B, P + o.W4, kH, 1, P + o.b4, nullptr, t.D1);
 }
 
+// ========================================================== fused step ====
+// The step of a network with one encoder shared by both endpoints (the
+// symmetric pair encoding of Sec. 4.1) runs in four kernels: a forward kernel
+// (grid gather, encoder for both endpoints, latent product, decoder, head, the
+// L1 loss and its gradient), a backward kernel (the data adjoint from the head
+// back to dL/dh0), the grid scatter (grid_bwd_kernel) and one kernel for every
+// weight and bias gradient.  A wave takes 32 pairs: the first endpoints are
+// MFMA column block q = 0, the second endpoints q = 1, so both share every
+// weight fragment and the latent product is register-local; the decoder runs
+// on the pair rows (q = 0).
+// What the backward pass and the weight gradients need is stored per 32-row
+// block ("slab") in the register order of the MFMA operands: chunk (kb, lane)
+// = 16 bytes = row lane % 32, features feat_perm(kb, lane / 32, e) for layer
+// outputs (the order the MFMA accumulators pack into) and feat_nat for the grid
+// features h0.  Every store and load of a slab is a coalesced 16-byte access.
+// Numerics are those of the layer-by-layer kernels: bf16 operands into every
+// MFMA, FP32 accumulators, FP32 latents into the product; the stored operands
+// of the weight gradients are the same bf16 values the MFMAs take, and bias
+// gradients sum those bf16 values (a bias is the weight of a constant input 1).
+__host__ __device__ inline int feat_perm(int kb, int h, int e) {
+    return 16 * kb + 8 * (e >> 2) + 4 * h + (e & 3);
+}
+__host__ __device__ inline int feat_nat(int kb, int h, int e) { return 16 * kb + 8 * h + e; }
+
+constexpr int kTW = 8;                 // waves per workgroup of the fused kernels
+constexpr int kTThreads = 64 * kTW;
+constexpr int kFragH = 4 * 8 * 64;     // bf16x8 per 128 x 128 layer fragment set
+constexpr int kFrag1 = 4 * 2 * 64;     // W1 (128 x 32), and W1^T (32 x 128): 8 x 64
+
+// Packed weights of one step: forward A fragments of W1..W5 (W[o][k], lane l
+// of fragment (ob, kb) holds row 32 ob + l % 32, inputs 8 (l / 32) + 16 kb + e in
+// the order of the layer's input), then the adjoint's A fragments of
+// W1^T..W5^T (row = the layer's input k, inputs = its outputs o in the packed
+// gradient's order feat_perm).
+struct TrainFrags {
+    bf16x8 *f[5];
+    bf16x8 *t[5];
+};
+
+__global__ void pack_train_kernel(const float *__restrict__ P, int64_t w1, int64_t w2,
+                                  int64_t w3, int64_t w4, int64_t w5, TrainFrags F) {
+    const int64_t wo[5] = {w1, w2, w3, w4, w5};
+    // 5 forward + 5 adjoint fragment sets: 2 x (4096 + 4 x 16384) elements
+    constexpr int kPer = kH * kK0 + 4 * kH * kH;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * kPer; t += gridDim.x * blockDim.x) {
+        const bool adj = t >= kPer;
+        int u = adj ? t - kPer : t;
+        const int L = u < kH * kK0 ? 0 : 1 + (u - kH * kK0) / (kH * kH);
+        if (L > 0) u = (u - kH * kK0) % (kH * kH);
+        const int KIN = L == 0 ? kK0 : kH;
+        const int e = u & 7, lane = (u >> 3) & 63, fi = u >> 9;
+        const int h = lane >> 5, il = lane & 31;
+        float v;
+        if (!adj) {
+            const int KB = KIN / 16, ob = fi / KB, kb = fi % KB;
+            const int k = L == 0 ? feat_nat(kb, h, e) : feat_perm(kb, h, e);
+            v = P[wo[L] + (int64_t)(32 * ob + il) * KIN + k];
+        } else {
+            const int mb = fi / 8, kb = fi % 8;
+            v = P[wo[L] + (int64_t)feat_perm(kb, h, e) * KIN + 32 * mb + il];
+        }
+        __bf16 *dst = reinterpret_cast<__bf16 *>(adj ? F.t[L] : F.f[L]);
+        dst[u] = f2bf(v);
+    }
+}
+
+struct FusedArgs {
+    const float *P;
+    int64_t grid[kL];  // offsets of the (single) encoder's grid levels in P
+    const bf16x8 *wf[5], *wt[5];
+    const float *b[5], *w6, *b6;
+    GridGeom g;
+    const int64_t *pairs;
+    const float *pos;
+    const float *targets;
+    int64_t B;
+    float inv_b;
+    // slabs: enc = [2 T] (block 2 t + q), dec = [T]
+    u32x4 *h0, *h1, *h2, *m, *d1, *d2, *da5, *da4, *dlat, *da2, *da1;
+    f32x4 *lat;     // FP32 latents [2 T][4 ob][4 g][64]
+    float *gy;      // [T * 32]
+    float *y;       // [B] or null
+    float *dh0;     // [2 B][32] FP32, rows q B + pair
+    double *partial;
+};
+
+__device__ __forceinline__ int64_t slab_chunk(int64_t blk, int nkb, int kb, int lane) {
+    return (blk * nkb + kb) * 64 + lane;
+}
+
+// Pack one output block's accumulators (acc index 8 s + e <-> chunk 2 ob + s,
+// element e) into two bf16 chunks.
+__device__ __forceinline__ void pack_block(const f32x16 &acc, u32x4 &c0, u32x4 &c1) {
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+        c0[e2] = pack_bf16x2(acc[2 * e2], acc[2 * e2 + 1]);
+        c1[e2] = pack_bf16x2(acc[8 + 2 * e2], acc[8 + 2 * e2 + 1]);
+    }
+}
+
+// Keep the halves of g whose forward activation (bf16 pair h, a ReLU output, so
+// +0 or positive) is non-zero: the ReLU derivative on packed pairs.
+__device__ __forceinline__ uint32_t relu_mask2(uint32_t g, uint32_t h) {
+    const uint32_t lo = (h & 0xffffu) ? 0xffffu : 0u;
+    const uint32_t hi = (h >> 16) ? 0xffff0000u : 0u;
+    return g & (lo | hi);
+}
+
+// acc[q] = bias (or 0) + W-block ob x in[.][q] over KB k-blocks.
+template <int KB, int NQ>
+__device__ __forceinline__ void mma_block(const bf16x8 *__restrict__ wf, int ob,
+                                          const float *__restrict__ bias_h,
+                                          const bf16x8 (&in)[8][2], f32x16 (&acc)[2], int lane) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        f32x4 bv = {0.f, 0.f, 0.f, 0.f};
+        if (bias_h) bv = *reinterpret_cast<const f32x4 *>(bias_h + 32 * ob + 8 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q][4 * g + i] = bv[i];
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const bf16x8 a = wf[(ob * KB + kb) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = mfma32(a, in[kb][q], acc[q]);
+    }
+}
+
+// Grid features of one endpoint for k-block kb: lane half h gathers level
+// 2 kb + h (8 FP32 features per cell, trilinear over 8 corners).
+template <bool POS>
+__device__ __forceinline__ bf16x8 gather_h0(const FusedArgs &A, int kb, int h, int64_t v,
+                                            const float (&p)[3]) {
+    const int l = 2 * kb + h;
+    int R[3];
+    level_dims(A.g, l, R);
+    const uint32_t hm = level_hmask(A.g, l);
+    int idx[8];
+    float w[8];
+    if (POS)
+        corners_pos32<true>(R, p, idx, w, hm);
+    else
+        corners_R32<true>(A.g, R, v, idx, w, hm);
+    const f32x4 *grid = reinterpret_cast<const f32x4 *>(A.P + (h ? A.grid[2 * kb + 1] : A.grid[2 * kb]));
+    f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = s0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const f32x4 c0 = grid[(int64_t)idx[c] * 2], c1 = grid[(int64_t)idx[c] * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            s0[i] = fmaf(w[c], c0[i], s0[i]);
+            s1[i] = fmaf(w[c], c1[i], s1[i]);
+        }
+    }
+    bf16x8 t;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        t[i] = f2bf(s0[i]);
+        t[4 + i] = f2bf(s1[i]);
+    }
+    return t;
+}
+
+__device__ __forceinline__ u32x4 as_u(const bf16x8 &v) { return __builtin_bit_cast(u32x4, v); }
+__device__ __forceinline__ bf16x8 as_b(const u32x4 &v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Forward of 32 pairs per wave; with targets also the loss partial sums, gy and
+// the first gradient da5 = gy w6 (masked by d2 > 0).
+template <bool POS>
+__global__ __launch_bounds__(kTThreads) void train_fwd_kernel(FusedArgs A) {
+    __shared__ bf16x8 s_w1[kFrag1];
+    __shared__ bf16x8 s_w[4][kFragH];
+    __shared__ __attribute__((aligned(16))) float s_b[5][kH];
+    __shared__ __attribute__((aligned(16))) float s_w6[kH];
+    __shared__ double s_part[kTW];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kFrag1; i += kTThreads) s_w1[i] = A.wf[0][i];
+    for (int L = 0; L < 4; ++L)
+        for (int i = tid; i < kFragH; i += kTThreads) s_w[L][i] = A.wf[L + 1][i];
+    for (int i = tid; i < 5 * kH; i += kTThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
+    for (int i = tid; i < kH; i += kTThreads) s_w6[i] = A.w6[i];
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    const int64_t T = ceil_div(A.B, 32);
+    const int64_t V = (int64_t)A.g.nx * A.g.ny * A.g.nz;
+    const float b6 = A.b6[0];
+    const float inv_b = 1.f / (float)A.B;
+    double loss_part = 0.0;
+    for (int64_t tile = (int64_t)blockIdx.x * kTW + wave; tile < T;
+         tile += (int64_t)gridDim.x * kTW) {
+        int h4 = 4 * h;
+        asm volatile("" : "+v"(h4));
+        const int64_t pair = tile * 32 + jl;
+        const bool ok = pair < A.B;
+        bf16x8 a[8][2], b[8][2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int64_t v = 0;
+            float p[3] = {0.f, 0.f, 0.f};
+            if (ok) {
+                if (POS) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p[c] = A.pos[(2 * pair + q) * 3 + c];
+                } else {
+                    v = A.pairs[2 * pair + q];
+                    v = v < 0 ? 0 : (v >= V ? V - 1 : v);  // out-of-range pairs are clamped
+                }
+            }
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                a[kb][q] = gather_h0<POS>(A, kb, h, v, p);
+                A.h0[slab_chunk(2 * tile + q, 2, kb, lane)] = as_u(a[kb][q]);
+            }
+        }
+        f32x16 acc[2];
+        // layer 1: 32 -> 128, ReLU (both endpoints)
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<2, 2>(s_w1, ob, s_b[0] + h4, a, acc, lane);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                u32x4 c0, c1;
+                pack_block(acc[q], c0, c1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    c0[i] = relu_bf16x2(c0[i]);
+                    c1[i] = relu_bf16x2(c1[i]);
+                }
+                b[2 * ob][q] = as_b(c0);
+                b[2 * ob + 1][q] = as_b(c1);
+                A.h1[slab_chunk(2 * tile + q, 8, 2 * ob, lane)] = c0;
+                A.h1[slab_chunk(2 * tile + q, 8, 2 * ob + 1, lane)] = c1;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 2: ReLU
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<8, 2>(s_w[0], ob, s_b[1] + h4, b, acc, lane);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                u32x4 c0, c1;
+                pack_block(acc[q], c0, c1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    c0[i] = relu_bf16x2(c0[i]);
+                    c1[i] = relu_bf16x2(c1[i]);
+                }
+                a[2 * ob][q] = as_b(c0);
+                a[2 * ob + 1][q] = as_b(c1);
+                A.h2[slab_chunk(2 * tile + q, 8, 2 * ob, lane)] = c0;
+                A.h2[slab_chunk(2 * tile + q, 8, 2 * ob + 1, lane)] = c1;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 3: the latents (FP32, kept for the product rule) and their product
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<8, 2>(s_w[1], ob, s_b[2] + h4, a, acc, lane);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    f32x4 t;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) t[i] = acc[q][4 * g + i];
+                    A.lat[((2 * tile + q) * 4 + ob) * 256 + g * 64 + lane] = t;
+                }
+            f32x16 mm;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) mm[r] = acc[0][r] * acc[1][r];
+            u32x4 c0, c1;
+            pack_block(mm, c0, c1);
+            b[2 * ob][0] = as_b(c0);
+            b[2 * ob + 1][0] = as_b(c1);
+            A.m[slab_chunk(tile, 8, 2 * ob, lane)] = c0;
+            A.m[slab_chunk(tile, 8, 2 * ob + 1, lane)] = c1;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 4: ReLU (pair rows)
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<8, 1>(s_w[2], ob, s_b[3] + h4, b, acc, lane);
+            u32x4 c0, c1;
+            pack_block(acc[0], c0, c1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                c0[i] = relu_bf16x2(c0[i]);
+                c1[i] = relu_bf16x2(c1[i]);
+            }
+            a[2 * ob][0] = as_b(c0);
+            a[2 * ob + 1][0] = as_b(c1);
+            A.d1[slab_chunk(tile, 8, 2 * ob, lane)] = c0;
+            A.d1[slab_chunk(tile, 8, 2 * ob + 1, lane)] = c1;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 5: ReLU, and the head y = w6 . d2 + b6 in FP32
+        float part = 0.f;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<8, 1>(s_w[3], ob, s_b[4] + h4, a, acc, lane);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 wv = *reinterpret_cast<const f32x4 *>(s_w6 + h4 + 32 * ob + 8 * g);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    acc[0][4 * g + i] = relu_f32(acc[0][4 * g + i]);
+                    part = fmaf(wv[i], acc[0][4 * g + i], part);
+                }
+            }
+            u32x4 c0, c1;
+            pack_block(acc[0], c0, c1);
+            b[2 * ob][0] = as_b(c0);
+            b[2 * ob + 1][0] = as_b(c1);
+            A.d2[slab_chunk(tile, 8, 2 * ob, lane)] = c0;
+            A.d2[slab_chunk(tile, 8, 2 * ob + 1, lane)] = c1;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const float y = part + __shfl_xor(part, 32, 64) + b6;
+        if (A.y && h == 0 && ok) A.y[pair] = y;
+        if (A.targets) {
+            const float r = ok ? y - A.targets[pair] : 0.f;
+            const float gyv = (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) * inv_b;
+            if (h == 0) {
+                A.gy[tile * 32 + jl] = gyv;
+                loss_part += ok ? fabs((double)r) : 0.0;
+            }
+            // da5 = gy w6 where d2 > 0, in the packed order of d2
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const u32x4 dd = as_u(b[j][0]);
+                u32x4 c;
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) {
+                    const int f0 = feat_perm(j, 0, 2 * e2) + h4;
+                    c[e2] = relu_mask2(pack_bf16x2(gyv * s_w6[f0], gyv * s_w6[f0 + 1]), dd[e2]);
+                }
+                A.da5[slab_chunk(tile, 8, j, lane)] = c;
+            }
+        }
+    }
+    if (A.targets) {
+        loss_part = wave_sum_f64(loss_part);
+        if (lane == 0) s_part[wave] = loss_part;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kTW; ++w) t += s_part[w];
+            A.partial[blockIdx.x] = t;
+        }
+    }
+}
+
+// One encoder adjoint layer for both endpoints: out = pack(W^T in) masked by the
+// forward activation hm > 0; the result is also stored as the layer's G slab.
+__device__ __forceinline__ void adj_masked_layer(const bf16x8 *__restrict__ wt,
+                                                 const u32x4 *__restrict__ hm,
+                                                 u32x4 *__restrict__ gout, int64_t tile,
+                                                 const bf16x8 (&in)[8][2], bf16x8 (&out)[8][2],
+                                                 int lane) {
+    f32x16 acc[2];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        mma_block<8, 2>(wt, ob, nullptr, in, acc, lane);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            u32x4 c0, c1;
+            pack_block(acc[q], c0, c1);
+            const u32x4 m0 = hm[slab_chunk(2 * tile + q, 8, 2 * ob, lane)];
+            const u32x4 m1 = hm[slab_chunk(2 * tile + q, 8, 2 * ob + 1, lane)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                c0[i] = relu_mask2(c0[i], m0[i]);
+                c1[i] = relu_mask2(c1[i], m1[i]);
+            }
+            out[2 * ob][q] = as_b(c0);
+            out[2 * ob + 1][q] = as_b(c1);
+            gout[slab_chunk(2 * tile + q, 8, 2 * ob, lane)] = c0;
+            gout[slab_chunk(2 * tile + q, 8, 2 * ob + 1, lane)] = c1;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Data adjoint of 32 pairs per wave: da5 -> da4 -> dlat (both endpoints) -> da2
+// -> da1 -> dL/dh0 (FP32, rows q B + pair, for the grid scatter).  Every G slab
+// is stored for the weight gradients.
+__global__ __launch_bounds__(kTThreads) void train_bwd_kernel(FusedArgs A) {
+    __shared__ bf16x8 s_t1[kFrag1];
+    __shared__ bf16x8 s_t[4][kFragH];  // W2^T .. W5^T
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kFrag1; i += kTThreads) s_t1[i] = A.wt[0][i];
+    for (int L = 0; L < 4; ++L)
+        for (int i = tid; i < kFragH; i += kTThreads) s_t[L][i] = A.wt[L + 1][i];
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    const int64_t T = ceil_div(A.B, 32);
+    for (int64_t tile = (int64_t)blockIdx.x * kTW + wave; tile < T;
+         tile += (int64_t)gridDim.x * kTW) {
+        const int64_t pair = tile * 32 + jl;
+        const bool ok = pair < A.B;
+        bf16x8 x[8][2], y[8][2];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) x[kb][0] = as_b(A.da5[slab_chunk(tile, 8, kb, lane)]);
+        f32x16 acc[2];
+        // W5^T: d(d1), masked by d1 > 0 -> da4
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<8, 1>(s_t[3], ob, nullptr, x, acc, lane);
+            u32x4 c0, c1;
+            pack_block(acc[0], c0, c1);
+            const u32x4 m0 = A.d1[slab_chunk(tile, 8, 2 * ob, lane)];
+            const u32x4 m1 = A.d1[slab_chunk(tile, 8, 2 * ob + 1, lane)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                c0[i] = relu_mask2(c0[i], m0[i]);
+                c1[i] = relu_mask2(c1[i], m1[i]);
+            }
+            y[2 * ob][0] = as_b(c0);
+            y[2 * ob + 1][0] = as_b(c1);
+            A.da4[slab_chunk(tile, 8, 2 * ob, lane)] = c0;
+            A.da4[slab_chunk(tile, 8, 2 * ob + 1, lane)] = c1;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // W4^T: dm, then the product rule: dlat_A = dm lat_B, dlat_B = dm lat_A
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            mma_block<8, 1>(s_t[2], ob, nullptr, y, acc, lane);
+            f32x16 la, lb;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 ta = A.lat[((2 * tile) * 4 + ob) * 256 + g * 64 + lane];
+                const f32x4 tb = A.lat[((2 * tile + 1) * 4 + ob) * 256 + g * 64 + lane];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    la[4 * g + i] = acc[0][4 * g + i] * tb[i];
+                    lb[4 * g + i] = acc[0][4 * g + i] * ta[i];
+                }
+            }
+            u32x4 c0, c1;
+            pack_block(la, c0, c1);
+            x[2 * ob][0] = as_b(c0);
+            x[2 * ob + 1][0] = as_b(c1);
+            A.dlat[slab_chunk(2 * tile, 8, 2 * ob, lane)] = c0;
+            A.dlat[slab_chunk(2 * tile, 8, 2 * ob + 1, lane)] = c1;
+            pack_block(lb, c0, c1);
+            x[2 * ob][1] = as_b(c0);
+            x[2 * ob + 1][1] = as_b(c1);
+            A.dlat[slab_chunk(2 * tile + 1, 8, 2 * ob, lane)] = c0;
+            A.dlat[slab_chunk(2 * tile + 1, 8, 2 * ob + 1, lane)] = c1;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // W3^T: dh2, masked by h2 > 0 -> da2;  W2^T: dh1, masked by h1 > 0 -> da1
+        adj_masked_layer(s_t[1], A.h2, A.da2, tile, x, y, lane);
+        adj_masked_layer(s_t[0], A.h1, A.da1, tile, y, x, lane);
+        // W1^T: dL/dh0 (32 features: level g = 0..3, features 4 h + i)
+        mma_block<8, 2>(s_t1, 0, nullptr, x, acc, lane);
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                float *dst = A.dh0 + ((int64_t)q * A.B + pair) * kK0 + 4 * h;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    f32x4 t;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) t[i] = acc[q][4 * g + i];
+                    *reinterpret_cast<f32x4 *>(dst + 8 * g) = t;
+                }
+            }
+        }
+    }
+}
+
+// Weight and bias gradients of every layer in one launch: workgroup ranges
+// [wg0[L], wg0[L + 1]) take layer L (0..4 = W1..W5, 5 = the head w6, b6), each
+// workgroup a strided share of its layer's 64-row slab pairs.  A slab pair of
+// G (the layer's output gradient) and X (its input) is loaded with 16-byte
+// reads (8 rows x 8 features per thread), transposed in registers and written
+// to LDS feature-major, s[f][row]; wave w then accumulates
+// dW[32 w + i][k] += sum_rows G[row][32 w + i] X[row][k] on MFMA (K = rows) and
+// threads f < 128 sum the bf16 G column f for the bias.  One atomic flush per
+// workgroup at the end.
+struct WgradArgs {
+    const u32x4 *g[5], *x[5];
+    int64_t nslab[6];
+    float *dW[6], *db[6];
+    const u32x4 *d2;
+    const float *gy;
+    int wg0[7];
+};
+
+constexpr int kWgLD = 64 + 8;  // bf16 per LDS feature row (64 rows + pad)
+
+// rows r = 0..7 of 8 features each (c[r]) -> features e = 0..7 of 8 rows each
+__device__ __forceinline__ void transpose8(const u32x4 (&c)[8], u32x4 (&t)[8]) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)      // word p = features 2 p, 2 p + 1
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {  // rows 2 i, 2 i + 1
+            const uint32_t a = c[2 * i][p], b = c[2 * i + 1][p];
+            t[2 * p][i] = __builtin_amdgcn_perm(b, a, 0x05040100u);
+            t[2 * p + 1][i] = __builtin_amdgcn_perm(b, a, 0x07060302u);
+        }
+}
+
+// The 8 x 8 block (slab blk, k-block kb, half h, rows 8 j .. 8 j + 7) of a slab
+// with nkb k-blocks: 8 coalesced 16-byte loads (zeros past the last slab) ...
+__device__ __forceinline__ void load8(const u32x4 *__restrict__ src, int64_t blk, int64_t nslab,
+                                      int nkb, int kb, int h, int j, u32x4 (&c)[8]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        c[r] = blk < nslab ? src[slab_chunk(blk, nkb, kb, 32 * h + 8 * j + r)]
+                           : u32x4{0u, 0u, 0u, 0u};
+}
+// ... written feature-major into s (the slab's rows at 32 sl).
+__device__ __forceinline__ void write8(const u32x4 (&c)[8], int kb, int h, int j, int sl,
+                                       bool nat, __bf16 *__restrict__ s) {
+    u32x4 t[8];
+    transpose8(c, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int f = nat ? feat_nat(kb, h, e) : feat_perm(kb, h, e);
+        *reinterpret_cast<u32x4 *>(s + f * kWgLD + 32 * sl + 8 * j) = t[e];
+    }
+}
+
+__global__ __launch_bounds__(256) void wgrad_all_kernel(WgradArgs A) {
+    __shared__ __attribute__((aligned(16))) __bf16 s_g[kH * kWgLD];
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[kH * kWgLD];
+    __shared__ float s_gy[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    int L = 0;
+    while (L < 5 && (int)blockIdx.x >= A.wg0[L + 1]) ++L;
+    const int part = (int)blockIdx.x - A.wg0[L], nparts = A.wg0[L + 1] - A.wg0[L];
+    const int64_t nslab = A.nslab[L];
+    if (2 * (int64_t)part >= nslab) return;
+    const int xkb = L == 0 ? 2 : 8, xcb = L == 0 ? 1 : 4;
+    // this thread's block: t < 128 a G block (or the head's gy), t >= 128 an X block
+    const int u = tid & 127, sl = u >> 6, kb = (u >> 3) & 7, hh = (u >> 2) & 1, j = u & 3;
+    const bool is_g = tid < 128;
+    const bool active = L == 5 ? (is_g ? tid < 64 : true) : (is_g || kb < xkb);
+    const u32x4 *src = L == 5 ? A.d2 : (is_g ? A.g[L] : A.x[L]);
+    const int nkb = is_g ? 8 : xkb;
+    const bool nat = !is_g && L == 0;
+    u32x4 c[8];
+    float gyv = 0.f;
+    // the first slab pair's block, then each next one while the MFMAs run
+    auto fetch = [&](int64_t sp) {
+        if (!active) return;
+        if (L == 5 && is_g) {
+            const int64_t r = 2 * sp * 32 + tid;
+            gyv = r < nslab * 32 ? A.gy[r] : 0.f;
+        } else {
+            load8(src, 2 * sp + sl, nslab, nkb, kb, hh, j, c);
+        }
+    };
+    f32x16 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[cb][r] = 0.f;
+    float bsum = 0.f;
+    fetch(part);
+    for (int64_t sp = part; 2 * sp < nslab; sp += nparts) {
+        if (active) {
+            if (L == 5 && is_g)
+                s_gy[tid] = gyv;
+            else
+                write8(c, kb, hh, j, sl, nat, is_g && L != 5 ? s_g : s_x);
+        }
+        __syncthreads();
+        if (2 * (sp + nparts) < nslab) fetch(sp + nparts);
+        if (L == 5) {
+            // dw6[k] = sum_rows gy d2[row][k] (thread k), db6 = sum_rows gy (thread 128)
+            if (tid < kH) {
+                const __bf16 *xr = s_x + tid * kWgLD;
+#pragma unroll 8
+                for (int r = 0; r < 64; ++r) bsum = fmaf(s_gy[r], (float)xr[r], bsum);
+            } else if (tid == kH) {
+                for (int r = 0; r < 64; ++r) bsum += s_gy[r];
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8 *>(s_g + (32 * wave + jl) * kWgLD + 16 * kk + 8 * h);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (cb >= xcb) continue;
+                    const bf16x8 b =
+                        *reinterpret_cast<const bf16x8 *>(s_x + (32 * cb + jl) * kWgLD + 16 * kk + 8 * h);
+                    acc[cb] = mfma32(a, b, acc[cb]);
+                }
+            }
+            if (tid < kH) {
+                const u32x4 *gr = reinterpret_cast<const u32x4 *>(s_g + tid * kWgLD);
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc) {
+                    const u32x4 v = gr[cc];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) bsum += bf_lo(v[i]) + bf_hi(v[i]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (L == 5) {
+        if (tid < kH) unsafeAtomicAdd(A.dW[5] + tid, bsum);
+        else if (tid == kH) unsafeAtomicAdd(A.db[5], bsum);
+        return;
+    }
+    const int kin = L == 0 ? kK0 : kH;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        if (cb >= xcb) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            unsafeAtomicAdd(A.dW[L] + (32 * wave + d_row(r, lane)) * kin + 32 * cb + jl, acc[cb][r]);
+    }
+    if (tid < kH) unsafeAtomicAdd(A.db[L] + tid, bsum);
+}
+
+// ------------------------------------------------------- fused host ----
+static bool fused_path(const ndf_net_config *c) { return c->n_enc == 1 && !c->grid_only; }
+
+struct FusedWS {
+    int32_t *status;
+    TrainFrags fr;
+    u32x4 *h0, *h1, *h2, *m, *d1, *d2, *da5, *da4, *dlat, *da2, *da1;
+    f32x4 *lat;
+    float *gy, *dh0;
+    double *partial;
+    size_t bytes;
+};
+
+constexpr int kFusedBlocksMax = 512;
+
+static FusedWS carve_fused(void *ws, int64_t B) {
+    FusedWS t{};
+    const int64_t T = ceil_div(B, 32);
+    char *base = (char *)ws;
+    size_t pos = 0;
+    auto take = [&](size_t n) {
+        char *p = base ? base + pos : nullptr;
+        pos += align_up(n, 256);
+        return p;
+    };
+    t.status = (int32_t *)take(kStatusBytes);
+    for (int L = 0; L < 5; ++L) t.fr.f[L] = (bf16x8 *)take((L == 0 ? kFrag1 : kFragH) * 16);
+    for (int L = 0; L < 5; ++L) t.fr.t[L] = (bf16x8 *)take((L == 0 ? kFrag1 : kFragH) * 16);
+    const size_t slab = 8 * 64 * 16;  // 128 features x 32 rows, bf16
+    t.h0 = (u32x4 *)take(2 * T * 2 * 64 * 16);
+    t.h1 = (u32x4 *)take(2 * T * slab);
+    t.h2 = (u32x4 *)take(2 * T * slab);
+    t.lat = (f32x4 *)take(2 * T * 2 * slab);
+    t.m = (u32x4 *)take(T * slab);
+    t.d1 = (u32x4 *)take(T * slab);
+    t.d2 = (u32x4 *)take(T * slab);
+    t.da5 = (u32x4 *)take(T * slab);
+    t.da4 = (u32x4 *)take(T * slab);
+    t.dlat = (u32x4 *)take(2 * T * slab);
+    t.da2 = (u32x4 *)take(2 * T * slab);
+    t.da1 = (u32x4 *)take(2 * T * slab);
+    t.gy = (float *)take(T * 32 * 4);
+    t.dh0 = (float *)take(2 * B * kK0 * 4);
+    t.partial = (double *)take(kFusedBlocksMax * 8);
+    t.bytes = pos;
+    return t;
+}
+
+static unsigned fused_blocks(int64_t B) {
+    const int64_t b = ceil_div(ceil_div(B, 32), kTW);
+    return (unsigned)(b < kFusedBlocksMax ? (b > 0 ? b : 1) : kFusedBlocksMax);
+}
+
+static FusedArgs fused_args(const ndf_net_config *c, const NetOffsets &o, const float *P,
+                            const int64_t *pairs, const float *pos, const float *targets,
+                            int64_t B, const FusedWS &t, float *y) {
+    FusedArgs a{};
+    a.P = P;
+    for (int l = 0; l < kL; ++l) a.grid[l] = o.grid[0][l];
+    for (int L = 0; L < 5; ++L) {
+        a.wf[L] = t.fr.f[L];
+        a.wt[L] = t.fr.t[L];
+    }
+    a.b[0] = P + o.b1[0];
+    a.b[1] = P + o.b2[0];
+    a.b[2] = P + o.b3[0];
+    a.b[3] = P + o.b4;
+    a.b[4] = P + o.b5;
+    a.w6 = P + o.w6;
+    a.b6 = P + o.b6;
+    a.g = grid_geom(c);
+    a.pairs = pairs;
+    a.pos = pos;
+    a.targets = targets;
+    a.B = B;
+    a.inv_b = 1.f / (float)B;
+    a.h0 = t.h0; a.h1 = t.h1; a.h2 = t.h2; a.m = t.m; a.d1 = t.d1; a.d2 = t.d2;
+    a.da5 = t.da5; a.da4 = t.da4; a.dlat = t.dlat; a.da2 = t.da2; a.da1 = t.da1;
+    a.lat = t.lat;
+    a.gy = t.gy;
+    a.y = y;
+    a.dh0 = t.dh0;
+    a.partial = t.partial;
+    return a;
+}
+
+static void fused_forward(const ndf_net_config *c, const NetOffsets &o, const float *P,
+                          const int64_t *pairs, const float *pos, const float *targets, int64_t B,
+                          const FusedWS &t, float *y, hipStream_t st) {
+    hipLaunchKernelGGL(pack_train_kernel, dim3(64), dim3(256), 0, st, P, o.W1[0], o.W2[0],
+                       o.W3[0], o.W4, o.W5, t.fr);
+    const FusedArgs a = fused_args(c, o, P, pairs, pos, targets, B, t, y);
+    if (pos)
+        hipLaunchKernelGGL(train_fwd_kernel<true>, dim3(fused_blocks(B)), dim3(kTThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(train_fwd_kernel<false>, dim3(fused_blocks(B)), dim3(kTThreads), 0, st, a);
+}
+
+static int fused_grad(const ndf_net_config *c, const float *P, const int64_t *pairs,
+                      const float *pos, const float *targets, int64_t B, float *G, float *loss,
+                      void *ws, hipStream_t st) {
+    const NetOffsets o = net_offsets(c);
+    const FusedWS t = carve_fused(ws, B);
+    launch_status_clear(t.status, st);
+    hipLaunchKernelGGL(fill_kernel, dim3(gs_blocks(o.total)), dim3(kThreads), 0, st, G, o.total,
+                       0.f);
+    fused_forward(c, o, P, pairs, pos, targets, B, t, nullptr, st);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, st, t.partial,
+                       (int)fused_blocks(B), B, loss, t.status);
+    const FusedArgs a = fused_args(c, o, P, pairs, pos, targets, B, t, nullptr);
+    hipLaunchKernelGGL(train_bwd_kernel, dim3(fused_blocks(B)), dim3(kTThreads), 0, st, a);
+    const int64_t rows = 2 * B;
+    hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)grid_bwd_blocks(rows)), dim3(kThreads), 0,
+                       st, G, grid_offs(o), grid_geom(c), 1, pairs, pos, B, (int64_t)0, rows,
+                       t.dh0);
+    WgradArgs w{};
+    const int64_t T = ceil_div(B, 32);
+    const u32x4 *gs[5] = {t.da1, t.da2, t.dlat, t.da4, t.da5};
+    const u32x4 *xs[5] = {t.h0, t.h1, t.h2, t.m, t.d1};
+    const int64_t ns[6] = {2 * T, 2 * T, 2 * T, T, T, T};
+    float *dws[6] = {G + o.W1[0], G + o.W2[0], G + o.W3[0], G + o.W4, G + o.W5, G + o.w6};
+    float *dbs[6] = {G + o.b1[0], G + o.b2[0], G + o.b3[0], G + o.b4, G + o.b5, G + o.b6};
+    // workgroups per layer in proportion to its MFMA work, at most one per slab pair
+    const int share[6] = {64, 256, 256, 128, 128, 32};
+    int acc_wg = 0;
+    for (int L = 0; L < 6; ++L) {
+        if (L < 5) {
+            w.g[L] = gs[L];
+            w.x[L] = xs[L];
+        }
+        w.nslab[L] = ns[L];
+        w.dW[L] = dws[L];
+        w.db[L] = dbs[L];
+        w.wg0[L] = acc_wg;
+        const int64_t pairs_l = ceil_div(ns[L], 2);
+        acc_wg += (int)(pairs_l < share[L] ? pairs_l : share[L]);
+    }
+    w.wg0[6] = acc_wg;
+    w.d2 = t.d2;
+    w.gy = t.gy;
+    hipLaunchKernelGGL(wgrad_all_kernel, dim3((unsigned)acc_wg), dim3(256), 0, st, w);
+    return status_of_launch();
+}
+
 }  // namespace
 
 size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B) {
-    (void)c;
-    return carve(nullptr, B).bytes;
+    return fused_path(c) ? carve_fused(nullptr, B).bytes : carve(nullptr, B).bytes;
 }
 
 int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t seed,
@@ -613,6 +1398,10 @@ int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t
 int launch_net_forward(const ndf_net_config *c, const float *params, const int64_t *pairs,
                        const float *pos, int64_t B, float *y, void *ws, hipStream_t st) {
     const NetOffsets o = net_offsets(c);
+    if (fused_path(c)) {
+        fused_forward(c, o, params, pairs, pos, nullptr, B, carve_fused(ws, B), y, st);
+        return status_of_launch();
+    }
     TrainWS t = carve(ws, B);
     t.y = y;
     forward(c, o, params, pairs, pos, nullptr, B, t, st);
@@ -622,6 +1411,7 @@ int launch_net_forward(const ndf_net_config *c, const float *params, const int64
 int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pairs,
                     const float *pos, const float *targets, int64_t B, float *G, float *loss,
                     void *ws, hipStream_t st) {
+    if (fused_path(c)) return fused_grad(c, P, pairs, pos, targets, B, G, loss, ws, st);
     const NetOffsets o = net_offsets(c);
     const TrainWS t = carve(ws, B);
     const int64_t R = 2 * B;
@@ -657,9 +1447,8 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
                            t.dA, t.H0, B, t.dH0, kK0);
         for (int e = 0; e < n_enc; ++e) {
             const int64_t r0 = n_enc == 1 ? 0 : e * B, rows = n_enc == 1 ? R : B;
-            const int64_t items = rows * kL, per_block = kThreads / 64;
-            const int64_t gb = ceil_div(items, per_block);
-            hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)(gb < 16384 ? gb : 16384)),
+            const int64_t gb = grid_bwd_blocks(rows);
+            hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)gb),
                                dim3(kThreads), 0, st, G, go, g, n_enc, pairs, pos, B, r0, rows,
                                t.dH0);
         }
@@ -691,9 +1480,8 @@ int launch_net_grad(const ndf_net_config *c, const float *P, const int64_t *pair
         hipLaunchKernelGGL((rows_mma_kernel<kH, kK0, EPI_PLAIN>), dim3(mma_blocks(rows)),
                            dim3(kThreads), 0, st, dP1, rows, P + o.W1[e], 1, kK0, nullptr, nullptr,
                            t.dH0 + r0 * kK0);
-        const int64_t items = rows * kL, per_block = kThreads / 64;
-        const int64_t gb = ceil_div(items, per_block);
-        hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)(gb < 16384 ? gb : 16384)),
+        const int64_t gb = grid_bwd_blocks(rows);
+        hipLaunchKernelGGL(grid_bwd_kernel, dim3((unsigned)gb),
                            dim3(kThreads), 0, st, G, go, g, n_enc, pairs, pos, B, r0, rows,
                            t.dH0);
     }

@@ -137,17 +137,19 @@ def test_forward_parity(name, n_enc):
     _check_floor(y, want, emul, f"forward {name} n_enc={n_enc}")
 
 
-@pytest.mark.parametrize("name,n_enc", [("tiny", 1), ("mid", 2)])
+@pytest.mark.parametrize("name,n_enc,B", [("tiny", 1, 2048), ("mid", 1, 2001), ("mid", 2, 2048)])
 @pytest.mark.parametrize("signs", ["same", "random"])
-def test_gradient_parity(name, n_enc, signs):
+def test_gradient_parity(name, n_enc, B, signs):
     """Adjoint kernels vs the FP64 adjoint, every parameter tensor held to 1.25 times
     the error of the FP64 adjoint with the kernels' bf16 operand rounding.  With
     one residual sign for every pair the per-pair gradients add up; with random
     signs the batch gradient is a sum with heavy cancellation and its floor is
     near 1e-1 in every tensor (rounding flips ReLU masks; the rounding of the
-    gradient operand itself contributes only a few 1e-3)."""
+    gradient operand itself contributes only a few 1e-3).  One encoder runs the
+    fused kernels (B = 2001: a ragged last tile of 17 pairs), two encoders the
+    layer-by-layer ones."""
     cfg, lay, c, P, net = _setup(name, n_enc, seed=2321)
-    pairs = gen.random_pairs(cfg.n_vertices, 2048, seed=12)
+    pairs = gen.random_pairs(cfg.n_vertices, B, seed=12)
     y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
     if signs == "same":
         s = -np.ones(len(pairs))
