@@ -742,6 +742,9 @@ __device__ __forceinline__ bf16x8 gather_h0(const FusedArgs &A, int kb, int h, i
     f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = s0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
+        // a corner of weight 0 adds nothing: on a level of the vertex grid's size
+        // only one corner of eight has weight, so most lanes skip the other reads
+        if (w[c] == 0.f) continue;
         const f32x4 c0 = grid[(int64_t)idx[c] * 2], c1 = grid[(int64_t)idx[c] * 2 + 1];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1074,11 +1077,11 @@ __global__ __launch_bounds__(kTThreads) void train_bwd_kernel(FusedArgs A) {
 // [wg0[L], wg0[L + 1]) take layer L (0..4 = W1..W5, 5 = the head w6, b6), each
 // workgroup a strided share of its layer's 64-row slab pairs.  A slab pair of
 // G (the layer's output gradient) and X (its input) is loaded with 16-byte
-// reads (8 rows x 8 features per thread), transposed in registers and written
-// to LDS feature-major, s[f][row]; wave w then accumulates
-// dW[32 w + i][k] += sum_rows G[row][32 w + i] X[row][k] on MFMA (K = rows) and
-// threads f < 128 sum the bf16 G column f for the bias.  One atomic flush per
-// workgroup at the end.
+// reads (4 rows x 8 features per thread), transposed in registers and written
+// to LDS feature-major, s[f][row]; the waves then accumulate
+// dW[o][k] += sum_rows G[row][o] X[row][k] on MFMA (K = rows) and threads
+// f < 128 sum the bf16 G column f for the bias.  One atomic flush per workgroup
+// at the end.
 struct WgradArgs {
     const u32x4 *g[5], *x[5];
     int64_t nslab[6];
@@ -1090,40 +1093,51 @@ struct WgradArgs {
 
 constexpr int kWgLD = 64 + 8;  // bf16 per LDS feature row (64 rows + pad)
 
-// rows r = 0..7 of 8 features each (c[r]) -> features e = 0..7 of 8 rows each
-__device__ __forceinline__ void transpose8(const u32x4 (&c)[8], u32x4 (&t)[8]) {
+// rows r = 0..3 of 8 features each (c[r]) -> features e = 0..7 of 4 rows each
+__device__ __forceinline__ void transpose4(const u32x4 (&c)[4], uint2 (&t)[8]) {
 #pragma unroll
     for (int p = 0; p < 4; ++p)      // word p = features 2 p, 2 p + 1
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {  // rows 2 i, 2 i + 1
+        for (int i = 0; i < 2; ++i) {  // rows 2 i, 2 i + 1
             const uint32_t a = c[2 * i][p], b = c[2 * i + 1][p];
-            t[2 * p][i] = __builtin_amdgcn_perm(b, a, 0x05040100u);
-            t[2 * p + 1][i] = __builtin_amdgcn_perm(b, a, 0x07060302u);
+            const uint32_t lo = __builtin_amdgcn_perm(b, a, 0x05040100u);
+            const uint32_t hi = __builtin_amdgcn_perm(b, a, 0x07060302u);
+            if (i == 0) {
+                t[2 * p].x = lo;
+                t[2 * p + 1].x = hi;
+            } else {
+                t[2 * p].y = lo;
+                t[2 * p + 1].y = hi;
+            }
         }
 }
 
-// The 8 x 8 block (slab blk, k-block kb, half h, rows 8 j .. 8 j + 7) of a slab
-// with nkb k-blocks: 8 coalesced 16-byte loads (zeros past the last slab) ...
-__device__ __forceinline__ void load8(const u32x4 *__restrict__ src, int64_t blk, int64_t nslab,
-                                      int nkb, int kb, int h, int j, u32x4 (&c)[8]) {
+// The 4 x 8 block (slab blk, k-block kb, half h, rows r0 .. r0 + 3) of a slab
+// with nkb k-blocks: 4 coalesced 16-byte loads (zeros past the last slab) ...
+__device__ __forceinline__ void load4(const u32x4 *__restrict__ src, int64_t blk, int64_t nslab,
+                                      int nkb, int kb, int h, int r0, u32x4 (&c)[4]) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-        c[r] = blk < nslab ? src[slab_chunk(blk, nkb, kb, 32 * h + 8 * j + r)]
+    for (int r = 0; r < 4; ++r)
+        c[r] = blk < nslab ? src[slab_chunk(blk, nkb, kb, 32 * h + r0 + r)]
                            : u32x4{0u, 0u, 0u, 0u};
 }
 // ... written feature-major into s (the slab's rows at 32 sl).
-__device__ __forceinline__ void write8(const u32x4 (&c)[8], int kb, int h, int j, int sl,
+__device__ __forceinline__ void write4(const u32x4 (&c)[4], int kb, int h, int r0, int sl,
                                        bool nat, __bf16 *__restrict__ s) {
-    u32x4 t[8];
-    transpose8(c, t);
+    uint2 t[8];
+    transpose4(c, t);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int f = nat ? feat_nat(kb, h, e) : feat_perm(kb, h, e);
-        *reinterpret_cast<u32x4 *>(s + f * kWgLD + 32 * sl + 8 * j) = t[e];
+        *reinterpret_cast<uint2 *>(s + f * kWgLD + 32 * sl + r0) = t[e];
     }
 }
 
-__global__ __launch_bounds__(256) void wgrad_all_kernel(WgradArgs A) {
+// Eight waves: wave w accumulates output rows 32 (w % 4) .. + 31 against input
+// columns 64 (w / 4) .. + 63 (two 32-column blocks).  Threads t < 256 stage G
+// (the head: t < 64 stage gy), t >= 256 stage X, four rows of one 8-feature
+// block each; the next slab pair's loads are in flight while the MFMAs run.
+__global__ __launch_bounds__(512) void wgrad_all_kernel(WgradArgs A) {
     __shared__ __attribute__((aligned(16))) __bf16 s_g[kH * kWgLD];
     __shared__ __attribute__((aligned(16))) __bf16 s_x[kH * kWgLD];
     __shared__ float s_gy[64];
@@ -1134,30 +1148,31 @@ __global__ __launch_bounds__(256) void wgrad_all_kernel(WgradArgs A) {
     const int64_t nslab = A.nslab[L];
     if (2 * (int64_t)part >= nslab) return;
     const int xkb = L == 0 ? 2 : 8, xcb = L == 0 ? 1 : 4;
-    // this thread's block: t < 128 a G block (or the head's gy), t >= 128 an X block
-    const int u = tid & 127, sl = u >> 6, kb = (u >> 3) & 7, hh = (u >> 2) & 1, j = u & 3;
-    const bool is_g = tid < 128;
+    const int ob = wave & 3, cb0 = 2 * (wave >> 2);
+    // this thread's block
+    const int u = tid & 255, sl = u >> 7, kb = (u >> 4) & 7, hh = (u >> 3) & 1,
+              r0 = 4 * (u & 7);
+    const bool is_g = tid < 256;
     const bool active = L == 5 ? (is_g ? tid < 64 : true) : (is_g || kb < xkb);
     const u32x4 *src = L == 5 ? A.d2 : (is_g ? A.g[L] : A.x[L]);
     const int nkb = is_g ? 8 : xkb;
     const bool nat = !is_g && L == 0;
-    u32x4 c[8];
+    u32x4 c[4];
     float gyv = 0.f;
-    // the first slab pair's block, then each next one while the MFMAs run
     auto fetch = [&](int64_t sp) {
         if (!active) return;
         if (L == 5 && is_g) {
             const int64_t r = 2 * sp * 32 + tid;
             gyv = r < nslab * 32 ? A.gy[r] : 0.f;
         } else {
-            load8(src, 2 * sp + sl, nslab, nkb, kb, hh, j, c);
+            load4(src, 2 * sp + sl, nslab, nkb, kb, hh, r0, c);
         }
     };
-    f32x16 acc[4];
+    f32x16 acc[2];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[cb][r] = 0.f;
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0.f;
     float bsum = 0.f;
     fetch(part);
     for (int64_t sp = part; 2 * sp < nslab; sp += nparts) {
@@ -1165,7 +1180,7 @@ __global__ __launch_bounds__(256) void wgrad_all_kernel(WgradArgs A) {
             if (L == 5 && is_g)
                 s_gy[tid] = gyv;
             else
-                write8(c, kb, hh, j, sl, nat, is_g && L != 5 ? s_g : s_x);
+                write4(c, kb, hh, r0, sl, nat, is_g && L != 5 ? s_g : s_x);
         }
         __syncthreads();
         if (2 * (sp + nparts) < nslab) fetch(sp + nparts);
@@ -1179,16 +1194,18 @@ __global__ __launch_bounds__(256) void wgrad_all_kernel(WgradArgs A) {
                 for (int r = 0; r < 64; ++r) bsum += s_gy[r];
             }
         } else {
+            if (cb0 < xcb) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const bf16x8 a =
-                    *reinterpret_cast<const bf16x8 *>(s_g + (32 * wave + jl) * kWgLD + 16 * kk + 8 * h);
+                for (int kk = 0; kk < 4; ++kk) {
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(
+                        s_g + (32 * ob + jl) * kWgLD + 16 * kk + 8 * h);
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    if (cb >= xcb) continue;
-                    const bf16x8 b =
-                        *reinterpret_cast<const bf16x8 *>(s_x + (32 * cb + jl) * kWgLD + 16 * kk + 8 * h);
-                    acc[cb] = mfma32(a, b, acc[cb]);
+                    for (int q = 0; q < 2; ++q) {
+                        if (cb0 + q >= xcb) continue;
+                        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
+                            s_x + (32 * (cb0 + q) + jl) * kWgLD + 16 * kk + 8 * h);
+                        acc[q] = mfma32(a, b, acc[q]);
+                    }
                 }
             }
             if (tid < kH) {
@@ -1210,11 +1227,12 @@ __global__ __launch_bounds__(256) void wgrad_all_kernel(WgradArgs A) {
     }
     const int kin = L == 0 ? kK0 : kH;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        if (cb >= xcb) continue;
+    for (int q = 0; q < 2; ++q) {
+        if (cb0 + q >= xcb) continue;
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            unsafeAtomicAdd(A.dW[L] + (32 * wave + d_row(r, lane)) * kin + 32 * cb + jl, acc[cb][r]);
+            unsafeAtomicAdd(A.dW[L] + (32 * ob + d_row(r, lane)) * kin + 32 * (cb0 + q) + jl,
+                            acc[q][r]);
     }
     if (tid < kH) unsafeAtomicAdd(A.db[L] + tid, bsum);
 }
@@ -1341,8 +1359,10 @@ static int fused_grad(const ndf_net_config *c, const float *P, const int64_t *pa
     const int64_t ns[6] = {2 * T, 2 * T, 2 * T, T, T, T};
     float *dws[6] = {G + o.W1[0], G + o.W2[0], G + o.W3[0], G + o.W4, G + o.W5, G + o.w6};
     float *dbs[6] = {G + o.b1[0], G + o.b2[0], G + o.b3[0], G + o.b4, G + o.b5, G + o.b6};
-    // workgroups per layer in proportion to its MFMA work, at most one per slab pair
-    const int share[6] = {64, 256, 256, 128, 128, 32};
+    // workgroups per layer in proportion to the bytes it reads (per decoder slab:
+    // W1 20 KB, W2 and W3 32, W4 and W5 16, the head 8), 511 in all, one round at
+    // two workgroups per CU; at most one per slab pair
+    const int share[6] = {82, 132, 132, 66, 66, 33};
     int acc_wg = 0;
     for (int L = 0; L < 6; ++L) {
         if (L < 5) {
@@ -1359,7 +1379,7 @@ static int fused_grad(const ndf_net_config *c, const float *P, const int64_t *pa
     w.wg0[6] = acc_wg;
     w.d2 = t.d2;
     w.gy = t.gy;
-    hipLaunchKernelGGL(wgrad_all_kernel, dim3((unsigned)acc_wg), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(wgrad_all_kernel, dim3((unsigned)acc_wg), dim3(512), 0, st, w);
     return status_of_launch();
 }
 
