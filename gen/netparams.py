@@ -51,12 +51,22 @@ class NetLayout:
     n_enc: int = 1        # 1: shared encoder + grid (self field), 2: separate
     log2_hashmap: int = 0  # T > 0: levels larger than 2^T cells are hash tables of 2^T
     grid_only: bool = False  # encoder MLP omitted: the latent is the grid features
+    fourier: int = 0      # L > 0: raw position and L Fourier frequencies appended to the
+                          # encoder input, padded to a multiple of 16
 
     @staticmethod
     def for_grid(nx, ny, nz, n_levels=4, feats=8, width=128, n_enc=1, log2_hashmap=0,
-                 grid_only=False):
+                 grid_only=False, fourier=0):
         return NetLayout(nx, ny, nz, tuple(level_resolutions(nx, ny, nz, n_levels)),
-                         feats, width, n_enc, log2_hashmap, grid_only)
+                         feats, width, n_enc, log2_hashmap, grid_only, fourier)
+
+    @property
+    def enc_in(self):
+        """Encoder input width: L*F grid features (+ 3 + 6 fourier, padded to 16)."""
+        n = self.n_levels * self.feats
+        if not self.fourier:
+            return n
+        return (n + 3 + 6 * self.fourier + 15) // 16 * 16
 
     def cells(self, l):
         rx, ry, rz = self.res[l]
@@ -76,7 +86,7 @@ class NetLayout:
             for l in range(self.n_levels):
                 out.append((f"grid{e}_{l}", (self.cells(l), F)))
             if not self.grid_only:
-                out += [(f"W1_{e}", (H, L * F)), (f"b1_{e}", (H,)),
+                out += [(f"W1_{e}", (H, self.enc_in)), (f"b1_{e}", (H,)),
                         (f"W2_{e}", (H, H)), (f"b2_{e}", (H,)),
                         (f"W3_{e}", (H, H)), (f"b3_{e}", (H,))]
         out += [("W4", (H, L * F if self.grid_only else H)), ("b4", (H,)), ("W5", (H, H)),

@@ -22,6 +22,11 @@ Readings where the paper is silent (the GPU path uses the same ones):
   (the paper's table is large enough that no level of its grids is hashed);
 * encoder: 3 layers, ReLU after the first two, linear latent; decoder: two ReLU
   layers and a linear scalar output; weights row-major [out][in];
+* Fourier features (Sec. 4.2, Eq. 4; fourier = L > 0): the encoder input is the
+  grid features, then the raw position p = 2u - 1 (of the clamped u), then for
+  i < L and j in (x, y, z) the pair sin(2^i pi p_j), cos(2^i pi p_j), zero-padded
+  to a multiple of 16 inputs (L = 12: 32 + 3 + 72 + 5 = 112); the order of the
+  concatenation is a layout choice, this one is the parameter blob's;
 * grid-only network (the TensoRF-like ablation of Sec. 6.3, Fig. 6: the encoder
   MLP omitted, predictions from the input embedding alone): the latent of a
   position is its concatenated grid features, so the merge multiplies two
@@ -39,15 +44,25 @@ import numpy as np
 ALIGN = 64
 
 
+def embed_width(grid_features, fourier):
+    """Encoder inputs: the grid features, plus 3 raw coordinates and 6 L Fourier
+    features padded to a multiple of 16 when fourier = L > 0."""
+    if not fourier:
+        return grid_features
+    n = grid_features + 3 + 6 * fourier
+    return (n + 15) // 16 * 16
+
+
 class Net:
     """Named float64 views over a copy of a flat parameter vector."""
 
     def __init__(self, flat, dims, res, feats=8, width=128, n_enc=1, log2_hashmap=0,
-                 grid_only=False):
+                 grid_only=False, fourier=0):
         self.nx, self.ny, self.nz = dims
         self.res = [tuple(r) for r in res]
         self.T = log2_hashmap
         self.grid_only = grid_only
+        self.fourier = fourier
         self.F = feats
         self.H = width
         self.n_enc = n_enc
@@ -67,7 +82,7 @@ class Net:
                 take(("grid", e, l), (level_cells(R, log2_hashmap), feats))
             if grid_only:
                 continue
-            take(("W1", e), (width, L * feats))
+            take(("W1", e), (width, embed_width(L * feats, fourier)))
             take(("b1", e), (width,))
             take(("W2", e), (width, width))
             take(("b2", e), (width,))
@@ -159,6 +174,33 @@ def grid_encode(net, e, u, rnd=None):
             g = rnd.grid(g)
         parts.append(np.einsum("nc,ncf->nf", w, g[idx]))
     return np.concatenate(parts, axis=1)
+
+
+def fourier_features(u, L):
+    """Raw positions and their Fourier features (Sec. 4.2, Eq. 4) for u in
+    [0,1]^3 (n,3): p = 2u - 1, then sin and cos of omega_i p_j for omega_i =
+    2^i pi, i < L, and the three axis-aligned unit vectors n_j."""
+    p = 2.0 * np.asarray(u, dtype=np.float64) - 1.0
+    cols = [p[:, 0], p[:, 1], p[:, 2]]
+    for i in range(L):
+        w = (2.0 ** i) * np.pi
+        for j in range(3):
+            cols.append(np.sin(w * p[:, j]))
+            cols.append(np.cos(w * p[:, j]))
+    return np.stack(cols, axis=1)
+
+
+def input_embedding(net, e, u, rnd=None):
+    """Encoder input h0 of positions u (n,3): the grid features, with Fourier
+    features the raw positions and their Fourier features after them, zero-padded
+    to the encoder's input width."""
+    h0 = grid_encode(net, e, u, rnd)
+    if not net.fourier:
+        return h0
+    ff = fourier_features(u, net.fourier)
+    width = embed_width(h0.shape[1], net.fourier)
+    pad = np.zeros((h0.shape[0], width - h0.shape[1] - ff.shape[1]))
+    return np.concatenate([h0, ff, pad], axis=1)
 
 
 def grid_scatter(net, e, u, dh0, grads):
@@ -374,8 +416,8 @@ def forward(net, v1, v2, rnd=None):
 def forward_unit(net, u1, u2, rnd=None):
     """Phi(p1, p2) for positions given as u in [0,1]^3 (n,3); returns (y, cache)."""
     ea, eb = _enc_index(net, 0), _enc_index(net, 1)
-    A = encoder(net, ea, grid_encode(net, ea, u1, rnd), rnd)
-    B = encoder(net, eb, grid_encode(net, eb, u2, rnd), rnd)
+    A = encoder(net, ea, input_embedding(net, ea, u1, rnd), rnd)
+    B = encoder(net, eb, input_embedding(net, eb, u2, rnd), rnd)
     if rnd is not None and rnd.latent is not None:
         m = rnd.latent(A["lat"]) * rnd.latent(B["lat"])
     else:

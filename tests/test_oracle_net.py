@@ -22,12 +22,13 @@ DIMS = (5, 4, 3)
 RES = [(2, 2, 2), (3, 3, 2), (4, 3, 3), (5, 4, 3)]
 
 
-def _layout(width=128, n_enc=1, dims=DIMS, res=RES, grid_only=False):
-    return gen.NetLayout(dims[0], dims[1], dims[2], tuple(res), 8, width, n_enc, 0, grid_only)
+def _layout(width=128, n_enc=1, dims=DIMS, res=RES, grid_only=False, fourier=0):
+    return gen.NetLayout(dims[0], dims[1], dims[2], tuple(res), 8, width, n_enc, 0, grid_only,
+                         fourier)
 
 
-def _net(flat, width=128, n_enc=1, dims=DIMS, res=RES, grid_only=False):
-    return nn.Net(flat, dims, res, 8, width, n_enc, grid_only=grid_only)
+def _net(flat, width=128, n_enc=1, dims=DIMS, res=RES, grid_only=False, fourier=0):
+    return nn.Net(flat, dims, res, 8, width, n_enc, grid_only=grid_only, fourier=fourier)
 
 
 def _cell_positions(R):
@@ -227,12 +228,13 @@ def test_two_encoder_swap_identity():
     assert np.max(np.abs(y - y_fwd)) > 1e-6           # the field itself is not symmetric
 
 
-@pytest.mark.parametrize("n_enc,grid_only", [(1, False), (2, False), (1, True), (2, True)])
-def test_adjoint_vs_finite_differences(n_enc, grid_only):
+@pytest.mark.parametrize("n_enc,grid_only,fourier",
+                         [(1, False, 0), (2, False, 0), (1, True, 0), (2, True, 0), (1, False, 12)])
+def test_adjoint_vs_finite_differences(n_enc, grid_only, fourier):
     width = 16
-    L = _layout(width=width, n_enc=n_enc, grid_only=grid_only)
+    L = _layout(width=width, n_enc=n_enc, grid_only=grid_only, fourier=fourier)
     flat = gen.make_net_params(L, seed=9, grid_scale=0.5, bias_scale=0.2).astype(np.float64)
-    net = _net(flat, width=width, n_enc=n_enc, grid_only=grid_only)
+    net = _net(flat, width=width, n_enc=n_enc, grid_only=grid_only, fourier=fourier)
     pairs = gen.random_pairs(60, 64, seed=8)
     y, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
     t = y - 10.0                      # every residual positive: L = mean(y) + 10, smooth
@@ -245,12 +247,72 @@ def test_adjoint_vs_finite_differences(n_enc, grid_only):
         d = np.zeros_like(flat)
         d[o:o + n] = rng.standard_normal(n)
         lp = nn.l1_loss(nn.forward(_net(flat + h * d, width=width, n_enc=n_enc,
-                                        grid_only=grid_only), pairs[:, 0], pairs[:, 1])[0], t)
+                                        grid_only=grid_only, fourier=fourier),
+                                   pairs[:, 0], pairs[:, 1])[0], t)
         lm = nn.l1_loss(nn.forward(_net(flat - h * d, width=width, n_enc=n_enc,
-                                        grid_only=grid_only), pairs[:, 0], pairs[:, 1])[0], t)
+                                        grid_only=grid_only, fourier=fourier),
+                                   pairs[:, 0], pairs[:, 1])[0], t)
         fd = (lp - lm) / (2 * h)
         an = float(np.dot(g.flat, d))
         assert abs(fd - an) <= 1e-6 * max(1e-3, abs(an)) + 1e-9, (key, fd, an)
+
+
+def test_fourier_features_identities():
+    """Fourier features (Sec. 4.2, Eq. 4) pinned by identities rather than by their
+    formula: every (sin, cos) pair lies on the unit circle; each frequency is
+    twice the previous one (double-angle formulas), with the same axis; the base
+    frequency is pi (p_j = 1/2 gives (1, 0)); a change of one coordinate changes
+    only that axis's raw column and features."""
+    rng = np.random.default_rng(31)
+    u = rng.random((50, 3))
+    F = nn.fourier_features(u, 12)
+    assert F.shape == (50, 3 + 72)
+    np.testing.assert_allclose(F[:, :3], 2 * u - 1, atol=0)
+    for i in range(12):
+        for j in range(3):
+            s_, c_ = F[:, 3 + 6 * i + 2 * j], F[:, 4 + 6 * i + 2 * j]
+            np.testing.assert_allclose(s_ ** 2 + c_ ** 2, 1.0, atol=1e-12)
+            if i < 11:
+                s2, c2 = F[:, 3 + 6 * (i + 1) + 2 * j], F[:, 4 + 6 * (i + 1) + 2 * j]
+                np.testing.assert_allclose(s2, 2 * s_ * c_, atol=1e-9)
+                np.testing.assert_allclose(c2, c_ ** 2 - s_ ** 2, atol=1e-9)
+    half = nn.fourier_features(np.array([[0.75, 0.75, 0.75]]), 1)[0]
+    np.testing.assert_allclose(half[3:], [1, 0, 1, 0, 1, 0], atol=1e-15)
+    for j in range(3):
+        v = u.copy()
+        v[:, j] = rng.random(50)
+        G = nn.fourier_features(v, 12)
+        changed = np.any(G != F, axis=0)
+        cols = {j} | {3 + 6 * i + 2 * j + k for i in range(12) for k in (0, 1)}
+        assert set(np.flatnonzero(changed)) == cols
+
+
+def test_fourier_input_embedding_layout():
+    """With L = 12 the encoder input is 112 wide: the 32 grid features, the raw
+    position and 72 Fourier features, then five zero columns; a network whose W1
+    reads only sin(2^3 pi p_y) gives that value through a closed form."""
+    L = _layout(width=16, fourier=12)
+    assert L.enc_in == 112
+    flat = gen.make_net_params(L, seed=4, grid_scale=0.5)
+    net = _net(flat, width=16, fourier=12)
+    u = np.random.default_rng(6).random((40, 3))
+    h0 = nn.input_embedding(net, 0, u)
+    assert h0.shape == (40, 112)
+    np.testing.assert_array_equal(h0[:, :32], nn.grid_encode(net, 0, u))
+    np.testing.assert_array_equal(h0[:, 107:], 0)
+    # W1 picks column 32 + 3 + 6 i + 2 j (i = 3, j = y), the encoder passes it on
+    # through identities: latent[0] = relu(relu(sin)) for a positive sine
+    net["W1", 0] = 0
+    net["b1", 0] = 0
+    W1 = net["W1", 0].copy()
+    W1[0, 32 + 3 + 6 * 3 + 2 * 1] = 1.0
+    net["W1", 0] = W1
+    for k in ("W2", "W3"):
+        net[k, 0] = np.eye(16)
+        net[k.replace("W", "b"), 0] = 0
+    enc = nn.encoder(net, 0, h0)
+    want = np.maximum(np.sin(8 * np.pi * (2 * u[:, 1] - 1)), 0)
+    np.testing.assert_allclose(enc["lat"][:, 0], want, atol=1e-15)
 
 
 def test_l1_gradient_sign_convention():
