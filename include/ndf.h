@@ -118,7 +118,13 @@ typedef struct ndf_ensemble {
  * the two 32-vectors and the decoder's first layer W4 is W x (L*F).  The
  * training, forward and BF16 field calls support it (ndf_infer_field with one
  * fused pass per reference, ndf_infer_points); FP8 and the query-latent calls
- * return NDF_E_UNSUPPORTED. */
+ * return NDF_E_UNSUPPORTED.
+ * Fourier features (fourier = 12; Sec. 4.2, Eq. 4): the encoder input is the 32
+ * grid features, then the raw position p in [-1, 1]^3 (vertex (i,j,k): p = 2u - 1;
+ * a continuous position clamped to the domain, NaN -> -1), then for i < 12 and
+ * j = x, y, z the pair sin(2^i pi p_j), cos(2^i pi p_j), then 5 zeros: 112
+ * inputs, W1 is W x 112.  Requires n_enc = 1 and grid_only = 0
+ * (NDF_E_UNSUPPORTED otherwise); every call supports it. */
 typedef struct ndf_net_config {
     int32_t nx, ny, nz;      /* data grid whose vertices are evaluated            */
     int32_t n_levels;        /* 4                                                 */
@@ -129,6 +135,7 @@ typedef struct ndf_net_config {
     int32_t log2_hashmap;    /* 0 (dense levels) or T in [8, 24]: hash tables of
                                 2^T cells for the levels larger than that        */
     int32_t grid_only;       /* 0: full network; 1: encoder MLP omitted          */
+    int32_t fourier;         /* 0, or 12: Fourier features of the position       */
 } ndf_net_config;
 
 /* Human-readable name of a status code (static storage). */

@@ -9,7 +9,14 @@ namespace ndf {
 constexpr int kH = 128;      // hidden width
 constexpr int kF = 8;        // features per grid level
 constexpr int kL = 4;        // grid levels
-constexpr int kK0 = kL * kF; // encoder input width
+constexpr int kK0 = kL * kF; // encoder input width (grid features)
+// With Fourier features (Sec. 4.2, Eq. 4): kFourierL frequencies; the encoder input
+// is the 32 grid features, the raw position (3) and 6 kFourierL sines and cosines,
+// zero-padded to kK0F = 112 (7 k-blocks of the MFMA).
+constexpr int kFourierL = 12;
+constexpr int kK0F = 112;
+
+inline int enc_in(const ndf_net_config *c) { return c->fourier ? kK0F : kK0; }
 constexpr int64_t kAlign = 64;
 
 struct NetOffsets {
@@ -30,6 +37,9 @@ inline int check_net_config(const ndf_net_config *c) {
     if (c->n_levels != kL || c->feats != kF || c->width != kH) return NDF_E_UNSUPPORTED;
     if (c->n_enc != 1 && c->n_enc != 2) return NDF_E_ARG;
     if (c->grid_only != 0 && c->grid_only != 1) return NDF_E_ARG;
+    if (c->fourier != 0 && c->fourier != kFourierL) return NDF_E_ARG;
+    // Fourier features feed the encoder MLP of a shared-encoder network
+    if (c->fourier && (c->n_enc != 1 || c->grid_only)) return NDF_E_UNSUPPORTED;
     for (int l = 0; l < kL; ++l)
         for (int a = 0; a < 3; ++a)
             if (c->res[l][a] < 2 || c->res[l][a] > (1 << 16)) return NDF_E_ARG;
@@ -69,7 +79,7 @@ inline NetOffsets net_offsets(const ndf_net_config *c) {
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) o.grid[e][l] = take(o.cells[l] * kF);
         if (c->grid_only) continue;  // no encoder MLP (W1..b3 offsets stay 0, unused)
-        o.W1[e] = take(kH * kK0);
+        o.W1[e] = take(kH * enc_in(c));
         o.b1[e] = take(kH);
         o.W2[e] = take(kH * kH);
         o.b2[e] = take(kH);
@@ -238,6 +248,60 @@ __device__ __forceinline__ float relu_f32(float x) {
 }
 __device__ __forceinline__ float bf_lo(uint32_t v) { return __uint_as_float(v << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
+
+// --------------------------------------------------- Fourier features ----
+// Position p in [-1, 1]^3 of grid vertex v: p_a = (2 i_a - (n_a - 1)) / (n_a - 1)
+// (one rounding), the vertex decomposed as in corners_R32.
+__device__ __forceinline__ void vertex_p(const GridGeom &g, int64_t v64, float p[3]) {
+    const uint32_t v = (uint32_t)v64;
+    const uint32_t t = (uint32_t)(((uint64_t)v * g.mx) >> 40);  // v / nx
+    const uint32_t k = (uint32_t)(((uint64_t)t * g.my) >> 40);  // t / ny
+    const int ii[3] = {(int)(v - t * (uint32_t)g.nx), (int)(t - k * (uint32_t)g.ny), (int)k};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = (float)(2 * ii[a] - (nn[a] - 1)) / (float)(nn[a] - 1);
+}
+// A continuous position clamped to the domain (NaN -> -1), as the lookup clamps it.
+__device__ __forceinline__ void clamp_p(const float q[3], float p[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf(q[a], -1.f), 1.f);
+}
+
+__host__ __device__ constexpr float pow2f(int n) {
+    return n >= 0 ? (float)(1u << n) : 1.f / (float)(1u << -n);
+}
+// Slot t of the 80 inputs after the grid features: the raw position (t < 3),
+// sin and cos of 2^i pi p_j (t = 3 + 6 i + 2 j, + 1 for cos), zero padding
+// (t >= 75).  sin(2^i pi p) is the hardware sine of x = 2^(i-1) p revolutions
+// reduced exactly to x - rint(x) in [-1/2, 1/2]; cos adds a quarter turn.
+__device__ __forceinline__ float ff_value(int t, const float (&p)[3]) {
+    if (t < 3) return p[t];
+    if (t >= 3 + 6 * kFourierL) return 0.f;
+    const int u = t - 3;
+    const float x = p[(u % 6) / 2] * pow2f(u / 6 - 1);
+    return __builtin_amdgcn_sinf(x - rintf(x) + ((u & 1) ? 0.25f : 0.f));
+}
+// Element e of k-block kb >= 2 of the encoder input, lane half h: slot
+// t = 16 (kb - 2) + 8 h + e.  Both halves' slots are known at compile time, so
+// the lane picks its argument first and evaluates one sine.
+__device__ __forceinline__ float ff_elem(int kb, int e, int h, const float (&p)[3]) {
+    const int t0 = 16 * (kb - 2) + e, t1 = t0 + 8;
+    const bool f0 = t0 >= 3 && t0 < 3 + 6 * kFourierL, f1 = t1 >= 3 && t1 < 3 + 6 * kFourierL;
+    if (f0 && f1) {
+        const int u0 = t0 - 3, u1 = t1 - 3;
+        const float x = h ? p[(u1 % 6) / 2] * pow2f(u1 / 6 - 1) : p[(u0 % 6) / 2] * pow2f(u0 / 6 - 1);
+        const float q = h ? ((u1 & 1) ? 0.25f : 0.f) : ((u0 & 1) ? 0.25f : 0.f);
+        return __builtin_amdgcn_sinf(x - rintf(x) + q);
+    }
+    const float v0 = ff_value(t0, p), v1 = ff_value(t1, p);
+    return h ? v1 : v0;
+}
+__device__ __forceinline__ bf16x8 ff_chunk(int kb, int h, const float (&p)[3]) {
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = f2bf(ff_elem(kb, e, h, p));
+    return r;
+}
 
 size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B);
 size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec);

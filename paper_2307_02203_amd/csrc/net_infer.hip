@@ -50,7 +50,7 @@ static QLayout qlayout(const ndf_net_config *c) {
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) q.grid[e][l] = take(o.cells[l] * kF * 2);
         if (c->grid_only) continue;  // no encoder MLP
-        q.w1[e] = take(kH * kK0 * 2);
+        q.w1[e] = take(kH * enc_in(c) * 2);
         q.w2[e] = take(kH * kH * 2);
         q.w3[e] = take(kH * kH * 2);
         q.b1[e] = take(kH * 4);
@@ -225,7 +225,7 @@ int launch_net_quantize(const ndf_net_config *c, const float *P, int prec, void 
                                0, st, P + o.grid[e][l], n, (uint16_t *)(Q + q.grid[e][l]));
         }
         if (c->grid_only) continue;
-        hipLaunchKernelGGL(pack_frag_kernel, dim3(16), dim3(256), 0, st, P + o.W1[e], kK0, 0,
+        hipLaunchKernelGGL(pack_frag_kernel, dim3(16), dim3(256), 0, st, P + o.W1[e], enc_in(c), 0,
                            (uint16_t *)(Q + q.w1[e]));
         hipLaunchKernelGGL(pack_frag_kernel, dim3(64), dim3(256), 0, st, P + o.W2[e], kH, 1,
                            (uint16_t *)(Q + q.w2[e]));
@@ -437,7 +437,7 @@ __device__ __forceinline__ void wave_max_into(const bf16x8 (&v)[8][2], const boo
 // grid features (32, in the gather's natural feature order 16 kb + 8 h + e), the
 // product with the reference's feeds W4 [128][32] (held in s_w1) and W5 sits in
 // s_w[3]; field modes only, shared grid or separate grids alike.
-template <int MODE, bool HASH, bool SEP = false, bool GO = false>
+template <int MODE, bool HASH, bool SEP = false, bool GO = false, bool FF = false>
 __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                                               const int64_t *__restrict__ qlist,
                                                               int64_t nq,
@@ -447,8 +447,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     // MODE 4: calibration of the FP8 activation scales: workgroup w takes reference
     // cal_vertex(w, gridDim.x) against the nq calibration queries and folds the
     // largest |input| of layers 2..5 into ((int *)out)[0..3]
+    // FF: Fourier features after the grid features (k-blocks 2 .. KB1 - 1)
     constexpr bool kField = MODE == 0 || MODE == 3 || MODE == 4;
-    __shared__ bf16x8 s_w1[kFragW1];
+    constexpr int KB1 = FF ? kK0F / 16 : 2;
+    constexpr int kW1 = 4 * KB1 * 64;
+    __shared__ bf16x8 s_w1[kW1];
     __shared__ bf16x8 s_w[4][kFragW];
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         for (int i = tid; i < 2 * kH; i += kInferThreads)
             s_b[3 + i / kH][i % kH] = A.b[3 + i / kH][i % kH];
     } else {
-        for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = (SEP ? A.rw[0] : A.w[0])[i];
+        for (int i = tid; i < kW1; i += kInferThreads) s_w1[i] = (SEP ? A.rw[0] : A.w[0])[i];
         const int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
         for (int L = 0; L < nlay; ++L)
             for (int i = tid; i < kFragW; i += kInferThreads)
@@ -517,9 +520,15 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                     for (int e = 0; e < 8; ++e) s_ref[16 * kb + 8 * h + e] = (float)t[e];
                 }
             }
+            if (FF) {
+                float pp[3];
+                vertex_p(A.g, fref, pp);
+#pragma unroll
+                for (int kb = 2; kb < KB1; ++kb) a[kb][0] = a[kb][1] = ff_chunk(kb, h, pp);
+            }
             float part[2] = {0.f, 0.f};
             if (!GO) {
-            dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok, lane, h4);
+            dense_layer<KB1, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok, lane, h4);
             dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0, ok, lane, h4);
             dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref, 0, ok,
                                            lane, h4);
@@ -527,7 +536,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         }
         __syncthreads();
         if (SEP && !GO) {  // the query encoder's layers replace the reference encoder's
-            for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[0][i];
+            for (int i = tid; i < kW1; i += kInferThreads) s_w1[i] = A.w[0][i];
             for (int L = 0; L < 2; ++L)
                 for (int i = tid; i < kFragW; i += kInferThreads) s_w[L][i] = A.w[L + 1][i];
             for (int i = tid; i < 3 * kH; i += kInferThreads)
@@ -594,6 +603,18 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                 a[kb][q] = t;
             }
         }
+        if (FF) {  // the raw position and its Fourier features
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                float pp[3];
+                if (MODE == 3)
+                    clamp_p(pq[q], pp);
+                else
+                    vertex_p(A.g, vq[q], pp);
+#pragma unroll
+                for (int kb = 2; kb < KB1; ++kb) a[kb][q] = ff_chunk(kb, h, pp);
+            }
+        }
         float part[2] = {0.f, 0.f};
         if (GO) {
             // product of the query's and the reference's grid features (exact in
@@ -611,8 +632,8 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
                                      lane, h4);
         } else if (MODE == 4) {
             int *amax = reinterpret_cast<int *>(out);
-            dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok,
-                                     lane, h4);
+            dense_layer<KB1, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok,
+                                       lane, h4);
             wave_max_into<8>(b, ok, amax + 0);
             dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok,
                                      lane, h4);
@@ -625,7 +646,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             wave_max_into<8>(a, ok, amax + 3);
             continue;
         } else {
-        dense_layer<2, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
+        dense_layer<KB1, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, row0, ok, lane, h4);
         dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, row0, ok, lane, h4);
         if (MODE == 1) {
             dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, out, row0, ok,
@@ -738,11 +759,11 @@ struct InferArgs8 {
 
 constexpr int kFrag8 = 4 * 2 * 64;  // i32x8 per 128x128 fp8 layer
 
-template <int KIND, bool BF16IN>
+template <int KIND, bool BF16IN, int KB1>
 __device__ __forceinline__ void dense_layer_fp8(
     const bf16x8 *__restrict__ w16, const i32x8 *__restrict__ w8, const int *__restrict__ se,
     const float *__restrict__ bias, const float *__restrict__ ref, const float *__restrict__ w6,
-    const bf16x8 (&in16)[2][2], const i32x8 (&in8)[2][2], int sin, i32x8 (&out8)[2][2],
+    const bf16x8 (&in16)[KB1][2], const i32x8 (&in8)[2][2], int sin, i32x8 (&out8)[2][2],
     float so, float clip, float (&part)[2], float *__restrict__ lat_out, int64_t row0,
     const bool (&ok)[2], int lane, int h4) {
     // sin: the E8M0 scale byte of this layer's inputs; so, clip: the scale of the
@@ -799,8 +820,8 @@ __device__ __forceinline__ void dense_layer_fp8(
             const int ob = 2 * op + o;
             if (BF16IN) {
 #pragma unroll
-                for (int kb = 0; kb < 2; ++kb) {
-                    const bf16x8 a = w16[(ob * 2 + kb) * 64 + lane];
+                for (int kb = 0; kb < KB1; ++kb) {
+                    const bf16x8 a = w16[(ob * KB1 + kb) * 64 + lane];
                     acc[o][0] = mfma32(a, in16[kb][0], acc[o][0]);
                     acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
                 }
@@ -854,7 +875,7 @@ __device__ __forceinline__ void dense_layer_fp8(
 
 // MODE 0: field (out[v] = Phi(ref, v)); MODE 1: latents of the vertices in
 // qlist (FP32); MODE 3: field at the continuous positions qpos[n][3].
-template <int MODE, bool HASH>
+template <int MODE, bool HASH, bool FF = false>
 __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   const int64_t *__restrict__ qlist,
                                                                   int64_t nq,
@@ -862,7 +883,8 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                                                                   float *__restrict__ out,
                                                                   const float *__restrict__ qpos) {
     constexpr bool kField = MODE == 0 || MODE == 3;
-    __shared__ bf16x8 s_w1[kFragW1];
+    constexpr int KB1 = FF ? kK0F / 16 : 2;  // k-blocks of the encoder input
+    __shared__ bf16x8 s_w1[4 * KB1 * 64];
     __shared__ i32x8 s_q[4][kFrag8];
     __shared__ int s_e[4][kH * 4];
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
@@ -870,7 +892,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
 
     const int tid = threadIdx.x;
-    for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w1[i];
+    for (int i = tid; i < 4 * KB1 * 64; i += kInferThreads) s_w1[i] = A.w1[i];
     const int nlay = kField ? 4 : 2;
     for (int L = 0; L < nlay; ++L)
         for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L][i];
@@ -892,7 +914,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         if (wave == 0) {
             const int h4 = 4 * h;
             const bool ok[2] = {jl == 0, false};
-            bf16x8 g16[2][2];
+            bf16x8 g16[KB1][2];
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb) {
                 const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
@@ -918,6 +940,12 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
 #pragma unroll
                 for (int e = 0; e < 8; ++e) t[e] = f2bf(sf[e]);
                 g16[kb][0] = g16[kb][1] = t;
+            }
+            if (FF) {
+                float pp[3];
+                vertex_p(A.g, A.fuse_ref, pp);
+#pragma unroll
+                for (int kb = 2; kb < KB1; ++kb) g16[kb][0] = g16[kb][1] = ff_chunk(kb, h, pp);
             }
             i32x8 a8[2][2], b8[2][2];
             float part[2] = {0.f, 0.f};
@@ -951,7 +979,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
 #pragma unroll
             for (int a = 0; a < 3; ++a) pq[q][a] = MODE == 3 && ok[q] ? qpos[3 * n + a] : 0.f;
         }
-        bf16x8 g16[2][2];
+        bf16x8 g16[KB1][2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
             const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
@@ -983,6 +1011,18 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
                 for (int e = 0; e < 8; ++e) t[e] = f2bf(s[e]);
                 g16[kb][q] = t;
                 __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (FF) {  // the raw position and its Fourier features
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                float pp[3];
+                if (MODE == 3)
+                    clamp_p(pq[q], pp);
+                else
+                    vertex_p(A.g, vq[q], pp);
+#pragma unroll
+                for (int kb = 2; kb < KB1; ++kb) g16[kb][q] = ff_chunk(kb, h, pp);
             }
         }
         i32x8 a8[2][2], b8[2][2];
@@ -1233,20 +1273,18 @@ static bool any_hashed(const ndf_net_config *c) {
 // Static activation scales of the E4M3 layers: the largest |input| of layers
 // 2..5 over a fixed calibration set (kCalRefs references x kCalQueries
 // queries spread evenly over the grid), run through the BF16 layers.
+template <int MODE>
+static void run_infer(const ndf_net_config *c, bool sep, dim3 g, const InferArgs &a,
+                      const int64_t *ql, int64_t nq, const float *rl, float *out,
+                      const float *qpos, hipStream_t st);
+
 static void launch_calibrate(const ndf_net_config *c, const QLayout &q, char *Q, hipStream_t st) {
     int *amax = (int *)(Q + q.amax);
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, amax, 4);
     const InferArgs a = fused_args(c, q, Q, 0);
-    const dim3 g(kCalRefs), b(kInferThreads);
-    const bool hash = any_hashed(c), sep = c->n_enc == 2;
-#define NDF_CAL(H, S) \
-    hipLaunchKernelGGL((infer_kernel<4, H, S>), g, b, 0, st, a, nullptr, (int64_t)kCalQueries, \
-                       nullptr, (float *)amax, nullptr)
-    if (hash && sep) NDF_CAL(true, true);
-    else if (hash) NDF_CAL(true, false);
-    else if (sep) NDF_CAL(false, true);
-    else NDF_CAL(false, false);
-#undef NDF_CAL
+    const dim3 g(kCalRefs);
+    run_infer<4>(c, c->n_enc == 2, g, a, nullptr, (int64_t)kCalQueries, nullptr, (float *)amax,
+                 nullptr, st);
 }
 
 static unsigned infer_blocks(int64_t nq) {
@@ -1260,16 +1298,56 @@ size_t net_latent_cache_bytes(const ndf_net_config *c) {
     return (size_t)ceil_div(V, 64) * 8 * 2 * 64 * 16;
 }
 
-int launch_infer_latents(const ndf_net_config *c, const void *qp, void *cache, hipStream_t st) {
+// infer_kernel<MODE, ...> for the network's hashing, encoders (sep: a field mode
+// whose reference latent comes from encoder 0) and input embedding.
+template <int MODE>
+static void run_infer(const ndf_net_config *c, bool sep, dim3 g, const InferArgs &a,
+                      const int64_t *ql, int64_t nq, const float *rl, float *out,
+                      const float *qpos, hipStream_t st) {
+    const dim3 b(kInferThreads);
     const bool hash = any_hashed(c);
+#define NDF_IK(H, S, F) \
+    hipLaunchKernelGGL((infer_kernel<MODE, H, S, false, F>), g, b, 0, st, a, ql, nq, rl, out, qpos)
+    if (c->fourier) {
+        if (hash) NDF_IK(true, false, true);
+        else NDF_IK(false, false, true);
+        return;
+    }
+    if constexpr (MODE == 0 || MODE == 3 || MODE == 4) {
+        if (sep) {
+            if (hash) NDF_IK(true, true, false);
+            else NDF_IK(false, true, false);
+            return;
+        }
+    }
+    if (hash) NDF_IK(true, false, false);
+    else NDF_IK(false, false, false);
+#undef NDF_IK
+}
+
+template <int MODE>
+static void run_infer8(const ndf_net_config *c, dim3 g, const InferArgs8 &a, const int64_t *ql,
+                       int64_t nq, const float *rl, float *out, const float *qpos,
+                       hipStream_t st) {
+    const dim3 b(kInferThreads);
+    const bool hash = any_hashed(c);
+#define NDF_IK8(H, F) \
+    hipLaunchKernelGGL((infer_fp8_kernel<MODE, H, F>), g, b, 0, st, a, ql, nq, rl, out, qpos)
+    if (c->fourier) {
+        if (hash) NDF_IK8(true, true);
+        else NDF_IK8(false, true);
+    } else {
+        if (hash) NDF_IK8(true, false);
+        else NDF_IK8(false, false);
+    }
+#undef NDF_IK8
+}
+
+int launch_infer_latents(const ndf_net_config *c, const void *qp, void *cache, hipStream_t st) {
     const QLayout q = qlayout(c);
     const InferArgs a = make_args(c, q, (const char *)qp, c->n_enc - 1);
-    if (hash)
-        hipLaunchKernelGGL((infer_kernel<2, true>), dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
-                           nullptr, a.V, nullptr, (float *)cache, nullptr);
-    else
-        hipLaunchKernelGGL((infer_kernel<2, false>), dim3(infer_blocks(a.V)), dim3(kInferThreads), 0, st, a,
-                           nullptr, a.V, nullptr, (float *)cache, nullptr);
+    run_infer<2>(c, false, dim3(infer_blocks(a.V)), a, nullptr, a.V, nullptr, (float *)cache,
+                 nullptr, st);
     return status_of_launch();
 }
 
@@ -1287,21 +1365,21 @@ static void decode_cached(const ndf_net_config *c, const QLayout &q, const char 
     }
 }
 
+// Reference latents lat[n][128] of the vertices refs[n] (device) with encoder 0.
+static void ref_latents(const ndf_net_config *c, const QLayout &q, const char *Q,
+                        const int64_t *refs, int n, float *lat, hipStream_t st) {
+    const InferArgs a0 = make_args(c, q, Q, 0);
+    run_infer<1>(c, false, dim3(infer_blocks(n)), a0, refs, (int64_t)n, nullptr, lat, nullptr, st);
+}
+
 int launch_infer_field_cached(const ndf_net_config *c, const void *qp, const int64_t *ref_v,
                               int n_ref, const void *cache, float *out, void *ws, hipStream_t st) {
-    const bool hash = any_hashed(c);
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
     if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
-    const InferArgs a0 = make_args(c, q, Q, 0);
-    if (hash)
-        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
-    else
-        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    ref_latents(c, q, Q, refs, n_ref, lat, st);
     decode_cached(c, q, Q, cache, lat, n_ref, out, st);
     return status_of_launch();
 }
@@ -1314,20 +1392,14 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
+    const int64_t V = (int64_t)c->nx * c->ny * c->nz;
     if (prec == NDF_PREC_FP8_E4M3 && c->n_enc == 1) {
         // shared encoder: each workgroup computes the reference latent itself
         InferArgs8 a = make_args8(c, q, Q, 0);
-        const int64_t V = (int64_t)c->nx * c->ny * c->nz;
         for (int r = 0; r < n_ref; ++r) {
             a.fuse_ref = ref_v[r];
-            if (hash)
-                hipLaunchKernelGGL((infer_fp8_kernel<0, true>), dim3(infer_blocks(V)),
-                                   dim3(kInferThreads), 0, st, a, nullptr, V, nullptr,
-                                   out + (int64_t)r * V, nullptr);
-            else
-                hipLaunchKernelGGL((infer_fp8_kernel<0, false>), dim3(infer_blocks(V)),
-                                   dim3(kInferThreads), 0, st, a, nullptr, V, nullptr,
-                                   out + (int64_t)r * V, nullptr);
+            run_infer8<0>(c, dim3(infer_blocks(V)), a, nullptr, V, nullptr, out + (int64_t)r * V,
+                          nullptr, st);
         }
         return status_of_launch();
     }
@@ -1356,13 +1428,7 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
         // the fused single-reference field)
         if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
         void *cache = (char *)ws + net_infer_lat_ws_bytes(n_ref);
-        const InferArgs a0 = make_args(c, q, Q, 0);
-        if (hash)
-            hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
-        else
-            hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        ref_latents(c, q, Q, refs, n_ref, lat, st);
         if (launch_infer_latents(c, qp, cache, st) != NDF_OK) return NDF_E_HIP;
         decode_cached(c, q, Q, cache, lat, n_ref, out, st);
         return status_of_launch();
@@ -1372,62 +1438,20 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
         const bool sep = c->n_enc == 2;
         for (int r = 0; r < n_ref; ++r) {
             const InferArgs a = fused_args(c, q, Q, ref_v[r]);
-            const dim3 g(infer_blocks(a.V)), b(kInferThreads);
-            float *o = out + (int64_t)r * a.V;
-            if (sep && hash)
-                hipLaunchKernelGGL((infer_kernel<0, true, true>), g, b, 0, st, a, nullptr, a.V,
-                                   nullptr, o, nullptr);
-            else if (sep)
-                hipLaunchKernelGGL((infer_kernel<0, false, true>), g, b, 0, st, a, nullptr, a.V,
-                                   nullptr, o, nullptr);
-            else if (hash)
-                hipLaunchKernelGGL((infer_kernel<0, true>), g, b, 0, st, a, nullptr, a.V, nullptr,
-                                   o, nullptr);
-            else
-                hipLaunchKernelGGL((infer_kernel<0, false>), g, b, 0, st, a, nullptr, a.V, nullptr,
-                                   o, nullptr);
+            run_infer<0>(c, sep, dim3(infer_blocks(a.V)), a, nullptr, a.V, nullptr,
+                         out + (int64_t)r * a.V, nullptr, st);
         }
         return status_of_launch();
     }
+    // FP8 with two encoders: reference latents with encoder 0 (p1), then one pass
+    // per reference with the query encoder (p2)
     if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
-    if (prec == NDF_PREC_FP8_E4M3) {
-        const InferArgs8 a0 = make_args8(c, q, Q, 0);
-        if (hash)
-            hipLaunchKernelGGL((infer_fp8_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
-        else
-            hipLaunchKernelGGL((infer_fp8_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
-        const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
-        const int64_t V = (int64_t)c->nx * c->ny * c->nz;
-        for (int r = 0; r < n_ref; ++r)
-            if (hash)
-                hipLaunchKernelGGL((infer_fp8_kernel<0, true>), dim3(infer_blocks(V)), dim3(kInferThreads), 0,
-                                   st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V,
-                                   nullptr);
-            else
-                hipLaunchKernelGGL((infer_fp8_kernel<0, false>), dim3(infer_blocks(V)), dim3(kInferThreads), 0,
-                                   st, a1, nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V,
-                                   nullptr);
-        return status_of_launch();
-    }
-    // reference latents with encoder 0 (p1), queries with the last encoder (p2)
-    const InferArgs a0 = make_args(c, q, Q, 0);
-    if (hash)
-        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
-    else
-        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
-    const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
-    const int64_t V = a1.V;
+    const InferArgs8 a0 = make_args8(c, q, Q, 0);
+    run_infer8<1>(c, dim3(infer_blocks(n_ref)), a0, refs, (int64_t)n_ref, nullptr, lat, nullptr, st);
+    const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
     for (int r = 0; r < n_ref; ++r)
-        if (hash)
-            hipLaunchKernelGGL((infer_kernel<0, true>), dim3(infer_blocks(V)), dim3(kInferThreads), 0, st, a1,
-                               nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V, nullptr);
-        else
-            hipLaunchKernelGGL((infer_kernel<0, false>), dim3(infer_blocks(V)), dim3(kInferThreads), 0, st, a1,
-                               nullptr, V, lat + (int64_t)r * kH, out + (int64_t)r * V, nullptr);
+        run_infer8<0>(c, dim3(infer_blocks(V)), a1, nullptr, V, lat + (int64_t)r * kH,
+                      out + (int64_t)r * V, nullptr, st);
     return status_of_launch();
 }
 
@@ -1462,26 +1486,14 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
             InferArgs8 a = make_args8(c, q, Q, 0);
             for (int r = 0; r < n_ref; ++r) {
                 a.fuse_ref = ref_v[r];
-                if (hash)
-                    hipLaunchKernelGGL((infer_fp8_kernel<3, true>), dim3(infer_blocks(n)),
-                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
-                                       out + (int64_t)r * n, pos);
-                else
-                    hipLaunchKernelGGL((infer_fp8_kernel<3, false>), dim3(infer_blocks(n)),
-                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
-                                       out + (int64_t)r * n, pos);
+                run_infer8<3>(c, dim3(infer_blocks(n)), a, nullptr, n, nullptr,
+                              out + (int64_t)r * n, pos, st);
             }
         } else {
             for (int r = 0; r < n_ref; ++r) {
                 const InferArgs a = fused_args(c, q, Q, ref_v[r]);
-                if (hash)
-                    hipLaunchKernelGGL((infer_kernel<3, true>), dim3(infer_blocks(n)),
-                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
-                                       out + (int64_t)r * n, pos);
-                else
-                    hipLaunchKernelGGL((infer_kernel<3, false>), dim3(infer_blocks(n)),
-                                       dim3(kInferThreads), 0, st, a, nullptr, n, nullptr,
-                                       out + (int64_t)r * n, pos);
+                run_infer<3>(c, false, dim3(infer_blocks(n)), a, nullptr, n, nullptr,
+                             out + (int64_t)r * n, pos, st);
             }
         }
         return status_of_launch();
@@ -1489,45 +1501,24 @@ int launch_infer_points(const ndf_net_config *c, const void *qp, int prec, const
     if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
     if (prec == NDF_PREC_FP8_E4M3) {
         const InferArgs8 a0 = make_args8(c, q, Q, 0);
-        if (hash)
-            hipLaunchKernelGGL((infer_fp8_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
-        else
-            hipLaunchKernelGGL((infer_fp8_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0,
-                               st, a0, refs, (int64_t)n_ref, nullptr, lat, nullptr);
+        run_infer8<1>(c, dim3(infer_blocks(n_ref)), a0, refs, (int64_t)n_ref, nullptr, lat, nullptr,
+                      st);
         const InferArgs8 a1 = make_args8(c, q, Q, c->n_enc - 1);
         for (int r = 0; r < n_ref; ++r)
-            if (hash)
-                hipLaunchKernelGGL((infer_fp8_kernel<3, true>), dim3(infer_blocks(n)), dim3(kInferThreads), 0,
-                                   st, a1, nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n,
-                                   pos);
-            else
-                hipLaunchKernelGGL((infer_fp8_kernel<3, false>), dim3(infer_blocks(n)), dim3(kInferThreads), 0,
-                                   st, a1, nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n,
-                                   pos);
+            run_infer8<3>(c, dim3(infer_blocks(n)), a1, nullptr, n, lat + (int64_t)r * kH,
+                          out + (int64_t)r * n, pos, st);
         return status_of_launch();
     }
-    const InferArgs a0 = make_args(c, q, Q, 0);
-    if (hash)
-        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
-    else
-        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(infer_blocks(n_ref)), dim3(kInferThreads), 0, st, a0,
-                           refs, (int64_t)n_ref, nullptr, lat, nullptr);
+    ref_latents(c, q, Q, refs, n_ref, lat, st);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     for (int r = 0; r < n_ref; ++r)
-        if (hash)
-            hipLaunchKernelGGL((infer_kernel<3, true>), dim3(infer_blocks(n)), dim3(kInferThreads), 0, st, a1,
-                               nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n, pos);
-        else
-            hipLaunchKernelGGL((infer_kernel<3, false>), dim3(infer_blocks(n)), dim3(kInferThreads), 0, st, a1,
-                               nullptr, n, lat + (int64_t)r * kH, out + (int64_t)r * n, pos);
+        run_infer<3>(c, false, dim3(infer_blocks(n)), a1, nullptr, n, lat + (int64_t)r * kH,
+                     out + (int64_t)r * n, pos, st);
     return status_of_launch();
 }
 
 int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref_a, int64_t ref_b,
                             const void *cache, float *out, void *ws, hipStream_t st) {
-    const bool hash = any_hashed(c);
     const QLayout q = qlayout(c);
     const char *Q = (const char *)qp;
     float *lat = (float *)ws;
@@ -1535,12 +1526,7 @@ int launch_infer_difference(const ndf_net_config *c, const void *qp, int64_t ref
     const int64_t both[2] = {ref_a, ref_b};
     if (put_refs(both, 2, refs, st) != NDF_OK) return NDF_E_HIP;
     const InferArgs a0 = make_args(c, q, Q, 0);
-    if (hash)
-        hipLaunchKernelGGL((infer_kernel<1, true>), dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
-                           nullptr, lat, nullptr);
-    else
-        hipLaunchKernelGGL((infer_kernel<1, false>), dim3(1), dim3(kInferThreads), 0, st, a0, refs, (int64_t)2,
-                           nullptr, lat, nullptr);
+    run_infer<1>(c, false, dim3(1), a0, refs, (int64_t)2, nullptr, lat, nullptr, st);
     const InferArgs a1 = make_args(c, q, Q, c->n_enc - 1);
     hipLaunchKernelGGL(infer_cached_kernel<true>, dim3(infer_blocks(a1.V)), dim3(kInferThreads), 0,
                        st, a1, (const u32x4 *)cache, a1.V, lat, 2, out, a1.V);

@@ -621,6 +621,7 @@ constexpr int kTW = 8;                 // waves per workgroup of the fused kerne
 constexpr int kTThreads = 64 * kTW;
 constexpr int kFragH = 4 * 8 * 64;     // bf16x8 per 128 x 128 layer fragment set
 constexpr int kFrag1 = 4 * 2 * 64;     // W1 (128 x 32), and W1^T (32 x 128): 8 x 64
+constexpr int kFrag1F = 4 * 7 * 64;    // W1 with Fourier features (128 x 112)
 
 // Packed weights of one step: forward A fragments of W1..W5 (W[o][k], lane l
 // of fragment (ob, kb) holds row 32 ob + l % 32, inputs 8 (l / 32) + 16 kb + e in
@@ -633,16 +634,18 @@ struct TrainFrags {
 };
 
 __global__ void pack_train_kernel(const float *__restrict__ P, int64_t w1, int64_t w2,
-                                  int64_t w3, int64_t w4, int64_t w5, TrainFrags F) {
+                                  int64_t w3, int64_t w4, int64_t w5, int kin1, TrainFrags F) {
     const int64_t wo[5] = {w1, w2, w3, w4, w5};
-    // 5 forward + 5 adjoint fragment sets: 2 x (4096 + 4 x 16384) elements
-    constexpr int kPer = kH * kK0 + 4 * kH * kH;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * kPer; t += gridDim.x * blockDim.x) {
-        const bool adj = t >= kPer;
-        int u = adj ? t - kPer : t;
-        const int L = u < kH * kK0 ? 0 : 1 + (u - kH * kK0) / (kH * kH);
-        if (L > 0) u = (u - kH * kK0) % (kH * kH);
-        const int KIN = L == 0 ? kK0 : kH;
+    // forward: W1 (128 x kin1) and W2..W5; adjoint: W1^T (the 32 grid inputs only:
+    // no gradient flows into the Fourier features) and W2^T..W5^T
+    const int n1 = kH * kin1, nf = n1 + 4 * kH * kH, na = kH * kK0 + 4 * kH * kH;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nf + na; t += gridDim.x * blockDim.x) {
+        const bool adj = t >= nf;
+        int u = adj ? t - nf : t;
+        const int m1 = adj ? kH * kK0 : n1;
+        const int L = u < m1 ? 0 : 1 + (u - m1) / (kH * kH);
+        if (L > 0) u = (u - m1) % (kH * kH);
+        const int KIN = L == 0 ? kin1 : kH;
         const int e = u & 7, lane = (u >> 3) & 63, fi = u >> 9;
         const int h = lane >> 5, il = lane & 31;
         float v;
@@ -766,15 +769,16 @@ __device__ __forceinline__ bf16x8 as_b(const u32x4 &v) { return __builtin_bit_ca
 
 // Forward of 32 pairs per wave; with targets also the loss partial sums, gy and
 // the first gradient da5 = gy w6 (masked by d2 > 0).
-template <bool POS>
+template <bool POS, bool FF>
 __global__ __launch_bounds__(kTThreads) void train_fwd_kernel(FusedArgs A) {
-    __shared__ bf16x8 s_w1[kFrag1];
+    constexpr int KB1 = FF ? kK0F / 16 : kK0 / 16;  // k-blocks of the encoder input
+    __shared__ bf16x8 s_w1[4 * KB1 * 64];
     __shared__ bf16x8 s_w[4][kFragH];
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
     __shared__ double s_part[kTW];
     const int tid = threadIdx.x;
-    for (int i = tid; i < kFrag1; i += kTThreads) s_w1[i] = A.wf[0][i];
+    for (int i = tid; i < 4 * KB1 * 64; i += kTThreads) s_w1[i] = A.wf[0][i];
     for (int L = 0; L < 4; ++L)
         for (int i = tid; i < kFragH; i += kTThreads) s_w[L][i] = A.wf[L + 1][i];
     for (int i = tid; i < 5 * kH; i += kTThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
@@ -810,14 +814,26 @@ __global__ __launch_bounds__(kTThreads) void train_fwd_kernel(FusedArgs A) {
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb) {
                 a[kb][q] = gather_h0<POS>(A, kb, h, v, p);
-                A.h0[slab_chunk(2 * tile + q, 2, kb, lane)] = as_u(a[kb][q]);
+                A.h0[slab_chunk(2 * tile + q, KB1, kb, lane)] = as_u(a[kb][q]);
+            }
+            if (FF) {  // the raw position and its Fourier features
+                float pp[3];
+                if (POS)
+                    clamp_p(p, pp);
+                else
+                    vertex_p(A.g, v, pp);
+#pragma unroll
+                for (int kb = 2; kb < KB1; ++kb) {
+                    a[kb][q] = ff_chunk(kb, h, pp);
+                    A.h0[slab_chunk(2 * tile + q, KB1, kb, lane)] = as_u(a[kb][q]);
+                }
             }
         }
         f32x16 acc[2];
         // layer 1: 32 -> 128, ReLU (both endpoints)
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
-            mma_block<2, 2>(s_w1, ob, s_b[0] + h4, a, acc, lane);
+            mma_block<KB1, 2>(s_w1, ob, s_b[0] + h4, a, acc, lane);
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 u32x4 c0, c1;
@@ -1084,6 +1100,7 @@ __global__ __launch_bounds__(kTThreads) void train_bwd_kernel(FusedArgs A) {
 // at the end.
 struct WgradArgs {
     const u32x4 *g[5], *x[5];
+    int kin1;  // inputs of W1 (32, or 112 with Fourier features)
     int64_t nslab[6];
     float *dW[6], *db[6];
     const u32x4 *d2;
@@ -1147,7 +1164,8 @@ __global__ __launch_bounds__(512) void wgrad_all_kernel(WgradArgs A) {
     const int part = (int)blockIdx.x - A.wg0[L], nparts = A.wg0[L + 1] - A.wg0[L];
     const int64_t nslab = A.nslab[L];
     if (2 * (int64_t)part >= nslab) return;
-    const int xkb = L == 0 ? 2 : 8, xcb = L == 0 ? 1 : 4;
+    const int kin = L == 0 ? A.kin1 : kH;
+    const int xkb = kin / 16, xcb = (kin + 31) / 32;
     const int ob = wave & 3, cb0 = 2 * (wave >> 2);
     // this thread's block
     const int u = tid & 255, sl = u >> 7, kb = (u >> 4) & 7, hh = (u >> 3) & 1,
@@ -1225,10 +1243,11 @@ __global__ __launch_bounds__(512) void wgrad_all_kernel(WgradArgs A) {
         else if (tid == kH) unsafeAtomicAdd(A.db[5], bsum);
         return;
     }
-    const int kin = L == 0 ? kK0 : kH;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        if (cb0 + q >= xcb) continue;
+        // columns past the input width (W1 with 112 inputs: 112..127) hold
+        // nothing and are not written
+        if (cb0 + q >= xcb || 32 * (cb0 + q) + jl >= kin) continue;
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             unsafeAtomicAdd(A.dW[L] + (32 * ob + d_row(r, lane)) * kin + 32 * (cb0 + q) + jl,
@@ -1252,7 +1271,7 @@ struct FusedWS {
 
 constexpr int kFusedBlocksMax = 512;
 
-static FusedWS carve_fused(void *ws, int64_t B) {
+static FusedWS carve_fused(const ndf_net_config *c, void *ws, int64_t B) {
     FusedWS t{};
     const int64_t T = ceil_div(B, 32);
     char *base = (char *)ws;
@@ -1263,10 +1282,11 @@ static FusedWS carve_fused(void *ws, int64_t B) {
         return p;
     };
     t.status = (int32_t *)take(kStatusBytes);
-    for (int L = 0; L < 5; ++L) t.fr.f[L] = (bf16x8 *)take((L == 0 ? kFrag1 : kFragH) * 16);
+    const int kb1 = enc_in(c) / 16;
+    for (int L = 0; L < 5; ++L) t.fr.f[L] = (bf16x8 *)take((L == 0 ? 4 * kb1 * 64 : kFragH) * 16);
     for (int L = 0; L < 5; ++L) t.fr.t[L] = (bf16x8 *)take((L == 0 ? kFrag1 : kFragH) * 16);
     const size_t slab = 8 * 64 * 16;  // 128 features x 32 rows, bf16
-    t.h0 = (u32x4 *)take(2 * T * 2 * 64 * 16);
+    t.h0 = (u32x4 *)take(2 * T * kb1 * 64 * 16);
     t.h1 = (u32x4 *)take(2 * T * slab);
     t.h2 = (u32x4 *)take(2 * T * slab);
     t.lat = (f32x4 *)take(2 * T * 2 * slab);
@@ -1327,19 +1347,27 @@ static void fused_forward(const ndf_net_config *c, const NetOffsets &o, const fl
                           const int64_t *pairs, const float *pos, const float *targets, int64_t B,
                           const FusedWS &t, float *y, hipStream_t st) {
     hipLaunchKernelGGL(pack_train_kernel, dim3(64), dim3(256), 0, st, P, o.W1[0], o.W2[0],
-                       o.W3[0], o.W4, o.W5, t.fr);
+                       o.W3[0], o.W4, o.W5, enc_in(c), t.fr);
     const FusedArgs a = fused_args(c, o, P, pairs, pos, targets, B, t, y);
-    if (pos)
-        hipLaunchKernelGGL(train_fwd_kernel<true>, dim3(fused_blocks(B)), dim3(kTThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL(train_fwd_kernel<false>, dim3(fused_blocks(B)), dim3(kTThreads), 0, st, a);
+    const dim3 g(fused_blocks(B)), b(kTThreads);
+    if (c->fourier) {
+        if (pos)
+            hipLaunchKernelGGL((train_fwd_kernel<true, true>), g, b, 0, st, a);
+        else
+            hipLaunchKernelGGL((train_fwd_kernel<false, true>), g, b, 0, st, a);
+    } else {
+        if (pos)
+            hipLaunchKernelGGL((train_fwd_kernel<true, false>), g, b, 0, st, a);
+        else
+            hipLaunchKernelGGL((train_fwd_kernel<false, false>), g, b, 0, st, a);
+    }
 }
 
 static int fused_grad(const ndf_net_config *c, const float *P, const int64_t *pairs,
                       const float *pos, const float *targets, int64_t B, float *G, float *loss,
                       void *ws, hipStream_t st) {
     const NetOffsets o = net_offsets(c);
-    const FusedWS t = carve_fused(ws, B);
+    const FusedWS t = carve_fused(c, ws, B);
     launch_status_clear(t.status, st);
     hipLaunchKernelGGL(fill_kernel, dim3(gs_blocks(o.total)), dim3(kThreads), 0, st, G, o.total,
                        0.f);
@@ -1379,6 +1407,7 @@ static int fused_grad(const ndf_net_config *c, const float *P, const int64_t *pa
     w.wg0[6] = acc_wg;
     w.d2 = t.d2;
     w.gy = t.gy;
+    w.kin1 = enc_in(c);
     hipLaunchKernelGGL(wgrad_all_kernel, dim3((unsigned)acc_wg), dim3(512), 0, st, w);
     return status_of_launch();
 }
@@ -1386,7 +1415,7 @@ static int fused_grad(const ndf_net_config *c, const float *P, const int64_t *pa
 }  // namespace
 
 size_t net_train_ws_bytes(const ndf_net_config *c, int64_t B) {
-    return fused_path(c) ? carve_fused(nullptr, B).bytes : carve(nullptr, B).bytes;
+    return fused_path(c) ? carve_fused(c, nullptr, B).bytes : carve(nullptr, B).bytes;
 }
 
 int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t seed,
@@ -1404,7 +1433,7 @@ int launch_net_init(const ndf_net_config *c, float *params, float *opt, uint64_t
     for (int e = 0; e < c->n_enc; ++e) {
         for (int l = 0; l < kL; ++l) uni(o.grid[e][l], o.cells[l] * kF, 1e-4f);
         if (c->grid_only) continue;
-        uni(o.W1[e], kH * kK0, sqrtf(6.f / kK0));
+        uni(o.W1[e], kH * enc_in(c), sqrtf(6.f / (float)enc_in(c)));
         uni(o.W2[e], kH * kH, sqrtf(6.f / kH));
         uni(o.W3[e], kH * kH, sqrtf(6.f / kH));
     }
@@ -1419,7 +1448,7 @@ int launch_net_forward(const ndf_net_config *c, const float *params, const int64
                        const float *pos, int64_t B, float *y, void *ws, hipStream_t st) {
     const NetOffsets o = net_offsets(c);
     if (fused_path(c)) {
-        fused_forward(c, o, params, pairs, pos, nullptr, B, carve_fused(ws, B), y, st);
+        fused_forward(c, o, params, pairs, pos, nullptr, B, carve_fused(c, ws, B), y, st);
         return status_of_launch();
     }
     TrainWS t = carve(ws, B);

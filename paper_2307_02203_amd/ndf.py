@@ -51,7 +51,8 @@ class ndf_net_config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("res", (ctypes.c_int32 * 3) * 4),
                 ("feats", ctypes.c_int32), ("width", ctypes.c_int32), ("n_enc", ctypes.c_int32),
-                ("log2_hashmap", ctypes.c_int32), ("grid_only", ctypes.c_int32)]
+                ("log2_hashmap", ctypes.c_int32), ("grid_only", ctypes.c_int32),
+                ("fourier", ctypes.c_int32)]
 
 
 _lib = None
@@ -307,7 +308,8 @@ def ksg_pairs(ens, pairs, k=4, counts=False, var_a=0, var_b=0, stream=None):
 
 
 # ------------------------------------------------------------------- network --
-def net_config(nx, ny, nz, res, n_enc=1, feats=8, width=128, log2_hashmap=0, grid_only=False):
+def net_config(nx, ny, nz, res, n_enc=1, feats=8, width=128, log2_hashmap=0, grid_only=False,
+               fourier=0):
     c = ndf_net_config()
     c.nx, c.ny, c.nz = nx, ny, nz
     c.n_levels = len(res)
@@ -317,6 +319,7 @@ def net_config(nx, ny, nz, res, n_enc=1, feats=8, width=128, log2_hashmap=0, gri
     c.feats, c.width, c.n_enc = feats, width, n_enc
     c.log2_hashmap = log2_hashmap
     c.grid_only = 1 if grid_only else 0
+    c.fourier = int(fourier)
     return c
 
 

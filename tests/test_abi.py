@@ -255,6 +255,22 @@ def test_hash_grid_config():
     assert ndf.ndf_net_param_bytes(ndf.net_config(2048, 2048, 2, huge, log2_hashmap=20)) > 0
 
 
+def test_fourier_config():
+    """Fourier features (12 frequencies) widen W1 to 112 inputs in the library's
+    parameter layout as in the generator's; other frequency counts, two encoders
+    or a grid-only network with them are refused."""
+    import gen
+    lay = gen.NetLayout.for_grid(16, 16, 8, fourier=12)
+    cfg = ndf.net_config(16, 16, 8, lay.res, fourier=12)
+    assert ndf.ndf_net_param_bytes(cfg) == 4 * lay.n_floats
+    plain = gen.NetLayout.for_grid(16, 16, 8)
+    assert lay.n_floats - plain.n_floats == 128 * (112 - 32)
+    for kw in ({"fourier": 5}, {"fourier": 12, "n_enc": 2}, {"fourier": 12, "grid_only": True}):
+        assert ndf.ndf_net_param_bytes(ndf.net_config(16, 16, 8, lay.res, **kw)) == 0, kw
+    q = ndf.ndf_net_qparam_bytes(cfg, ndf.NDF_PREC_BF16)
+    assert q > ndf.ndf_net_qparam_bytes(ndf.net_config(16, 16, 8, lay.res), ndf.NDF_PREC_BF16)
+
+
 def test_ksg_points_workspace_and_limits():
     """Workspace of the KSG targets at positions: the 2B code columns (4 B per member)
     and their sorted orders (2 B per member) dominate; B is limited to 2^29 and the

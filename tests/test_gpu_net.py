@@ -712,3 +712,75 @@ def test_grid_only_network(name, n_enc):
     cache = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
     with pytest.raises(ndf.NdfError):
         ndf.ndf_infer_latents(c, q, cache)
+
+
+@pytest.mark.parametrize("name,T", [("tiny", 0), ("mid", 0), ("mid", 10)])
+def test_fourier_feature_network(name, T):
+    """Fourier features of the position (Sec. 4.2, Eq. 4; L = 12, 112 encoder
+    inputs): the training forward and adjoint at vertex pairs (B = 2001, a
+    ragged last tile) and at continuous positions, BF16 and FP8 fields, the field
+    at positions, all against the FP64 network to the emulated rounding floors;
+    the query-latent path equals the fused field bit for bit; two encoders are
+    refused."""
+    cfg = gen.CONFIGS[name]
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    lay = gen.NetLayout.for_grid(*dims, log2_hashmap=T, fourier=12)
+    assert lay.enc_in == 112
+    flat = gen.make_net_params(lay, seed=2351, grid_scale=0.5, bias_scale=0.1)
+    c = ndf.net_config(*dims, lay.res, log2_hashmap=T, fourier=12)
+    assert ndf.ndf_net_param_bytes(c) == 4 * lay.n_floats
+    net = nn.Net(flat, dims, lay.res, 8, 128, 1, T, fourier=12)
+    P = torch.from_numpy(flat).cuda()
+    P0 = torch.empty_like(P)
+    ndf.ndf_net_init(c, P0, None, 12)
+    w1 = lay.view(P0.cpu().numpy(), "W1_0")
+    assert w1.shape == (128, 112) and np.all(np.abs(w1) <= math.sqrt(6.0 / 112))
+    pairs = gen.random_pairs(cfg.n_vertices, 2001, seed=79)
+    y = _forward_gpu(c, P, pairs)
+    want, _ = nn.forward(net, pairs[:, 0], pairs[:, 1])
+    _check_floor(y, want, nn.forward(net, pairs[:, 0], pairs[:, 1], TRAIN_OPS)[0],
+                 f"fourier forward {name} T={T}")
+    s = np.where(np.random.default_rng(8).random(len(pairs)) < 0.5, -1.0, 1.0)
+    t = want - s
+    loss_o, g_o, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t)
+    _, g_e, _ = nn.loss_and_grad(net, pairs[:, 0], pairs[:, 1], t, TRAIN_OPS)
+    g, loss = _grad_gpu(c, P, pairs, t.astype(np.float32))
+    assert abs(loss - loss_o) <= 1e-2 * loss_o
+    check_grad_floor(lay, g, g_o.flat, g_e.flat, f"fourier grad {name} T={T}")
+    # continuous positions, some outside the domain
+    pos = np.concatenate([gen.random_positions(2 * 1500, seed=80),
+                          gen.random_positions(2 * 100, seed=81, spread=1.5)]).reshape(1600, 2, 3)
+    y = nn.forward_points(net, pos)
+    t = y + 1.0
+    loss_o, g_o, _ = nn.loss_and_grad_points(net, pos, t)
+    _, g_e, _ = nn.loss_and_grad_points(net, pos, t, TRAIN_OPS)
+    gp = torch.empty_like(P)
+    lossp = torch.empty(1, device="cuda")
+    ws = torch.empty(ndf.train_ws_bytes(c, len(pos)), dtype=torch.uint8, device="cuda")
+    ndf.ndf_net_grad_at(c, P, torch.as_tensor(pos, device="cuda"),
+                        torch.as_tensor(t.astype(np.float32), device="cuda"), gp, lossp, ws)
+    assert abs(lossp.item() - loss_o) <= 1e-2 * loss_o
+    check_grad_floor(lay, gp.cpu().numpy().astype(np.float64), g_o.flat, g_e.flat,
+                     f"fourier grad at positions {name} T={T}")
+    # inference
+    V = cfg.n_vertices
+    refs = [cfg.ref_v, 0, V - 1]
+    q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
+    f16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
+    f8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
+    ops8 = fp8_ops(net)
+    for i, r in enumerate(refs):
+        want = nn.field(net, r)
+        _check_floor(f16[i].cpu().numpy(), want, nn.field(net, r, rnd=BF16_OPS),
+                     f"fourier field {name} T={T} ref={r}")
+        _check_floor(f8[i], want, nn.field(net, r, rnd=ops8),
+                     f"fourier field fp8 {name} T={T} ref={r}")
+        one = _infer_gpu(c, q, [r], V, ndf.NDF_PREC_BF16)
+        assert torch.equal(one[0], f16[i]), r  # query-latent path = fused field
+    pq = gen.random_positions(2500, seed=82)
+    pts = _points_gpu(c, q, refs[:1], pq, ndf.NDF_PREC_BF16)
+    p64 = pq.astype(np.float64)
+    _check_floor(pts[0], nn.field_points(net, refs[0], p64),
+                 nn.field_points(net, refs[0], p64, BF16_OPS), f"fourier points {name} T={T}")
+    c2 = ndf.net_config(*dims, lay.res, n_enc=2, log2_hashmap=T, fourier=12)
+    assert ndf.ndf_net_param_bytes(c2) == 0
