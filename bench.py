@@ -727,7 +727,9 @@ def _held_out(ens, cfg, net, P, P_mi, ws_t, log):
     return out, held, r_o
 
 
-SWEEP_T = (14, 16, 18, 20, 22)
+# (log2 table size, Fourier frequencies): the table-size sweep, and at the dense
+# size the input embedding with and without Fourier features (Sec. 4.2, Eq. 4)
+SWEEP_MODELS = ((14, 0), (16, 0), (18, 0), (20, 0), (22, 0), (22, 12))
 SWEEP_STEPS = 600
 
 
@@ -737,23 +739,24 @@ def _capacity_sweep(cfg, held, r_o, pearson_targets, ws_i, log):
     T = 22 every level of this grid is dense), each trained for SWEEP_STEPS steps
     on the same Pearson targets, and its error on the 10^6 held-out pairs against
     the FP64 oracle.  The MLP widths are fixed by the kernels (5 x 128), so only
-    the table size varies."""
+    the table size varies; at the dense size one more model adds the Fourier
+    features of the position (L = 12) to the input embedding."""
     import torch
     import gen
     from paper_2307_02203_amd import ndf
     V = cfg.n_vertices
     out = []
     loss = torch.empty(1, device="cuda")
-    for T in SWEEP_T:
-        lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, log2_hashmap=T)
-        net = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay.res, log2_hashmap=T)
+    for T, L in SWEEP_MODELS:
+        lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz, log2_hashmap=T, fourier=L)
+        net = ndf.net_config(cfg.nx, cfg.ny, cfg.nz, lay.res, log2_hashmap=T, fourier=L)
         P = torch.empty(lay.n_floats, device="cuda")
         opt = torch.empty(2 * lay.n_floats, device="cuda")
         ndf.ndf_net_init(net, P, opt, 2320)
         ws = torch.empty(ndf.train_ws_bytes(net, B_PAIRS) + lay.n_floats * 4 + 256,
                          dtype=torch.uint8, device="cuda")
         tr = _train(ndf, net, P, opt, SWEEP_STEPS, pearson_targets, 5000, ws, loss, "cuda", log,
-                    f"T={T}")
+                    f"T={T} fourier={L}")
         y = torch.empty(len(held), device="cuda")
         for c0 in range(0, len(held), B_PAIRS):
             pr = torch.as_tensor(held[c0:c0 + B_PAIRS], device="cuda")
@@ -765,14 +768,17 @@ def _capacity_sweep(cfg, held, r_o, pearson_targets, ws_i, log):
         f = torch.empty((1, V), device="cuda")
         ms = _timed(lambda it: ndf.ndf_infer_field(net, q, ndf.NDF_PREC_BF16, [cfg.ref_v], f,
                                                    ws_i), 5, 1)
-        out.append({"log2_hashmap": T, "cells_per_level": [lay.cells(l) for l in range(4)],
+        out.append({"log2_hashmap": T, "fourier": L,
+                    "cells_per_level": [lay.cells(l) for l in range(4)],
                     "param_mb": 4.0 * lay.n_floats / 1e6,
                     "inference_param_mb": ndf.ndf_net_qparam_bytes(net, ndf.NDF_PREC_BF16) / 1e6,
                     "held_out_mae_vs_oracle": float(np.mean(np.abs(y - r_o))),
                     "final_l1_loss": tr["final_l1_loss"], "field_ms": float(np.median(ms))})
         del P, opt, ws, q, f
+    dense = [m for m in out if m["log2_hashmap"] == 22]
+    emb = {f"fourier_{m['fourier']}": m["held_out_mae_vs_oracle"] for m in dense}
     return {"steps_per_model": SWEEP_STEPS, "lr_peak": LR, "held_out_pairs": len(held),
-            "models": out}
+            "models": out, "embedding_held_out_mae": emb}
 
 
 # ------------------------------------------------------------------------ gain --

@@ -338,10 +338,14 @@ int ndf_net_quantize(const ndf_net_config *cfg, const float *params, int32_t pre
  * n_ref >= 2: the query latents of all vertices are computed once into the
  * workspace (ndf_infer_latents) and every launch then decodes up to 16
  * references per read of them (ndf_infer_field_cached); the fields are the
- * single-reference fields bit for bit.  FP8 runs one fused pass per reference.
+ * single-reference fields bit for bit.  FP8 with n_ref = 1: layers 2..5 in E4M3
+ * in one fused pass (two encoders: the reference latent first, in E4M3 too);
+ * FP8 with n_ref >= 2: the query latents are cached in BF16 as above and only
+ * the decoder (layers 4, 5) runs in E4M3, 16 references per read of the cache
+ * (the BF16 network with an E4M3 decoder; its bar is that emulation's).
  * The call enqueues kernels only (no copies or memsets), so it can be captured
  * into a graph.  ws: ndf_workspace_bytes(NDF_OP_INFER, NULL, cfg, n_ref, prec)
- * bytes (BF16, n_ref >= 2: includes ndf_infer_latent_bytes(cfg) for the query
+ * bytes (n_ref >= 2: includes ndf_infer_latent_bytes(cfg) for the query
  * latents).  NDF_E_ARG for a null pointer, n_ref < 1 or a reference outside
  * [0, V). */
 int ndf_infer_field(const ndf_net_config *cfg, const void *qparams, int32_t prec,

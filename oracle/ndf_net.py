@@ -353,6 +353,24 @@ def fp8_inference_operands(net, maxima=None):
     return Operands(act=act, weight=weight, grid=round_bf16)
 
 
+def fp8_decoder_operands(net, maxima=None):
+    """Many fields of one network at FP8 (the query latents cached): the encoder
+    in BF16 as in bf16_inference_operands (bf16 latents), the decoder layers 4
+    and 5 in E4M3 with the static input scales of fp8_inference_operands and
+    microscaled weights."""
+    s = fp8_activation_scales(fp8_activation_maxima(net) if maxima is None else maxima)
+
+    def act(x, layer):
+        if layer <= 3:
+            return round_bf16(x)
+        return s[layer - 2] * round_e4m3(x / s[layer - 2])
+
+    def weight(W, layer):
+        return round_bf16(W) if layer <= 3 else round_mx_e4m3(W)
+
+    return Operands(act=act, weight=weight, latent=round_bf16, grid=round_bf16)
+
+
 def _lin(x, W, layer, rnd):
     """x @ W.T with the operands rounded as rnd says for this layer."""
     if rnd is None:

@@ -108,7 +108,8 @@ size_t net_latent_cache_bytes(const ndf_net_config *c);
 // latents of every vertex (they are computed once and decoded per reference).
 size_t net_infer_ws_bytes(const ndf_net_config *c, int64_t n_ref, int prec) {
     size_t b = net_infer_lat_ws_bytes(n_ref);
-    if (prec == NDF_PREC_BF16 && n_ref >= 2) b += align_up(net_latent_cache_bytes(c), 256);
+    // n_ref >= 2: the query latents are cached in the workspace (BF16 and FP8)
+    if (n_ref >= 2 && !c->grid_only) b += align_up(net_latent_cache_bytes(c), 256);
     return b;
 }
 
@@ -1200,6 +1201,101 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
     }
 }
 
+// E4M3 decoder on cached query latents (many fields of one network at FP8): per
+// 64-vertex tile the wave loads its bf16 latents once; per reference it forms
+// the product with the reference latent (exact in FP32 for two bf16 values),
+// clamps and quantises it with layer 4's static input scale and runs layers 4
+// and 5 on the scaled E4M3 MFMA (weights microscaled per row and 32 inputs) and
+// the head; kMultiRefs references per launch, the cache read once per launch.
+// The encoder ran in BF16 (the cache and the reference latents), so this is the
+// BF16 network with its decoder in E4M3.
+// The E4M3 operand of layer 4's k-block kb (inputs 64 kb .. 64 kb + 63) takes
+// byte t of lane (l, h) from the same lane's bf16 chunk j = 4 kb + 2 (t / 16) +
+// (t % 16) / 8, element 4 ((t / 4) % 2) + t % 4 (both hold input
+// fp8_feature(kb, h, t)), so the product and its quantisation are lane-local.
+__global__ __launch_bounds__(kInferThreads) void infer_cached_fp8_kernel(
+    InferArgs8 A, const u32x4 *__restrict__ cache, int64_t nq, const float *__restrict__ ref_lat,
+    int n_ref, float *__restrict__ out, int64_t ld_out) {
+    __shared__ i32x8 s_q[2][kFrag8];
+    __shared__ int s_e[2][kH * 4];
+    __shared__ __attribute__((aligned(16))) float s_b[2][kH];
+    __shared__ __attribute__((aligned(16))) float s_w6[kH];
+    __shared__ __attribute__((aligned(16))) float s_ref[kMultiRefs][kH];
+    // chunks 0..kLat8Lds-1 of each wave's tile latents (the rest in registers)
+    constexpr int kLat8Lds = 7;
+    __shared__ u32x4 s_lat[kInferWaves][kLat8Lds][2][64];
+    const int tid = threadIdx.x;
+    for (int L = 0; L < 2; ++L)
+        for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L + 2][i];
+    for (int i = tid; i < 2 * kH * 4; i += kInferThreads)
+        s_e[i / (kH * 4)][i % (kH * 4)] = A.se[2 + i / (kH * 4)][i % (kH * 4)];
+    for (int i = tid; i < 2 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[3 + i / kH][i % kH];
+    for (int i = tid; i < kH; i += kInferThreads) s_w6[i] = A.w6[i];
+    for (int i = tid; i < n_ref * kH; i += kInferThreads) s_ref[i / kH][i % kH] = ref_lat[i];
+    const ActScales as = act_scales(A.amax);
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
+    const float b6 = A.b6[0];
+    const int64_t ntiles = ceil_div(nq, 64);
+    const bf16x8 unused16[2][2] = {};
+    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
+         tile += (int64_t)gridDim.x * kInferWaves) {
+        const int64_t row0 = tile * 64;
+        int h4 = 4 * h;
+        asm volatile("" : "+v"(h4));
+        bool ok[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) ok[q] = row0 + q * 32 + jl < nq;
+        // each lane writes and later reads only its own LDS entries
+        u32x4 lat[8 - kLat8Lds][2];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const u32x4 v = __builtin_nontemporal_load(cache + cache_chunk(tile, kb, q, lane));
+                if (kb < kLat8Lds)
+                    s_lat[wave][kb][q][lane] = v;
+                else
+                    lat[kb - kLat8Lds][q] = v;
+            }
+#pragma unroll 1
+        for (int r = 0; r < n_ref; ++r) {
+            // opaque per reference: LDS addresses are formed inside the loop
+            asm volatile("" : "+v"(h4));
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const float *ref_h = &s_ref[r][0] + h4;
+            const float clip = as.clip[2];
+            i32x8 m8[2][2], d8[2][2];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    quant_static([&](int o, int rr) {
+                        const int j = 4 * kb + 2 * o + (rr >> 3), e = 4 * ((rr >> 2) & 1) + (rr & 3);
+                        const uint32_t w2 = j < kLat8Lds ? s_lat[wave][j][q][ln][e >> 1]
+                                                         : lat[j - kLat8Lds][q][e >> 1];
+                        const float lv = (e & 1) ? bf_hi(w2) : bf_lo(w2);
+                        const float rv = ref_h[64 * kb + 32 * o + 8 * (rr >> 2) + (rr & 3)];
+                        return __builtin_amdgcn_fmed3f(lv * rv, -clip, clip);
+                    }, as.s[2], m8[kb][q]);
+            float part[2] = {0.f, 0.f};
+            dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[0], ref_h - h4, s_w6,
+                                             unused16, m8, as.sbyte[2], d8, as.s[3], as.clip[3],
+                                             part, nullptr, row0, ok, lane, h4);
+            dense_layer_fp8<LAY_HEAD, false>(nullptr, s_q[1], s_e[1], s_b[1], ref_h - h4, s_w6,
+                                             unused16, d8, as.sbyte[3], m8, 0.f, 0.f, part,
+                                             nullptr, row0, ok, lane, h4);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float y = part[q] + __shfl_xor(part[q], 32, 64) + b6;
+                if (h == 0 && ok[q]) out[(int64_t)r * ld_out + row0 + q * 32 + jl] = y;
+            }
+        }
+    }
+}
+
 static InferArgs8 make_args8(const ndf_net_config *c, const QLayout &q, const char *Q, int e) {
     InferArgs8 a{};
     for (int l = 0; l < kL; ++l) a.grid[l] = (const uint16_t *)(Q + q.grid[e][l]);
@@ -1393,6 +1489,22 @@ int launch_infer_field(const ndf_net_config *c, const void *qp, int prec, const 
     float *lat = (float *)ws;
     int64_t *refs = (int64_t *)((char *)ws + align_up((size_t)n_ref * kH * sizeof(float), 256));
     const int64_t V = (int64_t)c->nx * c->ny * c->nz;
+    if (prec == NDF_PREC_FP8_E4M3 && n_ref >= 2 && !c->grid_only) {
+        // the BF16 query latents once into the workspace, then every reference's
+        // decoder in E4M3, kMultiRefs references per pass over the cache
+        if (put_refs(ref_v, n_ref, refs, st) != NDF_OK) return NDF_E_HIP;
+        void *cache = (char *)ws + net_infer_lat_ws_bytes(n_ref);
+        ref_latents(c, q, Q, refs, n_ref, lat, st);
+        if (launch_infer_latents(c, qp, cache, st) != NDF_OK) return NDF_E_HIP;
+        const InferArgs8 a8 = make_args8(c, q, Q, c->n_enc - 1);
+        for (int r0 = 0; r0 < n_ref; r0 += kMultiRefs) {
+            const int n = n_ref - r0 < kMultiRefs ? n_ref - r0 : kMultiRefs;
+            hipLaunchKernelGGL(infer_cached_fp8_kernel, dim3(infer_blocks(V)), dim3(kInferThreads),
+                               0, st, a8, (const u32x4 *)cache, V, lat + (int64_t)r0 * kH, n,
+                               out + (int64_t)r0 * V, V);
+        }
+        return status_of_launch();
+    }
     if (prec == NDF_PREC_FP8_E4M3 && c->n_enc == 1) {
         // shared encoder: each workgroup computes the reference latent itself
         InferArgs8 a = make_args8(c, q, Q, 0);

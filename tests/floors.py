@@ -27,8 +27,14 @@ BF16_OPS = nn.bf16_inference_operands()      # inference: also bf16 latents
 
 def fp8_ops(net):
     """Inference with layers 2-5 in E4M3 (static activation scales from the
-    network's own calibration)."""
+    network's own calibration): the one-reference FP8 field."""
     return nn.fp8_inference_operands(net)
+
+
+def fp8_decoder_ops(net):
+    """BF16 encoder, decoder layers 4-5 in E4M3: FP8 fields of several references,
+    decoded from the cached query latents."""
+    return nn.fp8_decoder_operands(net)
 
 
 def _log(*a):

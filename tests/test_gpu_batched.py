@@ -8,8 +8,9 @@ plus independent noise), through the C ABI.
   field, and 1 on the diagonal of the second variable's own batch;
 * KSG-MI across variables: |dI| <= 1e-4 on sampled vertices, neighbour counts of
   pairs bit-exact;
-* the learned field for all 256 references with E4M3 layers against BF16 layers,
-  both against the FP64 network oracle on sampled (reference, query) pairs.
+* the learned field for all 256 references with an E4M3 decoder (on the cached
+  BF16 query latents) and in BF16, both against the FP64 network oracle on
+  sampled (reference, query) pairs.
 """
 import sys
 
@@ -25,7 +26,7 @@ from paper_2307_02203_amd import ndf
 pytestmark = pytest.mark.gpu
 
 sys.path.insert(0, __file__.rsplit("/", 1)[0])
-from floors import BF16_OPS, check_floor, fp8_ops  # noqa: E402
+from floors import BF16_OPS, check_floor, fp8_decoder_ops  # noqa: E402
 
 PEARSON_TOL = 1e-5
 MI_TOL = 1e-4
@@ -146,7 +147,8 @@ def test_learned_field_256_refs_fp8_vs_bf16():
     want, _ = nn.forward(net, refs[ri], qv)
     ri_t = torch.as_tensor(ri, device="cuda")
     qv_t = torch.as_tensor(qv, device="cuda")
-    for prec, ops in ((ndf.NDF_PREC_BF16, BF16_OPS), (ndf.NDF_PREC_FP8_E4M3, fp8_ops(net))):
+    for prec, ops in ((ndf.NDF_PREC_BF16, BF16_OPS),
+                      (ndf.NDF_PREC_FP8_E4M3, fp8_decoder_ops(net))):
         g = out[prec][ri_t, qv_t].cpu().numpy().astype(np.float64)
         check_floor(g, want, nn.forward(net, refs[ri], qv, ops)[0], f"256 refs prec={prec}")
     # the reference latent of row i is that of refs[i]: a row equals the one-reference call

@@ -33,7 +33,7 @@ pytestmark = pytest.mark.gpu
 
 sys.path.insert(0, __file__.rsplit("/", 1)[0])
 from test_oracle_net import hand_built_params, hand_built_value, DIMS as HB_DIMS, RES as HB_RES  # noqa: E402
-from floors import (BF16_OPS, TRAIN_OPS, fp8_ops, check_floor as _check_floor,  # noqa: E402
+from floors import (BF16_OPS, TRAIN_OPS, fp8_decoder_ops, fp8_ops, check_floor as _check_floor,  # noqa: E402
                     check_grad_floor)
 
 
@@ -382,12 +382,18 @@ def test_infer_field_fp8_parity(name, n_enc):
     _log(f"calibrated maxima gpu {m_gpu} oracle {m_o}")
     assert np.all(np.abs(m_gpu - m_o) <= 2.0 ** -7 * m_o)
     ops8 = nn.fp8_inference_operands(net, m_gpu)
+    opsd = nn.fp8_decoder_operands(net, m_gpu)
+    # one reference per call: layers 2..5 in E4M3; several: E4M3 decoder on the
+    # cached BF16 query latents
+    one8 = [_infer_gpu(c, q, [r], V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()[0] for r in refs]
     out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
     out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16).cpu().numpy()
     for i, r in enumerate(refs):
         want = nn.field(net, r)
-        _check_floor(out8[i], want, nn.field(net, r, rnd=ops8),
+        _check_floor(one8[i], want, nn.field(net, r, rnd=ops8),
                      f"fp8 {name} n_enc={n_enc} ref={r}")
+        _check_floor(out8[i], want, nn.field(net, r, rnd=opsd),
+                     f"fp8 decoder {name} n_enc={n_enc} ref={r}")
         _check_floor(out16[i], want, nn.field(net, r, rnd=BF16_OPS),
                      f"bf16 of fp8 blob {name} n_enc={n_enc} ref={r}")
 
@@ -582,7 +588,7 @@ def test_hash_grid_inference(n_enc):
     q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
     out16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
     out8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
-    ops8 = fp8_ops(net)
+    ops8 = fp8_decoder_ops(net)
     for i, r in enumerate(refs):
         want = nn.field(net, r)
         _check_floor(out16[i].cpu().numpy(), want, nn.field(net, r, rnd=BF16_OPS),
@@ -768,12 +774,15 @@ def test_fourier_feature_network(name, T):
     q = _qparams(c, P, ndf.NDF_PREC_FP8_E4M3)
     f16 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_BF16)
     f8 = _infer_gpu(c, q, refs, V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()
-    ops8 = fp8_ops(net)
+    ops8, opsd = fp8_ops(net), fp8_decoder_ops(net)
     for i, r in enumerate(refs):
         want = nn.field(net, r)
         _check_floor(f16[i].cpu().numpy(), want, nn.field(net, r, rnd=BF16_OPS),
                      f"fourier field {name} T={T} ref={r}")
-        _check_floor(f8[i], want, nn.field(net, r, rnd=ops8),
+        _check_floor(f8[i], want, nn.field(net, r, rnd=opsd),
+                     f"fourier field fp8 decoder {name} T={T} ref={r}")
+        one8 = _infer_gpu(c, q, [r], V, ndf.NDF_PREC_FP8_E4M3).cpu().numpy()[0]
+        _check_floor(one8, want, nn.field(net, r, rnd=ops8),
                      f"fourier field fp8 {name} T={T} ref={r}")
         one = _infer_gpu(c, q, [r], V, ndf.NDF_PREC_BF16)
         assert torch.equal(one[0], f16[i]), r  # query-latent path = fused field

@@ -511,6 +511,27 @@ def test_fp8_static_activation_scales():
     assert 2 * rel16 < rel < 0.2
 
 
+def test_fp8_decoder_operands():
+    """The cached-latent FP8 mode rounds the encoder exactly as the BF16 inference
+    path (same latents bit for bit) and only the decoder to E4M3: its field error
+    lies between the BF16 path's and the all-E4M3 path's."""
+    cfg = gen.CONFIGS["tiny"]
+    lay = gen.NetLayout.for_grid(cfg.nx, cfg.ny, cfg.nz)
+    net = nn.Net(gen.make_net_params(lay, seed=2333, grid_scale=0.5, bias_scale=0.1),
+                 (cfg.nx, cfg.ny, cfg.nz), lay.res)
+    M = nn.fp8_activation_maxima(net)
+    dec = nn.fp8_decoder_operands(net, M)
+    b16 = nn.bf16_inference_operands()
+    u = nn.vertex_positions(np.arange(cfg.n_vertices), (cfg.nx, cfg.ny, cfg.nz))
+    h0 = nn.input_embedding(net, 0, u, b16)
+    np.testing.assert_array_equal(nn.encoder(net, 0, h0, dec)["lat"],
+                                  nn.encoder(net, 0, h0, b16)["lat"])
+    y = nn.field(net, cfg.ref_v)
+    err = {k: np.linalg.norm(nn.field(net, cfg.ref_v, rnd=o) - y) / np.linalg.norm(y)
+           for k, o in (("bf16", b16), ("dec", dec), ("fp8", nn.fp8_inference_operands(net, M)))}
+    assert err["bf16"] < err["dec"] < err["fp8"], err
+
+
 def test_unrounded_operands_reproduce_the_fp64_oracle():
     """An Operands whose every rounding is the identity gives the plain FP64 network
     and gradients bit for bit, so the rounding hooks change no arithmetic."""
