@@ -531,6 +531,14 @@ def _rooflines(med, N, V):
     del roof["prepare_moments_codes"]
     for r in roof.values():
         r["frac"] = r["achieved"] / r["peak"]
+    roof["ndf_field"]["traffic"] = _measured_traffic("ndf_field")
+    roof["ndf_field_fp8"]["traffic"] = _measured_traffic("ndf_field_fp8")
+    # the fused training step streams its slabs through HBM: the measured bytes per
+    # step over the step's time, beside the MFMA fraction
+    tr = _measured_traffic("train_step")
+    roof["train_step"]["traffic"] = tr
+    roof["train_step"]["hbm_gbs_measured"] = (tr / (med["train_step"] * 1e-3) / 1e9
+                                              if tr else None)
     roof["ksg_field"] = _ksg_roofline(med["ksg_field"], N, V)
     return roof
 
@@ -572,6 +580,13 @@ _PMC_TRAFFIC = {
     "ndf_field": ("profiles/pmc_infer_bf16_paper_1760000v.txt",
                   ["paper_2307_02203_amd/csrc/net_infer.hip",
                    "paper_2307_02203_amd/csrc/net.hpp"]),
+    "ndf_field_fp8": ("profiles/pmc_infer_fp8_paper_1760000v.txt",
+                      ["paper_2307_02203_amd/csrc/net_infer.hip",
+                       "paper_2307_02203_amd/csrc/net.hpp"]),
+    # the sum over the kernels of one step
+    "train_step": ("profiles/train_step_kernels_paper_2p18pairs.txt",
+                   ["paper_2307_02203_amd/csrc/net_train.hip",
+                    "paper_2307_02203_amd/csrc/net.hpp"]),
 }
 
 
@@ -1022,8 +1037,8 @@ def _config5(a, log):
         wsi = torch.empty(ndf.infer_ws_bytes(net, N_REF5, prec), dtype=torch.uint8,
                           device="cuda")
         st = _stats(_timed(lambda it: ndf.ndf_infer_field(net, qp, prec, refs, out, wsi), 3, 1))
-        flops = 2.0 * (DEC_MAC * N_REF5 * V + (36864 * V if prec == ndf.NDF_PREC_BF16
-                                               else 36864 * V * N_REF5))
+        # both precisions: the query encoder once, the decoder per reference
+        flops = 2.0 * (DEC_MAC * N_REF5 * V + 36864 * V)
         ri_t = torch.as_tensor(ri, device="cuda")
         qv_t = torch.as_tensor(qv, device="cuda")
         got = out[ri_t, qv_t].cpu().numpy().astype(np.float64)
@@ -1034,12 +1049,13 @@ def _config5(a, log):
             flat = P.cpu().numpy()
             onet = onn.Net(flat, (cfg.nx, cfg.ny, cfg.nz), lay.res, 8, 128, 2)
             want, _ = onn.forward(onet, refs[ri], qv)
-            res[name]["network_rel_l2_vs_fp64_network"] = float(
-                np.linalg.norm(got - want) / np.linalg.norm(want))
+        res[name]["network_rel_l2_vs_fp64_network"] = float(
+            np.linalg.norm(got - want) / np.linalg.norm(want))
         del wsi
     res["ndf_bf16"]["note"] = ("query latents computed once into the workspace, then 16 "
                                "references decoded per read of them")
-    res["ndf_fp8"]["note"] = "one fused pass (encoder + decoder) per reference"
+    res["ndf_fp8"]["note"] = ("query latents computed once (BF16) into the workspace, then 16 "
+                              "references per read of them through an E4M3 decoder")
     # direct KSG-MI across variables on two references
     wsk = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_KSG_FIELD, e, None, 2, 0),
                       dtype=torch.uint8, device="cuda")
