@@ -94,12 +94,24 @@ __global__ void pearson_afrag_kernel(const float *__restrict__ zr, int kpad, int
     }
 }
 
+// z = (x - mu) * sigma^-1 split into bf16 hi + lo: hi is z rounded, lo the
+// exact product minus hi (one FMA) rounded, so every kernel below splits an
+// element into the same two values.
+__device__ __forceinline__ void split_z(float x, float mu, float is, __bf16 &hi, __bf16 &lo) {
+    const float d = x - mu;
+    const __bf16 hb = f2bf(d * is);
+    hi = hb;
+    lo = f2bf(__builtin_fmaf(d, is, -(float)hb));
+}
+
 // Each wave computes NIB 32-ref blocks x 64 vertices.  Lane l loads the vertex
 // pair 2 (l%32), 2 (l%32) + 1 of its member rows as one 8-byte access, so tile
 // t (0, 1) column j is vertex v0 + 2 j + t: a 256-byte contiguous segment per
 // member row and lane half.  The next k-step's loads are issued before the
-// current one's MFMAs (two k-steps in flight per wave), and the per-wave
-// register footprint is kept small enough for three waves per SIMD.
+// current one's MFMAs, and the per-wave register footprint is kept small
+// enough for three waves per SIMD.  Skipped loads (past the last member or
+// vertex) read as 0: the reference operand is zero past the last member and
+// columns past the last vertex are never stored.
 constexpr int kGemmVerts = 64;
 
 template <int NIB, bool VEC>
@@ -157,16 +169,15 @@ __global__ __launch_bounds__(256) void pearson_gemm_kernel(
     load(0, cur);
     for (int ks = 0; ks < ksteps; ++ks) {
         if (ks + 1 < ksteps) load(ks + 1, nxt);
-        const int m0 = ks * 16 + 8 * h;
         bf16x8 bhi[2], blo[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float z = (ok[t] && m0 + e < N) ? (cur[e][t] - mu[t]) * is[t] : 0.f;
-                const __bf16 hb = f2bf(z);
+                __bf16 hb, lb;
+                split_z(cur[e][t], mu[t], is[t], hb, lb);
                 bhi[t][e] = hb;
-                blo[t][e] = f2bf(z - (float)hb);
+                blo[t][e] = lb;
             }
 #pragma unroll
         for (int i = 0; i < NIB; ++i) {
@@ -210,13 +221,17 @@ __global__ __launch_bounds__(256) void pearson_gemm_kernel(
 // all 128 vertices (four 32-vertex tiles, 128 accumulators: the reference
 // fragments, read from L2, are the per-MFMA traffic, so each is used for as
 // many vertices as the registers allow).  Each k-step (16 members) the
-// workgroup loads the 16 x 128 block of x once (16-byte loads, one member row
-// segment per 16 threads), standardises and splits it into hi/lo bf16 and
+// workgroup loads the 16 x 128 block of x once (one member row segment of 512
+// bytes per 128 threads), standardises and splits it into hi/lo bf16 and
 // stages it in LDS in MFMA B-operand order; all four waves read their B
-// operands from there (double-buffered, one barrier per k-step), and the next
-// k-step's x values and reference fragments are loaded during the MFMAs.  The
-// per-element arithmetic and the order of the MFMAs match pearson_gemm_kernel,
-// so both give the same bits.
+// operands from there (double-buffered, one barrier per k-step).  Step ks
+// issues the fragments of step ks + 1 and then the x loads of step ks + 2, so
+// the x values have two k-steps to arrive.  No load sits behind a branch (rows
+// past the last member read member N - 1, where the reference operand is zero,
+// and columns past the last vertex read a real vertex): with a branch the
+// compiler's wait for the fragments also drains the x loads just issued.  The
+// per-element split and the order of the MFMAs per accumulator match
+// pearson_gemm_kernel, so both give the same bits.
 constexpr int kWideVerts = 128;
 constexpr int kWideTiles = kWideVerts / 32;
 constexpr int kWideRefs = 256;
@@ -227,50 +242,51 @@ __global__ __launch_bounds__(256, 2) void pearson_gemm_wide_kernel(
     int n_ib_total, int n_ref, float *__restrict__ out) {
     __shared__ bf16x8 s_bop[2][kWideTiles][2][64];  // [buffer][vertex tile][hi, lo][lane]
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, jl = lane & 31;
+    const int lane = tid & 63, jl = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t vbase = (int64_t)blockIdx.x * kWideVerts;
     const int ib0 = blockIdx.y * (kWideRefs / 32) + 2 * wave;  // this wave's two 32-ref blocks
     const bool active = ib0 * 32 < n_ref;
+    // an idle wave (past the last reference) fetches real fragments it never uses
+    const int ibf = min(ib0, n_ib_total - 2);
 
-    // loader role: vertex vj of the block, members 8 mh .. 8 mh + 7 of the k-step
-    // (each load instruction reads 512 contiguous bytes of a member row over 128
-    // threads); the thread then owns one 16-byte B-operand slot per part, so
-    // the LDS writes of a wave are conflict-free.  Loads past the last member or
-    // vertex read the last one instead (clamped addresses, no branches) and are
-    // zeroed when staged.
+    // loader role: vertex vj of the block, members 8 mh .. 8 mh + 7 of the k-step;
+    // the thread then owns one 16-byte B-operand slot per part, so the LDS writes
+    // of a wave are conflict-free
     const int vj = tid & (kWideVerts - 1);
     const int mh = __builtin_amdgcn_readfirstlane(tid >> 7);  // uniform per wave
     const int64_t vg = vbase + vj;
-    const bool okv = vg < V;
-    const int vgc = (int)(okv ? vg : V - 1);
+    const int64_t vgc = vg < V ? vg : V - 1;
     const float mu = (float)mean[vgc], is = (float)inv_std[vgc];
+    const float *col = x + vgc;
     auto load = [&](int ks, float (&xv)[8]) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int m = min(ks * 16 + 8 * mh + e, N - 1);
-            xv[e] = __builtin_nontemporal_load(x + (int64_t)m * V + vgc);
+            xv[e] = __builtin_nontemporal_load(col + (int64_t)m * V);
         }
     };
     // B operand element (member k, vertex j): tile j / 32, lane 32 (k / 8) + j % 32,
     // position k % 8
-    auto stage = [&](int ks, const float (&xv)[8], int buf) {
+    auto stage = [&](const float (&xv)[8], int buf) {
         bf16x8 hi, lo;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const float zz = (xv[e] - mu) * is;
-            const float z = (okv && ks * 16 + 8 * mh + e < N) ? zz : 0.f;
-            const __bf16 hb = f2bf(z);
+            __bf16 hb, lb;
+            split_z(xv[e], mu, is, hb, lb);
             hi[e] = hb;
-            lo[e] = f2bf(z - (float)hb);
+            lo[e] = lb;
         }
         const int t = vj >> 5, ln = 32 * mh + (vj & 31);
         s_bop[buf][t][0][ln] = hi;
         s_bop[buf][t][1][ln] = lo;
     };
+    const int ksteps = (N + 15) / 16;
     auto afetch = [&](int ks, bf16x8 (&a)[2][2]) {
+        const int kc = min(ks, ksteps - 1);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int64_t fb = (((int64_t)ks * n_ib_total + ib0 + i) * 2) * 64;
+            const int64_t fb = (((int64_t)kc * n_ib_total + ibf + i) * 2) * 64;
             a[i][0] = afrag[fb + lane];
             a[i][1] = afrag[fb + 64 + lane];
         }
@@ -284,48 +300,52 @@ __global__ __launch_bounds__(256, 2) void pearson_gemm_wide_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][t][r] = 0.f;
 
-    const int ksteps = (N + 15) / 16;
-    // raw x of two k-steps in flight: at the start of step ks, xr[ks & 1] is free
-    // (staged) and xr[(ks + 1) & 1] holds step ks + 1, loaded a full step earlier
-    float xr0[8], xr1[8];
-    bf16x8 acur[2][2], anxt[2][2];
-    load(0, xr0);
-    if (ksteps > 1) load(1, xr1);
-    if (active) afetch(0, acur);
-    stage(0, xr0, 0);
-    __syncthreads();
-    auto step = [&](int ks, float (&xfree)[8], const float (&xnext)[8]) {
+    // step ks: MFMAs on LDS buffer ks & 1 with the fragments of step ks; x of
+    // step ks + 1 (xnext, loaded a step earlier) is staged into the other buffer,
+    // whose last reader was step ks - 1, before the previous barrier
+    auto step = [&](int ks, const bf16x8 (&acur)[2][2], bf16x8 (&anext)[2][2],
+                    float (&xfree)[8], const float (&xnext)[8]) {
         const int buf = ks & 1;
-        if (ks + 2 < ksteps) load(ks + 2, xfree);
-        if (ks + 1 < ksteps && active) afetch(ks + 1, anxt);
+        afetch(ks + 1, anext);
+        load(ks + 2, xfree);
         if (active) {
+            bf16x8 bhi[kWideTiles], blo[kWideTiles];
 #pragma unroll
             for (int t = 0; t < kWideTiles; ++t) {
-                const bf16x8 bhi = s_bop[buf][t][0][lane];
-                const bf16x8 blo = s_bop[buf][t][1][lane];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    acc[i][t] = mfma32(acur[i][0], bhi, acc[i][t]);
-                    acc[i][t] = mfma32(acur[i][0], blo, acc[i][t]);
-                    acc[i][t] = mfma32(acur[i][1], bhi, acc[i][t]);
-                }
+                bhi[t] = s_bop[buf][t][0][lane];
+                blo[t] = s_bop[buf][t][1][lane];
             }
-        }
-        // the other buffer was last read in step ks - 1, before the previous barrier
-        if (ks + 1 < ksteps) {
-            stage(ks + 1, xnext, buf ^ 1);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                acur[i][0] = anxt[i][0];
-                acur[i][1] = anxt[i][1];
-            }
+            for (int t = 0; t < kWideTiles; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][0], bhi[t], acc[i][t]);
+#pragma unroll
+            for (int t = 0; t < kWideTiles; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][0], blo[t], acc[i][t]);
+#pragma unroll
+            for (int t = 0; t < kWideTiles; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][1], bhi[t], acc[i][t]);
         }
+        stage(xnext, buf ^ 1);
         __syncthreads();
     };
-    for (int ks = 0; ks < ksteps; ks += 2) {
-        step(ks, xr0, xr1);
-        if (ks + 1 < ksteps) step(ks + 1, xr1, xr0);
+    // x of two k-steps in flight: entering step ks, xa / xb alternate as the
+    // free registers and those holding step ks + 1
+    float xa[8], xb[8];
+    bf16x8 a0[2][2], a1[2][2];
+    afetch(0, a0);
+    load(0, xa);
+    load(1, xb);
+    stage(xa, 0);
+    __syncthreads();
+    int ks = 0;
+    for (; ks + 1 < ksteps; ks += 2) {
+        step(ks, a0, a1, xa, xb);
+        step(ks + 1, a1, a0, xb, xa);
     }
+    if (ks < ksteps) step(ks, a0, a1, xa, xb);
     if (!active) return;
     const float invN = 1.0f / (float)N;
 #pragma unroll
