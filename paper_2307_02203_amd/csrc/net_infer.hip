@@ -547,8 +547,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
-    // MODE 4: every workgroup takes all calibration tiles (against its own reference)
-    const int64_t t0 = MODE == 4 ? wave : (int64_t)blockIdx.x * kInferWaves + wave;
+    // MODE 4: every workgroup takes all calibration tiles (against its own reference).
+    // Otherwise waves are numbered wave-major, so the tiles of the last, partial
+    // round land on every CU, at most one per SIMD (waves w and w + 4 of a
+    // workgroup share a SIMD), where each runs alone instead of beside another.
+    const int64_t t0 = MODE == 4 ? wave : (int64_t)wave * gridDim.x + blockIdx.x;
     const int64_t tstep = MODE == 4 ? kInferWaves : (int64_t)gridDim.x * kInferWaves;
     for (int64_t tile = t0; tile < ntiles; tile += tstep) {
         const int64_t row0 = tile * 64;
@@ -964,7 +967,8 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
-    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
+    // waves numbered wave-major, as in infer_kernel
+    for (int64_t tile = (int64_t)wave * gridDim.x + blockIdx.x; tile < ntiles;
          tile += (int64_t)gridDim.x * kInferWaves) {
         const int64_t row0 = tile * 64;
         int h4 = 4 * h;
@@ -1060,6 +1064,46 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     }
 }
 
+// Work of a launch that decodes several references per tile: whole tiles go
+// round-robin to all waves of the grid; the tiles of the last, partial round are
+// split over the references (2, 4, ... parts while the parts still fit in one
+// round), so that round takes a fraction of a tile's time instead of a whole
+// tile's on a fraction of the waves.  Wave-uniform throughout.
+struct RefSplit {
+    int64_t w, W, rounds, rem;
+    int split;
+};
+
+__device__ __forceinline__ RefSplit ref_split(int64_t ntiles, int n_ref, bool allow) {
+    RefSplit s;
+    s.W = (int64_t)gridDim.x * kInferWaves;
+    s.w = (int64_t)blockIdx.x * kInferWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    s.rounds = ntiles / s.W;
+    s.rem = ntiles - s.rounds * s.W;
+    s.split = 1;
+    if (allow)
+        while (2 * s.split <= n_ref && 2 * s.split * s.rem <= s.W) s.split *= 2;
+    return s;
+}
+
+// item k of the calling wave: its tile and reference range [r0, r1); false once
+// the wave has no more work
+__device__ __forceinline__ bool ref_split_item(const RefSplit &s, int64_t k, int n_ref,
+                                               int64_t &tile, int &r0, int &r1) {
+    if (k < s.rounds) {
+        tile = s.w + k * s.W;
+        r0 = 0;
+        r1 = n_ref;
+        return true;
+    }
+    if (k > s.rounds || s.w >= s.rem * s.split) return false;
+    tile = s.rounds * s.W + s.w / s.split;
+    const int part = (int)(s.w % s.split);
+    r0 = part * n_ref / s.split;
+    r1 = (part + 1) * n_ref / s.split;
+    return true;
+}
+
 // Fields from cached query latents, several references per pass: per 64-vertex
 // tile the wave loads the tile's bf16 latents once (16 loads, kept in registers),
 // then for each reference of the launch forms the product with that reference's
@@ -1099,8 +1143,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
     const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, jl = lane & 31;
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
-    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
-         tile += (int64_t)gridDim.x * kInferWaves) {
+    const RefSplit rs = ref_split(ntiles, n_ref, !DIFF);
+    for (int64_t k = 0;; ++k) {
+        int64_t tile;
+        int r0, r1;
+        if (!ref_split_item(rs, k, n_ref, tile, r0, r1)) break;
         const int64_t row0 = tile * 64;
         int h4 = 4 * h;
         asm volatile("" : "+v"(h4));
@@ -1122,7 +1169,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
             }
         float y0[2] = {0.f, 0.f};
 #pragma unroll 1
-        for (int r = 0; r < n_ref; ++r) {
+        for (int r = r0; r < r1; ++r) {
             // opaque per reference, so the LDS reads of weights and biases stay
             // inside the loop instead of being hoisted out of it into registers
             asm volatile("" : "+v"(h4));
@@ -1141,11 +1188,9 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc[ob][0][4 * g + i] = acc[ob][1][4 * g + i] = bv[i];
                 }
-#pragma unroll
-            for (int kb = 0; kb < 8; ++kb) {
-                // k-block kb = 2 ob + s holds rows r = 8 s + 2 e2, r + 1 of output block ob
+            // k-block kb = 2 ob + s holds rows r = 8 s + 2 e2, r + 1 of output block ob
+            auto product = [&](int kb, bf16x8 (&bq)[2]) {
                 const int obk = kb >> 1, sb = kb & 1;
-                bf16x8 bq[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const u32x4 lv = kb < kLatLds ? s_lat[wave][kb][q][ln] : lat[kb - kLatLds][q];
@@ -1159,11 +1204,20 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_kernel(InferArgs A
                     }
                     bq[q] = __builtin_bit_cast(bf16x8, t);
                 }
+            };
+            // software pipeline: k-block kb + 1's products are formed in the same
+            // scheduling region as k-block kb's MFMAs, so their VALU work issues
+            // while the matrix core runs
+            bf16x8 bq[2][2];
+            product(0, bq[0]);
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                if (kb + 1 < 8) product(kb + 1, bq[(kb + 1) & 1]);
 #pragma unroll
                 for (int ob = 0; ob < 4; ++ob) {
                     const bf16x8 w = s_w[0][(ob * 8 + kb) * 64 + ln];
-                    acc[ob][0] = mfma32(w, bq[0], acc[ob][0]);
-                    acc[ob][1] = mfma32(w, bq[1], acc[ob][1]);
+                    acc[ob][0] = mfma32(w, bq[kb & 1][0], acc[ob][0]);
+                    acc[ob][1] = mfma32(w, bq[kb & 1][1], acc[ob][1]);
                 }
                 // keep each k-block's weight reads with its MFMAs (128 accumulators
                 // and 64 cached-latent registers are live here)
@@ -1239,8 +1293,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_fp8_kernel(
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
     const bf16x8 unused16[2][2] = {};
-    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntiles;
-         tile += (int64_t)gridDim.x * kInferWaves) {
+    const RefSplit rs = ref_split(ntiles, n_ref, true);
+    for (int64_t k = 0;; ++k) {
+        int64_t tile;
+        int r0, r1;
+        if (!ref_split_item(rs, k, n_ref, tile, r0, r1)) break;
         const int64_t row0 = tile * 64;
         int h4 = 4 * h;
         asm volatile("" : "+v"(h4));
@@ -1260,7 +1317,7 @@ __global__ __launch_bounds__(kInferThreads) void infer_cached_fp8_kernel(
                     lat[kb - kLat8Lds][q] = v;
             }
 #pragma unroll 1
-        for (int r = 0; r < n_ref; ++r) {
+        for (int r = r0; r < r1; ++r) {
             // opaque per reference: LDS addresses are formed inside the loop
             asm volatile("" : "+v"(h4));
             int ln = lane;
