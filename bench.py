@@ -91,7 +91,8 @@ def _parse():
                     help="profile one row (prepare, pearson_fp32, pearson_b64, ksg_field, "
                          "targets, train_step, ndf_field, ndf_field_fp8, ndf_field_cached, "
                          "or one of the next rows: ndf_points_rays, ndf_field_difference, "
-                         "pearson_points, ksg_points, train_step_at, ndf_field_hash) W+K "
+                         "pearson_points, ksg_points, train_step_at, ndf_field_hash, "
+                         "pearson_b256) W+K "
                          "times and exit")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip timing the calls beyond the hot path")
@@ -301,8 +302,9 @@ def main():
               "pearson_b64": row_pearson_b64, "ksg_field": row_ksg_field,
               "targets": row_targets, "train_step": row_train_step, "ndf_field": row_ndf_field}
 
-    def next_rows():
-        """The calls beyond the hot path, with their own buffers."""
+    def next_rows(profile_row=None):
+        """The calls beyond the hot path, with their own buffers (and, for profiling
+        only, the many-reference GEMM)."""
         ens_t = ndf.Ensemble(x, cfg.nx, cfg.ny, cfg.nz, orders=False, transposed=True)
         ndf.ndf_prepare(ens_t)
         n_rays, n_steps = V // 256, 256
@@ -328,6 +330,16 @@ def main():
                            device=dev)
         ndf.ndf_net_quantize(net_h, P_h, ndf.NDF_PREC_BF16, qp_h)
         out_h = torch.empty((1, V), device=dev)
+        extra = {}
+        if profile_row == "pearson_b256":
+            # 256 references in one read of the ensemble (the many-reference GEMM)
+            refs256 = np.concatenate([[ref], gen.random_vertices(V, 255, seed=2311)])
+            out_256 = torch.empty((256, V), device=dev)
+            ws_256 = torch.empty(ndf.ndf_workspace_bytes(ndf.NDF_OP_PEARSON_FIELD, ens, None,
+                                                         256, ndf.NDF_PREC_SPLIT_BF16),
+                                 dtype=torch.uint8, device=dev)
+            extra["pearson_b256"] = lambda it: ndf.ndf_pearson_field(
+                ens, 0, 0, refs256, out_256, ndf.NDF_PREC_SPLIT_BF16, ws_256)
 
         def rays(it):
             ndf.ndf_infer_points(net, qp, ndf.NDF_PREC_BF16, [ref], ray_pos, out_rp, ws_i)
@@ -352,10 +364,10 @@ def main():
         ppoints(0)
         return {"ndf_points_rays": rays, "ndf_field_difference": diff,
                 "pearson_points": ppoints, "ksg_points": kpoints, "ndf_field_hash": hashed,
-                "train_step_at": train_at}, ray_pos.shape[0]
+                "train_step_at": train_at, **extra}, ray_pos.shape[0]
 
     if a.only:
-        fns = row_fn if a.only in row_fn else next_rows()[0]
+        fns = row_fn if a.only in row_fn else next_rows(a.only)[0]
         ms = _timed(fns[a.only], a.steps, a.warmup)
         print(json.dumps({"row": a.only, "ms": ms, "median_ms": float(np.median(ms))}))
         return

@@ -400,6 +400,22 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
     }
 }
 
+// Tile of round k for the calling wave, or -1 once it has none.  Whole rounds
+// go to the waves in workgroup-major order (the waves of a workgroup take
+// neighbouring tiles, which share grid corners in L2); the last, partial round
+// goes in wave-major order, so its tiles land on every CU, at most one per SIMD
+// (waves w and w + 4 of a workgroup share a SIMD), where each runs alone
+// instead of beside another wave.
+__device__ __forceinline__ int64_t round_tile(int64_t k, int64_t ntiles, int wave_id) {
+    const int wave = __builtin_amdgcn_readfirstlane(wave_id);  // scalar arithmetic below
+    const int64_t W = (int64_t)gridDim.x * kInferWaves;
+    const int64_t full = ntiles / W;
+    if (k < full) return (int64_t)blockIdx.x * kInferWaves + wave + k * W;
+    if (k > full) return -1;
+    const int64_t t = full * W + (int64_t)wave * gridDim.x + blockIdx.x;
+    return t < ntiles ? t : -1;
+}
+
 // MODE 0: field (out[v] = Phi(ref, v) for v < nq); MODE 1: latents of the
 // vertices in qlist (lat_out[n][128], bf16-rounded values stored as FP32);
 // MODE 2: latents of vertices 0 .. nq-1 into the query-latent cache (out);
@@ -547,13 +563,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
-    // MODE 4: every workgroup takes all calibration tiles (against its own reference).
-    // Otherwise waves are numbered wave-major, so the tiles of the last, partial
-    // round land on every CU, at most one per SIMD (waves w and w + 4 of a
-    // workgroup share a SIMD), where each runs alone instead of beside another.
-    const int64_t t0 = MODE == 4 ? wave : (int64_t)wave * gridDim.x + blockIdx.x;
-    const int64_t tstep = MODE == 4 ? kInferWaves : (int64_t)gridDim.x * kInferWaves;
-    for (int64_t tile = t0; tile < ntiles; tile += tstep) {
+    // MODE 4: every workgroup takes all calibration tiles (against its own reference)
+    for (int64_t k = 0;; ++k) {
+        const int64_t tile = MODE == 4 ? wave + k * kInferWaves : round_tile(k, ntiles, wave);
+        if (tile < 0 || tile >= ntiles) break;
         const int64_t row0 = tile * 64;
         // opaque per tile, so the per-lane LDS addresses derived from it are
         // formed inside the loop (base + immediate) instead of hoisted and spilled
@@ -967,9 +980,9 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
-    // waves numbered wave-major, as in infer_kernel
-    for (int64_t tile = (int64_t)wave * gridDim.x + blockIdx.x; tile < ntiles;
-         tile += (int64_t)gridDim.x * kInferWaves) {
+    for (int64_t k = 0;; ++k) {
+        const int64_t tile = round_tile(k, ntiles, wave);
+        if (tile < 0) break;
         const int64_t row0 = tile * 64;
         int h4 = 4 * h;
         asm volatile("" : "+v"(h4));
@@ -1064,20 +1077,22 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     }
 }
 
-// Work of a launch that decodes several references per tile: whole tiles go
-// round-robin to all waves of the grid; the tiles of the last, partial round are
-// split over the references (2, 4, ... parts while the parts still fit in one
-// round), so that round takes a fraction of a tile's time instead of a whole
-// tile's on a fraction of the waves.  Wave-uniform throughout.
+// Work of a launch that decodes several references per tile: whole rounds of
+// tiles as in round_tile; the tiles of the last, partial round are split over
+// the references (2, 4, ... parts while the parts still fit in one round, dealt
+// in wave-major order), so that round takes a fraction of a tile's time instead
+// of a whole tile's on a fraction of the waves.  Wave-uniform throughout.
 struct RefSplit {
-    int64_t w, W, rounds, rem;
+    int64_t w, wt, W, rounds, rem;  // wt: the wave's index in wave-major order (last round)
     int split;
 };
 
 __device__ __forceinline__ RefSplit ref_split(int64_t ntiles, int n_ref, bool allow) {
     RefSplit s;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     s.W = (int64_t)gridDim.x * kInferWaves;
-    s.w = (int64_t)blockIdx.x * kInferWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    s.w = (int64_t)blockIdx.x * kInferWaves + wave;
+    s.wt = (int64_t)wave * gridDim.x + blockIdx.x;
     s.rounds = ntiles / s.W;
     s.rem = ntiles - s.rounds * s.W;
     s.split = 1;
@@ -1096,9 +1111,9 @@ __device__ __forceinline__ bool ref_split_item(const RefSplit &s, int64_t k, int
         r1 = n_ref;
         return true;
     }
-    if (k > s.rounds || s.w >= s.rem * s.split) return false;
-    tile = s.rounds * s.W + s.w / s.split;
-    const int part = (int)(s.w % s.split);
+    if (k > s.rounds || s.wt >= s.rem * s.split) return false;
+    tile = s.rounds * s.W + s.wt / s.split;
+    const int part = (int)(s.wt % s.split);
     r0 = part * n_ref / s.split;
     r1 = (part + 1) * n_ref / s.split;
     return true;
