@@ -544,6 +544,7 @@ def _rooflines(med, N, V):
     for r in roof.values():
         r["frac"] = r["achieved"] / r["peak"]
     roof["ndf_field"]["traffic"] = _measured_traffic("ndf_field")
+    roof["pearson_b64"]["traffic"] = _measured_traffic("pearson_b64")
     roof["ndf_field_fp8"]["traffic"] = _measured_traffic("ndf_field_fp8")
     # the fused training step streams its slabs through HBM: the measured bytes per
     # step over the step's time, beside the MFMA fraction
@@ -595,6 +596,10 @@ _PMC_TRAFFIC = {
     "ndf_field_fp8": ("profiles/pmc_infer_fp8_paper_1760000v.txt",
                       ["paper_2307_02203_amd/csrc/net_infer.hip",
                        "paper_2307_02203_amd/csrc/net.hpp"]),
+    "pearson_b64": ("profiles/pmc_pearson_paper_1760000v_1000m.txt",
+                    ["paper_2307_02203_amd/csrc/pearson.hip"]),
+    "pearson_b256": ("profiles/pmc_pearson_paper_1760000v_1000m.txt",
+                     ["paper_2307_02203_amd/csrc/pearson.hip"]),
     # the sum over the kernels of one step
     "train_step": ("profiles/train_step_kernels_paper_2p18pairs.txt",
                    ["paper_2307_02203_amd/csrc/net_train.hip",
@@ -629,9 +634,15 @@ def _profile_text(row):
 
 
 def _measured_traffic(row):
+    """HBM bytes per launch from the row's counter profile: the line tagged with the row
+    (`traffic_bytes_per_launch[row]: X`, in a profile of several kernels), else the
+    profile's untagged line."""
     import re
     text = _profile_text(row)
-    m_val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text) if text else None
+    if not text:
+        return None
+    m_val = (re.search(r"traffic_bytes_per_launch\[" + re.escape(row) + r"\]: ([0-9.eE+]+)", text)
+             or re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text))
     return float(m_val.group(1)) if m_val else None
 
 
@@ -1005,10 +1016,15 @@ def _config5(a, log):
                      device="cuda")
     st = _stats(_timed(lambda it: ndf.ndf_pearson_field(e, 0, 1, refs, out,
                                                         ndf.NDF_PREC_SPLIT_BF16, ws), 5, 1))
+    kpad = (1000 + 15) // 16 * 16  # members padded to whole 16-member k-steps
     res["pearson_split_bf16_gemm"] = {
         **st, "ms_per_field": st["median"] / N_REF5,
         "hbm_gbs_algorithmic": (4.0 * 1000 * V + 4.0 * N_REF5 * V) / (st["median"] * 1e-3) / 1e9,
-        "mfma_tflops_algorithmic": 3 * 2.0 * N_REF5 * 1024 * V / (st["median"] * 1e-3) / 1e12}
+        # the contraction itself: one product over the members
+        "tflops_algorithmic": 2.0 * N_REF5 * 1000 * V / (st["median"] * 1e-3) / 1e12,
+        # what the matrix cores execute: three bf16 products (hi*hi, hi*lo, lo*hi)
+        "mfma_tflops_executed": 3 * 2.0 * N_REF5 * kpad * V / (st["median"] * 1e-3) / 1e12,
+        "traffic": _measured_traffic("pearson_b256")}
     sample = gen.random_vertices(V, 200, seed=93)
     s_t = torch.as_tensor(sample, device="cuda")
     g = out[:, s_t].cpu().numpy()
