@@ -151,12 +151,16 @@ def test_learned_field_256_refs_fp8_vs_bf16():
                       (ndf.NDF_PREC_FP8_E4M3, fp8_decoder_ops(net))):
         g = out[prec][ri_t, qv_t].cpu().numpy().astype(np.float64)
         check_floor(g, want, nn.forward(net, refs[ri], qv, ops)[0], f"256 refs prec={prec}")
-    # the reference latent of row i is that of refs[i]: a row equals the one-reference call
+    # the reference latent of row i is that of refs[i]: every row equals the one-reference
+    # call, bit for bit (at this size the last, partial round of tiles is split over the
+    # references of each launch, so both halves of a split tile are covered)
     q = torch.empty(ndf.ndf_net_qparam_bytes(c, ndf.NDF_PREC_BF16), dtype=torch.uint8,
                     device="cuda")
     ndf.ndf_net_quantize(c, P, ndf.NDF_PREC_BF16, q)
     o1 = torch.empty((1, V), dtype=torch.float32, device="cuda")
     ws = torch.empty(ndf.infer_ws_bytes(c, 1, ndf.NDF_PREC_BF16), dtype=torch.uint8,
                      device="cuda")
-    ndf.ndf_infer_field(c, q, ndf.NDF_PREC_BF16, refs[200:201], o1, ws)
-    assert torch.equal(o1[0], out[ndf.NDF_PREC_BF16][200])
+    _log("256 one-reference BF16 calls against the rows of the batched call")
+    for i in range(N_REF):
+        ndf.ndf_infer_field(c, q, ndf.NDF_PREC_BF16, refs[i:i + 1], o1, ws)
+        assert torch.equal(o1[0], out[ndf.NDF_PREC_BF16][i]), i
