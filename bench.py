@@ -79,6 +79,9 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--field-runs", type=int, default=50,
+                    help="after the timed steps, time each field row alone this many times "
+                         "(after 5 warm-up calls) for its median and p10/p90; 0 skips")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the oracle comparisons (accuracy, config3 errors, gain)")
@@ -399,6 +402,12 @@ def main():
     st = {r: _stats(v) for r, v in per_row.items()}
     med = {r: s["median"] for r, s in st.items()}
     ms_step = float(np.median(step_ms))
+    # each field row alone, outside the timed steps: a.field_runs calls after 5 warm-ups,
+    # HIP events around every call
+    field_rows = ("ndf_field", "ndf_field_fp8", "ndf_field_cached", "pearson_fp32",
+                  "pearson_b64", "ksg_field")
+    field_runs = ({r: _stats(_timed(row_fn[r], a.field_runs, 5)) for r in field_rows}
+                  if a.field_runs > 0 else {})
     names = {
         "ndf_field": "ndf_field_bf16", "ndf_field_fp8": "ndf_field_fp8",
         "ndf_field_cached": "ndf_field_bf16_cached_query_latents",
@@ -438,6 +447,7 @@ def main():
         },
         "fields": fields,
         "fields_p10_p90": spread,
+        "field_runs": {names[r]: v for r, v in field_runs.items()},
         "speedup_ndf_vs_pearson_fp32": med["pearson_fp32"] / med["ndf_field"],
         "speedup_ndf_vs_ksg": med["ksg_field"] / med["ndf_field"],
         "speedup_ndf_vs_pearson_batch64_per_field": med["pearson_b64"] / N_BATCH / med["ndf_field"],

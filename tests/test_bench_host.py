@@ -93,3 +93,30 @@ def test_recorded_ksg_issue_rates():
     assert 0.5 < issue <= 1.0 and 0.5 < lanes <= 1.0
     r = bench._ksg_roofline(48.0, 1000, 1_760_000)
     assert r["valu_issue_frac"] == issue and r["valu_lanes_active_frac"] == lanes
+
+
+def test_tagged_traffic_lines(tmp_path, monkeypatch):
+    """A profile of several kernels tags each traffic line with its row; a row reads
+    its own line, and an untagged line serves a profile of one kernel."""
+    src = tmp_path / "k.hip"
+    src.write_text("kernel\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    prof = tmp_path / "p.txt"
+    prof.write_text(f"k.hip sha256 prefix at measurement: {sha[:16]}\n"
+                    "  traffic_bytes_per_launch[a]: 1.0e+09\n"
+                    "  traffic_bytes_per_launch[b]: 2.0e+09\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "_PMC_TRAFFIC", {r: ("p.txt", ["k.hip"]) for r in "abc"})
+    assert bench._measured_traffic("a") == pytest.approx(1.0e9)
+    assert bench._measured_traffic("b") == pytest.approx(2.0e9)
+    assert bench._measured_traffic("c") is None
+
+
+def test_recorded_traffic_matches_the_current_sources():
+    """Every committed counter profile the benchmark reports belongs to the committed
+    kernel sources (else the benchmark would report the row's traffic as null)."""
+    for row, lo, hi in (("ndf_field", 1.5e8, 2.0e8), ("ndf_field_fp8", 1.5e8, 2.0e8),
+                        ("pearson_b64", 7.0e9, 8.0e9), ("pearson_b256", 8.5e9, 9.5e9),
+                        ("train_step", 4.0e9, 6.0e9)):
+        t = bench._measured_traffic(row)
+        assert t is not None and lo < t < hi, (row, t)
