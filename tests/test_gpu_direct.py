@@ -220,6 +220,43 @@ def test_odd_member_count_all_estimators():
         assert abs(mi[b] - w[0]) <= MI_TOL
 
 
+@pytest.mark.parametrize("n_members", [11, 75])
+def test_pearson_split_bf16_short_and_ragged_members(n_members):
+    """Split-BF16 Pearson with fewer members than one 16-member k-step (N = 11) and with a
+    ragged last k-step (N = 75), through every contraction kernel: 5 references (one
+    32-reference block), 33 (two blocks), 100 (the one-pass many-reference kernel, whose
+    loads past the last member read member N - 1 against a zero reference operand).
+    Against the oracle, and the 100-reference call bit for bit against calls of 64.
+
+    The bar is the split's own arithmetic bound.  With z = hi + lo in bf16 (unit
+    roundoff 2^-8) each side carries |hi + lo - z| <= 2^-16 |z|, and the dropped lo*lo term
+    is <= 2^-16 |z_r z_v|, so every product is off by at most 3 * 2^-16 |z_r z_v| and
+    |dr| <= 3 * 2^-16 * mean_m |z_r z_v| (<= 4.6e-5 by Cauchy-Schwarz), plus FP32 slack.
+    Over many members the per-member errors cancel far below it (the 1e-5 gate of the
+    configured ensembles); over 11 members they do not."""
+    cfg = gen.CONFIGS["tiny"].with_members(n_members)
+    e = _ens(cfg)
+    x = e.x[0].cpu().numpy()
+    V = cfg.n_vertices
+    xd = x.astype(np.float64)
+    z = (xd - xd.mean(axis=0)) / xd.std(axis=0)
+    refs = np.concatenate([[cfg.ref_v], gen.random_vertices(V, 99, seed=500 + n_members)])
+    for n_ref in (5, 33, 100):
+        _log(f"split-BF16 Pearson, N={n_members}, {n_ref} references")
+        got = ndf.pearson_field(e, refs[:n_ref], prec=ndf.NDF_PREC_SPLIT_BF16).cpu().numpy()
+        worst = 0.0
+        for i, r in enumerate(refs[:n_ref]):
+            err = np.abs(got[i] - direct.pearson_field(x[:, r], x))
+            bound = 3.0 * 2.0 ** -16 * np.mean(np.abs(z[:, r:r + 1] * z), axis=0) + 1e-6
+            assert np.all(err <= bound), (n_members, n_ref, i, float(np.max(err - bound)))
+            worst = max(worst, float(np.max(err)))
+        _log(f"  max|dr| {worst:.2e}")
+    whole = ndf.pearson_field(e, refs, prec=ndf.NDF_PREC_SPLIT_BF16)
+    for r0 in range(0, 100, 64):
+        part = ndf.pearson_field(e, refs[r0:r0 + 64], prec=ndf.NDF_PREC_SPLIT_BF16)
+        assert torch.equal(part, whole[r0:r0 + 64]), r0
+
+
 def test_ksg_without_stored_orders_matches(mid):
     """An ensemble prepared without the per-vertex sorted orders (order = NULL):
     the KSG kernels sort every column themselves and give bit-identical fields,
