@@ -242,7 +242,7 @@ def test_infer_field_parity(name, n_enc):
 
 @pytest.mark.parametrize("name,n_enc", [("mid", 1), ("mid", 2)])
 def test_infer_field_cached_latents_bitwise(name, n_enc):
-    """Fields from the query-latent cache, 35 references (a launch of 32 and a
+    """Fields from the query-latent cache, 35 references (two launches of 16 and a
     ragged one of 3), equal the fused single-reference fields bit for bit; so do
     the fields of one multi-reference ndf_infer_field call, which decodes from a
     latent cache in its workspace."""
