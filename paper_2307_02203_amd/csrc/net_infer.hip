@@ -403,9 +403,9 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 // Tile of round k for the calling wave, or -1 once it has none.  Whole rounds
 // go to the waves in workgroup-major order (the waves of a workgroup take
 // neighbouring tiles, which share grid corners in L2); the last, partial round
-// goes in wave-major order, so its tiles land on every CU, at most one per SIMD
-// (waves w and w + 4 of a workgroup share a SIMD), where each runs alone
-// instead of beside another wave.
+// goes in wave-major order, so its tiles land on every CU and, with the eight
+// waves of a workgroup placed round-robin on the CU's four SIMDs, at most one on
+// each SIMD, where it runs alone instead of beside another wave.
 __device__ __forceinline__ int64_t round_tile(int64_t k, int64_t ntiles, int wave_id) {
     const int wave = __builtin_amdgcn_readfirstlane(wave_id);  // scalar arithmetic below
     const int64_t W = (int64_t)gridDim.x * kInferWaves;
@@ -1120,7 +1120,8 @@ __device__ __forceinline__ bool ref_split_item(const RefSplit &s, int64_t k, int
 }
 
 // Fields from cached query latents, several references per pass: per 64-vertex
-// tile the wave loads the tile's bf16 latents once (16 loads, kept in registers),
+// tile the wave loads the tile's bf16 latents once (16 loads, kept in LDS and
+// registers),
 // then for each reference of the launch forms the product with that reference's
 // latent (the same packed arithmetic as the uncached kernel, so both give the
 // same bits) and runs layers 4, 5 and w6.  A launch decodes up to kMultiRefs
