@@ -313,7 +313,9 @@ __device__ __forceinline__ int64_t cache_chunk(int64_t tile, int kb, int q, int 
 // One 128-wide layer for the wave's 2 x 32 queries.  in: KB k-blocks of B
 // operands.  The accumulators start at the bias, so the epilogue is only the
 // bf16 packing (plus ReLU on the packed pairs, the latent product, or the head).
-template <int KB, int KIND>
+// NQ: query blocks computed (1: only block 0, for a single row such as the
+// reference vertex in a prologue; its bits are those of block 0 with NQ = 2)
+template <int KB, int KIND, int NQ = 2>
 __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                                             const float *__restrict__ bias,
                                             const float *__restrict__ ref,
@@ -339,7 +341,7 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
         for (int kb = 0; kb < KB; ++kb) {
             const bf16x8 a = wf[(ob * KB + kb) * 64 + lane];
             acc0 = mfma32(a, in[kb][0], acc0);
-            acc1 = mfma32(a, in[kb][1], acc1);
+            if (NQ == 2) acc1 = mfma32(a, in[kb][1], acc1);
         }
         if (KIND == LAY_HEAD) {
 #pragma unroll
@@ -348,7 +350,7 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     part[0] = fmaf(wv[i], relu_f32(acc0[4 * g + i]), part[0]);
-                    part[1] = fmaf(wv[i], relu_f32(acc1[4 * g + i]), part[1]);
+                    if (NQ == 2) part[1] = fmaf(wv[i], relu_f32(acc1[4 * g + i]), part[1]);
                 }
             }
         } else {
@@ -359,10 +361,10 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                 for (int e2 = 0; e2 < 4; ++e2) {
                     const int r = 8 * s + 2 * e2;  // rows r, r+1 (same 4-row group)
                     uint32_t p0 = pack_bf16x2(acc0[r], acc0[r + 1]);
-                    uint32_t p1 = pack_bf16x2(acc1[r], acc1[r + 1]);
+                    uint32_t p1 = NQ == 2 ? pack_bf16x2(acc1[r], acc1[r + 1]) : 0u;
                     if (KIND == LAY_RELU) {
                         p0 = relu_bf16x2(p0);
-                        p1 = relu_bf16x2(p1);
+                        if (NQ == 2) p1 = relu_bf16x2(p1);
                     } else if (KIND != LAY_LATENT_CACHE) {  // latent: bf16 values (exact
                                                             // products with the bf16 reference)
                         const int ic = 32 * ob + 8 * (r >> 2) + (r & 3);
@@ -372,7 +374,7 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                                 lat_out[n0 * kH + ic + h4] = bf_lo(p0);
                                 lat_out[n0 * kH + ic + h4 + 1] = bf_hi(p0);
                             }
-                            if (ok[1]) {
+                            if (NQ == 2 && ok[1]) {
                                 lat_out[n1 * kH + ic + h4] = bf_lo(p1);
                                 lat_out[n1 * kH + ic + h4 + 1] = bf_hi(p1);
                             }
@@ -380,7 +382,7 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                             const f32x2 rv = *reinterpret_cast<const f32x2 *>(ref_h + ic);
                             const float ra = rv[0], rb = rv[1];
                             p0 = pack_bf16x2(bf_lo(p0) * ra, bf_hi(p0) * rb);
-                            p1 = pack_bf16x2(bf_lo(p1) * ra, bf_hi(p1) * rb);
+                            if (NQ == 2) p1 = pack_bf16x2(bf_lo(p1) * ra, bf_hi(p1) * rb);
                         }
                     }
                     t0[e2] = p0;
@@ -388,7 +390,7 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
                 }
                 if (KIND == LAY_RELU || KIND == LAY_LATENT) {
                     out[2 * ob + s][0] = __builtin_bit_cast(bf16x8, t0);
-                    out[2 * ob + s][1] = __builtin_bit_cast(bf16x8, t1);
+                    if (NQ == 2) out[2 * ob + s][1] = __builtin_bit_cast(bf16x8, t1);
                 } else if (KIND == LAY_LATENT_CACHE) {
                     u32x4 *cache = reinterpret_cast<u32x4 *>(lat_out);
                     const int64_t tile = row0 / 64;
@@ -400,20 +402,30 @@ __device__ __forceinline__ void dense_layer(const bf16x8 *__restrict__ wf,
     }
 }
 
-// Tile of round k for the calling wave, or -1 once it has none.  Whole rounds
-// go to the waves in workgroup-major order (the waves of a workgroup take
-// neighbouring tiles, which share grid corners in L2); the last, partial round
-// goes in wave-major order, so its tiles land on every CU and, with the eight
-// waves of a workgroup placed round-robin on the CU's four SIMDs, at most one on
-// each SIMD, where it runs alone instead of beside another wave.
-__device__ __forceinline__ int64_t round_tile(int64_t k, int64_t ntiles, int wave_id) {
-    const int wave = __builtin_amdgcn_readfirstlane(wave_id);  // scalar arithmetic below
-    const int64_t W = (int64_t)gridDim.x * kInferWaves;
-    const int64_t full = ntiles / W;
-    if (k < full) return (int64_t)blockIdx.x * kInferWaves + wave + k * W;
-    if (k > full) return -1;
-    const int64_t t = full * W + (int64_t)wave * gridDim.x + blockIdx.x;
-    return t < ntiles ? t : -1;
+// Work of the field and latent kernels: workgroup b owns the contiguous tiles
+// [ntiles b / G, ntiles (b + 1) / G) (neighbouring tiles share grid corners in
+// L2), and its waves claim them one at a time from an LDS counter, so a wave that
+// starts late (wave 0, after the reference latent) simply takes fewer.
+__device__ __forceinline__ int64_t wg_tile_begin(int64_t ntiles, int64_t b) {
+    return ntiles * b / gridDim.x;
+}
+
+__device__ __forceinline__ int64_t claim_tile(int *counter) {
+    int c = 0;
+    if ((threadIdx.x & 63) == 0) c = atomicAdd(counter, 1);
+    return __builtin_amdgcn_readfirstlane(c);
+}
+
+// The reference latent computed in a field kernel's prologue is published with a
+// workgroup-scope release (after its LDS stores) and awaited with an acquire just
+// before its first use, so the other waves start their tiles meanwhile.
+__device__ __forceinline__ void publish_flag(int *flag) {
+    __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void await_flag(int *flag) {
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+        __builtin_amdgcn_s_sleep(1);
 }
 
 // MODE 0: field (out[v] = Phi(ref, v) for v < nq); MODE 1: latents of the
@@ -473,9 +485,17 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
+    __shared__ int s_sync[2];  // reference latent ready, next tile of the workgroup
     const int64_t fref = MODE == 4 ? cal_vertex(blockIdx.x, gridDim.x, A.V) : A.fuse_ref;
+    // a field of the shared encoder overlaps the reference latent with the first
+    // tiles (a two-encoder field swaps the encoder's weights after it: a barrier)
+    constexpr bool kOverlap = (MODE == 0 || MODE == 3) && !SEP;
 
     const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_sync[0] = 0;
+        s_sync[1] = 0;
+    }
     if (GO) {
         for (int i = tid; i < kFragW1; i += kInferThreads) s_w1[i] = A.w[3][i];
         for (int i = tid; i < kFragW; i += kInferThreads) s_w[3][i] = A.w[4][i];
@@ -545,12 +565,18 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             }
             float part[2] = {0.f, 0.f};
             if (!GO) {
-            dense_layer<KB1, LAY_RELU>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok, lane, h4);
-            dense_layer<8, LAY_RELU>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0, ok, lane, h4);
-            dense_layer<8, LAY_LATENT_OUT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref, 0, ok,
-                                           lane, h4);
+            // query block 0 only: the reference is its row 0
+            dense_layer<KB1, LAY_RELU, 1>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok,
+                                          lane, h4);
+            dense_layer<8, LAY_RELU, 1>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0, ok,
+                                        lane, h4);
+            dense_layer<8, LAY_LATENT_OUT, 1>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref, 0,
+                                              ok, lane, h4);
             }
+            if (kOverlap) publish_flag(&s_sync[0]);
         }
+    }
+    if (fuse && !kOverlap) {
         __syncthreads();
         if (SEP && !GO) {  // the query encoder's layers replace the reference encoder's
             for (int i = tid; i < kW1; i += kInferThreads) s_w1[i] = A.w[0][i];
@@ -564,9 +590,12 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
     // MODE 4: every workgroup takes all calibration tiles (against its own reference)
+    const int64_t t_lo = MODE == 4 ? 0 : wg_tile_begin(ntiles, blockIdx.x);
+    const int64_t t_hi = MODE == 4 ? ntiles : wg_tile_begin(ntiles, blockIdx.x + 1);
+    bool await_ref = kOverlap && fuse;
     for (int64_t k = 0;; ++k) {
-        const int64_t tile = MODE == 4 ? wave + k * kInferWaves : round_tile(k, ntiles, wave);
-        if (tile < 0 || tile >= ntiles) break;
+        const int64_t tile = MODE == 4 ? wave + k * kInferWaves : t_lo + claim_tile(&s_sync[1]);
+        if (tile >= t_hi) break;
         const int64_t row0 = tile * 64;
         // opaque per tile, so the per-lane LDS addresses derived from it are
         // formed inside the loop (base + immediate) instead of hoisted and spilled
@@ -634,6 +663,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         }
         float part[2] = {0.f, 0.f};
         if (GO) {
+            if (await_ref) {
+                await_flag(&s_sync[0]);
+                await_ref = false;
+            }
             // product of the query's and the reference's grid features (exact in
             // FP32 for bf16 values, then rounded to bf16), decoder on top
 #pragma unroll
@@ -674,6 +707,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             dense_layer<8, LAY_LATENT_CACHE>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, out, row0,
                                              ok, lane, h4);
             continue;
+        }
+        if (await_ref) {  // layer 3's epilogue forms the product with the reference latent
+            await_flag(&s_sync[0]);
+            await_ref = false;
         }
         dense_layer<8, LAY_LATENT>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, nullptr, row0, ok,
                                    lane, h4);
@@ -776,7 +813,8 @@ struct InferArgs8 {
 
 constexpr int kFrag8 = 4 * 2 * 64;  // i32x8 per 128x128 fp8 layer
 
-template <int KIND, bool BF16IN, int KB1>
+// NQ as in dense_layer
+template <int KIND, bool BF16IN, int KB1, int NQ = 2>
 __device__ __forceinline__ void dense_layer_fp8(
     const bf16x8 *__restrict__ w16, const i32x8 *__restrict__ w8, const int *__restrict__ se,
     const float *__restrict__ bias, const float *__restrict__ ref, const float *__restrict__ w6,
@@ -840,7 +878,7 @@ __device__ __forceinline__ void dense_layer_fp8(
                 for (int kb = 0; kb < KB1; ++kb) {
                     const bf16x8 a = w16[(ob * KB1 + kb) * 64 + lane];
                     acc[o][0] = mfma32(a, in16[kb][0], acc[o][0]);
-                    acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
+                    if (NQ == 2) acc[o][1] = mfma32(a, in16[kb][1], acc[o][1]);
                 }
             } else {
 #pragma unroll
@@ -848,14 +886,14 @@ __device__ __forceinline__ void dense_layer_fp8(
                     const i32x8 a = w8[(ob * 2 + kb) * 64 + lane];
                     const int sa = se[(32 * ob + il) * 4 + 2 * kb + hh];
                     acc[o][0] = mfma_fp8(a, sa, in8[kb][0], sin, acc[o][0]);
-                    acc[o][1] = mfma_fp8(a, sa, in8[kb][1], sin, acc[o][1]);
+                    if (NQ == 2) acc[o][1] = mfma_fp8(a, sa, in8[kb][1], sin, acc[o][1]);
                 }
             }
             // fetch one output block's weights at a time (32 registers, not 64)
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             if (KIND == LAY_LATENT_OUT) {
                 if (ok[q]) {
                     float *dst = lat_out + (row0 + 32 * q + il) * kH + h4;
@@ -907,8 +945,13 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
     __shared__ __attribute__((aligned(16))) float s_b[5][kH];
     __shared__ __attribute__((aligned(16))) float s_w6[kH];
     __shared__ __attribute__((aligned(16))) float s_ref[kH];
+    __shared__ int s_sync[2];  // reference latent ready, next tile of the workgroup
 
     const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_sync[0] = 0;
+        s_sync[1] = 0;
+    }
     for (int i = tid; i < 4 * KB1 * 64; i += kInferThreads) s_w1[i] = A.w1[i];
     const int nlay = kField ? 4 : 2;
     for (int L = 0; L < nlay; ++L)
@@ -966,23 +1009,28 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
             }
             i32x8 a8[2][2], b8[2][2];
             float part[2] = {0.f, 0.f};
-            dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8,
-                                            0, a8, as.s[0], as.clip[0], part, nullptr, 0, ok,
-                                            lane, h4);
-            dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16,
-                                             a8, as.sbyte[0], b8, as.s[1], as.clip[1], part,
-                                             nullptr, 0, ok, lane, h4);
-            dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6,
-                                                   g16, b8, as.sbyte[1], a8, 0.f, 0.f, part,
-                                                   s_ref, 0, ok, lane, h4);
+            // query block 0 only: the reference is its row 0
+            dense_layer_fp8<LAY_RELU, true, KB1, 1>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6,
+                                                    g16, b8, 0, a8, as.s[0], as.clip[0], part,
+                                                    nullptr, 0, ok, lane, h4);
+            dense_layer_fp8<LAY_RELU, false, KB1, 1>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6,
+                                                     g16, a8, as.sbyte[0], b8, as.s[1],
+                                                     as.clip[1], part, nullptr, 0, ok, lane, h4);
+            dense_layer_fp8<LAY_LATENT_OUT, false, KB1, 1>(nullptr, s_q[1], s_e[1], s_b[2], s_ref,
+                                                           s_w6, g16, b8, as.sbyte[1], a8, 0.f,
+                                                           0.f, part, s_ref, 0, ok, lane, h4);
+            // the other waves start their tiles meanwhile (as in infer_kernel)
+            publish_flag(&s_sync[0]);
         }
-        __syncthreads();
     }
     const float b6 = A.b6[0];
     const int64_t ntiles = ceil_div(nq, 64);
+    const int64_t t_hi = wg_tile_begin(ntiles, blockIdx.x + 1);
+    const int64_t t_lo = wg_tile_begin(ntiles, blockIdx.x);
+    bool await_ref = fuse;
     for (int64_t k = 0;; ++k) {
-        const int64_t tile = round_tile(k, ntiles, wave);
-        if (tile < 0) break;
+        const int64_t tile = t_lo + claim_tile(&s_sync[1]);
+        if (tile >= t_hi) break;
         const int64_t row0 = tile * 64;
         int h4 = 4 * h;
         asm volatile("" : "+v"(h4));
@@ -1060,6 +1108,10 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16, a8,
                                          as.sbyte[0], b8, as.s[1], as.clip[1], part, nullptr, row0,
                                          ok, lane, h4);
+        if (await_ref) {  // layer 3's epilogue forms the product with the reference latent
+            await_flag(&s_sync[0]);
+            await_ref = false;
+        }
         dense_layer_fp8<LAY_LATENT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6, g16, b8,
                                            as.sbyte[1], a8, as.s[2], as.clip[2], part, nullptr,
                                            row0, ok, lane, h4);
@@ -1078,10 +1130,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
 }
 
 // Work of a launch that decodes several references per tile: whole rounds of
-// tiles as in round_tile; the tiles of the last, partial round are split over
-// the references (2, 4, ... parts while the parts still fit in one round, dealt
-// in wave-major order), so that round takes a fraction of a tile's time instead
-// of a whole tile's on a fraction of the waves.  Wave-uniform throughout.
+// tiles go to the waves workgroup by workgroup (a workgroup's waves take
+// neighbouring tiles); the tiles of the last, partial round are split over the
+// references (2, 4, ... parts while the parts still fit in one round, dealt in
+// wave-major order), so that round takes a fraction of a tile's time instead of a
+// whole tile's on a fraction of the waves.  Wave-uniform throughout.
 struct RefSplit {
     int64_t w, wt, W, rounds, rem;  // wt: the wave's index in wave-major order (last round)
     int split;
