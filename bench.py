@@ -619,8 +619,8 @@ _PMC_TRAFFIC = {
 
 def _profile_text(row):
     """The counter profile of `row` while each of its kernel sources still matches
-    the hash recorded there (`<file> sha256 prefix at measurement: <hex>`), else
-    None."""
+    the hash recorded there (`<file> sha256 prefix at measurement: <hex>`, or after a
+    comment- or whitespace-only edit of it), else None."""
     import hashlib
     import re
     if row not in _PMC_TRAFFIC:
@@ -637,7 +637,7 @@ def _profile_text(row):
             return None
         base = os.path.basename(src)
         shas = re.findall(re.escape(base) + r" sha256 prefix (?:at measurement|after a "
-                          r"comment-only edit): ([0-9a-f]+)", text)
+                          r"(?:comment|whitespace)-only edit): ([0-9a-f]+)", text)
         if not shas or not any(sha.startswith(h) for h in shas):
             return None
     return text

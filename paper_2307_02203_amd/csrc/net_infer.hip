@@ -565,13 +565,13 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
             }
             float part[2] = {0.f, 0.f};
             if (!GO) {
-            // query block 0 only: the reference is its row 0
-            dense_layer<KB1, LAY_RELU, 1>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0, ok,
-                                          lane, h4);
-            dense_layer<8, LAY_RELU, 1>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0, ok,
-                                        lane, h4);
-            dense_layer<8, LAY_LATENT_OUT, 1>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref, 0,
+                // query block 0 only: the reference is its row 0
+                dense_layer<KB1, LAY_RELU, 1>(s_w1, s_b[0], s_ref, s_w6, a, b, part, nullptr, 0,
                                               ok, lane, h4);
+                dense_layer<8, LAY_RELU, 1>(s_w[0], s_b[1], s_ref, s_w6, b, a, part, nullptr, 0,
+                                            ok, lane, h4);
+                dense_layer<8, LAY_LATENT_OUT, 1>(s_w[1], s_b[2], s_ref, s_w6, a, b, part, s_ref,
+                                                  0, ok, lane, h4);
             }
             if (kOverlap) publish_flag(&s_sync[0]);
         }

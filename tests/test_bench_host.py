@@ -78,6 +78,12 @@ def test_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     prof.write_text(prof.read_text() +
                     f"k.hip sha256 prefix after a comment-only edit: {sha2[:16]}\n")
     assert bench._measured_traffic("k") == pytest.approx(1.5e9)
+    src.write_text("kernel  v2\n")
+    assert bench._measured_traffic("k") is None
+    sha3 = hashlib.sha256(src.read_bytes()).hexdigest()
+    prof.write_text(prof.read_text() +
+                    f"k.hip sha256 prefix after a whitespace-only edit: {sha3[:16]}\n")
+    assert bench._measured_traffic("k") == pytest.approx(1.5e9)
 
 
 def test_recorded_ksg_traffic_matches_the_current_source():
