@@ -224,14 +224,17 @@ __global__ __launch_bounds__(256) void pearson_gemm_kernel(
 // workgroup loads the 16 x 128 block of x once (one member row segment of 512
 // bytes per 128 threads), standardises and splits it into hi/lo bf16 and
 // stages it in LDS in MFMA B-operand order; all four waves read their B
-// operands from there (double-buffered, one barrier per k-step).  Step ks
-// issues the fragments of step ks + 1 and then the x loads of step ks + 2, so
-// the x values have two k-steps to arrive.  No load sits behind a branch (rows
-// past the last member read member N - 1, where the reference operand is zero,
-// and columns past the last vertex read a real vertex): with a branch the
-// compiler's wait for the fragments also drains the x loads just issued.  The
-// per-element split and the order of the MFMAs per accumulator match
-// pearson_gemm_kernel, so both give the same bits.
+// operands from there.  Three LDS buffers, one barrier per k-step: step ks
+// multiplies on buffer ks % 3, stages x of step ks + 2 into buffer (ks + 2) % 3
+// and loads x of step ks + 4 (two k-steps to arrive, three register sets); the
+// B operands of tiles 0 and 1 are read a step ahead (during the previous step's
+// MFMAs), those of tiles 2 and 3 at the start of the step, behind tiles 0 and
+// 1's MFMAs, so no MFMA waits for an LDS read issued after the barrier.  No load
+// sits behind a branch (rows past the last member read member N - 1, where the
+// reference operand is zero, and columns past the last vertex read a real
+// vertex): with a branch the compiler's wait for the fragments also drains the
+// x loads just issued.  The per-element split and the order of the MFMAs per
+// accumulator match pearson_gemm_kernel, so both give the same bits.
 constexpr int kWideVerts = 128;
 constexpr int kWideTiles = kWideVerts / 32;
 constexpr int kWideRefs = 256;
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(256, 2) void pearson_gemm_wide_kernel(
     const float *__restrict__ x, const double *__restrict__ mean,
     const double *__restrict__ inv_std, int N, int64_t V, const bf16x8 *__restrict__ afrag,
     int n_ib_total, int n_ref, float *__restrict__ out) {
-    __shared__ bf16x8 s_bop[2][kWideTiles][2][64];  // [buffer][vertex tile][hi, lo][lane]
+    __shared__ bf16x8 s_bop[3][kWideTiles][2][64];  // [buffer][vertex tile][hi, lo][lane]
     const int tid = threadIdx.x;
     const int lane = tid & 63, jl = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -291,6 +294,14 @@ __global__ __launch_bounds__(256, 2) void pearson_gemm_wide_kernel(
             a[i][1] = afrag[fb + 64 + lane];
         }
     };
+    // tiles 0 and 1 of a step's B operands (hi, lo), read a step ahead
+    auto bfetch01 = [&](int buf, bf16x8 (&bp)[2][2]) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            bp[t][0] = s_bop[buf][t][0][lane];
+            bp[t][1] = s_bop[buf][t][1][lane];
+        }
+    };
 
     f32x16 acc[2][kWideTiles];
 #pragma unroll
@@ -300,52 +311,80 @@ __global__ __launch_bounds__(256, 2) void pearson_gemm_wide_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][t][r] = 0.f;
 
-    // step ks: MFMAs on LDS buffer ks & 1 with the fragments of step ks; x of
-    // step ks + 1 (xnext, loaded a step earlier) is staged into the other buffer,
-    // whose last reader was step ks - 1, before the previous barrier
+    // step ks: MFMAs on buffer ks % 3 (tiles 0, 1 from registers read a step
+    // earlier, tiles 2, 3 read now), tiles 0, 1 of step ks + 1 read ahead, x of
+    // step ks + 2 staged into buffer (ks + 2) % 3 (last read in step ks - 1, before
+    // the previous barrier) and x of step ks + 4 loaded
     auto step = [&](int ks, const bf16x8 (&acur)[2][2], bf16x8 (&anext)[2][2],
-                    float (&xfree)[8], const float (&xnext)[8]) {
-        const int buf = ks & 1;
+                    const bf16x8 (&bcur)[2][2], bf16x8 (&bnext)[2][2],
+                    const float (&xstage)[8], float (&xload)[8]) {
+        const int buf = ks % 3;
         afetch(ks + 1, anext);
-        load(ks + 2, xfree);
         if (active) {
-            bf16x8 bhi[kWideTiles], blo[kWideTiles];
+            bf16x8 b23[2][2];
 #pragma unroll
-            for (int t = 0; t < kWideTiles; ++t) {
-                bhi[t] = s_bop[buf][t][0][lane];
-                blo[t] = s_bop[buf][t][1][lane];
+            for (int t = 0; t < 2; ++t) {
+                b23[t][0] = s_bop[buf][2 + t][0][lane];
+                b23[t][1] = s_bop[buf][2 + t][1][lane];
             }
+            // the same per-accumulator order as the other kernels: hi.hi, hi.lo, lo.hi
 #pragma unroll
-            for (int t = 0; t < kWideTiles; ++t)
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][0], bhi[t], acc[i][t]);
+                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][0], bcur[t][0], acc[i][t]);
 #pragma unroll
-            for (int t = 0; t < kWideTiles; ++t)
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][0], blo[t], acc[i][t]);
+                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][0], bcur[t][1], acc[i][t]);
 #pragma unroll
-            for (int t = 0; t < kWideTiles; ++t)
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][1], bhi[t], acc[i][t]);
+                for (int i = 0; i < 2; ++i) acc[i][t] = mfma32(acur[i][1], bcur[t][0], acc[i][t]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][2 + t] = mfma32(acur[i][0], b23[t][0], acc[i][2 + t]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][2 + t] = mfma32(acur[i][0], b23[t][1], acc[i][2 + t]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acc[i][2 + t] = mfma32(acur[i][1], b23[t][0], acc[i][2 + t]);
+            bfetch01((ks + 1) % 3, bnext);
         }
-        stage(xnext, buf ^ 1);
+        stage(xstage, (ks + 2) % 3);
+        load(ks + 4, xload);
         __syncthreads();
     };
-    // x of two k-steps in flight: entering step ks, xa / xb alternate as the
-    // free registers and those holding step ks + 1
-    float xa[8], xb[8];
-    bf16x8 a0[2][2], a1[2][2];
+    float x0[8], x1[8], x2[8];
+    bf16x8 a0[2][2], a1[2][2], b0[2][2], b1[2][2];
     afetch(0, a0);
-    load(0, xa);
-    load(1, xb);
-    stage(xa, 0);
+    load(0, x0);
+    load(1, x1);
+    load(2, x2);
+    stage(x0, 0);
+    stage(x1, 1);
+    load(3, x0);
     __syncthreads();
+    if (active) bfetch01(0, b0);
+    // x(j) lives in set j % 3 of {x0, x1, x2}: step ks stages x(ks + 2) and loads
+    // x(ks + 4) into the set that x(ks + 1) left in the step before
     int ks = 0;
-    for (; ks + 1 < ksteps; ks += 2) {
-        step(ks, a0, a1, xa, xb);
-        step(ks + 1, a1, a0, xb, xa);
+    for (; ks + 5 < ksteps; ks += 6) {
+        step(ks, a0, a1, b0, b1, x2, x1);
+        step(ks + 1, a1, a0, b1, b0, x0, x2);
+        step(ks + 2, a0, a1, b0, b1, x1, x0);
+        step(ks + 3, a1, a0, b1, b0, x2, x1);
+        step(ks + 4, a0, a1, b0, b1, x0, x2);
+        step(ks + 5, a1, a0, b1, b0, x1, x0);
     }
-    if (ks < ksteps) step(ks, a0, a1, xa, xb);
+    if (ks < ksteps) step(ks, a0, a1, b0, b1, x2, x1);
+    if (ks + 1 < ksteps) step(ks + 1, a1, a0, b1, b0, x0, x2);
+    if (ks + 2 < ksteps) step(ks + 2, a0, a1, b0, b1, x1, x0);
+    if (ks + 3 < ksteps) step(ks + 3, a1, a0, b1, b0, x2, x1);
+    if (ks + 4 < ksteps) step(ks + 4, a0, a1, b0, b1, x0, x2);
     if (!active) return;
     const float invN = 1.0f / (float)N;
 #pragma unroll
