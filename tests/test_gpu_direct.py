@@ -257,6 +257,34 @@ def test_pearson_split_bf16_short_and_ragged_members(n_members):
         assert torch.equal(part, whole[r0:r0 + 64]), r0
 
 
+@pytest.mark.parametrize("n_members", [96, 100, 120, 140, 150, 170, 192])
+def test_pearson_many_refs_every_kstep_count(n_members):
+    """The many-reference kernel runs its k-steps six to a loop iteration (three LDS
+    buffers, three x register sets, two fragment sets) with the remaining one to five
+    after the loop: member counts whose 16-member k-step counts are 6 .. 12 take every
+    remainder.  100 references through it, bit for bit against calls of 64 (the
+    64-reference kernel, another code path), and three of them against the oracle
+    within the split's arithmetic bound."""
+    cfg = gen.CONFIGS["tiny"].with_members(n_members)
+    e = _ens(cfg)
+    x = e.x[0].cpu().numpy()
+    V = cfg.n_vertices
+    xd = x.astype(np.float64)
+    z = (xd - xd.mean(axis=0)) / xd.std(axis=0)
+    refs = np.concatenate([[cfg.ref_v], gen.random_vertices(V, 99, seed=700 + n_members)])
+    _log(f"split-BF16 Pearson, N={n_members} ({(n_members + 15) // 16} k-steps), 100 references")
+    whole = ndf.pearson_field(e, refs, prec=ndf.NDF_PREC_SPLIT_BF16)
+    for r0 in range(0, 100, 64):
+        part = ndf.pearson_field(e, refs[r0:r0 + 64], prec=ndf.NDF_PREC_SPLIT_BF16)
+        assert torch.equal(part, whole[r0:r0 + 64]), r0
+    got = whole.cpu().numpy()
+    for i in (0, 37, 99):
+        r = refs[i]
+        err = np.abs(got[i] - direct.pearson_field(x[:, r], x))
+        bound = 3.0 * 2.0 ** -16 * np.mean(np.abs(z[:, r:r + 1] * z), axis=0) + 1e-6
+        assert np.all(err <= bound), (n_members, i, float(np.max(err - bound)))
+
+
 def test_ksg_without_stored_orders_matches(mid):
     """An ensemble prepared without the per-vertex sorted orders (order = NULL):
     the KSG kernels sort every column themselves and give bit-identical fields,
