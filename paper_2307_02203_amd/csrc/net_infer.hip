@@ -1023,7 +1023,8 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
             publish_flag(&s_sync[0]);
         }
     }
-    const float b6 = A.b6[0];
+    // uniform: a scalar register, not a VGPR held across the tile loop
+    const float b6 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.b6[0])));
     const int64_t ntiles = ceil_div(nq, 64);
     const int64_t t_hi = wg_tile_begin(ntiles, blockIdx.x + 1);
     const int64_t t_lo = wg_tile_begin(ntiles, blockIdx.x);
@@ -1032,8 +1033,12 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         const int64_t tile = t_lo + claim_tile(&s_sync[1]);
         if (tile >= t_hi) break;
         const int64_t row0 = tile * 64;
+        // opaque per tile, like h4: the lane-dependent selects and addresses below
+        // are formed inside the loop instead of hoisted and spilled
         int h4 = 4 * h;
         asm volatile("" : "+v"(h4));
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
         bool ok[2];
         int64_t vq[2];
         float pq[2][3];
@@ -1048,11 +1053,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         bf16x8 g16[KB1][2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-            const uint16_t *grid = h ? A.grid[2 * kb + 1] : A.grid[2 * kb];
+            const uint16_t *grid = h4 ? A.grid[2 * kb + 1] : A.grid[2 * kb];
             int R[3];
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) R[ax] = h ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
-            const uint32_t hm = HASH ? (h ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
+            for (int ax = 0; ax < 3; ++ax) R[ax] = h4 ? A.g.R[2 * kb + 1][ax] : A.g.R[2 * kb][ax];
+            const uint32_t hm = HASH ? (h4 ? A.g.hmask[2 * kb + 1] : A.g.hmask[2 * kb]) : 0u;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 int idx[8];
@@ -1094,32 +1099,32 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         i32x8 a8[2][2], b8[2][2];
         float part[2] = {0.f, 0.f};
         dense_layer_fp8<LAY_RELU, true>(s_w1, nullptr, nullptr, s_b[0], s_ref, s_w6, g16, b8, 0,
-                                        a8, as.s[0], as.clip[0], part, nullptr, row0, ok, lane,
+                                        a8, as.s[0], as.clip[0], part, nullptr, row0, ok, ln,
                                         h4);
         if (MODE == 1) {
             dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16,
                                              a8, as.sbyte[0], b8, as.s[1], as.clip[1], part,
-                                             nullptr, row0, ok, lane, h4);
+                                             nullptr, row0, ok, ln, h4);
             dense_layer_fp8<LAY_LATENT_OUT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6,
                                                    g16, b8, as.sbyte[1], a8, 0.f, 0.f, part, out,
-                                                   row0, ok, lane, h4);
+                                                   row0, ok, ln, h4);
             continue;
         }
         dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[0], s_e[0], s_b[1], s_ref, s_w6, g16, a8,
                                          as.sbyte[0], b8, as.s[1], as.clip[1], part, nullptr, row0,
-                                         ok, lane, h4);
+                                         ok, ln, h4);
         if (await_ref) {  // layer 3's epilogue forms the product with the reference latent
             await_flag(&s_sync[0]);
             await_ref = false;
         }
         dense_layer_fp8<LAY_LATENT, false>(nullptr, s_q[1], s_e[1], s_b[2], s_ref, s_w6, g16, b8,
                                            as.sbyte[1], a8, as.s[2], as.clip[2], part, nullptr,
-                                           row0, ok, lane, h4);
+                                           row0, ok, ln, h4);
         dense_layer_fp8<LAY_RELU, false>(nullptr, s_q[2], s_e[2], s_b[3], s_ref, s_w6, g16, a8,
                                          as.sbyte[2], b8, as.s[3], as.clip[3], part, nullptr, row0,
-                                         ok, lane, h4);
+                                         ok, ln, h4);
         dense_layer_fp8<LAY_HEAD, false>(nullptr, s_q[3], s_e[3], s_b[4], s_ref, s_w6, g16, b8,
-                                         as.sbyte[3], a8, 0.f, 0.f, part, nullptr, row0, ok, lane,
+                                         as.sbyte[3], a8, 0.f, 0.f, part, nullptr, row0, ok, ln,
                                          h4);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
