@@ -293,6 +293,23 @@ struct InferArgs {
 constexpr int kFragW1 = 4 * 2 * 64;   // bf16x8 elements
 constexpr int kFragW = 4 * 8 * 64;
 
+// Copy COUNT elements into LDS with every load of a thread issued before its
+// first store (a loop over i = tid, tid + 512, ... waits for each load in turn:
+// some twenty L2 round trips per workgroup before its first tile).  Loads past
+// COUNT read element COUNT - 1 and are not stored, so no load sits behind a branch.
+template <int COUNT, typename T>
+__device__ __forceinline__ void stage_lds(T *__restrict__ dst, const T *__restrict__ src,
+                                          int tid) {
+    constexpr int kIt = (COUNT + kInferThreads - 1) / kInferThreads;
+    T v[kIt];
+#pragma unroll
+    for (int j = 0; j < kIt; ++j) v[j] = src[min(tid + j * kInferThreads, COUNT - 1)];
+#pragma unroll
+    for (int j = 0; j < kIt; ++j)
+        if (COUNT % kInferThreads == 0 || tid + j * kInferThreads < COUNT)
+            dst[tid + j * kInferThreads] = v[j];
+}
+
 // Corner cells (int32) and weights of vertex v on a level of sizes R; same
 // arithmetic as the training lookup.  HASH: the level may be hashed (hm != 0).
 template <bool HASH>
@@ -502,11 +519,11 @@ __global__ __launch_bounds__(kInferThreads) void infer_kernel(InferArgs A,
         for (int i = tid; i < 2 * kH; i += kInferThreads)
             s_b[3 + i / kH][i % kH] = A.b[3 + i / kH][i % kH];
     } else {
-        for (int i = tid; i < kW1; i += kInferThreads) s_w1[i] = (SEP ? A.rw[0] : A.w[0])[i];
-        const int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
+        stage_lds<kW1>(s_w1, SEP ? A.rw[0] : A.w[0], tid);
+        constexpr int nlay = kField ? 4 : 2;  // latent modes need W2, W3 only
+#pragma unroll
         for (int L = 0; L < nlay; ++L)
-            for (int i = tid; i < kFragW; i += kInferThreads)
-                s_w[L][i] = (SEP && L < 2 ? A.rw[L + 1] : A.w[L + 1])[i];
+            stage_lds<kFragW>(s_w[L], SEP && L < 2 ? A.rw[L + 1] : A.w[L + 1], tid);
         for (int i = tid; i < 5 * kH; i += kInferThreads)
             s_b[i / kH][i % kH] = (SEP && i < 3 * kH ? A.rb[i / kH] : A.b[i / kH])[i % kH];
     }
@@ -952,12 +969,12 @@ __global__ __launch_bounds__(kInferThreads) void infer_fp8_kernel(InferArgs8 A,
         s_sync[0] = 0;
         s_sync[1] = 0;
     }
-    for (int i = tid; i < 4 * KB1 * 64; i += kInferThreads) s_w1[i] = A.w1[i];
-    const int nlay = kField ? 4 : 2;
-    for (int L = 0; L < nlay; ++L)
-        for (int i = tid; i < kFrag8; i += kInferThreads) s_q[L][i] = A.q[L][i];
-    for (int i = tid; i < 4 * kH * 4; i += kInferThreads)
-        s_e[i / (kH * 4)][i % (kH * 4)] = A.se[i / (kH * 4)][i % (kH * 4)];
+    stage_lds<4 * KB1 * 64>(s_w1, A.w1, tid);
+    constexpr int nlay = kField ? 4 : 2;
+#pragma unroll
+    for (int L = 0; L < nlay; ++L) stage_lds<kFrag8>(s_q[L], A.q[L], tid);
+#pragma unroll
+    for (int L = 0; L < 4; ++L) stage_lds<kH * 4>(s_e[L], A.se[L], tid);
     for (int i = tid; i < 5 * kH; i += kInferThreads) s_b[i / kH][i % kH] = A.b[i / kH][i % kH];
     const bool fuse = kField && A.fuse_ref >= 0;
     for (int i = tid; i < kH; i += kInferThreads) {
